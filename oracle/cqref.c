@@ -1,0 +1,560 @@
+/* CPU oracle for exact weighted k-means colour quantization.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the CPU
+ * baseline of the benchmark, never by the product path.  Single-threaded, plain
+ * C, FP64 distances, exact integer histogram and sums.  Build with
+ * -O2 -ffp-contract=off (no FMA contraction, no fast-math).
+ *
+ * Paper: M. E. Celebi, "Improving the Performance of K-Means for Color
+ * Quantization".  Section references below are to that paper.
+ *
+ * Readings where the paper is silent or loose (each is listed in the design
+ * notes of the repository):
+ *  - weights are the integer pixel counts n_i; the division by N of Section 2.2
+ *    cancels in the weighted mean and in the relative stopping test;
+ *  - the first iteration is a full search (Algo. 2 uses m[i] before any
+ *    assignment exists); later iterations scan row m[i] of the sorted table;
+ *  - each sorted row starts with its own centre and orders the others by
+ *    (distance, index); ties in the nearest-centre choice go to the lowest index;
+ *  - the pruning test stops only when d[p][t] > 4 prev (1 + 1e-12), so that a
+ *    skipped centre is provably farther than c_p despite FP64 rounding;
+ *  - an empty cluster keeps its previous centre;
+ *  - SSE_i is evaluated after the centre update from exact integer cluster
+ *    statistics; stop when (SSE_{i-1} - SSE_i) <= tol * SSE_i, when SSE_i == 0,
+ *    or at max_iters;
+ *  - random choices use splitmix64 with a fixed draw order (documented below).
+ */
+#include "cqref.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+#define NKEYS (1u << 24)
+
+/* ------------------------------------------------------------------------- */
+/* Random numbers: splitmix64 (G. L. Steele, D. Lea, C. H. Flood, "Fast      */
+/* splittable pseudorandom number generators", OOPSLA 2014).                 */
+/* ------------------------------------------------------------------------- */
+uint64_t cqref_splitmix64_next(uint64_t* s)
+{
+    uint64_t z;
+    *s += 0x9E3779B97F4A7C15ull;
+    z = *s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Uniform integer in [0, T): draws below (2^64 mod T) are rejected so that the
+ * accepted range is a whole number of copies of [0, T). */
+uint64_t cqref_uniform_below(uint64_t* s, uint64_t T)
+{
+    uint64_t reject_below = (0 - T) % T;
+    for (;;) {
+        uint64_t r = cqref_splitmix64_next(s);
+        if (r >= reject_below)
+            return r % T;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Colour helpers                                                            */
+/* ------------------------------------------------------------------------- */
+static void key_rgb(uint32_t key, int* r, int* g, int* b)
+{
+    *r = (int)((key >> 16) & 255u);
+    *g = (int)((key >> 8) & 255u);
+    *b = (int)(key & 255u);
+}
+
+/* Squared Euclidean distance between two integer colours (exact). */
+static int64_t dist_int(int r0, int g0, int b0, int r1, int g1, int b1)
+{
+    int64_t dr = r0 - r1, dg = g0 - g1, db = b0 - b1;
+    return dr * dr + dg * dg + db * db;
+}
+
+/* Squared Euclidean distance, FP64, evaluated as (dx*dx + dy*dy) + dz*dz. */
+static double dist_f64(double x0, double x1, double x2, const double* c)
+{
+    double d0 = x0 - c[0];
+    double d1 = x1 - c[1];
+    double d2 = x2 - c[2];
+    return d0 * d0 + d1 * d1 + d2 * d2;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Histogram: Section 2.2, items 1 and 2.                                    */
+/* The paper finds unique colours with a chained hash table; the result is   */
+/* the set of distinct colours with their frequencies, which a dense count    */
+/* over all 2^24 colours yields directly, in ascending key order.            */
+/* ------------------------------------------------------------------------- */
+int cqref_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride,
+                    uint32_t* keys, uint32_t* counts, int64_t capacity, int64_t* n_unique)
+{
+    if (!img || H <= 0 || W <= 0 || row_stride < 3 * (int64_t)W || !n_unique || capacity < 0)
+        return CQREF_EINVAL;
+    if (capacity > 0 && (!keys || !counts))
+        return CQREF_EINVAL;
+    uint32_t* cnt = (uint32_t*)calloc(NKEYS, sizeof(uint32_t));
+    if (!cnt)
+        return CQREF_ENOMEM;
+    for (int32_t y = 0; y < H; ++y) {
+        const uint8_t* row = img + (int64_t)y * row_stride;
+        for (int32_t x = 0; x < W; ++x) {
+            const uint8_t* p = row + 3 * (int64_t)x;
+            uint32_t key = ((uint32_t)p[0] << 16) | ((uint32_t)p[1] << 8) | (uint32_t)p[2];
+            cnt[key] += 1u;
+        }
+    }
+    int64_t n = 0;
+    for (uint32_t key = 0; key < NKEYS; ++key) {
+        if (cnt[key] == 0)
+            continue;
+        if (n < capacity) {
+            keys[n] = key;
+            counts[n] = cnt[key];
+        }
+        ++n;
+    }
+    free(cnt);
+    *n_unique = n;
+    return n > capacity ? CQREF_ECAPACITY : CQREF_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Initialization: Section 2.3.                                              */
+/* Draw order (shared definition with any other implementation):            */
+/*   FGY: for j = 0..K-1, r_j = j + U(N' - j), swap positions j and r_j of  */
+/*        the identity permutation, centre j = colour at position j.         */
+/*   MMX: first centre = colour U(N'); then K-1 farthest-first picks (no    */
+/*        further draws), ties to the lowest colour index.                   */
+/*   KPP: first centre = colour i with the first inclusive prefix of n_i    */
+/*        exceeding U(sum n); centre j = colour with the first inclusive     */
+/*        prefix of n_i D_i^2 exceeding U(sum n_i D_i^2).                    */
+/* U(T) is cqref_uniform_below on one splitmix64 stream seeded with `seed`.  */
+/* ------------------------------------------------------------------------- */
+static void set_center_from_key(double* c, uint32_t key)
+{
+    int r, g, b;
+    key_rgb(key, &r, &g, &b);
+    c[0] = (double)r;
+    c[1] = (double)g;
+    c[2] = (double)b;
+}
+
+/* D_i^2 <- min(D_i^2, |x_i - x_chosen|^2) over all colours. */
+static void update_min_d2(const uint32_t* keys, int64_t n, uint32_t chosen_key, int64_t* d2)
+{
+    int cr, cg, cb;
+    key_rgb(chosen_key, &cr, &cg, &cb);
+    for (int64_t i = 0; i < n; ++i) {
+        int r, g, b;
+        key_rgb(keys[i], &r, &g, &b);
+        int64_t d = dist_int(r, g, b, cr, cg, cb);
+        if (d < d2[i])
+            d2[i] = d;
+    }
+}
+
+int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K,
+               int32_t scheme, uint64_t seed, double* centers, int32_t* k_used)
+{
+    if (!keys || !counts || !centers || n < 1 || K < 1 || K > 256)
+        return CQREF_EINVAL;
+    if (scheme < CQREF_INIT_FORGY || scheme > CQREF_INIT_USER)
+        return CQREF_EINVAL;
+    if (n <= K) {
+        /* Fewer colours than palette entries: every colour is a centre. */
+        for (int32_t k = 0; k < K; ++k) {
+            if (k < n)
+                set_center_from_key(centers + 3 * k, keys[k]);
+            else
+                centers[3 * k] = centers[3 * k + 1] = centers[3 * k + 2] = 0.0;
+        }
+        if (k_used)
+            *k_used = (int32_t)n;
+        return CQREF_OK;
+    }
+    if (k_used)
+        *k_used = K;
+    if (scheme == CQREF_INIT_USER)
+        return CQREF_OK;
+
+    uint64_t rng = seed;
+    if (scheme == CQREF_INIT_FORGY) {
+        int64_t* perm = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+        if (!perm)
+            return CQREF_ENOMEM;
+        for (int64_t i = 0; i < n; ++i)
+            perm[i] = i;
+        for (int32_t j = 0; j < K; ++j) {
+            int64_t r = j + (int64_t)cqref_uniform_below(&rng, (uint64_t)(n - j));
+            int64_t t = perm[j];
+            perm[j] = perm[r];
+            perm[r] = t;
+            set_center_from_key(centers + 3 * j, keys[perm[j]]);
+        }
+        free(perm);
+        return CQREF_OK;
+    }
+
+    int64_t* d2 = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    if (!d2)
+        return CQREF_ENOMEM;
+    for (int64_t i = 0; i < n; ++i)
+        d2[i] = INT64_MAX;
+
+    int64_t first;
+    if (scheme == CQREF_INIT_MAXMIN) {
+        first = (int64_t)cqref_uniform_below(&rng, (uint64_t)n);
+    } else {
+        uint64_t total = 0;
+        for (int64_t i = 0; i < n; ++i)
+            total += counts[i];
+        uint64_t r = cqref_uniform_below(&rng, total);
+        uint64_t prefix = 0;
+        first = n - 1;
+        for (int64_t i = 0; i < n; ++i) {
+            prefix += counts[i];
+            if (prefix > r) {
+                first = i;
+                break;
+            }
+        }
+    }
+    set_center_from_key(centers, keys[first]);
+    update_min_d2(keys, n, keys[first], d2);
+
+    for (int32_t j = 1; j < K; ++j) {
+        int64_t pick = -1;
+        if (scheme == CQREF_INIT_MAXMIN) {
+            int64_t best = -1;
+            for (int64_t i = 0; i < n; ++i) {
+                if (d2[i] > best) {
+                    best = d2[i];
+                    pick = i;
+                }
+            }
+        } else {
+            uint64_t total = 0;
+            for (int64_t i = 0; i < n; ++i)
+                total += (uint64_t)counts[i] * (uint64_t)d2[i];
+            uint64_t r = cqref_uniform_below(&rng, total);
+            uint64_t prefix = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                prefix += (uint64_t)counts[i] * (uint64_t)d2[i];
+                if (prefix > r) {
+                    pick = i;
+                    break;
+                }
+            }
+        }
+        set_center_from_key(centers + 3 * j, keys[pick]);
+        update_min_d2(keys, n, keys[pick], d2);
+    }
+    free(d2);
+    return CQREF_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Weighted Lloyd / Weighted Sort-Means: Algo. 1, Algo. 2, Section 3.3.      */
+/* ------------------------------------------------------------------------- */
+
+/* Exact unsigned 128-bit value converted to double by the fixed rule
+ * hi * 2^64 + lo, each conversion and the sum rounded to nearest. */
+static double u128_to_f64(unsigned __int128 v)
+{
+    uint64_t hi = (uint64_t)(v >> 64);
+    uint64_t lo = (uint64_t)v;
+    return (double)hi * 18446744073709551616.0 + (double)lo;
+}
+
+int cqref_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K,
+                 double* centers, int32_t max_iters, double tol, int32_t prune,
+                 uint8_t* assign, uint8_t* palette, double* sse_trace, cqref_stats* stats)
+{
+    if (!keys || !counts || !centers || !assign || n < 1 || K < 1 || K > 256 || max_iters < 1)
+        return CQREF_EINVAL;
+    if (!(tol >= 0.0))
+        return CQREF_EINVAL;
+
+    cqref_stats st;
+    memset(&st, 0, sizeof st);
+    st.prune = prune ? 1 : 0;
+    st.n_unique = n;
+    uint64_t n_pixels = 0;
+    for (int64_t i = 0; i < n; ++i)
+        n_pixels += counts[i];
+
+    if (n <= K) {
+        /* Exact optimum: one centre per colour, SSE 0, no iteration needed. */
+        for (int32_t k = 0; k < K; ++k) {
+            if (k < n)
+                set_center_from_key(centers + 3 * k, keys[k]);
+            else
+                centers[3 * k] = centers[3 * k + 1] = centers[3 * k + 2] = 0.0;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            assign[i] = (uint8_t)i;
+        st.k_used = (int32_t)n;
+        st.converged = 1;
+    } else {
+        st.k_used = K;
+        double* D = (double*)malloc(sizeof(double) * (size_t)K * (size_t)K);
+        int32_t* M = (int32_t*)malloc(sizeof(int32_t) * (size_t)K * (size_t)K);
+        uint64_t* cn = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)K);
+        uint64_t* cs = (uint64_t*)malloc(sizeof(uint64_t) * 3 * (size_t)K);
+        uint64_t* cq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)K);
+        if (!D || !M || !cn || !cs || !cq) {
+            free(D); free(M); free(cn); free(cs); free(cq);
+            return CQREF_ENOMEM;
+        }
+        double sse_prev = 0.0;
+        for (int32_t it = 1; it <= max_iters; ++it) {
+            const int pruned_pass = prune && it >= 2;
+            if (pruned_pass) {
+                /* Pairwise centre distances and, per row a, the permutation of
+                 * centres by increasing distance from c_a (a itself first). */
+                for (int32_t a = 0; a < K; ++a)
+                    for (int32_t b = 0; b < K; ++b)
+                        D[a * K + b] = dist_f64(centers[3 * a], centers[3 * a + 1],
+                                                centers[3 * a + 2], centers + 3 * b);
+                for (int32_t a = 0; a < K; ++a) {
+                    int32_t* row = M + a * K;
+                    int32_t len = 0;
+                    row[len++] = a;
+                    for (int32_t b = 0; b < K; ++b) {
+                        if (b == a)
+                            continue;
+                        /* insertion by (distance, index) */
+                        int32_t pos = len;
+                        while (pos > 1) {
+                            int32_t o = row[pos - 1];
+                            double dox = D[a * K + o], dbx = D[a * K + b];
+                            if (dox > dbx || (dox == dbx && o > b)) {
+                                row[pos] = o;
+                                --pos;
+                            } else {
+                                break;
+                            }
+                        }
+                        row[pos] = b;
+                        ++len;
+                    }
+                }
+            }
+
+            /* Assignment step. */
+            for (int64_t i = 0; i < n; ++i) {
+                int r, g, b;
+                key_rgb(keys[i], &r, &g, &b);
+                const double x0 = (double)r, x1 = (double)g, x2 = (double)b;
+                int32_t best;
+                double bd, second = -1.0;
+                int have_second = 0;
+                int64_t evals;
+                if (!pruned_pass) {
+                    best = 0;
+                    bd = dist_f64(x0, x1, x2, centers);
+                    for (int32_t k = 1; k < K; ++k) {
+                        double d = dist_f64(x0, x1, x2, centers + 3 * k);
+                        if (d < bd) {
+                            second = bd;
+                            bd = d;
+                            best = k;
+                        } else if (!have_second || d < second) {
+                            second = d;
+                        }
+                        have_second = 1;
+                    }
+                    evals = K;
+                } else {
+                    const int32_t p = assign[i];
+                    const double prev = dist_f64(x0, x1, x2, centers + 3 * p);
+                    const double limit = 4.0 * prev * (1.0 + 1e-12);
+                    best = p;
+                    bd = prev;
+                    evals = 1;
+                    for (int32_t j = 1; j < K; ++j) {
+                        const int32_t t = M[p * K + j];
+                        if (D[p * K + t] > limit)
+                            break;
+                        double d = dist_f64(x0, x1, x2, centers + 3 * t);
+                        ++evals;
+                        if (d < bd || (d == bd && t < best)) {
+                            second = bd;
+                            bd = d;
+                            best = t;
+                        } else if (!have_second || d < second) {
+                            second = d;
+                        }
+                        have_second = 1;
+                    }
+                }
+                if (have_second && (second - bd) <= 1e-5 * second)
+                    st.near_ties += 1;
+                st.ndc_total += evals;
+                assign[i] = (uint8_t)best;
+            }
+
+            /* Update step: exact integer cluster statistics. */
+            memset(cn, 0, sizeof(uint64_t) * (size_t)K);
+            memset(cs, 0, sizeof(uint64_t) * 3 * (size_t)K);
+            memset(cq, 0, sizeof(uint64_t) * (size_t)K);
+            for (int64_t i = 0; i < n; ++i) {
+                int r, g, b;
+                key_rgb(keys[i], &r, &g, &b);
+                const uint64_t w = counts[i];
+                const int32_t k = assign[i];
+                cn[k] += w;
+                cs[3 * k + 0] += w * (uint64_t)r;
+                cs[3 * k + 1] += w * (uint64_t)g;
+                cs[3 * k + 2] += w * (uint64_t)b;
+                cq[k] += w * (uint64_t)(r * r + g * g + b * b);
+            }
+            /* Weighted means (the last line of Algo. 2); empty clusters stay. */
+            for (int32_t k = 0; k < K; ++k) {
+                if (cn[k] == 0)
+                    continue;
+                centers[3 * k + 0] = (double)cs[3 * k + 0] / (double)cn[k];
+                centers[3 * k + 1] = (double)cs[3 * k + 1] / (double)cn[k];
+                centers[3 * k + 2] = (double)cs[3 * k + 2] / (double)cn[k];
+            }
+            /* SSE of eq. (1) with the exact means:
+             * sum_k (n_k Q_k - |S_k|^2) / n_k, numerator in exact 128-bit. */
+            double sse = 0.0;
+            for (int32_t k = 0; k < K; ++k) {
+                if (cn[k] == 0)
+                    continue;
+                unsigned __int128 nq = (unsigned __int128)cn[k] * cq[k];
+                unsigned __int128 s2 = (unsigned __int128)cs[3 * k] * cs[3 * k]
+                                     + (unsigned __int128)cs[3 * k + 1] * cs[3 * k + 1]
+                                     + (unsigned __int128)cs[3 * k + 2] * cs[3 * k + 2];
+                sse += u128_to_f64(nq - s2) / (double)cn[k];
+            }
+            if (sse_trace)
+                sse_trace[it - 1] = sse;
+            st.iters = it;
+            st.sse_final = sse;
+            /* Stopping rule of Section 3.3 (Linde et al.), multiplied through. */
+            if (sse == 0.0 || (it >= 2 && (sse_prev - sse) <= tol * sse)) {
+                st.converged = 1;
+                break;
+            }
+            sse_prev = sse;
+        }
+        free(D); free(M); free(cn); free(cs); free(cq);
+    }
+    st.mse_float = st.sse_final / (double)n_pixels;
+    if (palette) {
+        for (int32_t k = 0; k < K; ++k) {
+            for (int c = 0; c < 3; ++c) {
+                /* round half up, clamped to [0, 255]: floor(c + 0.5) */
+                const double v = centers[3 * k + c] + 0.5;
+                int q;
+                if (!(v >= 1.0))
+                    q = 0;
+                else if (v >= 256.0)
+                    q = 255;
+                else
+                    q = (int)v; /* v >= 1: truncation is floor */
+                palette[3 * k + c] = (uint8_t)q;
+            }
+        }
+    }
+    if (stats)
+        *stats = st;
+    return CQREF_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Pixel mapping and MSE: Section 1 (mapping phase), Section 3.1 (MSE).      */
+/* Each pixel goes to the palette entry at the smallest integer squared      */
+/* distance, lowest index on ties.  The answer depends only on the colour,   */
+/* so it is memoised per colour.                                             */
+/* ------------------------------------------------------------------------- */
+int cqref_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride,
+              const uint8_t* palette, int32_t K, uint8_t* out_idx, uint8_t* out_rgb,
+              uint64_t* sq_err_sum)
+{
+    if (!img || !palette || H <= 0 || W <= 0 || row_stride < 3 * (int64_t)W || K < 1 || K > 256)
+        return CQREF_EINVAL;
+    int16_t* memo = (int16_t*)malloc(sizeof(int16_t) * (size_t)NKEYS);
+    if (!memo)
+        return CQREF_ENOMEM;
+    memset(memo, 0xff, sizeof(int16_t) * (size_t)NKEYS); /* -1: not yet known */
+    uint64_t err = 0;
+    for (int32_t y = 0; y < H; ++y) {
+        const uint8_t* row = img + (int64_t)y * row_stride;
+        for (int32_t x = 0; x < W; ++x) {
+            const uint8_t* p = row + 3 * (int64_t)x;
+            uint32_t key = ((uint32_t)p[0] << 16) | ((uint32_t)p[1] << 8) | (uint32_t)p[2];
+            int32_t idx = memo[key];
+            if (idx < 0) {
+                int64_t bd = INT64_MAX;
+                for (int32_t k = 0; k < K; ++k) {
+                    int64_t d = dist_int(p[0], p[1], p[2], palette[3 * k], palette[3 * k + 1],
+                                         palette[3 * k + 2]);
+                    if (d < bd) {
+                        bd = d;
+                        idx = k;
+                    }
+                }
+                memo[key] = (int16_t)idx;
+            }
+            const uint8_t* q = palette + 3 * idx;
+            err += (uint64_t)dist_int(p[0], p[1], p[2], q[0], q[1], q[2]);
+            const int64_t o = (int64_t)y * W + x;
+            if (out_idx)
+                out_idx[o] = (uint8_t)idx;
+            if (out_rgb) {
+                out_rgb[3 * o + 0] = q[0];
+                out_rgb[3 * o + 1] = q[1];
+                out_rgb[3 * o + 2] = q[2];
+            }
+        }
+    }
+    free(memo);
+    if (sq_err_sum)
+        *sq_err_sum = err;
+    return CQREF_OK;
+}
+
+int cqref_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, int32_t K,
+                   int32_t scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
+                   uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, cqref_stats* stats)
+{
+    if (!img || !palette || H <= 0 || W <= 0 || K < 1 || K > 256 || scheme == CQREF_INIT_USER)
+        return CQREF_EINVAL;
+    int64_t cap = (int64_t)H * W, n = 0;
+    uint32_t* keys = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)cap);
+    uint32_t* counts = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)cap);
+    uint8_t* assign = (uint8_t*)malloc((size_t)cap);
+    double centers[256 * 3];
+    int rc = CQREF_ENOMEM;
+    if (!keys || !counts || !assign)
+        goto out;
+    rc = cqref_histogram(img, H, W, row_stride, keys, counts, cap, &n);
+    if (rc)
+        goto out;
+    rc = cqref_init(keys, counts, n, K, scheme, seed, centers, NULL);
+    if (rc)
+        goto out;
+    cqref_stats st;
+    rc = cqref_kmeans(keys, counts, n, K, centers, max_iters, tol, prune, assign, palette, NULL, &st);
+    if (rc)
+        goto out;
+    uint64_t err = 0;
+    rc = cqref_map(img, H, W, row_stride, palette, st.k_used, out_idx, out_rgb, &err);
+    if (rc)
+        goto out;
+    st.mse_img = (double)err / ((double)H * (double)W);
+    if (stats)
+        *stats = st;
+out:
+    free(keys);
+    free(counts);
+    free(assign);
+    return rc;
+}

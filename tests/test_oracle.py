@@ -1,0 +1,389 @@
+"""Pins of the CPU oracle against the paper and against mathematics.
+
+Every test here is CPU-only.  None of them re-types the oracle's own formulas:
+they check published values, closed forms, library routines (numpy.unique,
+numpy argmin over a brute-force distance matrix, scikit-learn's Lloyd),
+invariants and brute force on tiny inputs.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1101_0395_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    rows = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            rows[parts[0]] = parts[1:]
+    return rows
+
+
+def _keys_of(img):
+    img = np.asarray(img)
+    return ((img[..., 0].astype(np.uint32) << 16) | (img[..., 1].astype(np.uint32) << 8)
+            | img[..., 2].astype(np.uint32))
+
+
+def _rgb_of(keys):
+    keys = np.asarray(keys, np.int64)
+    return np.stack([(keys >> 16) & 255, (keys >> 8) & 255, keys & 255], axis=1)
+
+
+def _random_small_image(rng, H, W, n_colors):
+    base = rng.integers(0, 256, (n_colors, 3))
+    pick = rng.integers(0, n_colors, H * W)
+    return base[pick].reshape(H, W, 3).astype(np.uint8)
+
+
+# --------------------------------------------------------------------------- RNG
+
+def test_splitmix64_published_sequence():
+    with open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt")) as f:
+        expect = [int(x) for x in f.read().split("\n") if x and not x.startswith("#")]
+    assert oracle.splitmix64(1234567, len(expect)) == expect
+
+
+def test_uniform_below_range_and_uniformity():
+    draws = np.array(oracle.uniform_below(99, 7, 70_000))
+    assert draws.min() >= 0 and draws.max() <= 6
+    obs = np.bincount(draws, minlength=7)
+    chi2 = (((obs - 10_000) ** 2) / 10_000).sum()
+    assert chi2 < 30.0  # 6 dof: P(chi2 > 30) ~ 4e-5
+    assert oracle.uniform_below(5, 1, 10) == [0] * 10
+    big = (1 << 63) + 1  # more than half of all outputs fall in the rejected band
+    assert all(v < big for v in oracle.uniform_below(3, big, 200))
+
+
+# --------------------------------------------------------------------- histogram
+
+@pytest.mark.parametrize("shape", [(1, 1), (3, 5), (17, 33), (64, 64)])
+def test_histogram_matches_numpy_unique(shape):
+    rng = np.random.default_rng(shape[0] * 100 + shape[1])
+    img = _random_small_image(rng, shape[0], shape[1], 40)
+    keys, counts = oracle.histogram(img)
+    u, c = np.unique(img.reshape(-1, 3), axis=0, return_counts=True)
+    # lexicographic (R, G, B) order is ascending 0xRRGGBB order
+    assert np.array_equal(_rgb_of(keys), u)
+    assert np.array_equal(counts, c)
+    assert int(counts.sum()) == shape[0] * shape[1]
+
+
+def test_histogram_brute_force_dict_and_stride():
+    rng = np.random.default_rng(5)
+    img = rng.integers(0, 4, (9, 11, 3)).astype(np.uint8)
+    padded = np.zeros((9, 11 * 3 + 7), np.uint8)  # rows with 7 bytes of padding
+    padded[:, : 33] = img.reshape(9, 33)
+    view = np.lib.stride_tricks.as_strided(padded, shape=(9, 11, 3), strides=(40, 3, 1))
+    keys, counts = oracle.histogram(view)
+    ref = {}
+    for px in img.reshape(-1, 3):
+        k = (int(px[0]) << 16) | (int(px[1]) << 8) | int(px[2])
+        ref[k] = ref.get(k, 0) + 1
+    assert list(keys) == sorted(ref)
+    assert [int(c) for c in counts] == [ref[k] for k in sorted(ref)]
+
+
+def test_histogram_capacity_error():
+    img = np.arange(30, dtype=np.uint8).reshape(1, 10, 3)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.histogram(img, capacity=3)
+    assert e.value.code == oracle.ECAPACITY
+
+
+# -------------------------------------------------------------------------- init
+
+def _hist_small(seed, n_colors=60, H=24, W=24):
+    rng = np.random.default_rng(seed)
+    img = _random_small_image(rng, H, W, n_colors)
+    return oracle.histogram(img)
+
+
+def test_forgy_picks_distinct_colours():
+    keys, counts = _hist_small(1)
+    C, k_used = oracle.init(keys, counts, 16, oracle.INIT_FORGY, 7)
+    assert k_used == 16
+    rgb = _rgb_of(keys)
+    picked = [int(np.flatnonzero((rgb == c).all(1))[0]) for c in C.astype(np.int64)]
+    assert len(set(picked)) == 16
+
+
+def test_maxmin_is_farthest_first():
+    keys, counts = _hist_small(2)
+    X = _rgb_of(keys).astype(np.int64)
+    for seed in range(5):
+        C, _ = oracle.init(keys, counts, 12, oracle.INIT_MAXMIN, seed)
+        C = C.astype(np.int64)
+        # first centre: colour number U(N') of the seed's stream
+        first = oracle.uniform_below(seed, len(keys), 1)[0]
+        assert np.array_equal(C[0], X[first])
+        for j in range(1, 12):
+            d = ((X[:, None, :] - C[None, :j, :]) ** 2).sum(-1).min(1)
+            best = int(np.argmax(d))  # numpy: first index of the maximum
+            assert np.array_equal(C[j], X[best])
+
+
+def test_kmeanspp_sampling_distribution():
+    # 5 colours with uneven counts; the second centre must follow n_i D_i^2.
+    img = np.zeros((1, 20, 3), np.uint8)
+    cols = [(0, 0, 0), (10, 0, 0), (0, 30, 0), (0, 0, 50), (40, 40, 40)]
+    reps = [8, 5, 3, 2, 2]
+    px = [c for c, r in zip(cols, reps) for _ in range(r)]
+    img[0] = np.array(px, np.uint8)
+    keys, counts = oracle.histogram(img)
+    X = _rgb_of(keys).astype(np.int64)
+    n_trials = 4000
+    first_hits = np.zeros(len(keys))
+    second_hits = {}
+    for seed in range(n_trials):
+        C, _ = oracle.init(keys, counts, 2, oracle.INIT_KMEANSPP, seed)
+        i0 = int(np.flatnonzero((X == C[0].astype(np.int64)).all(1))[0])
+        i1 = int(np.flatnonzero((X == C[1].astype(np.int64)).all(1))[0])
+        first_hits[i0] += 1
+        second_hits.setdefault(i0, np.zeros(len(keys)))[i1] += 1
+    p0 = counts / counts.sum()
+    chi2 = (((first_hits - n_trials * p0) ** 2) / (n_trials * p0)).sum()
+    assert chi2 < 25.0  # 4 dof
+    for i0, hits in second_hits.items():
+        d2 = ((X - X[i0]) ** 2).sum(1)
+        w = counts * d2
+        p = w / w.sum()
+        m = hits.sum()
+        mask = p > 0
+        assert hits[~mask].sum() == 0  # zero-weight colours are never drawn
+        chi2 = (((hits[mask] - m * p[mask]) ** 2) / (m * p[mask])).sum()
+        assert chi2 < 30.0
+
+
+def test_init_with_fewer_colours_than_k():
+    img = np.array([[[1, 2, 3], [1, 2, 3], [9, 9, 9]]], np.uint8)
+    keys, counts = oracle.histogram(img)
+    for scheme in (oracle.INIT_FORGY, oracle.INIT_MAXMIN, oracle.INIT_KMEANSPP):
+        C, k_used = oracle.init(keys, counts, 4, scheme, 0)
+        assert k_used == 2
+        assert np.array_equal(C[:2], [[1, 2, 3], [9, 9, 9]])
+        assert np.array_equal(C[2:], np.zeros((2, 3)))
+
+
+# ---------------------------------------------------------------- k-means steps
+
+def test_worked_example():
+    g = _read_golden("worked_example_k2.txt")
+    img = np.array([[[0, 0, 0], [0, 0, 0], [10, 0, 0], [100, 0, 0]]], np.uint8)
+    keys, counts = oracle.histogram(img)
+    assert list(keys) == [int(v) for v in g["keys"]]
+    assert list(counts) == [int(v) for v in g["counts"]]
+    res = oracle.kmeans(keys, counts, [[0, 0, 0], [100, 0, 0]], 10, 1e-4, prune=True)
+    assert list(res.assign) == [int(v) for v in g["assign"]]
+    assert res.stats["iters"] == int(g["iters"][0]) and res.stats["converged"] == 1
+    assert res.centers[0, 0] == 10 / 3 and res.centers[1, 0] == 100.0
+    assert res.sse_trace[-1] == pytest.approx(int(g["sse_numerator_over_9"][0]) / 9, rel=1e-15)
+    assert list(res.palette.reshape(-1)) == [int(v) for v in g["palette"]]
+    idx, rgb, err = oracle.map_image(img, res.palette)
+    assert list(idx.reshape(-1)) == [int(v) for v in g["idx"]]
+    assert err == int(g["sq_err_sum"][0])
+
+
+def test_first_assignment_is_bruteforce_argmin_with_lowest_index_ties():
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        keys, counts = _hist_small(100 + trial, n_colors=50)
+        X = _rgb_of(keys).astype(np.int64)
+        K = 9
+        # integer-valued centres with deliberate duplicates -> exact distance ties
+        C = rng.integers(0, 256, (K, 3))
+        C[5] = C[2]
+        C[8] = C[0]
+        res = oracle.kmeans(keys, counts, C.astype(np.float64), 1, 0.0, prune=False)
+        D = ((X[:, None, :] - C[None, :, :]) ** 2).sum(-1)
+        assert np.array_equal(res.assign, np.argmin(D, axis=1))  # first minimum
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_pruned_equals_unpruned(seed):
+    """Section 2.2: with the same initial centres WSM equals plain k-means."""
+    rng = np.random.default_rng(seed)
+    H, W = int(rng.integers(8, 48)), int(rng.integers(8, 48))
+    img = synth.blobs_on_gradient(H, W, seed)
+    keys, counts = oracle.histogram(img)
+    K = int(rng.choice([2, 3, 5, 16, 40]))
+    scheme = int(rng.choice([oracle.INIT_FORGY, oracle.INIT_MAXMIN, oracle.INIT_KMEANSPP]))
+    C, _ = oracle.init(keys, counts, K, scheme, seed)
+    if seed % 3 == 0 and K >= 3:
+        C[K - 1] = C[0]  # coincident centres exercise the tie rules of the sorted rows
+    a = oracle.kmeans(keys, counts, C, 60, 0.0, prune=False)
+    b = oracle.kmeans(keys, counts, C, 60, 0.0, prune=True)
+    assert np.array_equal(a.assign, b.assign)
+    assert np.array_equal(a.centers, b.centers)
+    assert np.array_equal(a.sse_trace, b.sse_trace)
+    assert a.stats["iters"] == b.stats["iters"]
+    if len(keys) > K:
+        assert b.stats["ndc_total"] <= a.stats["ndc_total"]
+        assert a.stats["ndc_total"] == a.stats["iters"] * len(keys) * K
+
+
+def _pixel_lloyd(pixels, C, iters):
+    """Unweighted Lloyd on every pixel (Algo. 1), numpy brute force."""
+    C = C.copy()
+    P = pixels.astype(np.float64)
+    for _ in range(iters):
+        D = ((P[:, None, :] - C[None, :, :]) ** 2).sum(-1)
+        m = np.argmin(D, axis=1)
+        for k in range(C.shape[0]):
+            sel = m == k
+            if sel.any():
+                C[k] = P[sel].mean(axis=0)
+    return C, m
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_weighted_histogram_lloyd_equals_pixel_lloyd(seed):
+    """Weighting unique colours by frequency (Section 2.2, item 2) reproduces
+    Lloyd on all pixels."""
+    img = synth.blobs_on_gradient(20, 24, seed)
+    keys, counts = oracle.histogram(img)
+    C0, _ = oracle.init(keys, counts, 6, oracle.INIT_KMEANSPP, seed)
+    for iters in (1, 2, 5):
+        res = oracle.kmeans(keys, counts, C0, iters, 0.0, prune=True)
+        if res.stats["iters"] < iters:
+            continue
+        Cp, mp = _pixel_lloyd(img.reshape(-1, 3), C0, iters)
+        np.testing.assert_allclose(res.centers, Cp, rtol=0, atol=1e-12)
+        # per-pixel membership equals the membership of the pixel's colour
+        pix_keys = _keys_of(img).reshape(-1)
+        lut = dict(zip(keys.tolist(), res.assign.tolist()))
+        assert np.array_equal(np.array([lut[k] for k in pix_keys.tolist()]), mp)
+
+
+def test_sse_identity_and_monotone():
+    img = synth.smooth_field_blobs(96, 80, 3)
+    keys, counts = oracle.histogram(img)
+    X = _rgb_of(keys).astype(np.float64)
+    C0, _ = oracle.init(keys, counts, 24, oracle.INIT_KMEANSPP, 3)
+    trace = []
+    C = C0
+    for it in range(1, 9):
+        res = oracle.kmeans(keys, counts, C0, it, 0.0, prune=True)
+        if res.stats["iters"] < it:
+            break
+        direct = (counts * ((X - res.centers[res.assign]) ** 2).sum(1)).sum()
+        assert res.sse_trace[-1] == pytest.approx(direct, rel=1e-12)
+        trace = res.sse_trace
+        C = res.centers
+    assert len(trace) >= 4
+    assert all(trace[i + 1] <= trace[i] * (1 + 1e-12) for i in range(len(trace) - 1))
+    del C
+
+
+def test_k1_closed_form():
+    img = synth.blobs_on_gradient(16, 16, 9)
+    keys, counts = oracle.histogram(img)
+    X = _rgb_of(keys)
+    res = oracle.kmeans(keys, counts, [[1.0, 2.0, 3.0]], 10, 1e-4, prune=True)
+    N = int(counts.sum())
+    S = [int((counts.astype(object) * X[:, c].astype(object)).sum()) for c in range(3)]
+    Q = int((counts.astype(object) * (X.astype(object) ** 2).sum(1)).sum())
+    for c in range(3):
+        assert res.centers[0, c] == S[c] / N
+    from fractions import Fraction
+    sse = Fraction(Q) - Fraction(sum(s * s for s in S), N)
+    assert res.sse_trace[0] == pytest.approx(float(sse), rel=1e-14)
+    assert res.stats["iters"] == 2 and res.stats["converged"] == 1
+
+
+def test_fewer_colours_than_k_gives_exact_palette():
+    img = np.array([[[5, 6, 7], [200, 100, 0], [5, 6, 7]]], np.uint8)
+    pal, idx, rgb, st = oracle.quantize(img, 8, oracle.INIT_KMEANSPP, 0, 20, 1e-4)
+    assert st["k_used"] == 2 and st["mse_img"] == 0.0 and st["iters"] == 0
+    assert np.array_equal(rgb, img)
+    assert np.array_equal(pal[:2], [[5, 6, 7], [200, 100, 0]])
+
+
+def test_two_separated_clusters_converge_to_cluster_means():
+    rng = np.random.default_rng(4)
+    a = rng.integers(0, 20, (200, 3))
+    b = rng.integers(230, 256, (300, 3))
+    img = np.concatenate([a, b]).reshape(20, 25, 3).astype(np.uint8)
+    keys, counts = oracle.histogram(img)
+    res = oracle.kmeans(keys, counts, [[0.0, 0.0, 0.0], [255.0, 255.0, 255.0]], 20, 0.0, True)
+    np.testing.assert_array_equal(res.centers[0], a.mean(0))
+    np.testing.assert_array_equal(res.centers[1], b.mean(0))
+
+
+def test_matches_scikit_learn_lloyd_on_separated_data():
+    sklearn_cluster = pytest.importorskip("sklearn.cluster")
+    rng = np.random.default_rng(8)
+    mus = np.array([[20, 30, 40], [200, 40, 60], [60, 210, 90], [100, 100, 230], [240, 240, 20]])
+    pts = np.concatenate([np.clip(np.rint(m + 6 * rng.standard_normal((400, 3))), 0, 255)
+                          for m in mus]).astype(np.uint8)
+    keys, counts = oracle.histogram(pts.reshape(1, -1, 3))
+    X = _rgb_of(keys).astype(np.float64)
+    C0 = mus.astype(np.float64) + 3.0
+    res = oracle.kmeans(keys, counts, C0, 3, 0.0, prune=True)
+    km = sklearn_cluster.KMeans(n_clusters=5, init=C0, n_init=1, algorithm="lloyd",
+                                max_iter=3, tol=0.0).fit(X, sample_weight=counts.astype(np.float64))
+    np.testing.assert_allclose(res.centers, km.cluster_centers_, rtol=0, atol=1e-9)
+
+
+def test_stopping_rule():
+    img = synth.blobs_on_gradient(32, 32, 1)
+    keys, counts = oracle.histogram(img)
+    C0, _ = oracle.init(keys, counts, 8, oracle.INIT_MAXMIN, 1)
+    one = oracle.kmeans(keys, counts, C0, 1, 1e-4, True)
+    assert one.stats["iters"] == 1 and one.stats["converged"] == 0
+    loose = oracle.kmeans(keys, counts, C0, 50, 1e9, True)
+    assert loose.stats["iters"] == 2 and loose.stats["converged"] == 1
+    tight = oracle.kmeans(keys, counts, C0, 500, 1e-4, True)
+    tr = tight.sse_trace
+    t = tight.stats["iters"]
+    assert tight.stats["converged"] == 1
+    assert (tr[t - 2] - tr[t - 1]) / tr[t - 1] <= 1e-4
+    assert all((tr[i - 1] - tr[i]) / tr[i] > 1e-4 for i in range(1, t - 1))
+
+
+def test_empty_cluster_keeps_centre():
+    img = np.array([[[0, 0, 0], [2, 0, 0], [4, 0, 0]]], np.uint8)
+    keys, counts = oracle.histogram(img)
+    res = oracle.kmeans(keys, counts, [[2.0, 0, 0], [250.0, 250.0, 250.0]], 5, 0.0, True)
+    assert np.array_equal(res.centers[1], [250.0, 250.0, 250.0])
+    assert np.array_equal(res.assign, [0, 0, 0])
+
+
+# ------------------------------------------------------------------------- map
+
+def test_map_is_nearest_palette_entry_and_mse():
+    img = synth.smooth_field_blobs(40, 56, 2)
+    rng = np.random.default_rng(0)
+    pal = rng.integers(0, 256, (20, 3)).astype(np.uint8)
+    pal[7] = pal[3]  # duplicate entry: ties go to the lower index
+    idx, rgb, err = oracle.map_image(img, pal)
+    P = pal.astype(np.int64)
+    X = img.reshape(-1, 3).astype(np.int64)
+    D = ((X[:, None, :] - P[None, :, :]) ** 2).sum(-1)
+    assert np.array_equal(idx.reshape(-1), np.argmin(D, axis=1))
+    assert np.array_equal(rgb, pal[idx])
+    mse = ((img.astype(np.float64) - rgb.astype(np.float64)) ** 2).sum(-1).mean()  # Section 3.1
+    assert err / (40 * 56) == pytest.approx(mse, rel=1e-15)
+
+
+def test_quantize_end_to_end_small_config():
+    img = synth.blobs_on_gradient(64, 64, 0)
+    pal, idx, rgb, st = oracle.quantize(img, 16, oracle.INIT_MAXMIN, 0, 50, 1e-4, prune=False)
+    assert st["k_used"] == 16 and 1 <= st["iters"] <= 50
+    assert st["n_unique"] == len(np.unique(_keys_of(img)))
+    mse = ((img.astype(np.float64) - rgb.astype(np.float64)) ** 2).sum(-1).mean()
+    assert st["mse_img"] == pytest.approx(mse, rel=1e-15)
+    psnr = 20 * math.log10(255 / math.sqrt(st["mse_img"]))
+    assert 10 < psnr < 60
+    again = oracle.quantize(img, 16, oracle.INIT_MAXMIN, 0, 50, 1e-4, prune=True)
+    assert np.array_equal(again[0], pal) and again[3]["sse_final"] == st["sse_final"]
