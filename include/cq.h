@@ -1,0 +1,158 @@
+/* cq: exact weighted k-means colour quantization on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the GPU library libcq.so.  The method is the Weighted Sort-Means
+ * (WSM) quantizer of M. E. Celebi, "Improving the Performance of K-Means for
+ * Color Quantization": data reduction to the unique colours of the image with
+ * their pixel counts as weights (Section 2.2, items 1-2), Lloyd iterations
+ * (Algo. 1) accelerated by sort-means triangle-inequality pruning (Section 2.2
+ * item 3, Algo. 2), the relative-SSE stopping rule of Section 3.3, and the
+ * pixel-mapping phase of Section 1 with the MSE of Section 3.1.
+ *
+ * General conventions
+ *  - Pointers are DEVICE pointers unless marked (host).  The caller owns every
+ *    buffer, including the workspace; the library never allocates device
+ *    memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it; a call that returns a value through a (host) pointer
+ *    synchronizes that stream before returning.
+ *  - Images are uint8 H x W x 3, interleaved R,G,B, rows `row_stride_bytes`
+ *    apart (>= 3 W).  A colour key is R<<16 | G<<8 | B.
+ *  - K (palette size) is in [1, 256]; H * W <= 2^28.
+ *  - Results are bit-identical to the CPU reference definition: integer
+ *    histograms, sums and MSE numerators; FP64 distances evaluated as
+ *    (dx*dx + dy*dy) + dz*dz without contraction.
+ *  - Errors: a non-zero cq_status is returned and cq_last_error() describes it.
+ *    No call aborts the process and no C++ exception crosses the ABI.  Outputs
+ *    are unspecified after an error.  After CQ_EDEVICE the workspace must be
+ *    prepared again with cq_workspace_prepare.
+ *  - Calls that share one workspace must be serialized (same stream or
+ *    external synchronization).
+ */
+#ifndef CQ_H
+#define CQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CQ_OK = 0,
+    CQ_EINVAL = 1,      /* invalid argument (range, null pointer, shape)       */
+    CQ_ECAPACITY = 2,   /* output capacity smaller than the number of colours  */
+    CQ_EWORKSPACE = 3,  /* workspace missing, too small or misaligned          */
+    CQ_EDEVICE = 4      /* HIP runtime error; see cq_last_error()              */
+} cq_status;
+
+/* Initialization schemes of Section 2.3. */
+typedef enum {
+    CQ_INIT_FORGY = 0,     /* K distinct colours drawn uniformly (FGY)              */
+    CQ_INIT_MAXMIN = 1,    /* farthest-first after a uniform first colour (MMX)     */
+    CQ_INIT_KMEANSPP = 2,  /* D^2 sampling, weighted by pixel counts (KPP)          */
+    CQ_INIT_USER = 3       /* centres supplied by the caller (WSM-X warm start)     */
+} cq_init_t;
+
+/* Run statistics (host structure). */
+typedef struct {
+    int32_t iters;      /* Lloyd iterations run                                     */
+    int32_t converged;  /* 1 if stopped by the relative-SSE test or SSE == 0        */
+    int32_t k_used;     /* min(K, N')                                               */
+    int32_t prune;      /* 1 if sort-means pruning was on                           */
+    int64_t n_unique;   /* N', the number of unique colours                         */
+    int64_t ndc_total;  /* distance calculations, summed over colours and iterations */
+    int64_t near_ties;  /* colour-iterations whose two smallest evaluated distances
+                           differ by at most 1e-5 relative                          */
+    double sse_final;   /* SSE (eq. 1) after the last centre update                 */
+    double mse_float;   /* sse_final / number of pixels                             */
+    double mse_img;     /* MSE (Section 3.1) of the mapped image (cq_quantize only) */
+} cq_stats;
+
+/* Bytes of workspace needed by every entry point for one image of H x W pixels
+ * with palette size K (the same buffer serves all five calls).  Returns 0 for
+ * invalid sizes. */
+size_t cq_workspace_bytes(int32_t H, int32_t W, int32_t K);
+
+/* Prepare a fresh workspace: clears the regions that must be zero between
+ * calls (the 2^24-entry colour count table and its presence bitmap).  Must be
+ * called once before the first use of a workspace and after any CQ_EDEVICE.
+ * The library leaves those regions cleared when a call returns CQ_OK or
+ * CQ_ECAPACITY.  `ws` must be 256-byte aligned. */
+cq_status cq_workspace_prepare(void* ws, size_t ws_bytes, void* stream);
+
+/* Section 2.2 items 1-2: the unique colours of the image with their pixel
+ * counts.  Writes keys[0..N') in ascending order and counts[0..N') (the
+ * weights before normalization by H W).  *n_unique (host) receives N'; if
+ * N' > capacity only the first `capacity` entries are written and
+ * CQ_ECAPACITY is returned.  Synchronizes `stream`. */
+cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
+                       uint32_t* keys, uint32_t* counts, int64_t capacity,
+                       int64_t* n_unique /* host */, void* ws, size_t ws_bytes, void* stream);
+
+/* Section 2.3: initial centres from the N' unique colours.  centers is a
+ * device double[K][3].  For N' <= K the centres are the colours in key order
+ * followed by zeros and *k_used (host, nullable) is N'.  Random draws come
+ * from one splitmix64 stream seeded with `seed`: FGY does a partial
+ * Fisher-Yates shuffle (draw j uniform in [j, N')); MMX draws the first colour
+ * uniformly; KPP draws the first colour with probability proportional to its
+ * count and colour j with probability proportional to count * D^2.  With
+ * CQ_INIT_USER the centres are left as given.  Synchronizes only if k_used is
+ * non-null. */
+cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique, int32_t K,
+                  cq_init_t scheme, uint64_t seed, double* centers, int32_t* k_used /* host */,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* Algo. 1 / Algo. 2: weighted Lloyd iterations on the unique colours starting
+ * from centers (device double[K][3], updated in place).
+ *  - prune = 0: full nearest-centre search every iteration (Algo. 1).
+ *  - prune = 1: sort-means (Algo. 2): iteration 1 is a full search; later
+ *    iterations scan the centres in increasing distance from the previous
+ *    centre and stop once d(c_p, c_t)^2 > 4 d(x, c_p)^2 (1 + 1e-12).  Both
+ *    modes give identical results; only the distance count differs.
+ *  - Ties go to the lowest centre index.  An empty cluster keeps its centre.
+ *  - After the update of iteration i, SSE_i is computed from exact integer
+ *    cluster sums; the run stops when SSE_i == 0, when i >= 2 and
+ *    SSE_{i-1} - SSE_i <= tol * SSE_i (Section 3.3), or at max_iters.
+ * assign (device uint8[N']) receives the final memberships; palette (device
+ * uint8[K][3], nullable) receives floor(c + 0.5) clamped to [0, 255];
+ * sse_trace (host double[max_iters], nullable) receives SSE_1..SSE_iters.
+ * For N' <= K the centres become the colours and no iteration runs.
+ * 1 <= max_iters <= 100000, tol >= 0.  Synchronizes `stream`. */
+cq_status cq_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n_unique, int32_t K,
+                    double* centers, int32_t max_iters, double tol, int32_t prune,
+                    uint8_t* assign, uint8_t* palette, double* sse_trace /* host */,
+                    cq_stats* stats /* host */, void* ws, size_t ws_bytes, void* stream);
+
+/* Pixel mapping (Section 1): every pixel goes to the palette entry at the
+ * smallest integer squared distance (lowest index on ties).  `keys` are the
+ * image's unique colours from cq_histogram (every pixel colour must be among
+ * them).  out_idx (device uint8[H][W], nullable) receives the palette index,
+ * out_rgb (device uint8[H][W][3], nullable) the palette colour.
+ * *sq_err_sum (host, nullable) receives the integer sum over pixels of the
+ * squared error, i.e. H W times the MSE of Section 3.1; it needs `counts`
+ * (device uint32[N'], nullable otherwise).  Synchronizes only if sq_err_sum is
+ * non-null. */
+cq_status cq_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
+                 const uint32_t* keys, const uint32_t* counts, int64_t n_unique,
+                 const uint8_t* palette, int32_t K, uint8_t* out_idx, uint8_t* out_rgb,
+                 uint64_t* sq_err_sum /* host */, void* ws, size_t ws_bytes, void* stream);
+
+/* The whole quantizer: histogram -> init (FGY, MMX or KPP) -> weighted
+ * sort-means (prune = 1) or plain weighted Lloyd (prune = 0) -> palette ->
+ * map.  palette is device uint8[K][3] (entries past k_used are zero); out_idx
+ * and out_rgb as in cq_map (nullable).  stats (host, nullable) includes
+ * mse_img.  Synchronizes `stream`. */
+cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
+                      int32_t K, cq_init_t scheme, uint64_t seed, int32_t max_iters, double tol,
+                      int32_t prune, uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb,
+                      cq_stats* stats /* host */, void* ws, size_t ws_bytes, void* stream);
+
+/* Thread-local description of the last error on this thread ("" if none);
+ * valid until the next cq_* call on the same thread. */
+const char* cq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CQ_H */

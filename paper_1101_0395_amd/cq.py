@@ -1,0 +1,212 @@
+"""Thin Python binding of libcq (the C ABI declared in include/cq.h).
+
+Argument marshalling only: every step of the quantizer runs in the library's
+HIP kernels.  Device buffers are torch tensors on a ROCm device; the stream is
+torch's current stream.  The library must have been built
+(``python -m paper_1101_0395_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcq.so")
+
+CQ_OK, CQ_EINVAL, CQ_ECAPACITY, CQ_EWORKSPACE, CQ_EDEVICE = 0, 1, 2, 3, 4
+INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER = 0, 1, 2, 3
+EXPORTS = ("cq_workspace_bytes", "cq_workspace_prepare", "cq_histogram", "cq_init", "cq_kmeans",
+           "cq_map", "cq_quantize", "cq_last_error")
+
+
+class CqStats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("k_used", ctypes.c_int32),
+        ("prune", ctypes.c_int32),
+        ("n_unique", ctypes.c_int64),
+        ("ndc_total", ctypes.c_int64),
+        ("near_ties", ctypes.c_int64),
+        ("sse_final", ctypes.c_double),
+        ("mse_float", ctypes.c_double),
+        ("mse_img", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class CqError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn}: status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libcq.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1101_0395_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u64, f64, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                     ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
+        L.cq_workspace_bytes.argtypes = [i32, i32, i32]
+        L.cq_workspace_bytes.restype = sz
+        L.cq_workspace_prepare.argtypes = [P, sz, P]
+        L.cq_histogram.argtypes = [P, i32, i32, i64, P, P, i64, ctypes.POINTER(i64), P, sz, P]
+        L.cq_init.argtypes = [P, P, i64, i32, ctypes.c_int, u64, P, ctypes.POINTER(i32), P, sz, P]
+        L.cq_kmeans.argtypes = [P, P, i64, i32, P, i32, f64, i32, P, P, P, ctypes.POINTER(CqStats),
+                                P, sz, P]
+        L.cq_map.argtypes = [P, i32, i32, i64, P, P, i64, P, i32, P, P, ctypes.POINTER(u64), P, sz, P]
+        L.cq_quantize.argtypes = [P, i32, i32, i64, i32, ctypes.c_int, u64, i32, f64, i32, P, P, P,
+                                  ctypes.POINTER(CqStats), P, sz, P]
+        for f in ("cq_workspace_prepare", "cq_histogram", "cq_init", "cq_kmeans", "cq_map",
+                  "cq_quantize"):
+            getattr(L, f).restype = ctypes.c_int
+        L.cq_last_error.argtypes = []
+        L.cq_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, rc: int, allow=()):
+    if rc != CQ_OK and rc not in allow:
+        raise CqError(fn, rc, lib().cq_last_error().decode(errors="replace"))
+    return rc
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _image_args(img: torch.Tensor):
+    if img.dtype != torch.uint8 or img.dim() != 3 or img.shape[2] != 3:
+        raise ValueError("image must be a uint8 tensor of shape [H, W, 3]")
+    if img.stride(2) != 1 or img.stride(1) != 3:
+        raise ValueError("image pixels must be packed RGB (strides [*, 3, 1])")
+    if not img.is_cuda:
+        raise ValueError("image must be on the GPU")
+    return img.shape[0], img.shape[1], img.stride(0)
+
+
+def workspace_bytes(H: int, W: int, K: int) -> int:
+    n = lib().cq_workspace_bytes(H, W, K)
+    if n == 0:
+        raise ValueError(f"invalid workspace request H={H} W={W} K={K}")
+    return n
+
+
+class Workspace:
+    """Caller-owned device workspace (a torch byte tensor), prepared once."""
+
+    def __init__(self, H: int, W: int, K: int = 256, device="cuda"):
+        self.nbytes = workspace_bytes(H, W, K)
+        self.device = torch.device(device)
+        # 256 extra bytes so the start can be aligned to 256
+        self._buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._buf.data_ptr()
+        self.offset = (-base) % 256
+        self.ptr = ctypes.c_void_p(base + self.offset)
+        _check("cq_workspace_prepare",
+               lib().cq_workspace_prepare(self.ptr, self.nbytes, _stream(self.device)))
+
+
+def cq_histogram(img: torch.Tensor, ws: Workspace, capacity: int | None = None):
+    """Unique colour keys (ascending) and pixel counts, as device uint32 tensors."""
+    H, W, stride = _image_args(img)
+    cap = H * W if capacity is None else capacity
+    keys = torch.empty(max(cap, 1), dtype=torch.int32, device=img.device)
+    counts = torch.empty(max(cap, 1), dtype=torch.int32, device=img.device)
+    n = ctypes.c_int64(0)
+    rc = lib().cq_histogram(_ptr(img), H, W, stride, _ptr(keys), _ptr(counts), cap, ctypes.byref(n),
+                            ws.ptr, ws.nbytes, _stream(img.device))
+    _check("cq_histogram", rc)
+    return keys[: n.value], counts[: n.value]
+
+
+def cq_init(keys: torch.Tensor, counts: torch.Tensor, K: int, scheme: int, seed: int, ws: Workspace,
+            centers: torch.Tensor | None = None):
+    """Initial centres (device float64 [K, 3]) and k_used."""
+    if centers is None:
+        centers = torch.zeros((K, 3), dtype=torch.float64, device=keys.device)
+    k_used = ctypes.c_int32(0)
+    rc = lib().cq_init(_ptr(keys), _ptr(counts), keys.numel(), K, scheme, seed, _ptr(centers),
+                       ctypes.byref(k_used), ws.ptr, ws.nbytes, _stream(keys.device))
+    _check("cq_init", rc)
+    return centers, k_used.value
+
+
+@dataclass
+class KMeansOut:
+    centers: torch.Tensor
+    assign: torch.Tensor
+    palette: torch.Tensor
+    sse_trace: list
+    stats: dict
+
+
+def cq_kmeans(keys: torch.Tensor, counts: torch.Tensor, centers: torch.Tensor, max_iters: int,
+              tol: float, prune: bool, ws: Workspace) -> KMeansOut:
+    """Weighted Lloyd / sort-means from ``centers`` (updated in place)."""
+    import numpy as np
+
+    K = centers.shape[0]
+    assign = torch.zeros(keys.numel(), dtype=torch.uint8, device=keys.device)
+    palette = torch.zeros((K, 3), dtype=torch.uint8, device=keys.device)
+    trace = np.zeros(max_iters, np.float64)
+    st = CqStats()
+    rc = lib().cq_kmeans(_ptr(keys), _ptr(counts), keys.numel(), K, _ptr(centers), max_iters, tol,
+                         int(bool(prune)), _ptr(assign), _ptr(palette),
+                         trace.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st), ws.ptr, ws.nbytes,
+                         _stream(keys.device))
+    _check("cq_kmeans", rc)
+    return KMeansOut(centers, assign, palette, trace[: st.iters].tolist(), st.as_dict())
+
+
+def cq_map(img: torch.Tensor, keys: torch.Tensor, counts: torch.Tensor | None, palette: torch.Tensor,
+           ws: Workspace, want_idx: bool = True, want_rgb: bool = True):
+    """Map every pixel to its nearest palette entry; returns (idx, rgb, sq_err_sum)."""
+    H, W, stride = _image_args(img)
+    K = palette.shape[0]
+    idx = torch.empty((H, W), dtype=torch.uint8, device=img.device) if want_idx else None
+    rgb = torch.empty((H, W, 3), dtype=torch.uint8, device=img.device) if want_rgb else None
+    err = ctypes.c_uint64(0)
+    rc = lib().cq_map(_ptr(img), H, W, stride, _ptr(keys), _ptr(counts), keys.numel(), _ptr(palette),
+                      K, _ptr(idx), _ptr(rgb), ctypes.byref(err) if counts is not None else None,
+                      ws.ptr, ws.nbytes, _stream(img.device))
+    _check("cq_map", rc)
+    return idx, rgb, (err.value if counts is not None else None)
+
+
+def cq_quantize(img: torch.Tensor, K: int, scheme: int, seed: int, max_iters: int, tol: float,
+                prune: bool, ws: Workspace, want_idx: bool = True, want_rgb: bool = True,
+                palette: torch.Tensor | None = None, out_idx: torch.Tensor | None = None,
+                out_rgb: torch.Tensor | None = None):
+    """Whole quantizer on one image; returns (palette, idx, rgb, stats)."""
+    H, W, stride = _image_args(img)
+    dev = img.device
+    if palette is None:
+        palette = torch.zeros((K, 3), dtype=torch.uint8, device=dev)
+    if out_idx is None and want_idx:
+        out_idx = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    if out_rgb is None and want_rgb:
+        out_rgb = torch.empty((H, W, 3), dtype=torch.uint8, device=dev)
+    st = CqStats()
+    rc = lib().cq_quantize(_ptr(img), H, W, stride, K, scheme, seed, max_iters, tol, int(bool(prune)),
+                           _ptr(palette), _ptr(out_idx), _ptr(out_rgb), ctypes.byref(st), ws.ptr,
+                           ws.nbytes, _stream(dev))
+    _check("cq_quantize", rc)
+    return palette, out_idx, out_rgb, st.as_dict()

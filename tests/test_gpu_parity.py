@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every comparison is bit-exact: histogram keys and counts, initial centres,
+memberships, FP64 centres, the SSE trace, iteration and distance counts, the
+palette, the mapped image and its integer squared-error sum.  The relative MSE
+error bound of 1e-6 is therefore met with zero error.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1101_0395_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cqm(dev):
+    from paper_1101_0395_amd import cq
+    cq.lib()
+    return cq
+
+
+@pytest.fixture(scope="module")
+def ws_small(cqm, dev):
+    return cqm.Workspace(1024, 1024, 256, dev)
+
+
+def _to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+RAGGED = [(1, 1), (1, 7), (3, 5), (7, 13), (33, 65), (64, 64), (127, 129), (512, 512)]
+
+
+@pytest.mark.parametrize("shape", RAGGED)
+def test_histogram_parity(cqm, dev, ws_small, shape):
+    H, W = shape
+    _say(f"histogram {H}x{W}")
+    img = synth.smooth_field_blobs(H, W, H * 1000 + W)
+    keys, counts = cqm.cq_histogram(_to_dev(img, dev), ws_small)
+    rk, rc = oracle.histogram(img)
+    assert np.array_equal(_u32(keys), rk)
+    assert np.array_equal(_u32(counts), rc)
+
+
+def test_histogram_strided_rows_and_capacity(cqm, dev, ws_small):
+    _say("histogram strided + capacity")
+    rng = np.random.default_rng(3)
+    base = rng.integers(0, 6, (37, 41, 3)).astype(np.uint8)
+    padded = torch.zeros((37, 41 * 3 + 5), dtype=torch.uint8, device=dev)
+    padded[:, :123] = _to_dev(base.reshape(37, 123), dev)
+    view = padded.as_strided((37, 41, 3), (128, 3, 1))
+    keys, counts = cqm.cq_histogram(view, ws_small)
+    rk, rc = oracle.histogram(base)
+    assert np.array_equal(_u32(keys), rk) and np.array_equal(_u32(counts), rc)
+    with pytest.raises(cqm.CqError) as e:
+        cqm.cq_histogram(view, ws_small, capacity=len(rk) - 1)
+    assert e.value.code == cqm.CQ_ECAPACITY
+    # the table was left clean: a second run still matches
+    keys, counts = cqm.cq_histogram(view, ws_small)
+    assert np.array_equal(_u32(keys), rk) and np.array_equal(_u32(counts), rc)
+
+
+def test_histogram_single_colour_and_all_distinct(cqm, dev, ws_small):
+    _say("histogram single colour / all distinct")
+    img = np.full((50, 70, 3), 77, np.uint8)
+    keys, counts = cqm.cq_histogram(_to_dev(img, dev), ws_small)
+    assert _u32(keys).tolist() == [(77 << 16) | (77 << 8) | 77] and _u32(counts).tolist() == [3500]
+    ks = np.random.default_rng(0).permutation(1 << 24)[: 300 * 300].astype(np.uint32)
+    img = np.stack([(ks >> 16) & 255, (ks >> 8) & 255, ks & 255], 1).astype(np.uint8).reshape(300, 300, 3)
+    keys, counts = cqm.cq_histogram(_to_dev(img, dev), ws_small)
+    assert np.array_equal(_u32(keys), np.sort(ks)) and (_u32(counts) == 1).all()
+
+
+def _hist_pair(img, cqm, dev, ws):
+    rk, rc = oracle.histogram(img)
+    return rk, rc, _to_dev(rk.view(np.int32), dev), _to_dev(rc.view(np.int32), dev)
+
+
+@pytest.mark.parametrize("scheme", [oracle.INIT_FORGY, oracle.INIT_MAXMIN, oracle.INIT_KMEANSPP])
+@pytest.mark.parametrize("K,seed", [(16, 0), (64, 3), (256, 1)])
+def test_init_parity(cqm, dev, ws_small, scheme, K, seed):
+    _say(f"init scheme={scheme} K={K} seed={seed}")
+    img = synth.smooth_field_blobs(200, 300, seed)
+    rk, rc, dk, dc = _hist_pair(img, cqm, dev, ws_small)
+    ref, ref_used = oracle.init(rk, rc, K, scheme, seed)
+    got, used = cqm.cq_init(dk, dc, K, scheme, seed, ws_small)
+    assert used == ref_used
+    assert np.array_equal(got.cpu().numpy(), ref)
+
+
+def test_init_fewer_colours_than_k(cqm, dev, ws_small):
+    _say("init N' <= K")
+    img = np.array([[[1, 2, 3], [1, 2, 3], [9, 9, 9]]], np.uint8)
+    rk, rc, dk, dc = _hist_pair(img, cqm, dev, ws_small)
+    for scheme in (0, 1, 2):
+        got, used = cqm.cq_init(dk, dc, 4, scheme, 0, ws_small)
+        ref, ref_used = oracle.init(rk, rc, 4, scheme, 0)
+        assert used == ref_used == 2 and np.array_equal(got.cpu().numpy(), ref)
+
+
+def _compare_kmeans(g, r):
+    assert np.array_equal(g.assign.cpu().numpy(), r.assign)
+    assert np.array_equal(g.centers.cpu().numpy(), r.centers)
+    assert np.array_equal(np.array(g.sse_trace), r.sse_trace)
+    assert np.array_equal(g.palette.cpu().numpy(), r.palette)
+    for key in ("iters", "converged", "k_used", "ndc_total", "near_ties", "sse_final", "mse_float"):
+        assert g.stats[key] == r.stats[key], key
+
+
+@pytest.mark.parametrize("prune", [False, True])
+@pytest.mark.parametrize("K,seed,scheme", [(1, 5, 2), (2, 4, 1), (16, 0, 1), (37, 2, 0), (64, 3, 2),
+                                          (256, 1, 2)])
+def test_kmeans_parity(cqm, dev, ws_small, prune, K, seed, scheme):
+    _say(f"kmeans K={K} seed={seed} scheme={scheme} prune={prune}")
+    img = synth.smooth_field_blobs(160, 224, seed) if K > 16 else synth.blobs_on_gradient(64, 64, seed)
+    rk, rc, dk, dc = _hist_pair(img, cqm, dev, ws_small)
+    c0, _ = oracle.init(rk, rc, K, scheme, seed)
+    r = oracle.kmeans(rk, rc, c0, 100, 1e-4, prune)
+    g = cqm.cq_kmeans(dk, dc, _to_dev(c0, dev), 100, 1e-4, prune, ws_small)
+    _compare_kmeans(g, r)
+
+
+def test_kmeans_coincident_user_centres(cqm, dev, ws_small):
+    _say("kmeans coincident centres")
+    img = synth.smooth_field_blobs(96, 128, 11)
+    rk, rc, dk, dc = _hist_pair(img, cqm, dev, ws_small)
+    c0, _ = oracle.init(rk, rc, 24, oracle.INIT_KMEANSPP, 11)
+    c0[23] = c0[0]
+    c0[22] = c0[5]
+    for prune in (False, True):
+        r = oracle.kmeans(rk, rc, c0, 40, 0.0, prune)
+        g = cqm.cq_kmeans(dk, dc, _to_dev(c0, dev), 40, 0.0, prune, ws_small)
+        _compare_kmeans(g, r)
+
+
+def test_kmeans_max_iters_one_and_nonfinite_start(cqm, dev, ws_small):
+    _say("kmeans max_iters=1 / non-finite start")
+    img = synth.blobs_on_gradient(64, 64, 7)
+    rk, rc, dk, dc = _hist_pair(img, cqm, dev, ws_small)
+    c0, _ = oracle.init(rk, rc, 16, oracle.INIT_MAXMIN, 7)
+    r = oracle.kmeans(rk, rc, c0, 1, 1e-4, True)
+    g = cqm.cq_kmeans(dk, dc, _to_dev(c0, dev), 1, 1e-4, True, ws_small)
+    _compare_kmeans(g, r)
+    bad = c0.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(cqm.CqError) as e:
+        cqm.cq_kmeans(dk, dc, _to_dev(bad, dev), 5, 1e-4, True, ws_small)
+    assert e.value.code == cqm.CQ_EINVAL
+
+
+@pytest.mark.parametrize("K", [1, 5, 16, 255, 256])
+def test_map_parity(cqm, dev, ws_small, K):
+    _say(f"map K={K}")
+    img = synth.smooth_field_blobs(123, 77, K)
+    rk, rc, dk, dc = _hist_pair(img, cqm, dev, ws_small)
+    pal = np.random.default_rng(K).integers(0, 256, (K, 3)).astype(np.uint8)
+    if K > 4:
+        pal[K - 1] = pal[1]  # duplicate entry: lowest index wins
+    idx, rgb, err = cqm.cq_map(_to_dev(img, dev), dk, dc, _to_dev(pal, dev), ws_small)
+    ridx, rrgb, rerr = oracle.map_image(img, pal)
+    assert np.array_equal(idx.cpu().numpy(), ridx)
+    assert np.array_equal(rgb.cpu().numpy(), rrgb)
+    assert err == rerr
+
+
+def _compare_quantize(g, r, img):
+    gp, gi, gr, gs = g
+    rp, ri, rr, rs = r
+    assert np.array_equal(gp.cpu().numpy(), rp)
+    assert np.array_equal(gi.cpu().numpy(), ri)
+    assert np.array_equal(gr.cpu().numpy(), rr)
+    for key in ("iters", "converged", "k_used", "n_unique", "ndc_total", "near_ties", "sse_final",
+                "mse_float", "mse_img"):
+        assert gs[key] == rs[key], key
+    mse = ((img.astype(np.float64) - gr.cpu().numpy().astype(np.float64)) ** 2).sum(-1).mean()
+    assert gs["mse_img"] == pytest.approx(mse, rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_quantize_small_config(cqm, dev, ws_small, seed):
+    _say(f"quantize 64x64 K=16 MMX plain seed={seed}")
+    img = synth.blobs_on_gradient(64, 64, seed)
+    r = oracle.quantize(img, 16, oracle.INIT_MAXMIN, seed, 50, 1e-4, prune=False)
+    g = cqm.cq_quantize(_to_dev(img, dev), 16, oracle.INIT_MAXMIN, seed, 50, 1e-4, False, ws_small)
+    _compare_quantize(g, r, img)
+
+
+@pytest.mark.parametrize("K", [32, 64, 128, 256])
+def test_quantize_512_config(cqm, dev, ws_small, K):
+    _say(f"quantize 512x512 K={K} KPP pruned seed=1")
+    img = synth.smooth_field_blobs(512, 512, 1)
+    r = oracle.quantize(img, K, oracle.INIT_KMEANSPP, 1, 100, 1e-4, prune=True)
+    g = cqm.cq_quantize(_to_dev(img, dev), K, oracle.INIT_KMEANSPP, 1, 100, 1e-4, True, ws_small)
+    _compare_quantize(g, r, img)
+
+
+def test_quantize_fewer_colours_than_k_and_ragged(cqm, dev, ws_small):
+    _say("quantize N' <= K, ragged 5x3")
+    img = np.array([[[5, 6, 7], [200, 100, 0], [5, 6, 7]]] * 5, np.uint8)
+    r = oracle.quantize(img, 8, oracle.INIT_KMEANSPP, 0, 20, 1e-4)
+    g = cqm.cq_quantize(_to_dev(img, dev), 8, oracle.INIT_KMEANSPP, 0, 20, 1e-4, True, ws_small)
+    _compare_quantize(g, r, img)
+
+
+def test_deterministic_repeat(cqm, dev, ws_small):
+    _say("determinism")
+    img = _to_dev(synth.smooth_field_blobs(300, 200, 9), dev)
+    a = cqm.cq_quantize(img, 128, oracle.INIT_KMEANSPP, 9, 100, 1e-4, True, ws_small)
+    b = cqm.cq_quantize(img, 128, oracle.INIT_KMEANSPP, 9, 100, 1e-4, True, ws_small)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[2], b[2]) and a[3] == b[3]
+
+
+def test_full_size_4096(cqm, dev):
+    """4096 x 4096 (16.7M pixels): histogram and map bit-exact against the
+    oracle, three k-means iterations bit-exact, and the end-to-end run's
+    image checked against its palette pixel by pixel on a sample."""
+    _say("full size 4096x4096")
+    H = W = 4096
+    img = synth.smooth_field_blobs(H, W, 42)
+    ws = cqm.Workspace(H, W, 256, dev)
+    dimg = _to_dev(img, dev)
+    keys, counts = cqm.cq_histogram(dimg, ws)
+    rk, rc = oracle.histogram(img)
+    assert np.array_equal(_u32(keys), rk) and np.array_equal(_u32(counts), rc)
+    _say(f"  N' = {len(rk)}")
+    c0, _ = oracle.init(rk, rc, 256, oracle.INIT_KMEANSPP, 42)
+    g0, _ = cqm.cq_init(keys, counts, 256, oracle.INIT_KMEANSPP, 42, ws)
+    assert np.array_equal(g0.cpu().numpy(), c0)
+    r = oracle.kmeans(rk, rc, c0, 3, 1e-4, True)
+    g = cqm.cq_kmeans(keys, counts, _to_dev(c0, dev), 3, 1e-4, True, ws)
+    _compare_kmeans(g, r)
+    idx, rgb, err = cqm.cq_map(dimg, keys, counts, g.palette, ws)
+    ridx, rrgb, rerr = oracle.map_image(img, r.palette)
+    assert np.array_equal(idx.cpu().numpy(), ridx) and np.array_equal(rgb.cpu().numpy(), rrgb)
+    assert err == rerr
+    pal, gi, gr, st = cqm.cq_quantize(dimg, 256, oracle.INIT_KMEANSPP, 42, 100, 1e-4, True, ws)
+    P = pal.cpu().numpy().astype(np.int64)
+    rng = np.random.default_rng(0)
+    ys, xs = rng.integers(0, H, 20000), rng.integers(0, W, 20000)
+    X = img[ys, xs].astype(np.int64)
+    D = ((X[:, None, :] - P[None, :, :]) ** 2).sum(-1)
+    assert np.array_equal(gi.cpu().numpy()[ys, xs], np.argmin(D, axis=1))
+    mse = ((img.astype(np.float64) - gr.cpu().numpy().astype(np.float64)) ** 2).sum(-1).mean()
+    assert st["mse_img"] == pytest.approx(mse, rel=1e-12)
+    assert st["converged"] == 1
