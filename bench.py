@@ -1,0 +1,165 @@
+"""Benchmark: exact weighted sort-means colour quantization on one MI355X.
+
+Workload: the eight 512 x 512 natural-image stand-ins (seeds 1..8), K = 256,
+k-means++ initialization, sort-means pruning, tol 1e-4, at most 100
+iterations, full pixel map (index and RGB images).  One step quantizes all
+eight images end to end (histogram, init, iterations, palette, map) from
+device-resident inputs.
+
+Prints one JSON line: images/s, the distance-evaluation rate of the
+assignment kernel, the MSE relative error against the CPU oracle, a roofline
+entry for the dominant kernel (timed live with HIP events on the launch
+stream) and the oracle's own throughput on the host CPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+H = W = 512
+K = 256
+SEEDS = list(range(1, 9))
+MAX_ITERS = 100
+TOL = 1e-4
+
+PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X vector FP64
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+FLOP_PER_EVAL = 8              # 3 sub, 3 mul, 2 add per FP64 squared distance
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=15.0,
+                    help="approximate CPU seconds for the oracle baseline sample")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(images are independent, see the sharding notes in the design document)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1101_0395_amd import cq, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cq.lib()
+    host_imgs = [synth.smooth_field_blobs(H, W, s) for s in SEEDS]
+    imgs = [torch.from_numpy(im).to(dev) for im in host_imgs]
+    ws = cq.Workspace(H, W, K, dev)
+    pal = [torch.zeros((K, 3), dtype=torch.uint8, device=dev) for _ in SEEDS]
+    oidx = [torch.empty((H, W), dtype=torch.uint8, device=dev) for _ in SEEDS]
+    orgb = [torch.empty((H, W, 3), dtype=torch.uint8, device=dev) for _ in SEEDS]
+
+    def step():
+        out = []
+        for i, img in enumerate(imgs):
+            out.append(cq.cq_quantize(img, K, cq.INIT_KMEANSPP, SEEDS[i], MAX_ITERS, TOL, True, ws,
+                                      palette=pal[i], out_idx=oidx[i], out_rgb=orgb[i])[3])
+        return out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    timer = cq.KernelTimer("k_assign_sm", max_launches=args.steps * len(SEEDS) * (MAX_ITERS + 1))
+    timer.enable()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        stats.extend(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, assign_ms = timer.read()
+    timer.disable()
+
+    elapsed = t1 - t0
+    n_img = args.steps * len(SEEDS)
+    ndc = sum(s["ndc_total"] for s in stats)
+    # distance evaluations of the sort-means passes (iteration 1 is a full search)
+    ndc_sm = sum(s["ndc_total"] - s["n_unique"] * K for s in stats if s["iters"] >= 1)
+    dense = sum(s["n_unique"] * K * s["iters"] for s in stats)
+    achieved_tflops = FLOP_PER_EVAL * ndc_sm / (assign_ms * 1e-3) / 1e12 if assign_ms > 0 else 0.0
+
+    line = {
+        "metric": "images/sec (512x512, K=256, plain one-image-per-call path)",
+        "value": n_img / elapsed,
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 distances, u32/u64 integer histogram and sums",
+        "data": "synthetic (seeded natural-image stand-ins)",
+        "config": {"workload": "8 images 512x512x3 uint8 (seeds 1-8), K=256, k-means++ init, "
+                               "sort-means pruned, tol 1e-4, max 100 iters, full pixel map",
+                   "images_per_step": len(SEEDS), "K": K, "H": H, "W": W,
+                   "mean_unique_colours": float(np.mean([s["n_unique"] for s in stats])),
+                   "mean_iters": float(np.mean([s["iters"] for s in stats]))},
+        "evals_per_s_assign_sm": ndc_sm / (assign_ms * 1e-3) if assign_ms > 0 else None,
+        "evals_per_s_wall": ndc / elapsed,
+        "dense_equiv_evals_per_s_wall": dense / elapsed,
+        "ndc_per_colour_iter": ndc / max(1, sum(s["n_unique"] * s["iters"] for s in stats)),
+        "roofline": {
+            "kernel": "k_assign_sm",
+            "bound": "alu",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP64_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP64_VALU_TFLOPS,
+            "traffic": None,
+            "launches": launches,
+            "avg_launch_us": 1e3 * assign_ms / max(1, launches),
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+
+        t = time.perf_counter()
+        done = 0
+        mse_err = []
+        for i, im in enumerate(host_imgs):
+            _, _, _, rs = oracle.quantize(im, K, oracle.INIT_KMEANSPP, SEEDS[i], MAX_ITERS, TOL,
+                                          prune=True, want_images=True)
+            done += 1
+            g = stats[i]
+            mse_err.append(abs(g["mse_img"] - rs["mse_img"]) / rs["mse_img"])
+            if time.perf_counter() - t > args.cpu_budget_s:
+                break
+        cpu_s = time.perf_counter() - t
+        line["cpu_baseline"] = {
+            "value": done / cpu_s,
+            "unit": "images/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"{done} of the 8 images, single-threaded C oracle, same settings",
+        }
+        line["mse_rel_err_max"] = max(mse_err)
+        line["mse_rel_err_mean"] = float(np.mean(mse_err))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

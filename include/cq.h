@@ -98,7 +98,8 @@ cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_str
  * uniformly; KPP draws the first colour with probability proportional to its
  * count and colour j with probability proportional to count * D^2.  With
  * CQ_INIT_USER the centres are left as given.  Synchronizes only if k_used is
- * non-null. */
+ * non-null; a device-side failure of the initialization is reported by that
+ * synchronization or by the next synchronizing call on the workspace. */
 cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique, int32_t K,
                   cq_init_t scheme, uint64_t seed, double* centers, int32_t* k_used /* host */,
                   void* ws, size_t ws_bytes, void* stream);
@@ -147,6 +148,52 @@ cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stri
                       int32_t K, cq_init_t scheme, uint64_t seed, int32_t max_iters, double tol,
                       int32_t prune, uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb,
                       cq_stats* stats /* host */, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batches: many images of different sizes and palette sizes quantized by one
+ * sequence of launches (every kernel covers all jobs; a job that has stopped
+ * iterating costs its blocks one early return).  Results are identical to
+ * cq_quantize on each image alone.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const uint8_t* img;         /* device uint8 [H][W][3], rows row_stride_bytes apart  */
+    int32_t H, W;
+    int64_t row_stride_bytes;
+    int32_t K;                  /* palette size, 1..256                                 */
+    cq_init_t scheme;           /* CQ_INIT_FORGY, CQ_INIT_MAXMIN or CQ_INIT_KMEANSPP    */
+    uint64_t seed;
+    int32_t max_iters;          /* 1..100000                                            */
+    double tol;                 /* >= 0                                                 */
+    int32_t prune;              /* 1: sort-means, 0: full search                        */
+    uint8_t* palette;           /* device uint8 [K][3] (entries past k_used are zero)   */
+    uint8_t* out_idx;           /* device uint8 [H][W], nullable                         */
+    uint8_t* out_rgb;           /* device uint8 [H][W][3], nullable                      */
+} cq_job;
+
+/* Workspace bytes for a batch (one slot per job plus descriptors); 0 for an
+ * invalid description.  At most 4096 jobs. */
+size_t cq_batch_workspace_bytes(const cq_job* jobs /* host */, int32_t n_jobs);
+
+/* Clears the zero-between-calls regions of every slot (once per workspace, and
+ * after CQ_EDEVICE).  The same job sizes must be used with the workspace. */
+cq_status cq_batch_workspace_prepare(const cq_job* jobs /* host */, int32_t n_jobs, void* ws,
+                                     size_t ws_bytes, void* stream);
+
+/* cq_quantize for every job of the batch.  stats (host, nullable) receives one
+ * cq_stats per job.  Synchronizes `stream`. */
+cq_status cq_quantize_batch(const cq_job* jobs /* host */, int32_t n_jobs, cq_stats* stats /* host */,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel timing for measurement harnesses (not needed for quantization).
+ * While enabled, every launch of the kernel named `kernel` (for example
+ * "k_assign", "k_hist_packed", "k_map_packed") is bracketed by a pair of HIP
+ * events recorded on the stream it is launched on, for at most max_launches
+ * launches.  cq_timer_read waits for those events and returns the number of
+ * bracketed launches and the sum of their durations in milliseconds.
+ * Process-global state: enable, run and read from one host thread. */
+cq_status cq_timer_enable(const char* kernel, int32_t max_launches);
+cq_status cq_timer_read(int64_t* launches /* host */, double* total_ms /* host */);
+cq_status cq_timer_disable(void);
 
 /* Thread-local description of the last error on this thread ("" if none);
  * valid until the next cq_* call on the same thread. */

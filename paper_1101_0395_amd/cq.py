@@ -19,7 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libcq.so")
 CQ_OK, CQ_EINVAL, CQ_ECAPACITY, CQ_EWORKSPACE, CQ_EDEVICE = 0, 1, 2, 3, 4
 INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER = 0, 1, 2, 3
 EXPORTS = ("cq_workspace_bytes", "cq_workspace_prepare", "cq_histogram", "cq_init", "cq_kmeans",
-           "cq_map", "cq_quantize", "cq_last_error")
+           "cq_map", "cq_quantize", "cq_batch_workspace_bytes", "cq_batch_workspace_prepare",
+           "cq_quantize_batch", "cq_timer_enable", "cq_timer_read", "cq_timer_disable",
+           "cq_last_error")
 
 
 class CqStats(ctypes.Structure):
@@ -38,6 +40,24 @@ class CqStats(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class CqJob(ctypes.Structure):
+    _fields_ = [
+        ("img", ctypes.c_void_p),
+        ("H", ctypes.c_int32),
+        ("W", ctypes.c_int32),
+        ("row_stride_bytes", ctypes.c_int64),
+        ("K", ctypes.c_int32),
+        ("scheme", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("max_iters", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("prune", ctypes.c_int32),
+        ("palette", ctypes.c_void_p),
+        ("out_idx", ctypes.c_void_p),
+        ("out_rgb", ctypes.c_void_p),
+    ]
 
 
 class CqError(RuntimeError):
@@ -72,10 +92,41 @@ def lib() -> ctypes.CDLL:
         for f in ("cq_workspace_prepare", "cq_histogram", "cq_init", "cq_kmeans", "cq_map",
                   "cq_quantize"):
             getattr(L, f).restype = ctypes.c_int
+        L.cq_batch_workspace_bytes.argtypes = [ctypes.POINTER(CqJob), i32]
+        L.cq_batch_workspace_bytes.restype = sz
+        L.cq_batch_workspace_prepare.argtypes = [ctypes.POINTER(CqJob), i32, P, sz, P]
+        L.cq_batch_workspace_prepare.restype = ctypes.c_int
+        L.cq_quantize_batch.argtypes = [ctypes.POINTER(CqJob), i32, ctypes.POINTER(CqStats), P, sz, P]
+        L.cq_quantize_batch.restype = ctypes.c_int
+        L.cq_timer_enable.argtypes = [ctypes.c_char_p, i32]
+        L.cq_timer_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(f64)]
+        L.cq_timer_disable.argtypes = []
+        for f in ("cq_timer_enable", "cq_timer_read", "cq_timer_disable"):
+            getattr(L, f).restype = ctypes.c_int
         L.cq_last_error.argtypes = []
         L.cq_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
+
+
+class KernelTimer:
+    """HIP-event timing of every launch of one named kernel (library-side)."""
+
+    def __init__(self, kernel: str, max_launches: int):
+        self.kernel = kernel
+        self.max_launches = int(max_launches)
+
+    def enable(self):
+        _check("cq_timer_enable", lib().cq_timer_enable(self.kernel.encode(), self.max_launches))
+
+    def read(self):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        _check("cq_timer_read", lib().cq_timer_read(ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def disable(self):
+        _check("cq_timer_disable", lib().cq_timer_disable())
 
 
 def _check(fn: str, rc: int, allow=()):
@@ -210,3 +261,45 @@ def cq_quantize(img: torch.Tensor, K: int, scheme: int, seed: int, max_iters: in
                            ws.nbytes, _stream(dev))
     _check("cq_quantize", rc)
     return palette, out_idx, out_rgb, st.as_dict()
+
+
+class BatchJob:
+    """One image of a batch with its outputs (device tensors)."""
+
+    def __init__(self, img: torch.Tensor, K: int, scheme: int, seed: int, max_iters: int, tol: float,
+                 prune: bool = True, want_idx: bool = True, want_rgb: bool = True):
+        H, W, stride = _image_args(img)
+        dev = img.device
+        self.img = img
+        self.palette = torch.zeros((K, 3), dtype=torch.uint8, device=dev)
+        self.idx = torch.empty((H, W), dtype=torch.uint8, device=dev) if want_idx else None
+        self.rgb = torch.empty((H, W, 3), dtype=torch.uint8, device=dev) if want_rgb else None
+        self.c = CqJob(ctypes.c_void_p(img.data_ptr()), H, W, stride, K, scheme, seed, max_iters, tol,
+                       int(bool(prune)), ctypes.c_void_p(self.palette.data_ptr()),
+                       ctypes.c_void_p(self.idx.data_ptr()) if want_idx else None,
+                       ctypes.c_void_p(self.rgb.data_ptr()) if want_rgb else None)
+
+
+class BatchWorkspace:
+    """Caller-owned workspace for one batch shape (job sizes), prepared once."""
+
+    def __init__(self, jobs: list[BatchJob], device="cuda"):
+        self.device = torch.device(device)
+        arr = (CqJob * len(jobs))(*[j.c for j in jobs])
+        self.nbytes = lib().cq_batch_workspace_bytes(arr, len(jobs))
+        if self.nbytes == 0:
+            raise ValueError("invalid batch description")
+        self._buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._buf.data_ptr()
+        self.ptr = ctypes.c_void_p(base + (-base) % 256)
+        _check("cq_batch_workspace_prepare",
+               lib().cq_batch_workspace_prepare(arr, len(jobs), self.ptr, self.nbytes, _stream(self.device)))
+
+
+def cq_quantize_batch(jobs: list[BatchJob], ws: BatchWorkspace) -> list[dict]:
+    """Quantize every job of the batch; returns one stats dict per job."""
+    arr = (CqJob * len(jobs))(*[j.c for j in jobs])
+    stats = (CqStats * len(jobs))()
+    rc = lib().cq_quantize_batch(arr, len(jobs), stats, ws.ptr, ws.nbytes, _stream(ws.device))
+    _check("cq_quantize_batch", rc)
+    return [st.as_dict() for st in stats]

@@ -1,8 +1,12 @@
-// C-ABI entry points of libcq: argument validation, workspace carving, kernel
-// sequencing and the host side of the iteration loop.
+// C-ABI entry points of libcq: argument validation, workspace carving, the
+// batch descriptors every kernel reads, and the host side of the iteration
+// loop.  The single-image calls run as batches of one job.
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
+
+#include <deque>
+#include <vector>
 
 #include "cq_internal.h"
 
@@ -10,23 +14,24 @@ namespace cq {
 
 // kernels launched from the other translation units
 cq_status launch_fill_zero(void* p, size_t bytes, hipStream_t s);
-cq_status launch_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride,
-                           uint32_t* keys, uint32_t* counts, int64_t capacity, void* ws,
-                           const Layout& L, hipStream_t s);
-cq_status launch_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int K, int scheme,
-                      uint64_t seed, double* centers, void* ws, const Layout& L, hipStream_t s);
-cq_status launch_kmeans_begin(const double* centers, int K, void* ws, const Layout& L, hipStream_t s);
-cq_status launch_kmeans_iters(const uint32_t* keys, const uint32_t* counts, int64_t n, int K,
-                              double* centers, uint8_t* assign, int prune, int it0, int it1,
-                              int max_iters, double tol, void* ws, const Layout& L, hipStream_t s);
-cq_status launch_palette(const double* centers, int K, uint8_t* palette, hipStream_t s);
-cq_status launch_identity_assign(uint8_t* assign, int64_t n, hipStream_t s);
-cq_status launch_lut(const uint32_t* keys, const uint32_t* counts, int64_t n, const uint8_t* palette,
-                     int K, void* ws, const Layout& L, hipStream_t s);
-cq_status launch_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride,
-                     const uint8_t* palette, int K, uint8_t* out_idx, uint8_t* out_rgb, void* ws,
-                     const Layout& L, hipStream_t s);
+int hist_blocks(int64_t npix);
+cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_hist_blocks, hipStream_t s);
+int coop_capacity();
+int coop_team_blocks(int64_t n);
+bool coop_fits_lds(int64_t C);
+cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s);
+cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s);
+cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, bool lds, hipStream_t s);
+cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s);
+cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, int assign_blocks,
+                             int update_blocks, hipStream_t s);
+cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s);
+int64_t assign_chunk(int64_t n);
+int map_blocks(int64_t npix);
+cq_status launch_lut(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s);
+cq_status launch_map(const JobDev* jobs, const int* maps, int B, int total, hipStream_t s);
 
+// ---------------------------------------------------------------- errors
 static thread_local char g_error[512];
 
 void set_error(const char* fmt, ...)
@@ -58,6 +63,48 @@ static cq_status einval(const char* fmt, ...)
     return CQ_EINVAL;
 }
 
+#define CQ_TRY(expr)                     \
+    do {                                 \
+        cq_status st_ = (expr);          \
+        if (st_ != CQ_OK) return st_;    \
+    } while (0)
+
+// ---------------------------------------------------------------- kernel timer
+struct KernelTimer {
+    bool enabled = false;
+    char name[64] = {0};
+    int32_t capacity = 0;
+    int32_t used = 0;
+    hipEvent_t* start = nullptr;
+    hipEvent_t* stop = nullptr;
+};
+static KernelTimer g_timer;
+
+void timer_begin(const char* kernel, hipStream_t s)
+{
+    if (!g_timer.enabled || g_timer.used >= g_timer.capacity || strcmp(kernel, g_timer.name) != 0) return;
+    (void)hipEventRecord(g_timer.start[g_timer.used], s);
+}
+
+void timer_end(const char* kernel, hipStream_t s)
+{
+    if (!g_timer.enabled || g_timer.used >= g_timer.capacity || strcmp(kernel, g_timer.name) != 0) return;
+    (void)hipEventRecord(g_timer.stop[g_timer.used], s);
+    ++g_timer.used;
+}
+
+static void timer_release()
+{
+    for (int32_t i = 0; i < g_timer.capacity; ++i) {
+        (void)hipEventDestroy(g_timer.start[i]);
+        (void)hipEventDestroy(g_timer.stop[i]);
+    }
+    delete[] g_timer.start;
+    delete[] g_timer.stop;
+    g_timer = KernelTimer{};
+}
+
+// ---------------------------------------------------------------- checks
 static cq_status check_image(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride)
 {
     if (!img) return einval("img is null");
@@ -90,67 +137,338 @@ static cq_status check_k(int32_t K)
     return CQ_OK;
 }
 
-#define CQ_TRY(expr)                     \
-    do {                                 \
-        cq_status st_ = (expr);          \
-        if (st_ != CQ_OK) return st_;    \
-    } while (0)
-
-static cq_status sync_read(void* dst, const void* src, size_t bytes, hipStream_t s)
+static cq_status check_iters_tol(int32_t max_iters, double tol)
 {
-    CQ_HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
-    CQ_HIP_TRY(hipStreamSynchronize(s));
+    if (max_iters < 1 || max_iters > kMaxIters) return einval("max_iters = %d outside [1, %d]", max_iters, kMaxIters);
+    if (!(tol >= 0.0) || tol > 1e300) return einval("tol must be a finite value >= 0");
     return CQ_OK;
 }
 
-// Host side of the iteration loop shared by cq_kmeans and cq_quantize.
-// Iterations are enqueued in groups; the kernels of an iteration enqueued
-// after the stop return immediately, so one readback per group suffices.
-static cq_status run_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n, int K,
-                            double* centers, int max_iters, double tol, int prune, uint8_t* assign,
-                            uint8_t* palette, double* sse_trace, cq_stats* out, void* ws,
-                            const Layout& L, hipStream_t s)
+// ---------------------------------------------------------------- batches
+// Host view of one launch sequence: job descriptors, block maps, and the
+// device descriptor region they are copied to.
+struct Batch {
+    int B = 0;
+    char* desc = nullptr;
+    hipStream_t s = nullptr;
+    std::vector<JobDev> h;
+    std::vector<int> maps;
+    std::vector<JobResult> res;
+    std::deque<std::vector<char>> staged;  // host copies behind every upload, kept until the call ends
+
+    Batch(int nb, char* d, hipStream_t st)
+        : B(nb), desc(d), s(st), h(size_t(nb)), maps(size_t(kNumMaps) * (nb + 1), 0), res(size_t(nb))
+    {
+        memset(static_cast<void*>(h.data()), 0, sizeof(JobDev) * h.size());
+    }
+    JobDev* d_jobs() const { return reinterpret_cast<JobDev*>(desc); }
+    int* d_maps() const { return reinterpret_cast<int*>(desc + desc_maps_off(B)); }
+    JobResult* d_results() const { return reinterpret_cast<JobResult*>(desc + desc_results_off(B)); }
+
+    // map `id` from per-job block counts; returns the total
+    template <typename F>
+    int set_map(int id, F blocks_of)
+    {
+        int* m = maps.data() + size_t(id) * (B + 1);
+        m[0] = 0;
+        for (int j = 0; j < B; ++j) m[j + 1] = m[j] + blocks_of(j);
+        return m[B];
+    }
+};
+
+// Points the workspace-backed fields of a job at one slot with layout L.
+static void bind_slot(JobDev& J, char* slot, const Layout& L)
 {
-    cq_stats st;
-    memset(&st, 0, sizeof st);
-    st.prune = prune ? 1 : 0;
-    st.n_unique = n;
-    Meta* meta = at<Meta>(ws, L.meta);
-    if (n <= K) {
-        CQ_TRY(launch_init(keys, counts, n, K, CQ_INIT_USER, 0, centers, ws, L, s));
-        CQ_TRY(launch_identity_assign(assign, n, s));
-        st.k_used = int32_t(n);
-        st.converged = 1;
-    } else {
-        st.k_used = K;
-        CQ_TRY(launch_kmeans_begin(centers, K, ws, L, s));
-        int it = 1;
-        const int group = 8;
-        while (it <= max_iters) {
-            const int last = (it + group - 1 < max_iters) ? it + group - 1 : max_iters;
-            CQ_TRY(launch_kmeans_iters(keys, counts, n, K, centers, assign, prune, it, last, max_iters,
-                                       tol, ws, L, s));
-            int32_t done = 0;
-            CQ_TRY(sync_read(&done, &meta->done, sizeof done, s));
-            if (done) break;
-            it = last + 1;
+    J.tbl = reinterpret_cast<uint32_t*>(slot + L.tbl);
+    J.bitmap = reinterpret_cast<uint32_t*>(slot + L.bitmap);
+    J.lut = reinterpret_cast<uint8_t*>(slot + L.lut);
+    J.meta = reinterpret_cast<Meta*>(slot + L.meta);
+    J.trace = reinterpret_cast<double*>(slot + L.trace);
+    J.td = reinterpret_cast<double*>(slot + L.td);
+    J.tm = reinterpret_cast<uint8_t*>(slot + L.tm);
+    J.sums = reinterpret_cast<unsigned long long*>(slot + L.sums);
+    J.blk = reinterpret_cast<uint32_t*>(slot + L.blk);
+    J.vals = reinterpret_cast<uint64_t*>(slot + L.chunks);
+    J.d2 = reinterpret_cast<uint32_t*>(slot + L.d2);
+}
+
+static void set_image(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride)
+{
+    J.img = img;
+    J.H = H;
+    J.W = W;
+    J.stride = stride;
+    J.packed = (stride == 3 * int64_t(W) && (reinterpret_cast<uintptr_t>(img) & 3u) == 0) ? 1 : 0;
+}
+
+// Copies the job descriptors and block maps to the device.  Each upload reads
+// its own host snapshot, which outlives the asynchronous copy.
+static cq_status upload(Batch& b)
+{
+    const size_t jb = sizeof(JobDev) * size_t(b.B), mb = sizeof(int) * b.maps.size();
+    b.staged.emplace_back(jb + mb);
+    char* snap = b.staged.back().data();
+    memcpy(snap, b.h.data(), jb);
+    memcpy(snap + jb, b.maps.data(), mb);
+    CQ_HIP_TRY(hipMemcpyAsync(b.desc, snap, jb, hipMemcpyHostToDevice, b.s));
+    CQ_HIP_TRY(hipMemcpyAsync(b.d_maps(), snap + jb, mb, hipMemcpyHostToDevice, b.s));
+    return CQ_OK;
+}
+
+__global__ void k_collect(const JobDev* __restrict__ jobs, int B, JobResult* __restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= B) return;
+    const Meta* m = jobs[j].meta;
+    JobResult r;
+    r.n_unique = m->n_unique;
+    r.ndc = m->ndc;
+    r.near_ties = m->near_ties;
+    r.sq_err = m->sq_err;
+    r.total_w = m->total_w;
+    r.sse_last = m->sse_last;
+    r.done = m->done;
+    r.iters = m->iters;
+    r.converged = m->converged;
+    r.bad_input = m->bad_input;
+    r.sync_error = m->sync_error;
+    r.pad_ = 0;
+    out[j] = r;
+}
+
+__global__ void k_zero_sq_err(const JobDev* __restrict__ jobs, int B)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < B) jobs[j].meta->sq_err = 0;
+}
+
+// Gathers every job's control block into b.res (synchronizes the stream).
+static cq_status collect(Batch& b)
+{
+    CQ_TIMED_LAUNCH("k_collect", b.s, k_collect<<<(b.B + 63) / 64, 64, 0, b.s>>>(b.d_jobs(), b.B, b.d_results()));
+    CQ_HIP_TRY(hipMemcpyAsync(b.res.data(), b.d_results(), sizeof(JobResult) * size_t(b.B), hipMemcpyDeviceToHost, b.s));
+    CQ_HIP_TRY(hipStreamSynchronize(b.s));
+    return CQ_OK;
+}
+
+// ---------------------------------------------------------------- phases
+static cq_status run_histogram(Batch& b)
+{
+    const int total = b.set_map(kMapHist, [&](int j) { return hist_blocks(int64_t(b.h[j].H) * b.h[j].W); });
+    CQ_TRY(upload(b));
+    return launch_histogram(b.d_jobs(), b.d_maps(), b.B, total, b.s);
+}
+
+// Once N' is known (from the histogram or from the caller).
+static void set_counts(Batch& b, const std::vector<int64_t>& n)
+{
+    for (int j = 0; j < b.B; ++j) {
+        JobDev& J = b.h[j];
+        J.n = n[j];
+        J.chunk = assign_chunk(J.n);
+        J.map_k = int32_t(J.n < J.K ? J.n : J.K);
+    }
+}
+
+static cq_status run_init(Batch& b)
+{
+    CQ_TRY(upload(b));
+    CQ_TRY(launch_init_begin(b.d_jobs(), b.B, b.s));
+    bool any_forgy = false;
+    std::vector<int> want(size_t(b.B), 0);
+    for (int j = 0; j < b.B; ++j) {
+        const JobDev& J = b.h[j];
+        if (J.n <= J.K) continue;
+        if (J.scheme == CQ_INIT_FORGY) any_forgy = true;
+        if (J.scheme == CQ_INIT_MAXMIN || J.scheme == CQ_INIT_KMEANSPP) want[j] = coop_team_blocks(J.n);
+    }
+    if (any_forgy) CQ_TRY(launch_forgy(b.d_jobs(), b.B, b.s));
+    const int cap = coop_capacity();
+    int next = 0;
+    while (true) {
+        while (next < b.B && want[next] == 0) ++next;
+        if (next >= b.B) break;
+        if (cap <= 0) {
+            set_error("cooperative launch is not available on this device");
+            return CQ_EDEVICE;
         }
-        Meta m;
-        CQ_TRY(sync_read(&m, meta, sizeof m, s));
-        if (m.bad_input) return einval("initial centres contain a non-finite value");
-        st.iters = m.iters;
-        st.converged = m.converged;
-        st.ndc_total = int64_t(m.ndc);
-        st.near_ties = int64_t(m.near_ties);
-        st.sse_final = m.sse_last;
-        st.mse_float = m.total_w ? m.sse_last / double(m.total_w) : 0.0;
-        if (sse_trace && st.iters > 0) {
-            CQ_TRY(sync_read(sse_trace, at<double>(ws, L.trace), sizeof(double) * size_t(st.iters), s));
+        // the next wave: consecutive jobs whose teams fit the co-resident capacity
+        const int first = next;
+        int last = first, used = 0;
+        for (int j = first; j < b.B; ++j) {
+            if (want[j] == 0) {
+                last = j + 1;
+                continue;
+            }
+            const int g = want[j] < cap ? want[j] : cap;
+            if (used > 0 && used + g > cap) break;
+            used += g;
+            last = j + 1;
+        }
+        bool lds = true;
+        for (int j = 0; j < b.B; ++j) {
+            JobDev& J = b.h[j];
+            J.init_blocks = 0;
+            if (j < first || j >= last || want[j] == 0) continue;
+            const int g = want[j] < cap ? want[j] : cap;
+            J.init_blocks = g;
+            J.init_C = (J.n + g - 1) / g;
+            if (!coop_fits_lds(J.init_C)) lds = false;
+        }
+        const int total = b.set_map(kMapInit, [&](int j) { return b.h[j].init_blocks; });
+        CQ_TRY(upload(b));
+        CQ_TRY(launch_init_coop(b.d_jobs(), b.d_maps() + kMapInit * (b.B + 1), b.B, total, lds, b.s));
+        next = last;
+    }
+    return CQ_OK;
+}
+
+// Iterations of every job until all have stopped.  Iterations are enqueued
+// in groups; a stopped job's blocks return at once, so one readback per group
+// suffices.
+static cq_status run_kmeans(Batch& b)
+{
+    int max_iters = 0;
+    for (const JobDev& J : b.h) max_iters = J.max_iters > max_iters ? J.max_iters : max_iters;
+    const int assign_total = b.set_map(kMapAssign, [&](int j) {
+        const JobDev& J = b.h[j];
+        return J.n <= J.K ? 0 : int((J.n + J.chunk - 1) / J.chunk);
+    });
+    const int update_total = b.set_map(kMapUpdate, [&](int j) {
+        const JobDev& J = b.h[j];
+        return J.n <= J.K ? 0 : (J.prune ? J.K : 1);
+    });
+    CQ_TRY(upload(b));
+    CQ_TRY(launch_kmeans_begin(b.d_jobs(), b.B, b.s));
+    if (assign_total == 0) return collect(b);
+    const int group = 8;
+    for (int it = 1; it <= max_iters; it += group) {
+        const int n_it = it + group - 1 <= max_iters ? group : max_iters - it + 1;
+        for (int q = 0; q < n_it; ++q)
+            CQ_TRY(launch_kmeans_iter(b.d_jobs(), b.d_maps(), b.B, assign_total, update_total, b.s));
+        CQ_TRY(collect(b));
+        bool all_done = true;
+        for (const JobResult& r : b.res) all_done = all_done && r.done;
+        if (all_done) break;
+    }
+    return CQ_OK;
+}
+
+static cq_status run_map(Batch& b, bool with_err)
+{
+    const int lut_total = b.set_map(kMapLut, [&](int j) {
+        const JobDev& J = b.h[j];
+        return int((J.n + J.chunk - 1) / J.chunk);
+    });
+    const int pix_total = b.set_map(kMapPix, [&](int j) {
+        const JobDev& J = b.h[j];
+        return (J.out_idx || J.out_rgb) ? map_blocks(int64_t(J.H) * J.W) : 0;
+    });
+    CQ_TRY(upload(b));
+    if (with_err) CQ_TIMED_LAUNCH("k_zero_sq_err", b.s, k_zero_sq_err<<<(b.B + 63) / 64, 64, 0, b.s>>>(b.d_jobs(), b.B));
+    if (lut_total > 0) CQ_TRY(launch_lut(b.d_jobs(), b.d_maps(), b.B, lut_total, with_err ? 1 : 0, b.s));
+    if (pix_total > 0) CQ_TRY(launch_map(b.d_jobs(), b.d_maps(), b.B, pix_total, b.s));
+    return CQ_OK;
+}
+
+static void fill_stats(const JobDev& J, const JobResult& r, cq_stats& st, bool with_img)
+{
+    memset(&st, 0, sizeof st);
+    st.iters = r.iters;
+    st.converged = r.converged;
+    st.k_used = int32_t(J.n < J.K ? J.n : J.K);
+    st.prune = J.prune ? 1 : 0;
+    st.n_unique = J.n;
+    st.ndc_total = int64_t(r.ndc);
+    st.near_ties = int64_t(r.near_ties);
+    st.sse_final = r.sse_last;
+    st.mse_float = r.total_w ? r.sse_last / double(r.total_w) : 0.0;
+    st.mse_img = with_img ? double(r.sq_err) / (double(J.H) * double(J.W)) : 0.0;
+}
+
+// After the initialization: a team barrier that gave up is a device error.
+static cq_status check_init(const Batch& b)
+{
+    for (int j = 0; j < b.B; ++j) {
+        if (b.res[j].sync_error) {
+            set_error("job %d: a barrier of the cooperative initialization timed out", j);
+            return CQ_EDEVICE;
         }
     }
-    if (palette) CQ_TRY(launch_palette(centers, K, palette, s));
-    if (out) *out = st;
     return CQ_OK;
+}
+
+// After the iterations (fields written by the k-means begin kernel).
+static cq_status check_kmeans(const Batch& b)
+{
+    for (int j = 0; j < b.B; ++j)
+        if (b.res[j].bad_input) return einval("job %d: initial centres contain a non-finite value", j);
+    return CQ_OK;
+}
+
+// Whole quantizer for a filled batch (histogram -> init -> k-means ->
+// palette -> map); fills stats (nullable, one per job).
+static cq_status run_quantize(Batch& b, cq_stats* stats)
+{
+    CQ_TRY(run_histogram(b));
+    CQ_TRY(collect(b));
+    std::vector<int64_t> n(size_t(b.B));
+    for (int j = 0; j < b.B; ++j) n[j] = b.res[j].n_unique;
+    set_counts(b, n);
+    CQ_TRY(run_init(b));
+    CQ_TRY(run_kmeans(b));
+    CQ_TRY(check_init(b));
+    CQ_TRY(check_kmeans(b));
+    CQ_TRY(launch_palette(b.d_jobs(), b.B, b.s));
+    CQ_TRY(run_map(b, true));
+    CQ_TRY(collect(b));
+    if (stats)
+        for (int j = 0; j < b.B; ++j) fill_stats(b.h[j], b.res[j], stats[j], true);
+    return CQ_OK;
+}
+
+static void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride, int32_t K,
+                              int scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
+                              uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, char* slot)
+{
+    const int64_t npix = int64_t(H) * W;
+    const Layout L = make_layout(npix, true);
+    set_image(J, img, H, W, stride);
+    bind_slot(J, slot, L);
+    J.keys = reinterpret_cast<uint32_t*>(slot + L.keys);
+    J.counts = reinterpret_cast<uint32_t*>(slot + L.counts);
+    J.assign = reinterpret_cast<uint8_t*>(slot + L.assign);
+    J.centers = reinterpret_cast<double*>(slot + L.centers);
+    J.capacity = npix;
+    J.K = K;
+    J.scheme = scheme;
+    J.seed = seed;
+    J.max_iters = max_iters;
+    J.tol = tol;
+    J.prune = prune ? 1 : 0;
+    J.palette = palette;
+    J.out_idx = out_idx;
+    J.out_rgb = out_rgb;
+    J.packed = J.packed && (reinterpret_cast<uintptr_t>(out_idx) & 3u) == 0 &&
+               (reinterpret_cast<uintptr_t>(out_rgb) & 3u) == 0;
+}
+
+static size_t slot_bytes(const cq_job& j) { return align256(make_layout(int64_t(j.H) * j.W, true).total); }
+
+static cq_status check_job(const cq_job& j, int idx)
+{
+    cq_status s = check_image(j.img, j.H, j.W, j.row_stride_bytes);
+    if (s == CQ_OK) s = check_k(j.K);
+    if (s == CQ_OK && !j.palette) s = einval("palette is null");
+    if (s == CQ_OK && (int(j.scheme) < CQ_INIT_FORGY || int(j.scheme) > CQ_INIT_KMEANSPP))
+        s = einval("scheme must be FORGY, MAXMIN or KMEANSPP");
+    if (s == CQ_OK) s = check_iters_tol(j.max_iters, j.tol);
+    if (s != CQ_OK) {
+        char msg[512];
+        snprintf(msg, sizeof msg, "job %d: %s", idx, g_error);
+        snprintf(g_error, sizeof g_error, "%s", msg);
+    }
+    return s;
 }
 
 }  // namespace cq
@@ -189,10 +507,16 @@ cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_str
     if (capacity > 0 && (!keys || !counts)) return einval("keys/counts are null");
     const Layout L = make_layout(0, false);
     CQ_TRY(check_ws(ws, ws_bytes, L.fixed_end));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    CQ_TRY(launch_histogram(img, H, W, row_stride_bytes, keys, counts, capacity, ws, L, s));
-    int64_t n = 0;
-    CQ_TRY(sync_read(&n, &at<Meta>(ws, L.meta)->n_unique, sizeof n, s));
+    Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
+    JobDev& J = b.h[0];
+    set_image(J, img, H, W, row_stride_bytes);
+    bind_slot(J, static_cast<char*>(ws), L);
+    J.keys = keys;
+    J.counts = counts;
+    J.capacity = capacity;
+    CQ_TRY(run_histogram(b));
+    CQ_TRY(collect(b));
+    const int64_t n = b.res[0].n_unique;
     *n_unique = n;
     if (n > capacity) {
         set_error("%lld unique colours exceed capacity %lld", (long long)n, (long long)capacity);
@@ -212,10 +536,20 @@ cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique
     if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_USER) return einval("unknown init scheme %d", int(scheme));
     const Layout L = make_layout(n_unique, false);
     CQ_TRY(check_ws(ws, ws_bytes, L.total));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    CQ_TRY(launch_init(keys, counts, n_unique, K, int(scheme), seed, centers, ws, L, s));
+    Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
+    JobDev& J = b.h[0];
+    bind_slot(J, static_cast<char*>(ws), L);
+    J.keys = const_cast<uint32_t*>(keys);
+    J.counts = const_cast<uint32_t*>(counts);
+    J.centers = centers;
+    J.K = K;
+    J.scheme = int(scheme);
+    J.seed = seed;
+    set_counts(b, {n_unique});
+    CQ_TRY(run_init(b));
     if (k_used) {
-        CQ_HIP_TRY(hipStreamSynchronize(s));
+        CQ_TRY(collect(b));
+        CQ_TRY(check_init(b));
         *k_used = int32_t(n_unique < K ? n_unique : K);
     }
     return CQ_OK;
@@ -230,13 +564,32 @@ cq_status cq_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n_uniq
     CQ_TRY(check_k(K));
     if (!keys || !counts || !centers || !assign) return einval("keys/counts/centers/assign is null");
     if (n_unique < 1 || n_unique > kMaxPixels) return einval("n_unique = %lld out of range", (long long)n_unique);
-    if (max_iters < 1 || max_iters > kMaxIters) return einval("max_iters = %d outside [1, %d]", max_iters, kMaxIters);
-    if (!(tol >= 0.0) || tol > 1e300) return einval("tol must be a finite value >= 0");
+    CQ_TRY(check_iters_tol(max_iters, tol));
     const Layout L = make_layout(0, false);
     CQ_TRY(check_ws(ws, ws_bytes, L.fixed_end));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    return run_kmeans(keys, counts, n_unique, K, centers, max_iters, tol, prune ? 1 : 0, assign,
-                      palette, sse_trace, stats, ws, L, s);
+    Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
+    JobDev& J = b.h[0];
+    bind_slot(J, static_cast<char*>(ws), L);
+    J.keys = const_cast<uint32_t*>(keys);
+    J.counts = const_cast<uint32_t*>(counts);
+    J.centers = centers;
+    J.assign = assign;
+    J.palette = palette;
+    J.K = K;
+    J.max_iters = max_iters;
+    J.tol = tol;
+    J.prune = prune ? 1 : 0;
+    set_counts(b, {n_unique});
+    CQ_TRY(run_kmeans(b));
+    CQ_TRY(check_kmeans(b));
+    if (palette) CQ_TRY(launch_palette(b.d_jobs(), 1, b.s));
+    const JobResult r = b.res[0];
+    if (sse_trace && r.iters > 0) {
+        CQ_HIP_TRY(hipMemcpyAsync(sse_trace, J.trace, sizeof(double) * size_t(r.iters), hipMemcpyDeviceToHost, b.s));
+    }
+    CQ_HIP_TRY(hipStreamSynchronize(b.s));
+    if (stats) fill_stats(J, r, *stats, false);
+    return CQ_OK;
 }
 
 cq_status cq_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
@@ -252,13 +605,24 @@ cq_status cq_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_by
     if (sq_err_sum && !counts) return einval("sq_err_sum needs counts");
     const Layout L = make_layout(0, false);
     CQ_TRY(check_ws(ws, ws_bytes, L.fixed_end));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    CQ_TRY(launch_lut(keys, sq_err_sum ? counts : nullptr, n_unique, palette, K, ws, L, s));
-    CQ_TRY(launch_map(img, H, W, row_stride_bytes, palette, K, out_idx, out_rgb, ws, L, s));
+    Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
+    JobDev& J = b.h[0];
+    set_image(J, img, H, W, row_stride_bytes);
+    bind_slot(J, static_cast<char*>(ws), L);
+    J.keys = const_cast<uint32_t*>(keys);
+    J.counts = const_cast<uint32_t*>(counts);
+    J.palette = const_cast<uint8_t*>(palette);
+    J.out_idx = out_idx;
+    J.out_rgb = out_rgb;
+    J.K = K;
+    set_counts(b, {n_unique});
+    J.map_k = K;
+    J.packed = J.packed && (reinterpret_cast<uintptr_t>(out_idx) & 3u) == 0 &&
+               (reinterpret_cast<uintptr_t>(out_rgb) & 3u) == 0;
+    CQ_TRY(run_map(b, sq_err_sum != nullptr));
     if (sq_err_sum) {
-        uint64_t e = 0;
-        CQ_TRY(sync_read(&e, &at<Meta>(ws, L.meta)->sq_err, sizeof e, s));
-        *sq_err_sum = e;
+        CQ_TRY(collect(b));
+        *sq_err_sum = b.res[0].sq_err;
     }
     return CQ_OK;
 }
@@ -274,31 +638,106 @@ cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stri
     if (!palette) return einval("palette is null");
     if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_KMEANSPP)
         return einval("cq_quantize needs scheme FORGY, MAXMIN or KMEANSPP");
-    if (max_iters < 1 || max_iters > kMaxIters) return einval("max_iters = %d outside [1, %d]", max_iters, kMaxIters);
-    if (!(tol >= 0.0) || tol > 1e300) return einval("tol must be a finite value >= 0");
+    CQ_TRY(check_iters_tol(max_iters, tol));
     const int64_t npix = int64_t(H) * W;
     const Layout L = make_layout(npix, true);
     CQ_TRY(check_ws(ws, ws_bytes, L.total));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    uint32_t* keys = at<uint32_t>(ws, L.keys);
-    uint32_t* counts = at<uint32_t>(ws, L.counts);
-    uint8_t* assign = at<uint8_t>(ws, L.assign);
-    double* centers = at<double>(ws, L.centers);
-    Meta* meta = at<Meta>(ws, L.meta);
+    Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
+    fill_quantize_job(b.h[0], img, H, W, row_stride_bytes, K, int(scheme), seed, max_iters, tol, prune, palette,
+                      out_idx, out_rgb, static_cast<char*>(ws));
+    return run_quantize(b, stats);
+}
 
-    CQ_TRY(launch_histogram(img, H, W, row_stride_bytes, keys, counts, npix, ws, L, s));
-    int64_t n = 0;
-    CQ_TRY(sync_read(&n, &meta->n_unique, sizeof n, s));
-    CQ_TRY(launch_init(keys, counts, n, K, int(scheme), seed, centers, ws, L, s));
-    cq_stats st;
-    CQ_TRY(run_kmeans(keys, counts, n, K, centers, max_iters, tol, prune ? 1 : 0, assign, palette,
-                      nullptr, &st, ws, L, s));
-    CQ_TRY(launch_lut(keys, counts, n, palette, st.k_used, ws, L, s));
-    CQ_TRY(launch_map(img, H, W, row_stride_bytes, palette, st.k_used, out_idx, out_rgb, ws, L, s));
-    uint64_t err = 0;
-    CQ_TRY(sync_read(&err, &meta->sq_err, sizeof err, s));
-    st.mse_img = double(err) / double(npix);
-    if (stats) *stats = st;
+size_t cq_batch_workspace_bytes(const cq_job* jobs, int32_t n_jobs)
+{
+    if (!jobs || n_jobs < 1 || n_jobs > kMaxBatch) return 0;
+    size_t total = align256(desc_bytes(n_jobs));
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const cq_job& j = jobs[i];
+        if (j.H <= 0 || j.W <= 0 || int64_t(j.H) * j.W > kMaxPixels) return 0;
+        total += slot_bytes(j);
+    }
+    return total;
+}
+
+cq_status cq_batch_workspace_prepare(const cq_job* jobs, int32_t n_jobs, void* ws, size_t ws_bytes, void* stream)
+{
+    clear_error();
+    const size_t need = cq_batch_workspace_bytes(jobs, n_jobs);
+    if (need == 0) return einval("invalid batch description");
+    CQ_TRY(check_ws(ws, ws_bytes, need));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* slot = static_cast<char*>(ws) + align256(desc_bytes(n_jobs));
+    const Layout L0 = make_layout(0, false);
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        CQ_TRY(launch_fill_zero(slot + L0.tbl, L0.lut - L0.tbl, s));
+        slot += slot_bytes(jobs[i]);
+    }
+    return CQ_OK;
+}
+
+cq_status cq_quantize_batch(const cq_job* jobs, int32_t n_jobs, cq_stats* stats, void* ws, size_t ws_bytes,
+                            void* stream)
+{
+    clear_error();
+    if (!jobs || n_jobs < 1 || n_jobs > kMaxBatch) return einval("n_jobs must be in [1, %d]", kMaxBatch);
+    for (int32_t i = 0; i < n_jobs; ++i) CQ_TRY(check_job(jobs[i], i));
+    const size_t need = cq_batch_workspace_bytes(jobs, n_jobs);
+    CQ_TRY(check_ws(ws, ws_bytes, need));
+    Batch b(n_jobs, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+    char* slot = static_cast<char*>(ws) + align256(desc_bytes(n_jobs));
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const cq_job& j = jobs[i];
+        fill_quantize_job(b.h[i], j.img, j.H, j.W, j.row_stride_bytes, j.K, int(j.scheme), j.seed, j.max_iters,
+                          j.tol, j.prune, j.palette, j.out_idx, j.out_rgb, slot);
+        slot += slot_bytes(j);
+    }
+    return run_quantize(b, stats);
+}
+
+cq_status cq_timer_enable(const char* kernel, int32_t max_launches)
+{
+    clear_error();
+    if (!kernel || !kernel[0] || strlen(kernel) >= sizeof g_timer.name) return einval("bad kernel name");
+    if (max_launches < 1 || max_launches > (1 << 22)) return einval("max_launches out of range");
+    timer_release();
+    g_timer.start = new hipEvent_t[max_launches];
+    g_timer.stop = new hipEvent_t[max_launches];
+    for (int32_t i = 0; i < max_launches; ++i) {
+        if (hipEventCreate(&g_timer.start[i]) != hipSuccess || hipEventCreate(&g_timer.stop[i]) != hipSuccess) {
+            g_timer.capacity = i;  // release what was created
+            timer_release();
+            set_error("hipEventCreate failed");
+            return CQ_EDEVICE;
+        }
+        g_timer.capacity = i + 1;
+    }
+    strncpy(g_timer.name, kernel, sizeof g_timer.name - 1);
+    g_timer.used = 0;
+    g_timer.enabled = true;
+    return CQ_OK;
+}
+
+cq_status cq_timer_read(int64_t* launches, double* total_ms)
+{
+    clear_error();
+    if (!launches || !total_ms) return einval("null output");
+    double total = 0.0;
+    for (int32_t i = 0; i < g_timer.used; ++i) {
+        CQ_HIP_TRY(hipEventSynchronize(g_timer.stop[i]));
+        float ms = 0.f;
+        CQ_HIP_TRY(hipEventElapsedTime(&ms, g_timer.start[i], g_timer.stop[i]));
+        total += double(ms);
+    }
+    *launches = g_timer.used;
+    *total_ms = total;
+    return CQ_OK;
+}
+
+cq_status cq_timer_disable(void)
+{
+    clear_error();
+    timer_release();
     return CQ_OK;
 }
 

@@ -15,6 +15,7 @@ constexpr uint32_t kBitmapWords = kNumKeys / 32;  // presence bitmap words
 constexpr int kMaxK = 256;
 constexpr int kMaxIters = 100000;
 constexpr int64_t kMaxPixels = int64_t(1) << 28;
+constexpr int kMaxBatch = 4096;
 
 // Bitmap compaction: each block owns a contiguous run of bitmap words.
 constexpr int kCompactThreads = 256;
@@ -22,11 +23,8 @@ constexpr int kCompactWordsPerThread = 8;
 constexpr int kCompactWordsPerBlock = kCompactThreads * kCompactWordsPerThread;
 constexpr int kCompactBlocks = kBitmapWords / kCompactWordsPerBlock;  // 256
 
-// Initialization: one chunk of colours per block.
-constexpr int kInitThreads = 256;
-constexpr int kInitItemsPerThread = 4;
-constexpr int kInitChunk = kInitThreads * kInitItemsPerThread;  // 1024
-constexpr int kSelectThreads = 1024;
+// Per-colour chunk bookkeeping of the initialization.
+constexpr int kInitChunk = 1024;
 
 // Sorted centre table: row stride (entries) independent of K.
 constexpr int kRow = kMaxK;
@@ -46,15 +44,90 @@ struct Meta {
     int32_t bad_input;    // k-means: a non-finite initial centre was seen
     double sse_prev;      // SSE of the previous iteration
     double sse_last;      // SSE of the last iteration
-    uint32_t pad[46];
+    uint32_t barrier;     // arrival counter of the grid barrier of a cooperative launch
+    int32_t sync_error;   // set when a grid barrier waited past its spin limit
+    int32_t cur_it;       // k-means: iteration whose cluster sums are being built
+    uint32_t pad[43];
 };
 static_assert(sizeof(Meta) <= 512, "Meta must fit its slot");
 
-// ---------------------------------------------------------------- layout
 constexpr size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// ---------------------------------------------------------------- jobs
+// One image of a launch.  Every kernel takes a device array of jobs and, where
+// jobs need different numbers of blocks, a prefix map of B + 1 block offsets
+// (block b belongs to the job j with map[j] <= b < map[j + 1]).
+struct JobDev {
+    const uint8_t* img;
+    int64_t stride;
+    int32_t H, W;
+    int32_t K, scheme, max_iters, prune;
+    uint64_t seed;
+    double tol;
+    uint8_t* palette;
+    uint8_t* out_idx;
+    uint8_t* out_rgb;
+    uint32_t* tbl;
+    uint32_t* bitmap;
+    uint8_t* lut;
+    Meta* meta;
+    double* trace;
+    double* td;
+    uint8_t* tm;
+    unsigned long long* sums;
+    uint32_t* blk;
+    uint64_t* vals;
+    uint32_t* d2;
+    uint32_t* keys;
+    uint32_t* counts;
+    uint8_t* assign;
+    double* centers;
+    int64_t capacity;    // entries of keys / counts
+    int64_t n;           // unique colours, set once the histogram is known
+    int64_t chunk;       // colours per assignment / LUT block
+    int64_t init_C;      // colours per block of the initialization team
+    int32_t init_first;  // first block of the initialization team
+    int32_t init_blocks; // blocks of the team (0: no cooperative initialization)
+    int32_t packed;      // image rows are contiguous and 4-byte aligned
+    int32_t map_k;       // palette entries the pixel map searches
+};
+
+// Per-job results gathered for one device-to-host copy.
+struct JobResult {
+    int64_t n_unique;
+    uint64_t ndc, near_ties, sq_err, total_w;
+    double sse_last;
+    int32_t done, iters, converged, bad_input, sync_error, pad_;
+};
+
+enum MapId { kMapHist = 0, kMapAssign, kMapUpdate, kMapLut, kMapPix, kMapInit, kNumMaps };
+
+__device__ __forceinline__ int find_job(const int* __restrict__ map, int B, int block)
+{
+    int lo = 0, hi = B;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (map[mid] <= block) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Descriptor region: jobs, block maps, gathered results.
+inline size_t desc_bytes(int B)
+{
+    return align256(sizeof(JobDev) * size_t(B)) + align256(sizeof(int) * size_t(kNumMaps) * size_t(B + 1)) +
+           align256(sizeof(JobResult) * size_t(B));
+}
+inline size_t desc_maps_off(int B) { return align256(sizeof(JobDev) * size_t(B)); }
+inline size_t desc_results_off(int B)
+{
+    return desc_maps_off(B) + align256(sizeof(int) * size_t(kNumMaps) * size_t(B + 1));
+}
+
+// ---------------------------------------------------------------- layout
+
 struct Layout {
-    size_t tbl, bitmap, lut, meta, trace, td, tm, sums, centers, palette, blk;
+    size_t tbl, bitmap, lut, meta, trace, td, tm, sums, centers, palette, blk, desc;
     size_t chunks, d2, keys, counts, assign;
     size_t fixed_end;  // end of the regions every call may use
     size_t total;      // end including the per-colour regions for n_cap colours
@@ -73,15 +146,17 @@ inline Layout make_layout(int64_t n_cap, bool with_colour_arrays)
     L.trace = o;    o = align256(o + sizeof(double) * kMaxIters);
     L.td = o;       o = align256(o + sizeof(double) * kMaxK * kRow);
     L.tm = o;       o = align256(o + kMaxK * kRow);
-    L.sums = o;     o = align256(o + sizeof(uint64_t) * 5 * kMaxK);
+    L.sums = o;     o = align256(o + sizeof(uint64_t) * 10 * kMaxK);  // two iterations
     L.centers = o;  o = align256(o + sizeof(double) * 3 * kMaxK);
     L.palette = o;  o = align256(o + 3 * kMaxK);
     L.blk = o;      o = align256(o + sizeof(uint32_t) * 2 * kCompactBlocks);
+    L.desc = o;     o = align256(o + desc_bytes(1));
     L.fixed_end = o;
     const size_t n = n_cap > 0 ? size_t(n_cap) : 0;
-    const size_t nchunks = (n + kInitChunk - 1) / kInitChunk;
-    L.chunks = o;   o = align256(o + sizeof(uint64_t) * (nchunks + 1));
-    L.d2 = o;       o = align256(o + sizeof(uint32_t) * n);
+    size_t nchunks = (n + kInitChunk - 1) / kInitChunk + 1;
+    if (nchunks < 2048) nchunks = 2048;  // also two rounds of up to 1024 cooperative blocks
+    L.chunks = o;   o = align256(o + sizeof(uint64_t) * nchunks);
+    L.d2 = o;       o = align256(o + sizeof(uint32_t) * 2 * n);  // double-buffered
     if (with_colour_arrays) {
         L.keys = o;   o = align256(o + sizeof(uint32_t) * n);
         L.counts = o; o = align256(o + sizeof(uint32_t) * n);
@@ -178,6 +253,40 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* tmp, T* total)
     return res;
 }
 
+// Barrier of a team of co-resident blocks (a cooperative launch).  `counter`
+// only grows: the e-th barrier (1-based) of a team of G blocks completes when
+// it reaches target = e * G.
+// Arrival is a release add (earlier writes of the block become visible first);
+// the wait polls with relaxed loads, which do not invalidate the L2 on every
+// poll, and a single acquire fence follows.  A wait longer than the spin limit,
+// or an error raised by another block, makes every block return false so that
+// the kernel can end.
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ bool grid_barrier(uint32_t* counter, uint32_t target, int32_t* error)
+{
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                ++spins > kSpinLimit) {
+                __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
@@ -204,7 +313,20 @@ namespace cq {
 void set_error(const char* fmt, ...);
 void clear_error();
 cq_status check_launch(const char* what);
+// Event bracketing of one kernel launch (active only for the timed kernel).
+void timer_begin(const char* kernel, hipStream_t s);
+void timer_end(const char* kernel, hipStream_t s);
 }  // namespace cq
+
+// Launch a kernel (the variadic part is the launch statement), bracketed by
+// the kernel timer, then check the launch.
+#define CQ_TIMED_LAUNCH(name, s, ...)                                                \
+    do {                                                                             \
+        ::cq::timer_begin(name, s);                                                  \
+        __VA_ARGS__;                                                                 \
+        ::cq::timer_end(name, s);                                                    \
+        CQ_LAUNCH_CHECK(name);                                                       \
+    } while (0)
 
 #define CQ_HIP_TRY(expr)                                                             \
     do {                                                                             \

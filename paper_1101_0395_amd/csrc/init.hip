@@ -3,14 +3,11 @@
 //
 // Every chosen centre is a colour, so D^2 (squared distance to the nearest
 // chosen centre) is an exact integer and the sampling weights n_i D_i^2 are
-// exact uint64 values.  Each round is two kernels:
-//   update : D^2 <- min(D^2, |x - chosen|^2) over all colours, one reduction
-//            value per chunk of 1024 colours (sum of n D^2, or the packed
-//            arg-max of D^2);
-//   select : one block scans the chunk values, draws from the splitmix64
-//            stream kept in the control block, locates the chunk and then the
-//            colour, and writes the new centre.
-// The draw order is the one documented for cq_init in cq.h.
+// exact uint64 values.  MMX and KPP run as one cooperative launch with a grid
+// barrier per round (below); FGY is a single wave.  The draw order is the one
+// documented for cq_init in cq.h.
+#include <stdlib.h>
+
 #include "cq_internal.h"
 
 namespace cq {
@@ -24,166 +21,18 @@ __device__ __forceinline__ void write_center(double* centers, int j, uint32_t ke
     centers[3 * j + 2] = double(b);
 }
 
-// mode 0: KPP first round, chunk value = sum of counts (d2 untouched)
-// mode 1: KPP later rounds, chunk value = sum of counts * d2
-// mode 2: MMX, chunk value = max over the chunk of (d2 << 32 | ~index)
-// first != 0: d2 is set to the distance to the chosen colour (no min).
-__global__ void __launch_bounds__(kInitThreads) k_init_update(const uint32_t* __restrict__ keys,
-                                                              const uint32_t* __restrict__ counts,
-                                                              int64_t n, uint32_t* __restrict__ d2,
-                                                              const Meta* __restrict__ meta, int mode,
-                                                              int first, uint64_t* __restrict__ chunk_val)
-{
-    __shared__ uint64_t tmp[kInitThreads / 64];
-    int cr = 0, cg = 0, cb = 0;
-    if (mode != 0) key_rgb(keys[meta->chosen], cr, cg, cb);
-    const int64_t base = int64_t(blockIdx.x) * kInitChunk;
-    uint64_t acc = 0;
-#pragma unroll
-    for (int j = 0; j < kInitItemsPerThread; ++j) {
-        const int64_t i = base + j * kInitThreads + threadIdx.x;
-        if (i >= n) break;
-        if (mode == 0) {
-            acc += counts[i];
-            continue;
-        }
-        int r, g, b;
-        key_rgb(keys[i], r, g, b);
-        const uint32_t d = dist_u32(r, g, b, cr, cg, cb);
-        uint32_t m = d;
-        if (!first) {
-            const uint32_t old = d2[i];
-            m = old < d ? old : d;
-        }
-        d2[i] = m;
-        if (mode == 1) {
-            acc += uint64_t(counts[i]) * m;
-        } else {
-            const uint64_t packed = (uint64_t(m) << 32) | uint64_t(0xFFFFFFFFu - uint32_t(i));
-            acc = packed > acc ? packed : acc;
-        }
-    }
-    acc = (mode == 2) ? wave_max(acc) : wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t v = tmp[0];
-        for (int w = 1; w < kInitThreads / 64; ++w) v = (mode == 2) ? (tmp[w] > v ? tmp[w] : v) : v + tmp[w];
-        chunk_val[blockIdx.x] = v;
-    }
-}
-
-// KPP draw for round j: pick the colour whose inclusive prefix of weights
-// first exceeds r = U(sum of weights).  weights = counts (j == 0) or
-// counts * d2.  One block of kSelectThreads threads.
-__global__ void __launch_bounds__(kSelectThreads) k_kpp_select(const uint32_t* __restrict__ keys,
-                                                               const uint32_t* __restrict__ counts,
-                                                               const uint32_t* __restrict__ d2,
-                                                               int64_t n, int64_t nchunks,
-                                                               uint64_t* __restrict__ chunk_val,
-                                                               Meta* __restrict__ meta, int j,
-                                                               double* __restrict__ centers)
-{
-    __shared__ uint64_t tmp[64];
-    __shared__ uint64_t s_r;
-    __shared__ int64_t s_chunk;
-    __shared__ uint64_t s_before;
-    // 1) exclusive prefix of chunk values, in place, segment by segment
-    static_assert(kSelectThreads == kInitChunk, "one select thread per colour of a chunk");
-    uint64_t carry = 0;
-    for (int64_t seg = 0; seg < nchunks; seg += kSelectThreads) {
-        const int64_t c = seg + threadIdx.x;
-        const uint64_t v = c < nchunks ? chunk_val[c] : 0;
-        uint64_t tot = 0;
-        const uint64_t ex = block_exclusive_scan<uint64_t>(v, tmp, &tot);
-        if (c < nchunks) chunk_val[c] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        uint64_t rng = meta->rng;
-        s_r = carry ? uniform_below(rng, carry) : 0;
-        meta->rng = rng;
-        s_chunk = -1;
-    }
-    __syncthreads();
-    // make the in-place prefixes of this block visible to itself
-    __threadfence_block();
-    const uint64_t r = s_r;
-    // 2) the chunk holding r: excl <= r < incl (zero-weight chunks never match)
-    for (int64_t c = threadIdx.x; c < nchunks; c += kSelectThreads) {
-        const uint64_t ex = chunk_val[c];
-        const uint64_t in = (c + 1 < nchunks) ? chunk_val[c + 1] : carry;
-        if (ex <= r && r < in) {
-            s_chunk = c;
-            s_before = ex;
-        }
-    }
-    __syncthreads();
-    int64_t c = s_chunk;
-    uint64_t rr = r - s_before;
-    if (c < 0) {  // unreachable: the weights sum to carry > 0
-        c = 0;
-        rr = 0;
-    }
-    // 3) inside the chunk: first colour whose inclusive prefix exceeds rr
-    const int64_t base = c * kInitChunk;
-    __shared__ int64_t s_pick;
-    if (threadIdx.x == 0) s_pick = -1;
-    __syncthreads();
-    uint64_t w = 0;
-    const int64_t i = base + threadIdx.x;  // kSelectThreads == kInitChunk
-    if (i < n) w = (j == 0) ? uint64_t(counts[i]) : uint64_t(counts[i]) * d2[i];
-    const uint64_t ex = block_exclusive_scan<uint64_t>(w, tmp, nullptr);
-    if (i < n && ex <= rr && rr < ex + w) s_pick = i;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t pick = s_pick;
-        if (pick < 0) pick = 0;  // unreachable when the weights are consistent
-        meta->chosen = pick;
-        write_center(centers, j, keys[pick]);
-    }
-}
-
-// MMX: round 0 draws the first colour uniformly; later rounds take the
-// arg-max of D^2 (lowest index on ties) from the packed chunk values.
-__global__ void __launch_bounds__(kSelectThreads) k_mmx_select(const uint32_t* __restrict__ keys,
-                                                               int64_t n, int64_t nchunks,
-                                                               const uint64_t* __restrict__ chunk_val,
-                                                               Meta* __restrict__ meta, int j,
-                                                               double* __restrict__ centers)
-{
-    __shared__ uint64_t tmp[kSelectThreads / 64];
-    int64_t pick;
-    if (j == 0) {
-        if (threadIdx.x != 0) return;
-        uint64_t rng = meta->rng;
-        pick = int64_t(uniform_below(rng, uint64_t(n)));
-        meta->rng = rng;
-    } else {
-        uint64_t best = 0;
-        for (int64_t c = threadIdx.x; c < nchunks; c += kSelectThreads) {
-            const uint64_t v = chunk_val[c];
-            best = v > best ? v : best;
-        }
-        best = wave_max(best);
-        if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = best;
-        __syncthreads();
-        if (threadIdx.x != 0) return;
-        for (int w = 1; w < kSelectThreads / 64; ++w) best = tmp[w] > best ? tmp[w] : best;
-        best = tmp[0] > best ? tmp[0] : best;
-        pick = int64_t(0xFFFFFFFFu - uint32_t(best & 0xFFFFFFFFull));
-        if (pick >= n) pick = 0;  // unreachable: every colour packs a non-zero value
-    }
-    meta->chosen = pick;
-    write_center(centers, j, keys[pick]);
-}
-
 // FGY: partial Fisher-Yates over positions [0, N').  Position j swaps with
 // r_j = j + U(N' - j); the values held by displaced positions are kept in a
 // small map searched by one wave.
-__global__ void __launch_bounds__(64) k_forgy(const uint32_t* __restrict__ keys, int64_t n, int K,
-                                              Meta* __restrict__ meta, double* __restrict__ centers)
+__global__ void __launch_bounds__(64) k_forgy(const JobDev* __restrict__ jobs)
 {
+    const JobDev& J = jobs[blockIdx.x];
+    if (J.scheme != CQ_INIT_FORGY || J.n <= J.K) return;
+    const uint32_t* __restrict__ keys = J.keys;
+    const int64_t n = J.n;
+    const int K = J.K;
+    Meta* __restrict__ meta = J.meta;
+    double* __restrict__ centers = J.centers;
     __shared__ int64_t pos[2 * kMaxK];
     __shared__ int64_t val[2 * kMaxK];
     __shared__ int cnt;
@@ -223,64 +72,276 @@ __global__ void __launch_bounds__(64) k_forgy(const uint32_t* __restrict__ keys,
     if (lane == 0) meta->rng = rng;
 }
 
-// N' <= K: the centres are the colours followed by zeros.
-__global__ void k_centers_from_colours(const uint32_t* __restrict__ keys, int64_t n, int K,
-                                       double* __restrict__ centers)
+// Per job: seed the stream and reset the team barrier; for N' <= K the
+// centres are the colours followed by zeros (whatever the scheme).
+__global__ void __launch_bounds__(kMaxK) k_init_begin(const JobDev* __restrict__ jobs)
 {
+    const JobDev& J = jobs[blockIdx.x];
     const int k = threadIdx.x;
-    if (k >= K) return;
-    if (k < n) {
-        write_center(centers, k, keys[k]);
+    if (k == 0) {
+        J.meta->rng = J.seed;
+        J.meta->barrier = 0;
+        J.meta->sync_error = 0;
+    }
+    if (J.n > J.K || k >= J.K) return;
+    if (k < J.n) {
+        write_center(J.centers, k, J.keys[k]);
     } else {
-        centers[3 * k] = centers[3 * k + 1] = centers[3 * k + 2] = 0.0;
+        J.centers[3 * k] = J.centers[3 * k + 1] = J.centers[3 * k + 2] = 0.0;
     }
 }
 
-__global__ void k_set_rng(Meta* meta, uint64_t seed) { meta->rng = seed; }
+// ------------------------------------------------------------------------
+// Cooperative MMX / KPP: one launch runs all K rounds.  Block b owns the
+// colours [b C, (b+1) C).  Round j:
+//   1. every block lowers D^2 of its colours with the colour picked in round
+//      j-1 (KPP round 0 uses the counts alone) and publishes one value for its
+//      chunk: the sum of n D^2 (KPP) or the packed arg-max of D^2 (MMX);
+//   2. grid barrier;
+//   3. every block reads all chunk values and makes the same pick: KPP draws
+//      r = U(total) from its own copy of the splitmix64 stream, finds the chunk
+//      holding r and scans that chunk's weights; MMX decodes the arg-max.
+// D^2 and the chunk values are double-buffered by round parity, so a block
+// never rewrites what another block may still be reading.
+constexpr int kCoopThreads = 256;
+constexpr int kCoopMaxSegs = 4;    // up to 1024 blocks
+constexpr int kCoopLdsCap = 4096;  // colours per block kept in LDS (48 KiB)
+
+// kLds: the block's colours (key, count, D^2) stay in LDS for all rounds;
+// otherwise they are streamed from global memory every round.
+template <bool kLds>
+__global__ void __launch_bounds__(kCoopThreads) k_init_coop(const JobDev* __restrict__ jobs,
+                                                            const int* __restrict__ map, int B)
+{
+    __shared__ uint64_t tmp[64];
+    __shared__ uint64_t s_r;
+    __shared__ int64_t s_chunk;
+    __shared__ uint64_t s_before;
+    __shared__ int64_t s_pick;
+    __shared__ uint32_t s_pick_key;
+    __shared__ uint32_t lkey[kLds ? kCoopLdsCap : 1];
+    __shared__ uint32_t lcnt[kLds ? kCoopLdsCap : 1];
+    __shared__ uint32_t ld2[kLds ? kCoopLdsCap : 1];
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int G = J.init_blocks;  // team size, <= kCoopMaxSegs * kCoopThreads
+    const int tb = blockIdx.x - map[jb];
+    const uint32_t* __restrict__ keys = J.keys;
+    const uint32_t* __restrict__ counts = J.counts;
+    const int64_t n = J.n;
+    const int K = J.K;
+    const int kpp = J.scheme == CQ_INIT_KMEANSPP;
+    const uint64_t seed = J.seed;
+    const int64_t C = J.init_C;
+    uint32_t* __restrict__ d2buf = J.d2;
+    uint64_t* __restrict__ vals = J.vals;
+    Meta* __restrict__ meta = J.meta;
+    double* __restrict__ centers = J.centers;
+    const int64_t lo = int64_t(tb) * C;
+    const int64_t hi = lo + C < n ? lo + C : n;
+    const int mine_n = hi > lo ? int(hi - lo) : 0;
+    if (kLds) {
+        for (int q = threadIdx.x; q < mine_n; q += kCoopThreads) {
+            lkey[q] = keys[lo + q];
+            lcnt[q] = counts[lo + q];
+            ld2[q] = 0xFFFFFFFFu;
+        }
+    }
+    uint64_t rng = seed;  // the stream lives in thread 0 of every block
+    int64_t pick = -1;
+    uint32_t pick_key = 0;
+    int cr = 0, cg = 0, cb = 0;
+    for (int j = 0; j < K; ++j) {
+        __syncthreads();  // the previous round's readers of tmp and s_* are done
+        const int par = j & 1;
+        uint32_t* d2_now = d2buf + int64_t(par) * n;
+        const uint32_t* d2_old = d2buf + int64_t(par ^ 1) * n;
+        // 1. own chunk
+        uint64_t acc = 0;
+        if (j > 0 || kpp) {
+            for (int q = threadIdx.x; q < mine_n; q += kCoopThreads) {
+                const int64_t i = lo + q;
+                if (j == 0) {
+                    acc += kLds ? lcnt[q] : counts[i];
+                    continue;
+                }
+                int r, g, b;
+                key_rgb(kLds ? lkey[q] : keys[i], r, g, b);
+                const uint32_t d = dist_u32(r, g, b, cr, cg, cb);
+                const uint32_t old = kLds ? ld2[q] : (j == 1 ? 0xFFFFFFFFu : d2_old[i]);
+                const uint32_t m = old < d ? old : d;
+                if (kLds) ld2[q] = m;
+                if (kpp) {
+                    d2_now[i] = m;  // read by every block if this chunk is drawn
+                    acc += uint64_t(kLds ? lcnt[q] : counts[i]) * m;
+                } else {
+                    if (!kLds) d2_now[i] = m;
+                    const uint64_t packed = (uint64_t(m) << 32) | uint64_t(0xFFFFFFFFu - uint32_t(i));
+                    acc = packed > acc ? packed : acc;
+                }
+            }
+            acc = kpp ? wave_sum(acc) : wave_max(acc);
+            if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = acc;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint64_t v = tmp[0];
+                for (int w = 1; w < kCoopThreads / 64; ++w)
+                    v = kpp ? v + tmp[w] : (tmp[w] > v ? tmp[w] : v);
+                vals[int64_t(par) * G + tb] = v;
+            }
+        }
+        // 2. everyone has published
+        if (!grid_barrier(&meta->barrier, uint32_t(j + 1) * uint32_t(G), &meta->sync_error)) return;
+        const uint64_t* v_now = vals + int64_t(par) * G;
+        // 3. the same pick in every block
+        if (!kpp) {
+            if (j == 0) {
+                if (threadIdx.x == 0) s_pick = int64_t(uniform_below(rng, uint64_t(n)));
+                __syncthreads();
+                pick = s_pick;
+            } else {
+                uint64_t best = 0;
+                for (int c = threadIdx.x; c < G; c += kCoopThreads) best = v_now[c] > best ? v_now[c] : best;
+                best = wave_max(best);
+                if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = best;
+                __syncthreads();
+                for (int w = 0; w < kCoopThreads / 64; ++w) best = tmp[w] > best ? tmp[w] : best;
+                pick = int64_t(0xFFFFFFFFu - uint32_t(best & 0xFFFFFFFFull));
+                if (pick >= n) pick = 0;  // unreachable: every colour packs a non-zero value
+            }
+            pick_key = keys[pick];
+        } else {
+            // exclusive prefix of the chunk values (at most kCoopMaxSegs per thread)
+            uint64_t ex[kCoopMaxSegs], vv[kCoopMaxSegs];
+            uint64_t carry = 0;
+#pragma unroll
+            for (int q = 0; q < kCoopMaxSegs; ++q) {
+                const int c = q * kCoopThreads + threadIdx.x;
+                const uint64_t v = c < G ? v_now[c] : 0;
+                uint64_t tot = 0;
+                const uint64_t e = block_exclusive_scan<uint64_t>(v, tmp, &tot);
+                ex[q] = carry + e;
+                vv[q] = v;
+                carry += tot;
+            }
+            if (threadIdx.x == 0) {
+                s_r = carry ? uniform_below(rng, carry) : 0;
+                s_chunk = -1;
+            }
+            __syncthreads();
+            const uint64_t r = s_r;
+#pragma unroll
+            for (int q = 0; q < kCoopMaxSegs; ++q) {
+                if (vv[q] != 0 && ex[q] <= r && r < ex[q] + vv[q]) {
+                    s_chunk = q * kCoopThreads + threadIdx.x;
+                    s_before = ex[q];
+                }
+            }
+            if (threadIdx.x == 0) s_pick = -1;
+            __syncthreads();
+            int64_t c = s_chunk;
+            uint64_t rr = r - s_before;
+            if (c < 0) {  // unreachable: the chunk values sum to carry > 0
+                c = 0;
+                rr = 0;
+            }
+            // inside chunk c: contiguous sub-range per thread, then a block scan
+            const int64_t clo = c * C;
+            const int64_t chi = clo + C < n ? clo + C : n;
+            const int64_t len = chi - clo;
+            const int64_t per = (len + kCoopThreads - 1) / kCoopThreads;
+            const int64_t tlo = clo + per * threadIdx.x;
+            const int64_t thi = tlo + per < chi ? tlo + per : chi;
+            uint64_t mine = 0;
+            for (int64_t i = tlo; i < thi; ++i)
+                mine += j == 0 ? uint64_t(counts[i]) : uint64_t(counts[i]) * d2_now[i];
+            const uint64_t off = block_exclusive_scan<uint64_t>(mine, tmp, nullptr);
+            if (mine != 0 && off <= rr && rr < off + mine) {
+                uint64_t acc2 = off;
+                for (int64_t i = tlo; i < thi; ++i) {
+                    acc2 += j == 0 ? uint64_t(counts[i]) : uint64_t(counts[i]) * d2_now[i];
+                    if (acc2 > rr) {
+                        s_pick = i;
+                        s_pick_key = keys[i];
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+            pick = s_pick;
+            pick_key = s_pick_key;
+            if (pick < 0) {  // unreachable when the weights are consistent
+                pick = 0;
+                pick_key = keys[0];
+            }
+        }
+        if (threadIdx.x == 0 && tb == 0) {
+            write_center(centers, j, pick_key);
+            if (j == K - 1) meta->rng = rng;
+        }
+        key_rgb(pick_key, cr, cg, cb);
+    }
+}
 
 // ------------------------------------------------------------------ host
-cq_status launch_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int K, int scheme,
-                      uint64_t seed, double* centers, void* ws, const Layout& L, hipStream_t s)
+// Co-resident blocks of k_init_coop<true> on this device (0: no cooperative launch).
+int coop_capacity()
 {
-    Meta* meta = at<Meta>(ws, L.meta);
-    if (n <= K) {
-        k_centers_from_colours<<<1, kMaxK, 0, s>>>(keys, n, K, centers);
-        CQ_LAUNCH_CHECK("k_centers_from_colours");
-        return CQ_OK;
+    static int max_coop = -1;
+    if (max_coop < 0) {
+        int dev = 0, cus = 0, per_cu = 0, coop_ok = 0;
+        max_coop = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&coop_ok, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess &&
+            coop_ok &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(k_init_coop<true>), kCoopThreads, 0) == hipSuccess)
+            max_coop = cus * per_cu;
     }
-    if (scheme == CQ_INIT_USER) return CQ_OK;
-    k_set_rng<<<1, 1, 0, s>>>(meta, seed);
-    CQ_LAUNCH_CHECK("k_set_rng");
-    if (scheme == CQ_INIT_FORGY) {
-        k_forgy<<<1, 64, 0, s>>>(keys, n, K, meta, centers);
-        CQ_LAUNCH_CHECK("k_forgy");
-        return CQ_OK;
+    return max_coop;
+}
+
+// Preferred team size for a job of n colours (before the whole-launch cap).
+int coop_team_blocks(int64_t n)
+{
+    static int override_blocks = -1;
+    if (override_blocks < 0) {
+        const char* env = getenv("CQ_INIT_BLOCKS");
+        override_blocks = env ? atoi(env) : 0;
     }
-    uint64_t* chunk = at<uint64_t>(ws, L.chunks);
-    uint32_t* d2 = at<uint32_t>(ws, L.d2);
-    const int64_t nchunks = (n + kInitChunk - 1) / kInitChunk;
-    const int grid = int(nchunks);
-    if (scheme == CQ_INIT_KMEANSPP) {
-        k_init_update<<<grid, kInitThreads, 0, s>>>(keys, counts, n, d2, meta, 0, 1, chunk);
-        CQ_LAUNCH_CHECK("k_init_update");
-        k_kpp_select<<<1, kSelectThreads, 0, s>>>(keys, counts, d2, n, nchunks, chunk, meta, 0, centers);
-        CQ_LAUNCH_CHECK("k_kpp_select");
-        for (int j = 1; j < K; ++j) {
-            k_init_update<<<grid, kInitThreads, 0, s>>>(keys, counts, n, d2, meta, 1, j == 1, chunk);
-            CQ_LAUNCH_CHECK("k_init_update");
-            k_kpp_select<<<1, kSelectThreads, 0, s>>>(keys, counts, d2, n, nchunks, chunk, meta, j,
-                                                      centers);
-            CQ_LAUNCH_CHECK("k_kpp_select");
-        }
-    } else {  // CQ_INIT_MAXMIN
-        k_mmx_select<<<1, kSelectThreads, 0, s>>>(keys, n, nchunks, chunk, meta, 0, centers);
-        CQ_LAUNCH_CHECK("k_mmx_select");
-        for (int j = 1; j < K; ++j) {
-            k_init_update<<<grid, kInitThreads, 0, s>>>(keys, counts, n, d2, meta, 2, j == 1, chunk);
-            CQ_LAUNCH_CHECK("k_init_update");
-            k_mmx_select<<<1, kSelectThreads, 0, s>>>(keys, n, nchunks, chunk, meta, j, centers);
-            CQ_LAUNCH_CHECK("k_mmx_select");
-        }
+    int64_t g = override_blocks > 0 ? override_blocks : (n + kCoopLdsCap - 1) / kCoopLdsCap;
+    if (g < 1) g = 1;
+    if (g > kCoopMaxSegs * kCoopThreads) g = kCoopMaxSegs * kCoopThreads;
+    return int(g);
+}
+
+bool coop_fits_lds(int64_t C) { return C <= kCoopLdsCap; }
+
+cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s)
+{
+    CQ_TIMED_LAUNCH("k_init_begin", s, k_init_begin<<<B, kMaxK, 0, s>>>(jobs));
+    return CQ_OK;
+}
+
+cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s)
+{
+    CQ_TIMED_LAUNCH("k_forgy", s, k_forgy<<<B, 64, 0, s>>>(jobs));
+    return CQ_OK;
+}
+
+// One cooperative launch running the teams of `B` jobs (`total` blocks).
+cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, bool lds, hipStream_t s)
+{
+    void* args[] = {(void*)&jobs, (void*)&map, (void*)&B};
+    const void* fn = lds ? reinterpret_cast<const void*>(k_init_coop<true>)
+                         : reinterpret_cast<const void*>(k_init_coop<false>);
+    timer_begin("k_init_coop", s);
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(total), dim3(kCoopThreads), args, 0, s);
+    timer_end("k_init_coop", s);
+    if (e != hipSuccess) {
+        set_error("cooperative init launch failed: %s", hipGetErrorString(e));
+        return CQ_EDEVICE;
     }
     return CQ_OK;
 }

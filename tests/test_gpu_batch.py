@@ -1,0 +1,99 @@
+"""GPU parity of the batch entry point: every job of a mixed batch (sizes,
+palette sizes, schemes, pruning, stopping settings) equals the CPU oracle and
+the same image quantized alone, bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1101_0395_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cqm(dev):
+    from paper_1101_0395_amd import cq
+    cq.lib()
+    return cq
+
+
+MIXED = [
+    # (H, W, K, scheme, seed, prune, max_iters, tol)
+    (64, 64, 16, oracle.INIT_MAXMIN, 0, False, 50, 1e-4),
+    (1, 1, 4, oracle.INIT_KMEANSPP, 1, True, 20, 1e-4),
+    (7, 13, 2, oracle.INIT_FORGY, 2, True, 30, 0.0),
+    (300, 200, 256, oracle.INIT_KMEANSPP, 3, True, 100, 1e-4),
+    (128, 96, 37, oracle.INIT_FORGY, 4, False, 40, 1e-3),
+    (512, 512, 64, oracle.INIT_KMEANSPP, 5, True, 100, 1e-4),
+    (33, 65, 1, oracle.INIT_MAXMIN, 6, True, 10, 1e-4),
+    (200, 301, 128, oracle.INIT_MAXMIN, 7, True, 5, 1e-4),
+    (5, 3, 8, oracle.INIT_KMEANSPP, 8, True, 20, 1e-4),
+    (257, 129, 256, oracle.INIT_KMEANSPP, 9, False, 15, 1e-4),
+]
+
+
+def _image(H, W, seed):
+    if H * W < 64:
+        return np.array(np.random.default_rng(seed).integers(0, 3, (H, W, 3)) * 80, np.uint8)
+    return synth.smooth_field_blobs(H, W, seed) if H * W > 20000 else synth.blobs_on_gradient(H, W, seed)
+
+
+def test_mixed_batch_matches_oracle_and_solo(cqm, dev):
+    _say("batch of %d mixed jobs" % len(MIXED))
+    imgs = [_image(H, W, seed) for (H, W, _, _, seed, _, _, _) in MIXED]
+    jobs = [cqm.BatchJob(torch.from_numpy(im).to(dev), K, scheme, seed, mi, tol, prune)
+            for im, (H, W, K, scheme, seed, prune, mi, tol) in zip(imgs, MIXED)]
+    ws = cqm.BatchWorkspace(jobs, dev)
+    stats = cqm.cq_quantize_batch(jobs, ws)
+    solo_ws = cqm.Workspace(512, 512, 256, dev)
+    for job, im, st, (H, W, K, scheme, seed, prune, mi, tol) in zip(jobs, imgs, stats, MIXED):
+        _say(f"  job {H}x{W} K={K} scheme={scheme} prune={prune}")
+        rp, ri, rr, rs = oracle.quantize(im, K, scheme, seed, mi, tol, prune=prune)
+        assert np.array_equal(job.palette.cpu().numpy(), rp)
+        assert np.array_equal(job.idx.cpu().numpy(), ri)
+        assert np.array_equal(job.rgb.cpu().numpy(), rr)
+        for key in ("iters", "converged", "k_used", "n_unique", "ndc_total", "near_ties", "sse_final",
+                    "mse_float", "mse_img"):
+            assert st[key] == rs[key], key
+        sp, si, sr, ss = cqm.cq_quantize(job.img, K, scheme, seed, mi, tol, prune, solo_ws)
+        assert torch.equal(sp, job.palette) and torch.equal(sr, job.rgb) and ss == st
+
+
+def test_batch_rerun_is_deterministic(cqm, dev):
+    _say("batch rerun")
+    imgs = [synth.smooth_field_blobs(256, 256, s) for s in range(3)]
+    jobs = [cqm.BatchJob(torch.from_numpy(im).to(dev), 256, oracle.INIT_KMEANSPP, s, 100, 1e-4)
+            for s, im in enumerate(imgs)]
+    ws = cqm.BatchWorkspace(jobs, dev)
+    a = cqm.cq_quantize_batch(jobs, ws)
+    pals = [j.palette.clone() for j in jobs]
+    b = cqm.cq_quantize_batch(jobs, ws)
+    assert a == b
+    assert all(torch.equal(p, j.palette) for p, j in zip(pals, jobs))
+
+
+def test_batch_rejects_bad_job(cqm, dev):
+    _say("batch argument check")
+    img = torch.zeros((4, 4, 3), dtype=torch.uint8, device=dev)
+    good = cqm.BatchJob(img, 4, oracle.INIT_KMEANSPP, 0, 10, 1e-4)
+    bad = cqm.BatchJob(img, 4, oracle.INIT_KMEANSPP, 0, 10, 1e-4)
+    bad.c.K = 0
+    ws = cqm.BatchWorkspace([good, good], dev)
+    with pytest.raises(cqm.CqError) as e:
+        cqm.cq_quantize_batch([good, bad], ws)
+    assert e.value.code == cqm.CQ_EINVAL and "job 1" in str(e.value)
