@@ -179,22 +179,22 @@ struct Batch {
 // Points the workspace-backed fields of a job at one slot with layout L.
 static void bind_slot(JobDev& J, char* slot, const Layout& L)
 {
-    J.tbl = reinterpret_cast<uint32_t*>(slot + L.tbl);
-    J.bitmap = reinterpret_cast<uint32_t*>(slot + L.bitmap);
-    J.lut = reinterpret_cast<uint8_t*>(slot + L.lut);
-    J.meta = reinterpret_cast<Meta*>(slot + L.meta);
-    J.trace = reinterpret_cast<double*>(slot + L.trace);
-    J.td = reinterpret_cast<double*>(slot + L.td);
-    J.tm = reinterpret_cast<uint8_t*>(slot + L.tm);
-    J.sums = reinterpret_cast<unsigned long long*>(slot + L.sums);
-    J.blk = reinterpret_cast<uint32_t*>(slot + L.blk);
-    J.vals = reinterpret_cast<uint64_t*>(slot + L.chunks);
-    J.d2 = reinterpret_cast<uint32_t*>(slot + L.d2);
+    J.tbl = to_dev(reinterpret_cast<uint32_t*>(slot + L.tbl));
+    J.bitmap = to_dev(reinterpret_cast<uint32_t*>(slot + L.bitmap));
+    J.lut = to_dev(reinterpret_cast<uint8_t*>(slot + L.lut));
+    J.meta = to_dev(reinterpret_cast<Meta*>(slot + L.meta));
+    J.trace = to_dev(reinterpret_cast<double*>(slot + L.trace));
+    J.td = to_dev(reinterpret_cast<double*>(slot + L.td));
+    J.tm = to_dev(reinterpret_cast<uint8_t*>(slot + L.tm));
+    J.sums = to_dev(reinterpret_cast<unsigned long long*>(slot + L.sums));
+    J.blk = to_dev(reinterpret_cast<uint32_t*>(slot + L.blk));
+    J.vals = to_dev(reinterpret_cast<uint64_t*>(slot + L.chunks));
+    J.d2 = to_dev(reinterpret_cast<uint32_t*>(slot + L.d2));
 }
 
 static void set_image(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride)
 {
-    J.img = img;
+    J.img = to_dev(img);
     J.H = H;
     J.W = W;
     J.stride = stride;
@@ -219,7 +219,7 @@ __global__ void k_collect(const JobDev* __restrict__ jobs, int B, JobResult* __r
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= B) return;
-    const Meta* m = jobs[j].meta;
+    const Meta* m = gp(jobs[j].meta);
     JobResult r;
     r.n_unique = m->n_unique;
     r.ndc = m->ndc;
@@ -239,7 +239,7 @@ __global__ void k_collect(const JobDev* __restrict__ jobs, int B, JobResult* __r
 __global__ void k_zero_sq_err(const JobDev* __restrict__ jobs, int B)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < B) jobs[j].meta->sq_err = 0;
+    if (j < B) gp(jobs[j].meta)->sq_err = 0;
 }
 
 // Gathers every job's control block into b.res (synchronizes the stream).
@@ -435,10 +435,10 @@ static void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t 
     const Layout L = make_layout(npix, true);
     set_image(J, img, H, W, stride);
     bind_slot(J, slot, L);
-    J.keys = reinterpret_cast<uint32_t*>(slot + L.keys);
-    J.counts = reinterpret_cast<uint32_t*>(slot + L.counts);
-    J.assign = reinterpret_cast<uint8_t*>(slot + L.assign);
-    J.centers = reinterpret_cast<double*>(slot + L.centers);
+    J.keys = to_dev(reinterpret_cast<uint32_t*>(slot + L.keys));
+    J.counts = to_dev(reinterpret_cast<uint32_t*>(slot + L.counts));
+    J.assign = to_dev(reinterpret_cast<uint8_t*>(slot + L.assign));
+    J.centers = to_dev(reinterpret_cast<double*>(slot + L.centers));
     J.capacity = npix;
     J.K = K;
     J.scheme = scheme;
@@ -446,9 +446,9 @@ static void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t 
     J.max_iters = max_iters;
     J.tol = tol;
     J.prune = prune ? 1 : 0;
-    J.palette = palette;
-    J.out_idx = out_idx;
-    J.out_rgb = out_rgb;
+    J.palette = to_dev(palette);
+    J.out_idx = to_dev(out_idx);
+    J.out_rgb = to_dev(out_rgb);
     J.packed = J.packed && (reinterpret_cast<uintptr_t>(out_idx) & 3u) == 0 &&
                (reinterpret_cast<uintptr_t>(out_rgb) & 3u) == 0;
 }
@@ -511,8 +511,8 @@ cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_str
     JobDev& J = b.h[0];
     set_image(J, img, H, W, row_stride_bytes);
     bind_slot(J, static_cast<char*>(ws), L);
-    J.keys = keys;
-    J.counts = counts;
+    J.keys = to_dev(keys);
+    J.counts = to_dev(counts);
     J.capacity = capacity;
     CQ_TRY(run_histogram(b));
     CQ_TRY(collect(b));
@@ -539,9 +539,9 @@ cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
     JobDev& J = b.h[0];
     bind_slot(J, static_cast<char*>(ws), L);
-    J.keys = const_cast<uint32_t*>(keys);
-    J.counts = const_cast<uint32_t*>(counts);
-    J.centers = centers;
+    J.keys = to_dev(const_cast<uint32_t*>(keys));
+    J.counts = to_dev(const_cast<uint32_t*>(counts));
+    J.centers = to_dev(centers);
     J.K = K;
     J.scheme = int(scheme);
     J.seed = seed;
@@ -570,11 +570,11 @@ cq_status cq_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n_uniq
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
     JobDev& J = b.h[0];
     bind_slot(J, static_cast<char*>(ws), L);
-    J.keys = const_cast<uint32_t*>(keys);
-    J.counts = const_cast<uint32_t*>(counts);
-    J.centers = centers;
-    J.assign = assign;
-    J.palette = palette;
+    J.keys = to_dev(const_cast<uint32_t*>(keys));
+    J.counts = to_dev(const_cast<uint32_t*>(counts));
+    J.centers = to_dev(centers);
+    J.assign = to_dev(assign);
+    J.palette = to_dev(palette);
     J.K = K;
     J.max_iters = max_iters;
     J.tol = tol;
@@ -585,7 +585,7 @@ cq_status cq_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n_uniq
     if (palette) CQ_TRY(launch_palette(b.d_jobs(), 1, b.s));
     const JobResult r = b.res[0];
     if (sse_trace && r.iters > 0) {
-        CQ_HIP_TRY(hipMemcpyAsync(sse_trace, J.trace, sizeof(double) * size_t(r.iters), hipMemcpyDeviceToHost, b.s));
+        CQ_HIP_TRY(hipMemcpyAsync(sse_trace, from_dev(J.trace), sizeof(double) * size_t(r.iters), hipMemcpyDeviceToHost, b.s));
     }
     CQ_HIP_TRY(hipStreamSynchronize(b.s));
     if (stats) fill_stats(J, r, *stats, false);
@@ -609,11 +609,11 @@ cq_status cq_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_by
     JobDev& J = b.h[0];
     set_image(J, img, H, W, row_stride_bytes);
     bind_slot(J, static_cast<char*>(ws), L);
-    J.keys = const_cast<uint32_t*>(keys);
-    J.counts = const_cast<uint32_t*>(counts);
-    J.palette = const_cast<uint8_t*>(palette);
-    J.out_idx = out_idx;
-    J.out_rgb = out_rgb;
+    J.keys = to_dev(const_cast<uint32_t*>(keys));
+    J.counts = to_dev(const_cast<uint32_t*>(counts));
+    J.palette = to_dev(const_cast<uint8_t*>(palette));
+    J.out_idx = to_dev(out_idx);
+    J.out_rgb = to_dev(out_rgb);
     J.K = K;
     set_counts(b, {n_unique});
     J.map_k = K;

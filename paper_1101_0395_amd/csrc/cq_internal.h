@@ -47,7 +47,10 @@ struct Meta {
     uint32_t barrier;     // arrival counter of the grid barrier of a cooperative launch
     int32_t sync_error;   // set when a grid barrier waited past its spin limit
     int32_t cur_it;       // k-means: iteration whose cluster sums are being built
-    uint32_t pad[43];
+    uint32_t pick_epoch;  // init: rounds whose pick has been published
+    uint32_t pad0;
+    int64_t pick_slot[2]; // init: published pick (colour index) by round parity
+    uint32_t pad[38];
 };
 static_assert(sizeof(Meta) <= 512, "Meta must fit its slot");
 
@@ -57,31 +60,40 @@ constexpr size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // One image of a launch.  Every kernel takes a device array of jobs and, where
 // jobs need different numbers of blocks, a prefix map of B + 1 block offsets
 // (block b belongs to the job j with map[j] <= b < map[j + 1]).
+// Device code sees the buffers of a job descriptor as global-memory pointers,
+// so loads through them are global or scalar loads rather than generic ones;
+// host code sees plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CQ_GLOBAL __attribute__((address_space(1)))
+#else
+#define CQ_GLOBAL
+#endif
+
 struct JobDev {
-    const uint8_t* img;
+    const uint8_t CQ_GLOBAL* img;
     int64_t stride;
     int32_t H, W;
     int32_t K, scheme, max_iters, prune;
     uint64_t seed;
     double tol;
-    uint8_t* palette;
-    uint8_t* out_idx;
-    uint8_t* out_rgb;
-    uint32_t* tbl;
-    uint32_t* bitmap;
-    uint8_t* lut;
-    Meta* meta;
-    double* trace;
-    double* td;
-    uint8_t* tm;
-    unsigned long long* sums;
-    uint32_t* blk;
-    uint64_t* vals;
-    uint32_t* d2;
-    uint32_t* keys;
-    uint32_t* counts;
-    uint8_t* assign;
-    double* centers;
+    uint8_t CQ_GLOBAL* palette;
+    uint8_t CQ_GLOBAL* out_idx;
+    uint8_t CQ_GLOBAL* out_rgb;
+    uint32_t CQ_GLOBAL* tbl;
+    uint32_t CQ_GLOBAL* bitmap;
+    uint8_t CQ_GLOBAL* lut;
+    Meta CQ_GLOBAL* meta;
+    double CQ_GLOBAL* trace;
+    double CQ_GLOBAL* td;
+    uint8_t CQ_GLOBAL* tm;
+    unsigned long long CQ_GLOBAL* sums;
+    uint32_t CQ_GLOBAL* blk;
+    uint64_t CQ_GLOBAL* vals;
+    uint32_t CQ_GLOBAL* d2;
+    uint32_t CQ_GLOBAL* keys;
+    uint32_t CQ_GLOBAL* counts;
+    uint8_t CQ_GLOBAL* assign;
+    double CQ_GLOBAL* centers;
     int64_t capacity;    // entries of keys / counts
     int64_t n;           // unique colours, set once the histogram is known
     int64_t chunk;       // colours per assignment / LUT block
@@ -91,6 +103,20 @@ struct JobDev {
     int32_t packed;      // image rows are contiguous and 4-byte aligned
     int32_t map_k;       // palette entries the pixel map searches
 };
+
+// Host-side stores into a descriptor, and host-side reads of one.
+template <typename T>
+inline T CQ_GLOBAL* to_dev(T* p) { return (T CQ_GLOBAL*)p; }
+template <typename T>
+inline T* from_dev(T CQ_GLOBAL* p) { return (T*)p; }
+
+// A descriptor pointer as a plain pointer; the compiler keeps treating every
+// access derived from it as global memory.
+template <typename T>
+__device__ __forceinline__ T* gp(T CQ_GLOBAL* p)
+{
+    return (T*)p;
+}
 
 // Per-job results gathered for one device-to-host copy.
 struct JobResult {
@@ -285,6 +311,31 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* counter, uint32_t target,
     }
     __syncthreads();
     return s_ok != 0;
+}
+
+// Wait (thread 0 of the block) until *flag >= target, published with a
+// release store by another block; relaxed polling, one acquire fence, and the
+// same spin limit and error convention as grid_barrier.
+__device__ __forceinline__ bool wait_flag(uint32_t* flag, uint32_t target, int32_t* error)
+{
+    __shared__ int s_ok2;
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        uint32_t spins = 0;
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                ++spins > kSpinLimit) {
+                __hip_atomic_store(error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_ok2 = ok;
+    }
+    __syncthreads();
+    return s_ok2 != 0;
 }
 
 template <typename T>

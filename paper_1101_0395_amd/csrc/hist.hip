@@ -82,9 +82,9 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_tiles(const JobDev* __res
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
-    const uint8_t* __restrict__ img = J.img;
-    uint32_t* __restrict__ tbl = J.tbl;
-    uint32_t* __restrict__ bitmap = J.bitmap;
+    const uint8_t* __restrict__ img = gp(J.img);
+    uint32_t* __restrict__ tbl = gp(J.tbl);
+    uint32_t* __restrict__ bitmap = gp(J.bitmap);
     const int32_t W = J.W;
     const int64_t row_stride = J.stride;
     const bool packed = J.packed != 0;
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_bitmap_count(const JobDev* 
     __shared__ uint32_t tmp[64];
     const JobDev& J = jobs[blockIdx.x / kCompactBlocks];
     const uint32_t blk_id = blockIdx.x % kCompactBlocks;
-    const uint32_t* __restrict__ bitmap = J.bitmap;
+    const uint32_t* __restrict__ bitmap = gp(J.bitmap);
     const uint32_t base = blk_id * kCompactWordsPerBlock + threadIdx.x * kCompactWordsPerThread;
     const uint4* p = reinterpret_cast<const uint4*>(bitmap + base);
     const uint4 u = p[0], v = p[1];
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kCompactThreads) k_bitmap_count(const JobDev* 
     if (threadIdx.x == 0) {
         uint32_t s = 0;
         for (int w = 0; w < kCompactThreads / 64; ++w) s += tmp[w];
-        J.blk[blk_id] = s;
+        gp(J.blk)[blk_id] = s;
     }
 }
 
@@ -148,8 +148,8 @@ __global__ void __launch_bounds__(kCompactBlocks) k_bitmap_scan(const JobDev* __
     const JobDev& J = jobs[blockIdx.x];
     uint32_t total = 0;
     const uint32_t off = block_exclusive_scan<uint32_t>(J.blk[threadIdx.x], tmp, &total);
-    J.blk[kCompactBlocks + threadIdx.x] = off;
-    if (threadIdx.x == 0) J.meta->n_unique = int64_t(total);
+    gp(J.blk)[kCompactBlocks + threadIdx.x] = off;
+    if (threadIdx.x == 0) gp(J.meta)->n_unique = int64_t(total);
 }
 
 // Pass 3: emit the keys in ascending order and clear the bitmap words.  Keys
@@ -159,9 +159,9 @@ __global__ void __launch_bounds__(kCompactThreads) k_bitmap_emit(const JobDev* _
     __shared__ uint32_t tmp[64];
     const JobDev& J = jobs[blockIdx.x / kCompactBlocks];
     const uint32_t blk_id = blockIdx.x % kCompactBlocks;
-    uint32_t* __restrict__ bitmap = J.bitmap;
-    uint32_t* __restrict__ tbl = J.tbl;
-    uint32_t* __restrict__ keys = J.keys;
+    uint32_t* __restrict__ bitmap = gp(J.bitmap);
+    uint32_t* __restrict__ tbl = gp(J.tbl);
+    uint32_t* __restrict__ keys = gp(J.keys);
     const int64_t capacity = J.capacity;
     const uint32_t base = blk_id * kCompactWordsPerBlock + threadIdx.x * kCompactWordsPerThread;
     uint4* p = reinterpret_cast<uint4*>(bitmap + base);
@@ -199,10 +199,10 @@ __global__ void __launch_bounds__(256) k_gather_counts(const JobDev* __restrict_
 {
     const JobDev& J = jobs[blockIdx.x / kGatherBlocks];
     const int lb = blockIdx.x % kGatherBlocks;
-    const uint32_t* __restrict__ keys = J.keys;
-    uint32_t* __restrict__ counts = J.counts;
-    uint32_t* __restrict__ tbl = J.tbl;
-    const int64_t n = J.meta->n_unique < J.capacity ? J.meta->n_unique : J.capacity;
+    const uint32_t* __restrict__ keys = gp(J.keys);
+    uint32_t* __restrict__ counts = gp(J.counts);
+    uint32_t* __restrict__ tbl = gp(J.tbl);
+    const int64_t n = gp(J.meta)->n_unique < J.capacity ? gp(J.meta)->n_unique : J.capacity;
     const int64_t stride = int64_t(kGatherBlocks) * blockDim.x;
     for (int64_t o = int64_t(lb) * blockDim.x + threadIdx.x; o < n; o += stride) {
         const uint32_t key = keys[o];

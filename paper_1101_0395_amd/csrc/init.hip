@@ -28,11 +28,11 @@ __global__ void __launch_bounds__(64) k_forgy(const JobDev* __restrict__ jobs)
 {
     const JobDev& J = jobs[blockIdx.x];
     if (J.scheme != CQ_INIT_FORGY || J.n <= J.K) return;
-    const uint32_t* __restrict__ keys = J.keys;
+    const uint32_t* __restrict__ keys = gp(J.keys);
     const int64_t n = J.n;
     const int K = J.K;
-    Meta* __restrict__ meta = J.meta;
-    double* __restrict__ centers = J.centers;
+    Meta* __restrict__ meta = gp(J.meta);
+    double* __restrict__ centers = gp(J.centers);
     __shared__ int64_t pos[2 * kMaxK];
     __shared__ int64_t val[2 * kMaxK];
     __shared__ int cnt;
@@ -79,46 +79,50 @@ __global__ void __launch_bounds__(kMaxK) k_init_begin(const JobDev* __restrict__
     const JobDev& J = jobs[blockIdx.x];
     const int k = threadIdx.x;
     if (k == 0) {
-        J.meta->rng = J.seed;
-        J.meta->barrier = 0;
-        J.meta->sync_error = 0;
+        gp(J.meta)->rng = J.seed;
+        gp(J.meta)->barrier = 0;
+        gp(J.meta)->sync_error = 0;
+        gp(J.meta)->pick_epoch = 0;
     }
     if (J.n > J.K || k >= J.K) return;
     if (k < J.n) {
-        write_center(J.centers, k, J.keys[k]);
+        write_center(J.centers, k, gp(J.keys)[k]);
     } else {
-        J.centers[3 * k] = J.centers[3 * k + 1] = J.centers[3 * k + 2] = 0.0;
+        gp(J.centers)[3 * k] = gp(J.centers)[3 * k + 1] = gp(J.centers)[3 * k + 2] = 0.0;
     }
 }
 
 // ------------------------------------------------------------------------
-// Cooperative MMX / KPP: one launch runs all K rounds.  Block b owns the
-// colours [b C, (b+1) C).  Round j:
+// Cooperative MMX / KPP: one launch runs all K rounds of every job, each job
+// with its own team of blocks.  Block b of a team owns the colours
+// [b C, (b+1) C).  Round j:
 //   1. every block lowers D^2 of its colours with the colour picked in round
-//      j-1 (KPP round 0 uses the counts alone) and publishes one value for its
-//      chunk: the sum of n D^2 (KPP) or the packed arg-max of D^2 (MMX);
-//   2. grid barrier;
-//   3. every block reads all chunk values and makes the same pick: KPP draws
-//      r = U(total) from its own copy of the splitmix64 stream, finds the chunk
-//      holding r and scans that chunk's weights; MMX decodes the arg-max.
-// D^2 and the chunk values are double-buffered by round parity, so a block
-// never rewrites what another block may still be reading.
+//      j-1 and publishes one value for its chunk: the sum of n D^2 (KPP; the
+//      counts alone in round 0) or the packed arg-max of (D^2, -index) (MMX);
+//   2. team barrier;
+//   3. every block reads the team's chunk values.  MMX: the largest packed
+//      value names the colour.  KPP: every block draws r = U(total) from its
+//      own copy of the splitmix64 stream and finds the chunk holding r; the
+//      block owning that chunk finds the colour inside its own chunk and
+//      publishes it with a release flag, which the other blocks wait for.
+// Chunk values and published picks are double-buffered by round parity, so a
+// block never rewrites what another block may still be reading.
 constexpr int kCoopThreads = 256;
-constexpr int kCoopMaxSegs = 4;    // up to 1024 blocks
+constexpr int kCoopMaxSegs = 4;    // up to 1024 blocks per team
 constexpr int kCoopLdsCap = 4096;  // colours per block kept in LDS (48 KiB)
+constexpr int kRun = kCoopLdsCap / kCoopThreads;  // colours per thread per pass of a chunk search
 
 // kLds: the block's colours (key, count, D^2) stay in LDS for all rounds;
-// otherwise they are streamed from global memory every round.
+// otherwise they are streamed from global memory every round (D^2 in d2buf).
 template <bool kLds>
 __global__ void __launch_bounds__(kCoopThreads) k_init_coop(const JobDev* __restrict__ jobs,
                                                             const int* __restrict__ map, int B)
 {
     __shared__ uint64_t tmp[64];
     __shared__ uint64_t s_r;
-    __shared__ int64_t s_chunk;
+    __shared__ int s_chunk;
     __shared__ uint64_t s_before;
     __shared__ int64_t s_pick;
-    __shared__ uint32_t s_pick_key;
     __shared__ uint32_t lkey[kLds ? kCoopLdsCap : 1];
     __shared__ uint32_t lcnt[kLds ? kCoopLdsCap : 1];
     __shared__ uint32_t ld2[kLds ? kCoopLdsCap : 1];
@@ -126,58 +130,83 @@ __global__ void __launch_bounds__(kCoopThreads) k_init_coop(const JobDev* __rest
     const JobDev& J = jobs[jb];
     const int G = J.init_blocks;  // team size, <= kCoopMaxSegs * kCoopThreads
     const int tb = blockIdx.x - map[jb];
-    const uint32_t* __restrict__ keys = J.keys;
-    const uint32_t* __restrict__ counts = J.counts;
+    const uint32_t* __restrict__ keys = gp(J.keys);
+    const uint32_t* __restrict__ counts = gp(J.counts);
     const int64_t n = J.n;
     const int K = J.K;
     const int kpp = J.scheme == CQ_INIT_KMEANSPP;
-    const uint64_t seed = J.seed;
     const int64_t C = J.init_C;
-    uint32_t* __restrict__ d2buf = J.d2;
-    uint64_t* __restrict__ vals = J.vals;
-    Meta* __restrict__ meta = J.meta;
-    double* __restrict__ centers = J.centers;
+    uint32_t* __restrict__ d2own = gp(J.d2);
+    uint64_t* __restrict__ vals = gp(J.vals);
+    Meta* __restrict__ meta = gp(J.meta);
+    double* __restrict__ centers = gp(J.centers);
     const int64_t lo = int64_t(tb) * C;
     const int64_t hi = lo + C < n ? lo + C : n;
     const int mine_n = hi > lo ? int(hi - lo) : 0;
+    const int nseg = (G + kCoopThreads - 1) / kCoopThreads;
     if (kLds) {
-        for (int q = threadIdx.x; q < mine_n; q += kCoopThreads) {
-            lkey[q] = keys[lo + q];
-            lcnt[q] = counts[lo + q];
-            ld2[q] = 0xFFFFFFFFu;
+        // all loads issued before the stores (mine_n <= kCoopLdsCap)
+        uint32_t kk[kRun], cc[kRun];
+#pragma unroll
+        for (int r = 0; r < kRun; ++r) {
+            const int q = r * kCoopThreads + threadIdx.x;
+            kk[r] = q < mine_n ? keys[lo + q] : 0u;
+            cc[r] = q < mine_n ? counts[lo + q] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kRun; ++r) {
+            const int q = r * kCoopThreads + threadIdx.x;
+            if (q < mine_n) {
+                lkey[q] = kk[r];
+                lcnt[q] = cc[r];
+                ld2[q] = 0xFFFFFFFFu;
+            }
         }
     }
-    uint64_t rng = seed;  // the stream lives in thread 0 of every block
+    uint64_t rng = J.seed;  // the stream lives in thread 0 of every block
     int64_t pick = -1;
-    uint32_t pick_key = 0;
     int cr = 0, cg = 0, cb = 0;
     for (int j = 0; j < K; ++j) {
         __syncthreads();  // the previous round's readers of tmp and s_* are done
         const int par = j & 1;
-        uint32_t* d2_now = d2buf + int64_t(par) * n;
-        const uint32_t* d2_old = d2buf + int64_t(par ^ 1) * n;
         // 1. own chunk
         uint64_t acc = 0;
         if (j > 0 || kpp) {
-            for (int q = threadIdx.x; q < mine_n; q += kCoopThreads) {
-                const int64_t i = lo + q;
-                if (j == 0) {
-                    acc += kLds ? lcnt[q] : counts[i];
-                    continue;
+            // four colours per thread per step, loads first
+            for (int q0 = threadIdx.x; q0 < mine_n; q0 += 4 * kCoopThreads) {
+                uint32_t kq[4], cq[4], oq[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = q0 + u * kCoopThreads;
+                    const int64_t i = lo + q;
+                    const bool in = q < mine_n;
+                    kq[u] = in ? (kLds ? lkey[q] : keys[i]) : 0u;
+                    cq[u] = in ? (kLds ? lcnt[q] : counts[i]) : 0u;
+                    oq[u] = (in && j > 1) ? (kLds ? ld2[q] : d2own[i]) : 0xFFFFFFFFu;
                 }
-                int r, g, b;
-                key_rgb(kLds ? lkey[q] : keys[i], r, g, b);
-                const uint32_t d = dist_u32(r, g, b, cr, cg, cb);
-                const uint32_t old = kLds ? ld2[q] : (j == 1 ? 0xFFFFFFFFu : d2_old[i]);
-                const uint32_t m = old < d ? old : d;
-                if (kLds) ld2[q] = m;
-                if (kpp) {
-                    d2_now[i] = m;  // read by every block if this chunk is drawn
-                    acc += uint64_t(kLds ? lcnt[q] : counts[i]) * m;
-                } else {
-                    if (!kLds) d2_now[i] = m;
-                    const uint64_t packed = (uint64_t(m) << 32) | uint64_t(0xFFFFFFFFu - uint32_t(i));
-                    acc = packed > acc ? packed : acc;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = q0 + u * kCoopThreads;
+                    if (q >= mine_n) continue;
+                    const int64_t i = lo + q;
+                    if (j == 0) {
+                        acc += cq[u];
+                        continue;
+                    }
+                    int r, g, b;
+                    key_rgb(kq[u], r, g, b);
+                    const uint32_t d = dist_u32(r, g, b, cr, cg, cb);
+                    const uint32_t m = oq[u] < d ? oq[u] : d;
+                    if (kLds)
+                        ld2[q] = m;
+                    else
+                        d2own[i] = m;
+                    if (kpp) {
+                        acc += uint64_t(cq[u]) * m;
+                    } else {
+                        const uint64_t packed = (uint64_t(m) << 32) | uint64_t(0xFFFFFFFFu - uint32_t(i));
+                        acc = packed > acc ? packed : acc;
+                    }
                 }
             }
             acc = kpp ? wave_sum(acc) : wave_max(acc);
@@ -209,13 +238,14 @@ __global__ void __launch_bounds__(kCoopThreads) k_init_coop(const JobDev* __rest
                 pick = int64_t(0xFFFFFFFFu - uint32_t(best & 0xFFFFFFFFull));
                 if (pick >= n) pick = 0;  // unreachable: every colour packs a non-zero value
             }
-            pick_key = keys[pick];
         } else {
-            // exclusive prefix of the chunk values (at most kCoopMaxSegs per thread)
+            // exclusive prefix of the chunk values, one segment of 256 blocks at a time
             uint64_t ex[kCoopMaxSegs], vv[kCoopMaxSegs];
             uint64_t carry = 0;
 #pragma unroll
             for (int q = 0; q < kCoopMaxSegs; ++q) {
+                ex[q] = vv[q] = 0;
+                if (q >= nseg) continue;
                 const int c = q * kCoopThreads + threadIdx.x;
                 const uint64_t v = c < G ? v_now[c] : 0;
                 uint64_t tot = 0;
@@ -237,44 +267,60 @@ __global__ void __launch_bounds__(kCoopThreads) k_init_coop(const JobDev* __rest
                     s_before = ex[q];
                 }
             }
-            if (threadIdx.x == 0) s_pick = -1;
             __syncthreads();
-            int64_t c = s_chunk;
-            uint64_t rr = r - s_before;
-            if (c < 0) {  // unreachable: the chunk values sum to carry > 0
-                c = 0;
-                rr = 0;
-            }
-            // inside chunk c: contiguous sub-range per thread, then a block scan
-            const int64_t clo = c * C;
-            const int64_t chi = clo + C < n ? clo + C : n;
-            const int64_t len = chi - clo;
-            const int64_t per = (len + kCoopThreads - 1) / kCoopThreads;
-            const int64_t tlo = clo + per * threadIdx.x;
-            const int64_t thi = tlo + per < chi ? tlo + per : chi;
-            uint64_t mine = 0;
-            for (int64_t i = tlo; i < thi; ++i)
-                mine += j == 0 ? uint64_t(counts[i]) : uint64_t(counts[i]) * d2_now[i];
-            const uint64_t off = block_exclusive_scan<uint64_t>(mine, tmp, nullptr);
-            if (mine != 0 && off <= rr && rr < off + mine) {
-                uint64_t acc2 = off;
-                for (int64_t i = tlo; i < thi; ++i) {
-                    acc2 += j == 0 ? uint64_t(counts[i]) : uint64_t(counts[i]) * d2_now[i];
-                    if (acc2 > rr) {
-                        s_pick = i;
-                        s_pick_key = keys[i];
-                        break;
+            int c = s_chunk;
+            const uint64_t rr = c >= 0 ? r - s_before : 0;
+            if (c < 0) c = 0;  // unreachable: the chunk values sum to carry > 0
+            if (c == tb) {
+                // the owner finds the colour in its own chunk: each thread takes
+                // a run of kRun consecutive colours per pass, loads first
+                if (threadIdx.x == 0) s_pick = -1;
+                uint64_t before = 0;
+                for (int pbase = 0; pbase < mine_n; pbase += kCoopThreads * kRun) {
+                    const int tlo = pbase + threadIdx.x * kRun;
+                    uint32_t cq[kRun], dq[kRun];
+#pragma unroll
+                    for (int q = 0; q < kRun; ++q) {
+                        const int qq = tlo + q;
+                        const bool in = qq < mine_n;
+                        cq[q] = in ? (kLds ? lcnt[qq] : counts[lo + qq]) : 0u;
+                        dq[q] = (in && j > 0) ? (kLds ? ld2[qq] : d2own[lo + qq]) : 1u;
                     }
+                    uint64_t mine = 0;
+#pragma unroll
+                    for (int q = 0; q < kRun; ++q) mine += uint64_t(cq[q]) * dq[q];
+                    uint64_t tot = 0;
+                    const uint64_t off = before + block_exclusive_scan<uint64_t>(mine, tmp, &tot);
+                    if (mine != 0 && off <= rr && rr < off + mine) {
+                        uint64_t acc2 = off;
+#pragma unroll
+                        for (int q = 0; q < kRun; ++q) {
+                            acc2 += uint64_t(cq[q]) * dq[q];
+                            if (acc2 > rr) {
+                                s_pick = lo + tlo + q;
+                                break;
+                            }
+                        }
+                    }
+                    before += tot;
                 }
-            }
-            __syncthreads();
-            pick = s_pick;
-            pick_key = s_pick_key;
-            if (pick < 0) {  // unreachable when the weights are consistent
-                pick = 0;
-                pick_key = keys[0];
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int64_t pk = s_pick;
+                    if (pk < 0) pk = lo;  // unreachable when the weights are consistent
+                    meta->pick_slot[par] = pk;
+                    __hip_atomic_store(&meta->pick_epoch, uint32_t(j + 1), __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    s_pick = pk;
+                }
+                __syncthreads();
+                pick = s_pick;
+            } else {
+                if (!wait_flag(&meta->pick_epoch, uint32_t(j + 1), &meta->sync_error)) return;
+                pick = __hip_atomic_load(&meta->pick_slot[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+        const uint32_t pick_key = keys[pick];
         if (threadIdx.x == 0 && tb == 0) {
             write_center(centers, j, pick_key);
             if (j == K - 1) meta->rng = rng;

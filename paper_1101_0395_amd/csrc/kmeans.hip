@@ -23,8 +23,9 @@
 namespace cq {
 
 constexpr int kAssignThreads = 256;
-constexpr int kRowCache = 16;   // leading entries of a sorted row staged in LDS
+constexpr int kRowCache = 32;   // leading entries of a sorted row staged in LDS
 constexpr int kRowSlots = 64;   // rows staged per block
+constexpr int kFetch = 16;      // row entries per global round trip past the staged prefix
 
 // Adds (n, S_r, S_g, S_b, Q) of the valid lanes to the LDS bins of their
 // clusters.  Lanes of one wave that share a cluster are summed first (up to
@@ -166,32 +167,50 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
     __shared__ int row_of[kRowSlots];
     __shared__ int need[kMaxK];
     __shared__ int scan_tmp[64];
+    static_assert(kAssignThreads == kMaxK, "one thread per table row");
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
-    Meta* __restrict__ meta = J.meta;
-    const int done = meta->done;
-    const int it = meta->iters + 1;
+    Meta* __restrict__ meta = gp(J.meta);
     const int K = J.K;
     const int64_t n = J.n;
-    const double* __restrict__ centers = J.centers;
-    const bool pruned = J.prune && it >= 2;
-    if (done) return;
-    if (lb == 0 && threadIdx.x == 0) meta->cur_it = it;
-    unsigned long long* __restrict__ sums = J.sums + (it & 1) * 5 * kMaxK;
-    const uint32_t* __restrict__ keys = J.keys;
-    const uint32_t* __restrict__ counts = J.counts;
-    uint8_t* __restrict__ assign = J.assign;
+    const double* __restrict__ centers = gp(J.centers);
+    const uint32_t* __restrict__ keys = gp(J.keys);
+    const uint32_t* __restrict__ counts = gp(J.counts);
+    uint8_t* __restrict__ assign = gp(J.assign);
     const int64_t lo = int64_t(lb) * J.chunk;
     const int64_t hi = lo + J.chunk < n ? lo + J.chunk : n;
+    // every load this block needs first is issued before anything waits on it:
+    // the control block, the centres, and the colours of the first pass
+    const int done = meta->done;
+    const int it = meta->iters + 1;
+    double cv[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        const int t = u * kAssignThreads + threadIdx.x;
+        cv[u] = t < 3 * K ? centers[t] : 0.0;
+    }
+    const int64_t i0 = lo + threadIdx.x;
+    const bool valid0 = i0 < hi;
+    const uint32_t key0 = valid0 ? keys[i0] : 0u;
+    const uint32_t cnt0 = valid0 ? counts[i0] : 0u;
+    const int p0 = valid0 ? assign[i0] : 0;
+    if (done) return;
+    const bool pruned = J.prune && it >= 2;
+    if (lb == 0 && threadIdx.x == 0) meta->cur_it = it;
+    unsigned long long* __restrict__ sums = gp(J.sums) + (it & 1) * 5 * kMaxK;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        const int t = u * kAssignThreads + threadIdx.x;
+        if (t < 3 * K) c[t] = cv[u];
+    }
     for (int t = threadIdx.x; t < 5 * kMaxK; t += blockDim.x) bins[t] = 0ull;
     if (pruned) {
-        for (int t = threadIdx.x; t < 3 * K; t += blockDim.x) c[t] = centers[t];
-        for (int t = threadIdx.x; t < kMaxK; t += blockDim.x) need[t] = 0;
+        need[threadIdx.x] = 0;
         __syncthreads();
-        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) need[assign[i]] = 1;
+        if (valid0) need[p0] = 1;
+        for (int64_t i = i0 + blockDim.x; i < hi; i += blockDim.x) need[assign[i]] = 1;
         __syncthreads();
-        static_assert(kAssignThreads == kMaxK, "one thread per table row");
         int total = 0;
         const int f = need[threadIdx.x];
         const int pos = block_exclusive_scan<int>(f, scan_tmp, &total);
@@ -199,11 +218,28 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
         slot_of[threadIdx.x] = slot;
         if (slot >= 0) row_of[slot] = threadIdx.x;
         __syncthreads();
+        // stage the leading entries of the needed rows: loads first, then stores
         const int nslots = total < kRowSlots ? total : kRowSlots;
-        for (int e = threadIdx.x; e < nslots * kRowCache; e += blockDim.x) {
-            const int r = row_of[e / kRowCache], j = e % kRowCache;
-            ltd[e] = J.td[r * kRow + j];
-            ltm[e] = J.tm[r * kRow + j];
+        constexpr int kPer = kRowSlots * kRowCache / kAssignThreads;
+        double dv[kPer];
+        uint32_t mv[kPer];
+        const double* __restrict__ td = gp(J.td);
+        const uint8_t* __restrict__ tm = gp(J.tm);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = u * kAssignThreads + threadIdx.x;
+            const bool in = e < nslots * kRowCache;
+            const int r = in ? row_of[e / kRowCache] : 0;
+            dv[u] = in ? td[r * kRow + e % kRowCache] : 0.0;
+            mv[u] = in ? tm[r * kRow + e % kRowCache] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = u * kAssignThreads + threadIdx.x;
+            if (e < nslots * kRowCache) {
+                ltd[e] = dv[u];
+                ltm[e] = uint8_t(mv[u]);
+            }
         }
     }
     __syncthreads();
@@ -212,36 +248,66 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
     for (int64_t base = lo; base < hi; base += blockDim.x) {
         const int64_t i = base + threadIdx.x;
         const bool valid = i < hi;
-        int r = 0, g = 0, b = 0;
-        unsigned long long w = 0;
-        if (valid) {
-            key_rgb(keys[i], r, g, b);
-            w = counts[i];
-        }
+        const bool first = base == lo;
+        const uint32_t key = first ? key0 : (valid ? keys[i] : 0u);
+        const unsigned long long w = first ? cnt0 : (valid ? counts[i] : 0u);
+        int r, g, b;
+        key_rgb(key, r, g, b);
         const double x0 = double(r), x1 = double(g), x2 = double(b);
         Best v{0.0, __builtin_inf(), 0};
         if (!pruned) {
             v = full_search(x0, x1, x2, centers, K);
             if (valid) ndc += unsigned(K);
         } else if (valid) {
-            const int p = assign[i];
+            const int p = first ? p0 : assign[i];
             const double prev = dist_f64(x0, x1, x2, c[3 * p], c[3 * p + 1], c[3 * p + 2]);
             const double limit = 4.0 * prev * (1.0 + 1e-12);
             v.bd = prev;
             v.best = p;
             unsigned evals = 1;
             const int slot = slot_of[p];
-            const double* crow_d = ltd + (slot >= 0 ? slot : 0) * kRowCache;
-            const uint8_t* crow_m = ltm + (slot >= 0 ? slot : 0) * kRowCache;
-            const double* grow_d = J.td + p * kRow;
-            const uint8_t* grow_m = J.tm + p * kRow;
-            for (int j = 1; j < K; ++j) {
-                const bool cached = slot >= 0 && j < kRowCache;
-                const double dj = cached ? crow_d[j] : grow_d[j];
-                if (dj > limit) break;
-                const int t = cached ? crow_m[j] : grow_m[j];
-                best_push(v, dist_f64(x0, x1, x2, c[3 * t], c[3 * t + 1], c[3 * t + 2]), t);
-                ++evals;
+            int j = 1;
+            bool stopped = false;
+            if (slot >= 0) {
+                // staged prefix of row p: LDS reads only
+                const int jend = K < kRowCache ? K : kRowCache;
+                for (; j < jend; ++j) {
+                    const double dj = ltd[slot * kRowCache + j];
+                    const int t = ltm[slot * kRowCache + j];
+                    if (dj > limit) {
+                        stopped = true;
+                        break;
+                    }
+                    best_push(v, dist_f64(x0, x1, x2, c[3 * t], c[3 * t + 1], c[3 * t + 2]), t);
+                    ++evals;
+                }
+            }
+            if (!stopped) {
+                // rest of the row (or a row that was not staged) from global
+                // memory, kFetch entries per round trip
+                const double* __restrict__ grow_d = gp(J.td) + p * kRow;
+                const uint8_t* __restrict__ grow_m = gp(J.tm) + p * kRow;
+                for (; j < K && !stopped; j += kFetch) {
+                    double dq[kFetch];
+                    int tq[kFetch];
+#pragma unroll
+                    for (int q = 0; q < kFetch; ++q) {
+                        const int jj = j + q < kRow ? j + q : kRow - 1;  // stays inside the row
+                        dq[q] = grow_d[jj];
+                        tq[q] = grow_m[jj];
+                    }
+#pragma unroll
+                    for (int q = 0; q < kFetch; ++q) {
+                        if (stopped) break;
+                        if (j + q >= K || dq[q] > limit) {
+                            stopped = true;
+                            break;
+                        }
+                        const int t = tq[q];
+                        best_push(v, dist_f64(x0, x1, x2, c[3 * t], c[3 * t + 1], c[3 * t + 2]), t);
+                        ++evals;
+                    }
+                }
             }
             ndc += evals;
         }
@@ -293,16 +359,18 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     __shared__ double term[kMaxK];
     __shared__ unsigned long long wsum[kMaxK];
     __shared__ double key[kMaxK];
+    __shared__ double sdist[kMaxK];
+    __shared__ int sidx[kMaxK];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int a = blockIdx.x - map[jb];
-    Meta* __restrict__ meta = J.meta;
+    Meta* __restrict__ meta = gp(J.meta);
     if (meta->done) return;
     const int it = meta->cur_it;
     const int K = J.K;
-    double* __restrict__ centers = J.centers;
-    const unsigned long long* __restrict__ cur = J.sums + (it & 1) * 5 * kMaxK;
-    unsigned long long* __restrict__ nxt = J.sums + ((it + 1) & 1) * 5 * kMaxK;
+    double* __restrict__ centers = gp(J.centers);
+    const unsigned long long* __restrict__ cur = gp(J.sums) + (it & 1) * 5 * kMaxK;
+    unsigned long long* __restrict__ nxt = gp(J.sums) + ((it + 1) & 1) * 5 * kMaxK;
     const int k = threadIdx.x;
     double t = 0.0;
     unsigned long long nk = 0;
@@ -350,7 +418,7 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
         sse = ordered_wave_sum(sse, t3);
         if (k == 0) {
             meta->total_w = total;
-            J.trace[it - 1] = sse;
+            gp(J.trace)[it - 1] = sse;
             meta->iters = it;
             meta->sse_last = sse;
             bool stop = false, conv = false;
@@ -369,24 +437,38 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
         }
     }
     if (!J.prune) return;
-    // row a of the table for the next iteration: centre b ranked by
-    // (distance, index) with a forced first
+    // row a of the table for the next iteration: the centres ordered by
+    // (distance from c_a, index), a itself first (key -1); a bitonic sort of
+    // kMaxK (key, index) pairs in LDS, slots past K keyed +inf
     const int b = k;
     double d = 0.0;
     if (b < K)
         d = dist_f64(c[3 * a], c[3 * a + 1], c[3 * a + 2], c[3 * b], c[3 * b + 1], c[3 * b + 2]);
-    const double kb = b >= K ? __builtin_inf() : (b == a ? -1.0 : d);
-    key[b] = kb;
+    key[b] = b >= K ? __builtin_inf() : (b == a ? -1.0 : d);
+    sidx[b] = b;
+    sdist[b] = d;
     __syncthreads();
-    if (b >= K) return;
-    int rank = 0;
-#pragma unroll 8
-    for (int o = 0; o < kMaxK; ++o) {
-        const double e = key[o];
-        rank += (e < kb || (e == kb && o < b)) ? 1 : 0;
+    for (int size = 2; size <= kMaxK; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int partner = b ^ stride;
+            const double mk = key[b], pk = key[partner];
+            const int mi = sidx[b], pi = sidx[partner];
+            const bool partner_less = pk < mk || (pk == mk && pi < mi);
+            const bool ascending = (b & size) == 0;
+            const bool lower = b < partner;
+            const bool take = (lower == ascending) ? partner_less : !partner_less;
+            __syncthreads();
+            if (take) {
+                key[b] = pk;
+                sidx[b] = pi;
+            }
+            __syncthreads();
+        }
     }
-    J.td[a * kRow + rank] = d;
-    J.tm[a * kRow + rank] = uint8_t(b);
+    if (b >= K) return;
+    const int src = sidx[b];
+    gp(J.td)[a * kRow + b] = sdist[src];
+    gp(J.tm)[a * kRow + b] = uint8_t(src);
 }
 
 // Palette: floor(c + 0.5) clamped to [0, 255]; also clears the squared-error
@@ -395,9 +477,9 @@ __global__ void __launch_bounds__(3 * kMaxK) k_palette(const JobDev* __restrict_
 {
     const JobDev& J = jobs[blockIdx.x];
     const int t = threadIdx.x;
-    if (t == 0) J.meta->sq_err = 0;
+    if (t == 0) gp(J.meta)->sq_err = 0;
     if (t >= 3 * J.K) return;
-    const double v = J.centers[t] + 0.5;
+    const double v = gp(J.centers)[t] + 0.5;
     int q;
     if (!(v >= 1.0))
         q = 0;
@@ -405,7 +487,7 @@ __global__ void __launch_bounds__(3 * kMaxK) k_palette(const JobDev* __restrict_
         q = 255;
     else
         q = int(v);
-    J.palette[t] = uint8_t(q);
+    gp(J.palette)[t] = uint8_t(q);
 }
 
 // Per job: reset the run fields and both cluster-sum buffers; flag a
@@ -414,7 +496,7 @@ __global__ void __launch_bounds__(3 * kMaxK) k_palette(const JobDev* __restrict_
 __global__ void __launch_bounds__(kMaxK) k_kmeans_begin(const JobDev* __restrict__ jobs)
 {
     const JobDev& J = jobs[blockIdx.x];
-    Meta* __restrict__ meta = J.meta;
+    Meta* __restrict__ meta = gp(J.meta);
     const int k = threadIdx.x;
     const int K = J.K;
     __shared__ int bad;
@@ -426,19 +508,19 @@ __global__ void __launch_bounds__(kMaxK) k_kmeans_begin(const JobDev* __restrict
             if (k < J.n) {
                 int r, g, b;
                 key_rgb(J.keys[k], r, g, b);
-                J.centers[3 * k + 0] = double(r);
-                J.centers[3 * k + 1] = double(g);
-                J.centers[3 * k + 2] = double(b);
-                J.assign[k] = uint8_t(k);
+                gp(J.centers)[3 * k + 0] = double(r);
+                gp(J.centers)[3 * k + 1] = double(g);
+                gp(J.centers)[3 * k + 2] = double(b);
+                gp(J.assign)[k] = uint8_t(k);
             } else {
-                J.centers[3 * k] = J.centers[3 * k + 1] = J.centers[3 * k + 2] = 0.0;
+                gp(J.centers)[3 * k] = gp(J.centers)[3 * k + 1] = gp(J.centers)[3 * k + 2] = 0.0;
             }
         }
     } else if (k < K) {
         for (int c = 0; c < 3; ++c)
             if (!__builtin_isfinite(J.centers[3 * k + c])) atomicOr(&bad, 1);
     }
-    for (int j = k; j < 10 * kMaxK; j += blockDim.x) J.sums[j] = 0;
+    for (int j = k; j < 10 * kMaxK; j += blockDim.x) gp(J.sums)[j] = 0;
     __syncthreads();
     if (k == 0) {
         meta->ndc = 0;

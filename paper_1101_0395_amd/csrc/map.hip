@@ -28,10 +28,10 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ 
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
     const int K = J.map_k;
-    const uint32_t* __restrict__ keys = J.keys;
-    const uint32_t* __restrict__ counts = J.counts;
-    uint8_t* __restrict__ lut = J.lut;
-    for (int t = threadIdx.x; t < 3 * K; t += blockDim.x) pal[t] = J.palette[t];
+    const uint32_t* __restrict__ keys = gp(J.keys);
+    const uint32_t* __restrict__ counts = gp(J.counts);
+    uint8_t* __restrict__ lut = gp(J.lut);
+    for (int t = threadIdx.x; t < 3 * K; t += blockDim.x) pal[t] = gp(J.palette)[t];
     __syncthreads();
     const int64_t lo = int64_t(lb) * J.chunk;
     const int64_t hi = lo + J.chunk < J.n ? lo + J.chunk : J.n;
@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ 
     if (threadIdx.x == 0) {
         unsigned long long s = 0;
         for (int w = 0; w < kLutThreads / 64; ++w) s += red[w];
-        atomicAdd(reinterpret_cast<unsigned long long*>(&J.meta->sq_err), s);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&gp(J.meta)->sq_err), s);
     }
 }
 
@@ -77,12 +77,12 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
     const int K = J.map_k;
-    for (int t = threadIdx.x; t < 3 * kMaxK; t += blockDim.x) pal[t] = t < 3 * K ? J.palette[t] : 0;
+    for (int t = threadIdx.x; t < 3 * kMaxK; t += blockDim.x) pal[t] = t < 3 * K ? gp(J.palette)[t] : 0;
     __syncthreads();
-    const uint8_t* __restrict__ img = J.img;
-    const uint8_t* __restrict__ lut = J.lut;
-    uint8_t* __restrict__ out_idx = J.out_idx;
-    uint8_t* __restrict__ out_rgb = J.out_rgb;
+    const uint8_t* __restrict__ img = gp(J.img);
+    const uint8_t* __restrict__ lut = gp(J.lut);
+    uint8_t* __restrict__ out_idx = gp(J.out_idx);
+    uint8_t* __restrict__ out_rgb = gp(J.out_rgb);
     const int64_t npix = int64_t(J.H) * J.W;
     const int64_t g0 = int64_t(lb) * kMapGroupsPerBlock;
     const int64_t g1 = g0 + kMapGroupsPerBlock;
