@@ -119,7 +119,9 @@ cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique
  * uint8[K][3], nullable) receives floor(c + 0.5) clamped to [0, 255];
  * sse_trace (host double[max_iters], nullable) receives SSE_1..SSE_iters.
  * For N' <= K the centres become the colours and no iteration runs.
- * 1 <= max_iters <= 100000, tol >= 0.  Synchronizes `stream`. */
+ * 1 <= max_iters <= 100000, tol >= 0.  A pruned run keeps two 8-byte
+ * records per colour in the workspace: cq_workspace_bytes(H, W, K) of any
+ * image with H W >= N' is enough.  Synchronizes `stream`. */
 cq_status cq_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n_unique, int32_t K,
                     double* centers, int32_t max_iters, double tol, int32_t prune,
                     uint8_t* assign, uint8_t* palette, double* sse_trace /* host */,

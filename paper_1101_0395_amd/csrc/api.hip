@@ -23,10 +23,12 @@ cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s);
 cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s);
 cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, bool lds, hipStream_t s);
 cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s);
-cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, int assign_blocks,
-                             int update_blocks, hipStream_t s);
+cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool first, int all_blocks,
+                             int full_blocks, int walk_blocks, int update_blocks, hipStream_t s);
 cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s);
 int64_t assign_chunk(int64_t n);
+int64_t regroup_blocks(int64_t n);
+cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int blocks, hipStream_t s);
 int map_blocks(int64_t npix);
 cq_status launch_lut(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s);
 cq_status launch_map(const JobDev* jobs, const int* maps, int B, int total, hipStream_t s);
@@ -184,12 +186,14 @@ static void bind_slot(JobDev& J, char* slot, const Layout& L)
     J.lut = to_dev(reinterpret_cast<uint8_t*>(slot + L.lut));
     J.meta = to_dev(reinterpret_cast<Meta*>(slot + L.meta));
     J.trace = to_dev(reinterpret_cast<double*>(slot + L.trace));
-    J.td = to_dev(reinterpret_cast<double*>(slot + L.td));
-    J.tm = to_dev(reinterpret_cast<uint8_t*>(slot + L.tm));
+    J.rec = to_dev(reinterpret_cast<Rec*>(slot + L.rec));
+    J.tix = to_dev(reinterpret_cast<int32_t*>(slot + L.tix));
     J.sums = to_dev(reinterpret_cast<unsigned long long*>(slot + L.sums));
     J.blk = to_dev(reinterpret_cast<uint32_t*>(slot + L.blk));
+    J.part = to_dev(reinterpret_cast<unsigned long long*>(slot + L.part));
     J.vals = to_dev(reinterpret_cast<uint64_t*>(slot + L.chunks));
     J.d2 = to_dev(reinterpret_cast<uint32_t*>(slot + L.d2));
+    J.grp = to_dev(reinterpret_cast<uint64_t*>(slot + L.d2));
 }
 
 static void set_image(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride)
@@ -330,13 +334,16 @@ static cq_status run_kmeans(Batch& b)
 {
     int max_iters = 0;
     for (const JobDev& J : b.h) max_iters = J.max_iters > max_iters ? J.max_iters : max_iters;
-    const int assign_total = b.set_map(kMapAssign, [&](int j) {
+    auto assign_blocks = [&](int j) {
         const JobDev& J = b.h[j];
         return J.n <= J.K ? 0 : int((J.n + J.chunk - 1) / J.chunk);
-    });
+    };
+    const int assign_total = b.set_map(kMapAssign, assign_blocks);
+    const int full_total = b.set_map(kMapAssignFull, [&](int j) { return b.h[j].prune ? 0 : assign_blocks(j); });
+    const int walk_total = b.set_map(kMapAssignWalk, [&](int j) { return b.h[j].prune ? assign_blocks(j) : 0; });
     const int update_total = b.set_map(kMapUpdate, [&](int j) {
         const JobDev& J = b.h[j];
-        return J.n <= J.K ? 0 : (J.prune ? J.K : 1);
+        return J.n <= J.K ? 0 : (J.prune ? J.K + int(regroup_blocks(J.n)) : 1);
     });
     CQ_TRY(upload(b));
     CQ_TRY(launch_kmeans_begin(b.d_jobs(), b.B, b.s));
@@ -345,12 +352,16 @@ static cq_status run_kmeans(Batch& b)
     for (int it = 1; it <= max_iters; it += group) {
         const int n_it = it + group - 1 <= max_iters ? group : max_iters - it + 1;
         for (int q = 0; q < n_it; ++q)
-            CQ_TRY(launch_kmeans_iter(b.d_jobs(), b.d_maps(), b.B, assign_total, update_total, b.s));
+            CQ_TRY(launch_kmeans_iter(b.d_jobs(), b.d_maps(), b.B, it + q == 1, assign_total, full_total,
+                                      walk_total, update_total, b.s));
         CQ_TRY(collect(b));
         bool all_done = true;
         for (const JobResult& r : b.res) all_done = all_done && r.done;
         if (all_done) break;
     }
+    bool grouped = false;
+    for (const JobDev& J : b.h) grouped = grouped || (J.prune && J.n > J.K);
+    if (grouped) CQ_TRY(launch_unpermute(b.d_jobs(), b.d_maps(), b.B, assign_total, b.s));
     return CQ_OK;
 }
 
@@ -565,8 +576,9 @@ cq_status cq_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n_uniq
     if (!keys || !counts || !centers || !assign) return einval("keys/counts/centers/assign is null");
     if (n_unique < 1 || n_unique > kMaxPixels) return einval("n_unique = %lld out of range", (long long)n_unique);
     CQ_TRY(check_iters_tol(max_iters, tol));
-    const Layout L = make_layout(0, false);
-    CQ_TRY(check_ws(ws, ws_bytes, L.fixed_end));
+    // a pruned run keeps two packed records per colour in the workspace
+    const Layout L = make_layout(prune ? n_unique : 0, false);
+    CQ_TRY(check_ws(ws, ws_bytes, prune ? L.total : L.fixed_end));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
     JobDev& J = b.h[0];
     bind_slot(J, static_cast<char*>(ws), L);

@@ -16,6 +16,7 @@ constexpr int kMaxK = 256;
 constexpr int kMaxIters = 100000;
 constexpr int64_t kMaxPixels = int64_t(1) << 28;
 constexpr int kMaxBatch = 4096;
+constexpr int kMaxAssignBlocks = 4096;  // assignment blocks of one job
 
 // Bitmap compaction: each block owns a contiguous run of bitmap words.
 constexpr int kCompactThreads = 256;
@@ -28,6 +29,29 @@ constexpr int kInitChunk = 1024;
 
 // Sorted centre table: row stride (entries) independent of K.
 constexpr int kRow = kMaxK;
+
+// One entry of a sorted table row: the centre (c0, c1, c2) and its squared
+// distance d from the row's own centre, so that a scan needs no second lookup.
+struct alignas(32) Rec {
+    double c0, c1, c2, d;
+};
+
+// Entries a row walk reads per round, and the padding past the last row that
+// lets the final round of any row read whole rounds.
+constexpr int kWalk = 8;
+constexpr int kTablePad = kWalk;
+
+// Cluster statistics of one iteration (uint64 each): n_k, S_k (3 per
+// cluster), Q_k, then the number of unique colours and the counting-sort
+// cursor of every (cluster, distance bucket) pair, pair index k kBuckets + b.
+// Two such blocks alternate between iterations.
+constexpr int kBuckets = 16;
+constexpr int kSumN = 0;
+constexpr int kSumS = kMaxK;
+constexpr int kSumQ = 4 * kMaxK;
+constexpr int kSumColours = 5 * kMaxK;
+constexpr int kSumCursor = kSumColours + kMaxK * kBuckets;
+constexpr int kSumStride = kSumCursor + kMaxK * kBuckets;
 
 // Device-side control block, one per workspace.
 struct Meta {
@@ -84,12 +108,14 @@ struct JobDev {
     uint8_t CQ_GLOBAL* lut;
     Meta CQ_GLOBAL* meta;
     double CQ_GLOBAL* trace;
-    double CQ_GLOBAL* td;
-    uint8_t CQ_GLOBAL* tm;
+    Rec CQ_GLOBAL* rec;   // sorted table rows (kMaxK x kRow)
+    int32_t CQ_GLOBAL* tix; // centre index of every table entry (kMaxK x kRow)
     unsigned long long CQ_GLOBAL* sums;
     uint32_t CQ_GLOBAL* blk;
+    unsigned long long CQ_GLOBAL* part;  // per assignment block: distance count, near-tie count
     uint64_t CQ_GLOBAL* vals;
     uint32_t CQ_GLOBAL* d2;
+    uint64_t CQ_GLOBAL* grp;  // k-means colour records, two buffers of n (shares d2's region)
     uint32_t CQ_GLOBAL* keys;
     uint32_t CQ_GLOBAL* counts;
     uint8_t CQ_GLOBAL* assign;
@@ -103,6 +129,19 @@ struct JobDev {
     int32_t packed;      // image rows are contiguous and 4-byte aligned
     int32_t map_k;       // palette entries the pixel map searches
 };
+
+// Read-only view of global memory that a kernel does not write: loads with a
+// wave-uniform address through it become scalar loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CQ_CONST __attribute__((address_space(4)))
+#else
+#define CQ_CONST
+#endif
+template <typename T>
+__device__ __forceinline__ const T CQ_CONST* cp(T CQ_GLOBAL* p)
+{
+    return (const T CQ_CONST*)p;
+}
 
 // Host-side stores into a descriptor, and host-side reads of one.
 template <typename T>
@@ -126,7 +165,17 @@ struct JobResult {
     int32_t done, iters, converged, bad_input, sync_error, pad_;
 };
 
-enum MapId { kMapHist = 0, kMapAssign, kMapUpdate, kMapLut, kMapPix, kMapInit, kNumMaps };
+enum MapId {
+    kMapHist = 0,
+    kMapAssign,      // every job with iterations (first iteration, final pass)
+    kMapAssignFull,  // unpruned jobs (full searches after the first iteration)
+    kMapAssignWalk,  // pruned jobs (sort-means passes)
+    kMapUpdate,
+    kMapLut,
+    kMapPix,
+    kMapInit,
+    kNumMaps
+};
 
 __device__ __forceinline__ int find_job(const int* __restrict__ map, int B, int block)
 {
@@ -153,7 +202,7 @@ inline size_t desc_results_off(int B)
 // ---------------------------------------------------------------- layout
 
 struct Layout {
-    size_t tbl, bitmap, lut, meta, trace, td, tm, sums, centers, palette, blk, desc;
+    size_t tbl, bitmap, lut, meta, trace, rec, tix, sums, centers, palette, blk, part, desc;
     size_t chunks, d2, keys, counts, assign;
     size_t fixed_end;  // end of the regions every call may use
     size_t total;      // end including the per-colour regions for n_cap colours
@@ -170,19 +219,22 @@ inline Layout make_layout(int64_t n_cap, bool with_colour_arrays)
     L.lut = o;      o = align256(o + kNumKeys);
     L.meta = o;     o = align256(o + 512);
     L.trace = o;    o = align256(o + sizeof(double) * kMaxIters);
-    L.td = o;       o = align256(o + sizeof(double) * kMaxK * kRow);
-    L.tm = o;       o = align256(o + kMaxK * kRow);
-    L.sums = o;     o = align256(o + sizeof(uint64_t) * 10 * kMaxK);  // two iterations
+    // both tables: kTablePad entries past the last row for the final round of a walk
+    L.rec = o;      o = align256(o + sizeof(Rec) * (kMaxK * kRow + kTablePad));
+    L.tix = o;      o = align256(o + sizeof(int32_t) * (kMaxK * kRow + kTablePad));
+    L.sums = o;     o = align256(o + sizeof(uint64_t) * 2 * kSumStride);  // two iterations
     L.centers = o;  o = align256(o + sizeof(double) * 3 * kMaxK);
     L.palette = o;  o = align256(o + 3 * kMaxK);
     L.blk = o;      o = align256(o + sizeof(uint32_t) * 2 * kCompactBlocks);
+    L.part = o;     o = align256(o + sizeof(uint64_t) * 2 * kMaxAssignBlocks);
     L.desc = o;     o = align256(o + desc_bytes(1));
     L.fixed_end = o;
     const size_t n = n_cap > 0 ? size_t(n_cap) : 0;
     size_t nchunks = (n + kInitChunk - 1) / kInitChunk + 1;
     if (nchunks < 2048) nchunks = 2048;  // also two rounds of up to 1024 cooperative blocks
     L.chunks = o;   o = align256(o + sizeof(uint64_t) * nchunks);
-    L.d2 = o;       o = align256(o + sizeof(uint32_t) * 2 * n);  // double-buffered
+    // init: two uint32 per colour; k-means afterwards: two uint64 records per colour
+    L.d2 = o;       o = align256(o + sizeof(uint64_t) * 2 * n);
     if (with_colour_arrays) {
         L.keys = o;   o = align256(o + sizeof(uint32_t) * n);
         L.counts = o; o = align256(o + sizeof(uint32_t) * n);

@@ -15,6 +15,8 @@
 //              matrices d and M of Algo. 2) for the next iteration.
 // The iteration number lives in each job's control block, so the same two
 // launches serve every iteration and a stopped job's blocks return at once.
+#include <stdlib.h>
+
 #include "cq_internal.h"
 
 // Every floating-point operation in this file is rounded on its own.
@@ -23,48 +25,93 @@
 namespace cq {
 
 constexpr int kAssignThreads = 256;
-constexpr int kRowCache = 32;   // leading entries of a sorted row staged in LDS
-constexpr int kRowSlots = 64;   // rows staged per block
-constexpr int kFetch = 16;      // row entries per global round trip past the staged prefix
+constexpr int kScatterChunk = 2048;  // colours per regrouping block
 
-// Adds (n, S_r, S_g, S_b, Q) of the valid lanes to the LDS bins of their
-// clusters.  Lanes of one wave that share a cluster are summed first (up to
-// four distinct clusters per wave); the rest add their own values.
-__device__ __forceinline__ void bin_add(unsigned long long* bins, bool valid, int best,
-                                        unsigned long long w, int r, int g, int b)
+// Adds the five cluster statistics (n, S_r, S_g, S_b, Q) of the valid lanes
+// to the LDS bins of their clusters.  Lanes of one wave that share a cluster
+// are summed first (up to four distinct clusters per wave); the rest add their
+// own values.
+__device__ __forceinline__ void bin_add_vals(unsigned long long* bins, bool valid, int k,
+                                             unsigned long long v0, unsigned long long v1,
+                                             unsigned long long v2, unsigned long long v3,
+                                             unsigned long long v4)
 {
-    const unsigned long long v1 = w * unsigned(r), v2 = w * unsigned(g), v3 = w * unsigned(b);
-    const unsigned long long v4 = w * unsigned(r * r + g * g + b * b);
     const int lane = threadIdx.x & 63;
     unsigned long long active = __ballot(valid);
 #pragma unroll 1
     for (int round = 0; round < 4 && active; ++round) {
         const int leader = __ffsll(active) - 1;
-        const int kb = __shfl(best, leader, 64);
-        const bool mine = valid && best == kb;
+        const int kb = __shfl(k, leader, 64);
+        const bool mine = valid && k == kb;
         const unsigned long long mask = __ballot(mine);
-        const unsigned long long s0 = wave_sum(mine ? w : 0ull);
+        const unsigned long long s0 = wave_sum(mine ? v0 : 0ull);
         const unsigned long long s1 = wave_sum(mine ? v1 : 0ull);
         const unsigned long long s2 = wave_sum(mine ? v2 : 0ull);
         const unsigned long long s3 = wave_sum(mine ? v3 : 0ull);
         const unsigned long long s4 = wave_sum(mine ? v4 : 0ull);
         if (lane == leader) {
-            atomicAdd(&bins[kb], s0);
-            atomicAdd(&bins[kMaxK + 3 * kb + 0], s1);
-            atomicAdd(&bins[kMaxK + 3 * kb + 1], s2);
-            atomicAdd(&bins[kMaxK + 3 * kb + 2], s3);
-            atomicAdd(&bins[4 * kMaxK + kb], s4);
+            atomicAdd(&bins[kSumN + kb], s0);
+            atomicAdd(&bins[kSumS + 3 * kb + 0], s1);
+            atomicAdd(&bins[kSumS + 3 * kb + 1], s2);
+            atomicAdd(&bins[kSumS + 3 * kb + 2], s3);
+            atomicAdd(&bins[kSumQ + kb], s4);
         }
         if (mine) valid = false;
         active &= ~mask;
     }
     if (valid) {
-        atomicAdd(&bins[best], w);
-        atomicAdd(&bins[kMaxK + 3 * best + 0], v1);
-        atomicAdd(&bins[kMaxK + 3 * best + 1], v2);
-        atomicAdd(&bins[kMaxK + 3 * best + 2], v3);
-        atomicAdd(&bins[4 * kMaxK + best], v4);
+        atomicAdd(&bins[kSumN + k], v0);
+        atomicAdd(&bins[kSumS + 3 * k + 0], v1);
+        atomicAdd(&bins[kSumS + 3 * k + 1], v2);
+        atomicAdd(&bins[kSumS + 3 * k + 2], v3);
+        atomicAdd(&bins[kSumQ + k], v4);
     }
+}
+
+// One colour (weight w, channels r, g, b) per valid lane into its cluster's bins.
+__device__ __forceinline__ void bin_add(unsigned long long* bins, bool valid, int best,
+                                        unsigned long long w, int r, int g, int b)
+{
+    bin_add_vals(bins, valid, best, w, w * unsigned(r), w * unsigned(g), w * unsigned(b),
+                 w * unsigned(r * r + g * g + b * b));
+}
+
+// Running statistics of the colours a lane has put into one cluster.
+struct Acc {
+    int k;  // -1: empty
+    unsigned long long n, s0, s1, s2, q;
+};
+
+__device__ __forceinline__ void acc_add(Acc& a, unsigned long long* bins, int k,
+                                        unsigned long long w, int r, int g, int b)
+{
+    if (k != a.k) {
+        if (a.k >= 0) {
+            atomicAdd(&bins[kSumN + a.k], a.n);
+            atomicAdd(&bins[kSumS + 3 * a.k + 0], a.s0);
+            atomicAdd(&bins[kSumS + 3 * a.k + 1], a.s1);
+            atomicAdd(&bins[kSumS + 3 * a.k + 2], a.s2);
+            atomicAdd(&bins[kSumQ + a.k], a.q);
+        }
+        a = Acc{k, 0ull, 0ull, 0ull, 0ull, 0ull};
+    }
+    a.n += w;
+    a.s0 += w * unsigned(r);
+    a.s1 += w * unsigned(g);
+    a.s2 += w * unsigned(b);
+    a.q += w * unsigned(r * r + g * g + b * b);
+}
+
+// Distance bucket of a colour: two per octave of d + 1, from 4 up (bucket 0
+// also takes d + 1 < 4, bucket 15 everything from 1024 on).  Colours of a
+// cluster that are about as far from its centre scan about as far along its
+// table row, so the regrouping orders them by bucket within the cluster.
+__device__ __forceinline__ int dist_bucket(double d)
+{
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(d + 1.0);
+    const int e = int((bits >> 52) & 0x7ffu) - 1023;
+    const int b = 2 * e + int((bits >> 51) & 1u) - 4;
+    return b < 0 ? 0 : (b > kBuckets - 1 ? kBuckets - 1 : b);
 }
 
 // Candidate-set summary of one colour: smallest distance, its centre (lowest
@@ -87,9 +134,12 @@ __device__ __forceinline__ void best_push(Best& v, double d, int t)
     }
 }
 
-// Block reduction of the distance and near-tie counters, then one atomic each.
+// Block reduction of the distance and near-tie counters into the block's own
+// slot of the job's partial counts (plain stores: many blocks adding to one
+// address would serialize); the update step adds the slots up.
 __device__ __forceinline__ void flush_counters(unsigned long long ndc, unsigned long long ties,
-                                               unsigned long long* red, Meta* meta)
+                                               unsigned long long* red,
+                                               unsigned long long* __restrict__ slot)
 {
     ndc = wave_sum(ndc);
     ties = wave_sum(ties);
@@ -104,22 +154,29 @@ __device__ __forceinline__ void flush_counters(unsigned long long ndc, unsigned 
             a += red[w];
             t += red[kAssignThreads / 64 + w];
         }
-        atomicAdd(reinterpret_cast<unsigned long long*>(&meta->ndc), a);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&meta->near_ties), t);
+        slot[0] = a;
+        slot[1] = t;
     }
 }
 
-__device__ __forceinline__ void flush_bins(const unsigned long long* bins, int K,
+// Adds the block's non-empty cluster bins and (cluster, bucket) colour
+// counts to the job's statistics.
+__device__ __forceinline__ void flush_bins(const unsigned long long* bins, const uint32_t* ccount, int K,
                                            unsigned long long* __restrict__ sums)
 {
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
-        const unsigned long long nk = bins[k];
+        const unsigned long long nk = bins[kSumN + k];
         if (nk == 0) continue;
-        atomicAdd(&sums[k], nk);
-        atomicAdd(&sums[kMaxK + 3 * k + 0], bins[kMaxK + 3 * k + 0]);
-        atomicAdd(&sums[kMaxK + 3 * k + 1], bins[kMaxK + 3 * k + 1]);
-        atomicAdd(&sums[kMaxK + 3 * k + 2], bins[kMaxK + 3 * k + 2]);
-        atomicAdd(&sums[4 * kMaxK + k], bins[4 * kMaxK + k]);
+        atomicAdd(&sums[kSumN + k], nk);
+        atomicAdd(&sums[kSumS + 3 * k + 0], bins[kSumS + 3 * k + 0]);
+        atomicAdd(&sums[kSumS + 3 * k + 1], bins[kSumS + 3 * k + 1]);
+        atomicAdd(&sums[kSumS + 3 * k + 2], bins[kSumS + 3 * k + 2]);
+        atomicAdd(&sums[kSumQ + k], bins[kSumQ + k]);
+    }
+    if (!ccount) return;
+    for (int cb = threadIdx.x; cb < K * kBuckets; cb += blockDim.x) {
+        const uint32_t c = ccount[cb];
+        if (c != 0) atomicAdd(&sums[kSumColours + cb], (unsigned long long)c);
     }
 }
 
@@ -129,7 +186,7 @@ __device__ __forceinline__ bool near_tie(const Best& v)
 }
 
 // Full search over the centres for one colour per lane.  All lanes walk the
-// same centre index, so the centres come through scalar loads.
+// same centre index, so every centre load has one address per wave.
 __device__ __forceinline__ Best full_search(double x0, double x1, double x2,
                                             const double* __restrict__ centers, int K)
 {
@@ -148,177 +205,162 @@ __device__ __forceinline__ Best full_search(double x0, double x1, double x2,
     return v;
 }
 
-// Assignment fused with the cluster sums.  Block b of job j takes the colours
-// [b chunk, (b + 1) chunk) (keys ascending, so a run is compact in colour space
-// and touches few clusters), one colour per lane.  In a sort-means pass the
-// block first gathers the previous centres p of its colours and stages the
-// first kRowCache entries of each of those rows (at most kRowSlots rows) in
-// LDS; scans read global memory only past that prefix or for rows beyond the
-// staged ones.
+// Packed colour record of the sort-means passes: bits 0-23 the colour key,
+// bits 24-31 its cluster, bits 32-59 its pixel count (below 2^28 whenever
+// there are two colours or more), bits 60-63 its distance bucket.
+__device__ __forceinline__ uint64_t pack_colour(uint32_t key, int cluster, uint32_t count, int bucket)
+{
+    return uint64_t(key | (uint32_t(cluster) << 24)) | (uint64_t(count) << 32) | (uint64_t(bucket) << 60);
+}
+
+// Assignment fused with the cluster sums; block b of job j takes the colours
+// [b chunk, (b + 1) chunk), one colour per lane.
+//
+// A full search (Algo. 1, the first iteration of Algo. 2) reads the colours in
+// key order.  In a pruned run it also writes each colour as a packed record
+// with its new cluster; the update step then regroups those records by
+// cluster, so the sort-means passes that follow read colours that share their
+// previous centre p.  A wave takes the distinct p of its lanes one at a time
+// (nearly always one) and walks row p of the sorted table with one address per
+// wave: entry j is evaluated by the lanes whose bound 4 d(x, c_p) (1 + 1e-12)
+// it does not exceed, and the walk ends at the first entry beyond every
+// lane's bound.  Rows are sorted, so each lane evaluates exactly the prefix of
+// its row that the sequential scan of Algo. 2 evaluates.
+//
+// The two kinds of pass are separate kernels (kSortMeans false / true) so that each
+// gets its own register allocation; a block whose job needs the other kind in
+// this iteration returns at once.
+template <bool kSortMeans>
 __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restrict__ jobs,
                                                            const int* __restrict__ map, int B)
 {
-    __shared__ double c[3 * kMaxK];
-    __shared__ unsigned long long bins[5 * kMaxK];  // n, S0, S1, S2, Q per cluster
+    __shared__ unsigned long long bins[5 * kMaxK];     // n, S0, S1, S2, Q per cluster
+    __shared__ uint32_t ccount[kMaxK * kBuckets];     // colours per (cluster, bucket), pruned runs
     __shared__ unsigned long long red[2 * (kAssignThreads / 64)];
-    __shared__ double ltd[kRowSlots * kRowCache];
-    __shared__ uint8_t ltm[kRowSlots * kRowCache];
-    __shared__ int slot_of[kMaxK];
-    __shared__ int row_of[kRowSlots];
-    __shared__ int need[kMaxK];
-    __shared__ int scan_tmp[64];
-    static_assert(kAssignThreads == kMaxK, "one thread per table row");
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
     Meta* __restrict__ meta = gp(J.meta);
     const int K = J.K;
     const int64_t n = J.n;
-    const double* __restrict__ centers = gp(J.centers);
-    const uint32_t* __restrict__ keys = gp(J.keys);
-    const uint32_t* __restrict__ counts = gp(J.counts);
-    uint8_t* __restrict__ assign = gp(J.assign);
     const int64_t lo = int64_t(lb) * J.chunk;
     const int64_t hi = lo + J.chunk < n ? lo + J.chunk : n;
-    // every load this block needs first is issued before anything waits on it:
-    // the control block, the centres, and the colours of the first pass
     const int done = meta->done;
     const int it = meta->iters + 1;
-    double cv[3];
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-        const int t = u * kAssignThreads + threadIdx.x;
-        cv[u] = t < 3 * K ? centers[t] : 0.0;
-    }
-    const int64_t i0 = lo + threadIdx.x;
-    const bool valid0 = i0 < hi;
-    const uint32_t key0 = valid0 ? keys[i0] : 0u;
-    const uint32_t cnt0 = valid0 ? counts[i0] : 0u;
-    const int p0 = valid0 ? assign[i0] : 0;
     if (done) return;
-    const bool pruned = J.prune && it >= 2;
+    const bool grouped = J.prune && it >= 2;
+    if (grouped != kSortMeans) return;
     if (lb == 0 && threadIdx.x == 0) meta->cur_it = it;
-    unsigned long long* __restrict__ sums = gp(J.sums) + (it & 1) * 5 * kMaxK;
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-        const int t = u * kAssignThreads + threadIdx.x;
-        if (t < 3 * K) c[t] = cv[u];
-    }
+    unsigned long long* __restrict__ sums = gp(J.sums) + (it & 1) * kSumStride;
+    uint64_t* __restrict__ grp = gp(J.grp) + (it & 1) * n;
     for (int t = threadIdx.x; t < 5 * kMaxK; t += blockDim.x) bins[t] = 0ull;
-    if (pruned) {
-        need[threadIdx.x] = 0;
-        __syncthreads();
-        if (valid0) need[p0] = 1;
-        for (int64_t i = i0 + blockDim.x; i < hi; i += blockDim.x) need[assign[i]] = 1;
-        __syncthreads();
-        int total = 0;
-        const int f = need[threadIdx.x];
-        const int pos = block_exclusive_scan<int>(f, scan_tmp, &total);
-        const int slot = (f && pos < kRowSlots) ? pos : -1;
-        slot_of[threadIdx.x] = slot;
-        if (slot >= 0) row_of[slot] = threadIdx.x;
-        __syncthreads();
-        // stage the leading entries of the needed rows: loads first, then stores
-        const int nslots = total < kRowSlots ? total : kRowSlots;
-        constexpr int kPer = kRowSlots * kRowCache / kAssignThreads;
-        double dv[kPer];
-        uint32_t mv[kPer];
-        const double* __restrict__ td = gp(J.td);
-        const uint8_t* __restrict__ tm = gp(J.tm);
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = u * kAssignThreads + threadIdx.x;
-            const bool in = e < nslots * kRowCache;
-            const int r = in ? row_of[e / kRowCache] : 0;
-            dv[u] = in ? td[r * kRow + e % kRowCache] : 0.0;
-            mv[u] = in ? tm[r * kRow + e % kRowCache] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = u * kAssignThreads + threadIdx.x;
-            if (e < nslots * kRowCache) {
-                ltd[e] = dv[u];
-                ltm[e] = uint8_t(mv[u]);
-            }
-        }
-    }
+    if (J.prune)
+        for (int t = threadIdx.x; t < K * kBuckets; t += blockDim.x) ccount[t] = 0u;
     __syncthreads();
 
     unsigned long long ndc = 0, ties = 0;
-    for (int64_t base = lo; base < hi; base += blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const bool valid = i < hi;
-        const bool first = base == lo;
-        const uint32_t key = first ? key0 : (valid ? keys[i] : 0u);
-        const unsigned long long w = first ? cnt0 : (valid ? counts[i] : 0u);
-        int r, g, b;
-        key_rgb(key, r, g, b);
-        const double x0 = double(r), x1 = double(g), x2 = double(b);
-        Best v{0.0, __builtin_inf(), 0};
-        if (!pruned) {
-            v = full_search(x0, x1, x2, centers, K);
-            if (valid) ndc += unsigned(K);
-        } else if (valid) {
-            const int p = first ? p0 : assign[i];
-            const double prev = dist_f64(x0, x1, x2, c[3 * p], c[3 * p + 1], c[3 * p + 2]);
-            const double limit = 4.0 * prev * (1.0 + 1e-12);
-            v.bd = prev;
-            v.best = p;
-            unsigned evals = 1;
-            const int slot = slot_of[p];
-            int j = 1;
-            bool stopped = false;
-            if (slot >= 0) {
-                // staged prefix of row p: LDS reads only
-                const int jend = K < kRowCache ? K : kRowCache;
-                for (; j < jend; ++j) {
-                    const double dj = ltd[slot * kRowCache + j];
-                    const int t = ltm[slot * kRowCache + j];
-                    if (dj > limit) {
-                        stopped = true;
-                        break;
-                    }
-                    best_push(v, dist_f64(x0, x1, x2, c[3 * t], c[3 * t + 1], c[3 * t + 2]), t);
-                    ++evals;
+    if constexpr (!kSortMeans) {
+        const double* __restrict__ centers = gp(J.centers);
+        const uint32_t* __restrict__ keys = gp(J.keys);
+        const uint32_t* __restrict__ counts = gp(J.counts);
+        uint8_t* __restrict__ assign = gp(J.assign);
+        for (int64_t base = lo; base < hi; base += blockDim.x) {
+            const int64_t i = base + threadIdx.x;
+            const bool valid = i < hi;
+            const uint32_t key = valid ? keys[i] : 0u;
+            const uint32_t w = valid ? counts[i] : 0u;
+            int r, g, b;
+            key_rgb(key, r, g, b);
+            const Best v = full_search(double(r), double(g), double(b), centers, K);
+            if (valid) {
+                ndc += unsigned(K);
+                ties += near_tie(v) ? 1 : 0;
+                assign[i] = uint8_t(v.best);
+                if (J.prune) {
+                    const int bk = dist_bucket(v.bd);
+                    grp[i] = pack_colour(key, v.best, w, bk);
+                    atomicAdd(&ccount[v.best * kBuckets + bk], 1u);
                 }
             }
-            if (!stopped) {
-                // rest of the row (or a row that was not staged) from global
-                // memory, kFetch entries per round trip
-                const double* __restrict__ grow_d = gp(J.td) + p * kRow;
-                const uint8_t* __restrict__ grow_m = gp(J.tm) + p * kRow;
-                for (; j < K && !stopped; j += kFetch) {
-                    double dq[kFetch];
-                    int tq[kFetch];
-#pragma unroll
-                    for (int q = 0; q < kFetch; ++q) {
-                        const int jj = j + q < kRow ? j + q : kRow - 1;  // stays inside the row
-                        dq[q] = grow_d[jj];
-                        tq[q] = grow_m[jj];
-                    }
-#pragma unroll
-                    for (int q = 0; q < kFetch; ++q) {
-                        if (stopped) break;
-                        if (j + q >= K || dq[q] > limit) {
-                            stopped = true;
-                            break;
-                        }
-                        const int t = tq[q];
-                        best_push(v, dist_f64(x0, x1, x2, c[3 * t], c[3 * t + 1], c[3 * t + 2]), t);
-                        ++evals;
-                    }
+            bin_add(bins, valid, v.best, w, r, g, b);
+        }
+    } else {
+        const Rec CQ_CONST* rec = cp(J.rec);
+        const int32_t CQ_CONST* tix = cp(J.tix);
+        Acc acc{-1, 0ull, 0ull, 0ull, 0ull, 0ull};
+        uint64_t g_next = lo + threadIdx.x < hi ? grp[lo + threadIdx.x] : 0ull;
+        for (int64_t base = lo; base < hi; base += blockDim.x) {
+            const int64_t i = base + threadIdx.x;
+            const bool valid = i < hi;
+            const uint64_t g0 = g_next;
+            g_next = i + blockDim.x < hi ? grp[i + blockDim.x] : 0ull;  // next pass, in flight
+            const uint32_t key = uint32_t(g0) & 0xffffffu;
+            const int p = int((uint32_t(g0) >> 24) & 255u);
+            const uint32_t w = uint32_t(g0 >> 32) & 0x0fffffffu;
+            int r, g, b;
+            key_rgb(key, r, g, b);
+            const double x0 = double(r), x1 = double(g), x2 = double(b);
+            Best v{0.0, __builtin_inf(), 0};
+            unsigned evals = 0;
+            unsigned long long pending = __ballot(valid);
+            while (pending) {
+                const int leader = __ffsll(pending) - 1;
+                const int ps = __builtin_amdgcn_readfirstlane(__shfl(p, leader, 64));
+                const bool mine = valid && p == ps;
+                const Rec CQ_CONST* row = rec + ps * kRow;
+                const int32_t CQ_CONST* trow = tix + ps * kRow;
+                const Rec own = row[0];
+                const double prev = dist_f64(x0, x1, x2, own.c0, own.c1, own.c2);
+                const double limit = 4.0 * prev * (1.0 + 1e-12);
+                const double reach = wave_max(mine ? limit : -1.0);  // same value in every lane
+                if (mine) {
+                    v.bd = prev;
+                    v.second = __builtin_inf();
+                    v.best = ps;
+                    evals = 1;
                 }
+                // entries j .. j + kWalk - 1 per round; the table is padded so
+                // that the last round of a row stays inside the allocation
+                for (int j = 1; j < K; j += kWalk) {
+                    Rec q[kWalk];
+                    int tq[kWalk];
+#pragma unroll
+                    for (int u = 0; u < kWalk; ++u) {
+                        q[u] = row[j + u];
+                        tq[u] = trow[j + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kWalk; ++u) {
+                        // bitwise logic keeps the round free of branches
+                        const bool within = mine & (j + u < K) & (q[u].d <= limit);
+                        const double d = dist_f64(x0, x1, x2, q[u].c0, q[u].c1, q[u].c2);
+                        const bool better = within & ((d < v.bd) | ((d == v.bd) & (tq[u] < v.best)));
+                        const bool sec = within & !better & (d < v.second);
+                        v.second = better ? v.bd : (sec ? d : v.second);
+                        v.bd = better ? d : v.bd;
+                        v.best = better ? tq[u] : v.best;
+                        evals += within ? 1u : 0u;
+                        // one entry at a time: fewer registers, more waves per SIMD
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    if (j + kWalk >= K || q[kWalk - 1].d > reach) break;
+                }
+                pending &= ~__ballot(mine);
             }
-            ndc += evals;
+            if (valid) {
+                ndc += evals;
+                ties += near_tie(v) ? 1 : 0;
+                const int bk = dist_bucket(v.bd);
+                grp[i] = pack_colour(key, v.best, w, bk);
+                atomicAdd(&ccount[v.best * kBuckets + bk], 1u);
+                acc_add(acc, bins, v.best, w, r, g, b);
+            }
         }
-        if (valid) {
-            ties += near_tie(v) ? 1 : 0;
-            assign[i] = uint8_t(v.best);
-        }
-        bin_add(bins, valid, v.best, w, r, g, b);
+        bin_add_vals(bins, acc.k >= 0, acc.k, acc.n, acc.s0, acc.s1, acc.s2, acc.q);
     }
-    flush_counters(ndc, ties, red, meta);
-    flush_bins(bins, K, sums);
+    __syncthreads();
+    flush_counters(ndc, ties, red, gp(J.part) + 2 * lb);
+    flush_bins(bins, J.prune ? ccount : nullptr, K, sums);
 }
 
 // Exact unsigned 128-bit value converted to double by the fixed rule
@@ -345,13 +387,93 @@ __device__ __forceinline__ double ordered_wave_sum(double acc, double v)
     return acc;
 }
 
-// Update step, SSE, stopping rule and (pruned runs) the sorted table of the
-// next iteration.  Job j gets K_j blocks of kMaxK threads when pruned, else 1.
-// Every block derives the new centres from the cluster sums of this iteration
+// Regrouping of a pruned run: this iteration's colour records (new cluster
+// in bits 24-31, distance bucket in bits 60-63) are moved into the other
+// record buffer ordered by (cluster, bucket), a counting sort whose offsets
+// are the prefix sums of the (cluster, bucket) colour counts.  The order
+// inside a pair is whatever the atomics give; no result depends on it.  Block
+// s of the job's regrouping blocks takes the records
+// [s kScatterChunk, (s + 1) kScatterChunk).
+__device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const unsigned long long* __restrict__ cur,
+                                        unsigned long long* __restrict__ cursor)
+{
+    constexpr int kPairs = kMaxK * kBuckets;
+    constexpr int kPer = kPairs / kMaxK;  // pairs per thread in the scan
+    __shared__ uint32_t start[kPairs];
+    __shared__ uint32_t scan_tmp[64];
+    const int k = threadIdx.x;
+    const int lane = k & 63;
+    const int npairs = J.K * kBuckets;
+    uint32_t c[kPer];
+    uint32_t tsum = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int cb = k * kPer + u;
+        c[u] = cb < npairs ? uint32_t(cur[kSumColours + cb]) : 0u;
+        tsum += c[u];
+    }
+    uint32_t run = block_exclusive_scan<uint32_t>(tsum, scan_tmp, nullptr);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        start[k * kPer + u] = run;
+        run += c[u];
+    }
+    __syncthreads();
+    const int64_t n = J.n;
+    const uint64_t* __restrict__ src = gp(J.grp) + (it & 1) * n;
+    uint64_t* __restrict__ dst = gp(J.grp) + ((it + 1) & 1) * n;
+    const int64_t lo = int64_t(s) * kScatterChunk;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // every record of the block is loaded and ranked within its wave's group of
+    // equal (cluster, bucket) first; the group leaders then reserve their
+    // places with atomics that are all in flight together
+    constexpr int kPasses = kScatterChunk / kMaxK;
+    uint64_t g[kPasses];
+    int cbv[kPasses], lead[kPasses], rank[kPasses];
+    unsigned long long pos[kPasses];
+#pragma unroll
+    for (int u = 0; u < kPasses; ++u) {
+        const int64_t i = lo + u * kMaxK + k;
+        g[u] = i < n ? src[i] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kPasses; ++u) {
+        const bool valid = lo + u * kMaxK + k < n;
+        cbv[u] = int((uint32_t(g[u]) >> 24) & 255u) * kBuckets + int(g[u] >> 60);
+        lead[u] = -1;
+        rank[u] = 0;
+        int gsize = 0;
+        unsigned long long pending = __ballot(valid);
+        while (pending) {
+            const int leader = __ffsll(pending) - 1;
+            const int cs = __builtin_amdgcn_readfirstlane(__shfl(cbv[u], leader, 64));
+            const bool mine = valid && cbv[u] == cs;
+            const unsigned long long mask = __ballot(mine);
+            if (mine) {
+                lead[u] = leader;
+                rank[u] = __popcll(mask & below);
+            }
+            if (lane == leader) gsize = __popcll(mask);
+            pending &= ~mask;
+        }
+        pos[u] = 0;
+        if (gsize > 0) pos[u] = atomicAdd(&cursor[cbv[u]], (unsigned long long)gsize);
+    }
+#pragma unroll
+    for (int u = 0; u < kPasses; ++u) {
+        const unsigned long long base = __shfl(pos[u], lead[u] < 0 ? 0 : lead[u], 64);
+        if (lead[u] >= 0) dst[start[cbv[u]] + base + rank[u]] = g[u];
+    }
+}
+
+// Update step, SSE, stopping rule and, in pruned runs, the sorted table and
+// colour order of the next iteration.  A pruned job gets K_j + S_j blocks of
+// kMaxK threads (S_j regrouping blocks), an unpruned one a single block.
+// Every table block derives the new centres from this iteration's cluster sums
 // in LDS; the job's block 0 alone writes the centres, the SSE trace and the
-// control block and clears the sums of the next iteration.  An empty cluster
-// keeps its centre: its global entry is neither rewritten nor changed, so the
-// other blocks may read it.
+// control block and clears the statistics of the next iteration.  An empty
+// cluster keeps its centre: its global entry is neither rewritten nor changed,
+// so the other blocks may read it.
 __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ jobs,
                                                   const int* __restrict__ map, int B)
 {
@@ -368,19 +490,23 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     if (meta->done) return;
     const int it = meta->cur_it;
     const int K = J.K;
+    unsigned long long* __restrict__ cur = gp(J.sums) + (it & 1) * kSumStride;
+    unsigned long long* __restrict__ nxt = gp(J.sums) + ((it + 1) & 1) * kSumStride;
+    if (a >= K) {
+        regroup(J, a - K, it, cur, cur + kSumCursor);
+        return;
+    }
     double* __restrict__ centers = gp(J.centers);
-    const unsigned long long* __restrict__ cur = gp(J.sums) + (it & 1) * 5 * kMaxK;
-    unsigned long long* __restrict__ nxt = gp(J.sums) + ((it + 1) & 1) * 5 * kMaxK;
     const int k = threadIdx.x;
     double t = 0.0;
     unsigned long long nk = 0;
     if (k < K) {
-        nk = cur[k];
+        nk = cur[kSumN + k];
         if (nk != 0) {
-            const unsigned long long s0 = cur[kMaxK + 3 * k + 0];
-            const unsigned long long s1 = cur[kMaxK + 3 * k + 1];
-            const unsigned long long s2 = cur[kMaxK + 3 * k + 2];
-            const unsigned long long q = cur[4 * kMaxK + k];
+            const unsigned long long s0 = cur[kSumS + 3 * k + 0];
+            const unsigned long long s1 = cur[kSumS + 3 * k + 1];
+            const unsigned long long s2 = cur[kSumS + 3 * k + 2];
+            const unsigned long long q = cur[kSumQ + k];
             const double dn = double(nk);
             c[3 * k + 0] = double(s0) / dn;
             c[3 * k + 1] = double(s1) / dn;
@@ -402,8 +528,23 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     }
     term[k] = t;  // zero for k >= K and for empty clusters
     wsum[k] = nk;
+    __shared__ unsigned long long cnt_red[2 * (kMaxK / 64)];
     if (a == 0) {
-        for (int j = k; j < 5 * kMaxK; j += blockDim.x) nxt[j] = 0ull;
+        for (int j = k; j < kSumStride; j += blockDim.x) nxt[j] = 0ull;
+        // distance and near-tie counts of this iteration's assignment blocks
+        const int nblk = int((J.n + J.chunk - 1) / J.chunk);
+        const unsigned long long* __restrict__ part = gp(J.part);
+        unsigned long long pn = 0, pt = 0;
+        for (int j = k; j < nblk; j += blockDim.x) {
+            pn += part[2 * j];
+            pt += part[2 * j + 1];
+        }
+        pn = wave_sum(pn);
+        pt = wave_sum(pt);
+        if ((k & 63) == 0) {
+            cnt_red[k >> 6] = pn;
+            cnt_red[(kMaxK / 64) + (k >> 6)] = pt;
+        }
     }
     __syncthreads();
     if (a == 0 && k < 64) {
@@ -417,6 +558,13 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
         sse = ordered_wave_sum(sse, t2);
         sse = ordered_wave_sum(sse, t3);
         if (k == 0) {
+            unsigned long long pn = 0, pt = 0;
+            for (int w = 0; w < kMaxK / 64; ++w) {
+                pn += cnt_red[w];
+                pt += cnt_red[(kMaxK / 64) + w];
+            }
+            meta->ndc += pn;
+            meta->near_ties += pt;
             meta->total_w = total;
             gp(J.trace)[it - 1] = sse;
             meta->iters = it;
@@ -467,8 +615,42 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     }
     if (b >= K) return;
     const int src = sidx[b];
-    gp(J.td)[a * kRow + b] = sdist[src];
-    gp(J.tm)[a * kRow + b] = uint8_t(src);
+    Rec e;
+    e.c0 = c[3 * src];
+    e.c1 = c[3 * src + 1];
+    e.c2 = c[3 * src + 2];
+    e.d = sdist[src];
+    gp(J.rec)[a * kRow + b] = e;
+    gp(J.tix)[a * kRow + b] = src;
+}
+
+// Pruned runs that grouped their colours: the final cluster of every colour
+// back into key order (the keys ascend, so a binary search finds a colour's
+// index).  Block b of job j takes the records [b chunk, (b + 1) chunk).
+__global__ void __launch_bounds__(kAssignThreads) k_unpermute(const JobDev* __restrict__ jobs,
+                                                              const int* __restrict__ map, int B)
+{
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int lb = blockIdx.x - map[jb];
+    const int iters = gp(J.meta)->iters;
+    if (!J.prune || iters < 2) return;
+    const int64_t n = J.n;
+    const uint64_t* __restrict__ g = gp(J.grp) + (iters & 1) * n;
+    const uint32_t* __restrict__ keys = gp(J.keys);
+    uint8_t* __restrict__ assign = gp(J.assign);
+    const int64_t lo = int64_t(lb) * J.chunk;
+    const int64_t hi = lo + J.chunk < n ? lo + J.chunk : n;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const uint32_t v = uint32_t(g[i]);
+        const uint32_t key = v & 0xffffffu;
+        int64_t l = 0, h = n;  // first index with keys[index] >= key
+        while (l < h) {
+            const int64_t m = (l + h) >> 1;
+            if (keys[m] < key) l = m + 1; else h = m;
+        }
+        if (l < n) assign[l] = uint8_t(v >> 24);
+    }
 }
 
 // Palette: floor(c + 0.5) clamped to [0, 255]; also clears the squared-error
@@ -520,7 +702,7 @@ __global__ void __launch_bounds__(kMaxK) k_kmeans_begin(const JobDev* __restrict
         for (int c = 0; c < 3; ++c)
             if (!__builtin_isfinite(J.centers[3 * k + c])) atomicOr(&bad, 1);
     }
-    for (int j = k; j < 10 * kMaxK; j += blockDim.x) gp(J.sums)[j] = 0;
+    for (int j = k; j < 2 * kSumStride; j += blockDim.x) gp(J.sums)[j] = 0;
     __syncthreads();
     if (k == 0) {
         meta->ndc = 0;
@@ -543,14 +725,31 @@ cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s)
     return CQ_OK;
 }
 
-// One iteration of every job that has not stopped.
-cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, int assign_blocks,
-                             int update_blocks, hipStream_t s)
+// One iteration of every job that has not stopped.  The first iteration is
+// a full search for every job; later ones search fully for the unpruned jobs
+// and walk the sorted table for the pruned ones.
+cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool first, int all_blocks,
+                             int full_blocks, int walk_blocks, int update_blocks, hipStream_t s)
 {
-    CQ_TIMED_LAUNCH("k_assign", s, k_assign<<<assign_blocks, kAssignThreads, 0, s>>>(jobs, maps + kMapAssign * (B + 1), B));
+    if (first) {
+        CQ_TIMED_LAUNCH("k_assign_full", s, k_assign<false><<<all_blocks, kAssignThreads, 0, s>>>(jobs, maps + kMapAssign * (B + 1), B));
+    } else {
+        if (full_blocks > 0)
+            CQ_TIMED_LAUNCH("k_assign_full", s, k_assign<false><<<full_blocks, kAssignThreads, 0, s>>>(jobs, maps + kMapAssignFull * (B + 1), B));
+        if (walk_blocks > 0)
+            CQ_TIMED_LAUNCH("k_assign_walk", s, k_assign<true><<<walk_blocks, kAssignThreads, 0, s>>>(jobs, maps + kMapAssignWalk * (B + 1), B));
+    }
     CQ_TIMED_LAUNCH("k_update", s, k_update<<<update_blocks, kMaxK, 0, s>>>(jobs, maps + kMapUpdate * (B + 1), B));
     return CQ_OK;
 }
+
+cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int blocks, hipStream_t s)
+{
+    CQ_TIMED_LAUNCH("k_unpermute", s, k_unpermute<<<blocks, kAssignThreads, 0, s>>>(jobs, maps + kMapAssign * (B + 1), B));
+    return CQ_OK;
+}
+
+int64_t regroup_blocks(int64_t n) { return (n + kScatterChunk - 1) / kScatterChunk; }
 
 cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s)
 {
@@ -558,12 +757,17 @@ cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s)
     return CQ_OK;
 }
 
-// Colours per assignment block.
+// Colours per assignment block (a multiple of the block size); the
+// environment variable CQ_ASSIGN_CHUNK overrides the default.
 int64_t assign_chunk(int64_t n)
 {
-    int64_t blocks = (n + kAssignThreads - 1) / kAssignThreads;
-    if (blocks <= 4096) return kAssignThreads;
-    const int64_t chunk = (n + 4095) / 4096;
+    static const int64_t forced = [] {
+        const char* e = getenv("CQ_ASSIGN_CHUNK");
+        return e ? int64_t(atoll(e)) : int64_t(0);
+    }();
+    int64_t chunk = 4 * kAssignThreads;
+    if (forced > 0) chunk = forced;
+    if ((n + chunk - 1) / chunk > kMaxAssignBlocks) chunk = (n + kMaxAssignBlocks - 1) / kMaxAssignBlocks;
     return (chunk + kAssignThreads - 1) / kAssignThreads * kAssignThreads;
 }
 
