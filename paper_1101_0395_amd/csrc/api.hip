@@ -24,7 +24,9 @@ cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s);
 cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, bool lds, hipStream_t s);
 cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s);
 cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool first, int all_blocks,
-                             int full_blocks, int walk_blocks, int update_blocks, hipStream_t s);
+                             int full_blocks, int walk_blocks, int update_blocks, bool regroup,
+                             int table_blocks, hipStream_t s);
+int regroup_period();
 cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s);
 int64_t assign_chunk(int64_t n);
 int64_t regroup_blocks(int64_t n);
@@ -332,6 +334,10 @@ static cq_status run_init(Batch& b)
 // suffices.
 static cq_status run_kmeans(Batch& b)
 {
+    // every job iterates in step with the launches, so the host knows which
+    // iterations regroup (the same rule as on the device)
+    const int period = regroup_period();
+    for (JobDev& J : b.h) J.regroup_period = period;
     int max_iters = 0;
     for (const JobDev& J : b.h) max_iters = J.max_iters > max_iters ? J.max_iters : max_iters;
     auto assign_blocks = [&](int j) {
@@ -345,6 +351,10 @@ static cq_status run_kmeans(Batch& b)
         const JobDev& J = b.h[j];
         return J.n <= J.K ? 0 : (J.prune ? J.K + int(regroup_blocks(J.n)) : 1);
     });
+    const int table_total = b.set_map(kMapUpdateTable, [&](int j) {
+        const JobDev& J = b.h[j];
+        return J.n <= J.K ? 0 : (J.prune ? J.K : 1);
+    });
     CQ_TRY(upload(b));
     CQ_TRY(launch_kmeans_begin(b.d_jobs(), b.B, b.s));
     if (assign_total == 0) return collect(b);
@@ -353,7 +363,8 @@ static cq_status run_kmeans(Batch& b)
         const int n_it = it + group - 1 <= max_iters ? group : max_iters - it + 1;
         for (int q = 0; q < n_it; ++q)
             CQ_TRY(launch_kmeans_iter(b.d_jobs(), b.d_maps(), b.B, it + q == 1, assign_total, full_total,
-                                      walk_total, update_total, b.s));
+                                      walk_total, update_total, regroup_at(it + q, period), table_total,
+                                      b.s));
         CQ_TRY(collect(b));
         bool all_done = true;
         for (const JobResult& r : b.res) all_done = all_done && r.done;

@@ -24,8 +24,12 @@ constexpr int kCompactWordsPerThread = 8;
 constexpr int kCompactWordsPerBlock = kCompactThreads * kCompactWordsPerThread;
 constexpr int kCompactBlocks = kBitmapWords / kCompactWordsPerBlock;  // 256
 
-// Per-colour chunk bookkeeping of the initialization.
-constexpr int kInitChunk = 1024;
+// Cooperative initialization: at most kInitMaxBlocks blocks of kInitThreads
+// threads per team.  Thread t of a block owns a run of R consecutive colours;
+// every round the block publishes a tagged value and each thread the sum of
+// its run (both for two round parities).
+constexpr int kInitMaxBlocks = 256;
+constexpr int kInitThreads = 512;
 
 // Sorted centre table: row stride (entries) independent of K.
 constexpr int kRow = kMaxK;
@@ -113,7 +117,7 @@ struct JobDev {
     unsigned long long CQ_GLOBAL* sums;
     uint32_t CQ_GLOBAL* blk;
     unsigned long long CQ_GLOBAL* part;  // per assignment block: distance count, near-tie count
-    uint64_t CQ_GLOBAL* vals;
+    uint64_t CQ_GLOBAL* vals;  // init: tagged block values, then the run sums
     uint32_t CQ_GLOBAL* d2;
     uint64_t CQ_GLOBAL* grp;  // k-means colour records, two buffers of n (shares d2's region)
     uint32_t CQ_GLOBAL* keys;
@@ -128,7 +132,29 @@ struct JobDev {
     int32_t init_blocks; // blocks of the team (0: no cooperative initialization)
     int32_t packed;      // image rows are contiguous and 4-byte aligned
     int32_t map_k;       // palette entries the pixel map searches
+    int32_t regroup_period;  // pruned runs: regroup the colours at iterations 1-4 and every this many
+    int32_t pad_;
 };
+
+// Pruned runs regroup their colour records (a counting sort by cluster and
+// distance bucket) in the update step of iterations 1-4 and of every
+// multiple of `period` after that; between regroupings the records keep their
+// order and only their cluster fields change.  Results never depend on the
+// order, only the speed of the sort-means passes does.
+__host__ __device__ __forceinline__ bool regroup_at(int it, int period)
+{
+    return it <= 4 || it % period == 0;
+}
+
+// Record buffer (0 or 1) that holds the colour records during iteration it:
+// the number of regroupings before it, modulo 2.
+__host__ __device__ __forceinline__ int record_buffer(int it, int period)
+{
+    const int before = it - 1;
+    int c = before < 4 ? before : 4;
+    if (before >= 5) c += before / period - 4 / period;
+    return c & 1;
+}
 
 // Read-only view of global memory that a kernel does not write: loads with a
 // wave-uniform address through it become scalar loads.
@@ -170,7 +196,8 @@ enum MapId {
     kMapAssign,      // every job with iterations (first iteration, final pass)
     kMapAssignFull,  // unpruned jobs (full searches after the first iteration)
     kMapAssignWalk,  // pruned jobs (sort-means passes)
-    kMapUpdate,
+    kMapUpdate,      // table blocks and regrouping blocks
+    kMapUpdateTable, // table blocks only (iterations without regrouping)
     kMapLut,
     kMapPix,
     kMapInit,
@@ -230,11 +257,14 @@ inline Layout make_layout(int64_t n_cap, bool with_colour_arrays)
     L.desc = o;     o = align256(o + desc_bytes(1));
     L.fixed_end = o;
     const size_t n = n_cap > 0 ? size_t(n_cap) : 0;
-    size_t nchunks = (n + kInitChunk - 1) / kInitChunk + 1;
-    if (nchunks < 2048) nchunks = 2048;  // also two rounds of up to 1024 cooperative blocks
-    L.chunks = o;   o = align256(o + sizeof(uint64_t) * nchunks);
-    // init: two uint32 per colour; k-means afterwards: two uint64 records per colour
-    L.d2 = o;       o = align256(o + sizeof(uint64_t) * 2 * n);
+    // init: tagged block values and per-thread run sums, both for two round parities
+    L.chunks = o;   o = align256(o + sizeof(uint64_t) * 2 * kInitMaxBlocks * (1 + kInitThreads));
+    // init: D^2 for two round parities, kInitThreads R entries per block
+    // (below n + kInitThreads per block); k-means afterwards: two uint64
+    // records per colour
+    const size_t d2_init = sizeof(uint32_t) * 2 * (n + size_t(kInitThreads + 1) * kInitMaxBlocks);
+    const size_t d2_km = sizeof(uint64_t) * 2 * n;
+    L.d2 = o;       o = align256(o + (d2_init > d2_km ? d2_init : d2_km));
     if (with_colour_arrays) {
         L.keys = o;   o = align256(o + sizeof(uint32_t) * n);
         L.counts = o; o = align256(o + sizeof(uint32_t) * n);
@@ -286,13 +316,34 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t& s)
     return z ^ (z >> 31);
 }
 
+// r mod T (T >= 1), exactly.  The quotient is estimated in FP64 twice (the
+// first estimate is within 2^12 / T + 1 of r / T, so the remainder left by it
+// has magnitude below 2^12 + 2 T, which the second estimate resolves to within
+// one step) and the integer remainder is corrected; anything outside [0, T)
+// after that falls back to the integer division, so the result never depends
+// on the estimates.
+__host__ __device__ __forceinline__ uint64_t mod_u64(uint64_t r, uint64_t T)
+{
+    if (T == 1) return 0;
+    const double dT = double(T);
+    const double q1d = double(r) / dT;  // below 2^63 for T >= 2
+    const uint64_t q1 = uint64_t(q1d);
+    int64_t m = int64_t(r - q1 * T);
+    const int64_t q2 = int64_t(__builtin_floor(double(m) / dT));
+    m -= q2 * int64_t(T);
+    if (m < 0) m += int64_t(T);
+    if (m >= int64_t(T)) m -= int64_t(T);
+    if (T >= (1ull << 52) || m < 0 || m >= int64_t(T)) return r % T;
+    return uint64_t(m);
+}
+
 // Uniform integer in [0, T), T >= 1: outputs below 2^64 mod T are redrawn.
 __device__ __forceinline__ uint64_t uniform_below(uint64_t& s, uint64_t T)
 {
-    const uint64_t reject_below = (0ull - T) % T;
+    const uint64_t reject_below = mod_u64(0ull - T, T);
     for (;;) {
         const uint64_t r = splitmix64(s);
-        if (r >= reject_below) return r % T;
+        if (r >= reject_below) return mod_u64(r, T);
     }
 }
 

@@ -84,6 +84,8 @@ __global__ void __launch_bounds__(kMaxK) k_init_begin(const JobDev* __restrict__
         gp(J.meta)->sync_error = 0;
         gp(J.meta)->pick_epoch = 0;
     }
+    // round tags of the cooperative initialization start below round 1
+    for (int t = k; t < 2 * kInitMaxBlocks; t += blockDim.x) gp(J.vals)[t] = 0ull;
     if (J.n > J.K || k >= J.K) return;
     if (k < J.n) {
         write_center(J.centers, k, gp(J.keys)[k]);
@@ -94,234 +96,281 @@ __global__ void __launch_bounds__(kMaxK) k_init_begin(const JobDev* __restrict__
 
 // ------------------------------------------------------------------------
 // Cooperative MMX / KPP: one launch runs all K rounds of every job, each job
-// with its own team of blocks.  Block b of a team owns the colours
-// [b C, (b+1) C).  Round j:
-//   1. every block lowers D^2 of its colours with the colour picked in round
-//      j-1 and publishes one value for its chunk: the sum of n D^2 (KPP; the
-//      counts alone in round 0) or the packed arg-max of (D^2, -index) (MMX);
-//   2. team barrier;
-//   3. every block reads the team's chunk values.  MMX: the largest packed
-//      value names the colour.  KPP: every block draws r = U(total) from its
-//      own copy of the splitmix64 stream and finds the chunk holding r; the
-//      block owning that chunk finds the colour inside its own chunk and
-//      publishes it with a release flag, which the other blocks wait for.
-// Chunk values and published picks are double-buffered by round parity, so a
-// block never rewrites what another block may still be reading.
-constexpr int kCoopThreads = 256;
-constexpr int kCoopMaxSegs = 4;    // up to 1024 blocks per team
-constexpr int kCoopLdsCap = 4096;  // colours per block kept in LDS (48 KiB)
-constexpr int kRun = kCoopLdsCap / kCoopThreads;  // colours per thread per pass of a chunk search
+// with its own team of G co-resident blocks.  Block b of a team owns the
+// colours [b C, (b+1) C); thread t of a block owns the run of R = C / 512
+// (rounded up) consecutive colours from t R on.  Round j (its pick is the same
+// in every block):
+//   1. every thread lowers D^2 of its run with the colour picked in round j-1;
+//      KPP: it publishes the sum of n D^2 over its run (the counts alone in
+//      round 0) and the new D^2, and the block publishes the sum over its
+//      colours tagged with j + 1 (bits 46-63) in its own slot; MMX: the block
+//      publishes the largest (D^2, -index) packed into 46 bits, tagged;
+//   2. every block waits until all G slots carry the tag j + 1 (a shared
+//      arrival counter would serialize G atomics on one address);
+//   3. MMX: the largest value names the colour.  KPP: r = U(total) from the
+//      block's own copy of the splitmix64 stream, then the block, the run and
+//      the colour whose inclusive prefix of n D^2 first exceeds r, read from
+//      what was published: every block finds the same colour, so no block
+//      waits for another to announce it.
+// Everything published is double-buffered by round parity: a block writes a
+// parity again only after every block has published the next round, that is
+// after all of them have finished reading it.  Runs are stored transposed
+// (entry u of thread t at u 256 + t), so the threads of a wave touch
+// consecutive words.
+constexpr int kCoopLdsCap = 8192;                    // colours per block kept in LDS (96 KiB)
+constexpr int kMaxRun = kCoopLdsCap / kInitThreads;  // run length when the colours fit in LDS
+constexpr int kTagShift = 46;      // KPP sums stay below 2^46 (2^28 pixels x 3 x 255^2)
+constexpr uint64_t kValMask = (1ull << kTagShift) - 1ull;
+constexpr uint32_t kIndexBits = 28;  // MMX: colour index below 2^28, D^2 below 2^18
 
-// kLds: the block's colours (key, count, D^2) stay in LDS for all rounds;
-// otherwise they are streamed from global memory every round (D^2 in d2buf).
+// Wave-wide inclusive prefix sum.
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t up = __shfl_up(v, d, 64);
+        if (lane >= d) v += up;
+    }
+    return v;
+}
+
+// One wave: the first of `cnt` weights (read through `get`) whose running
+// sum, started at *base, exceeds r; *base becomes the sum before it.  Returns
+// -1 if there is none.
+template <typename F>
+__device__ __forceinline__ int64_t wave_find(int64_t cnt, uint64_t r, uint64_t* base, F get)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t carry = *base;
+    for (int64_t c0 = 0; c0 < cnt; c0 += 64) {
+        const int64_t c = c0 + lane;
+        const uint64_t v = c < cnt ? get(c) : 0ull;
+        const uint64_t incl = carry + wave_incl_scan(v);
+        const unsigned long long hit = __ballot(c < cnt && incl > r);
+        if (hit) {
+            const int l = __ffsll(hit) - 1;
+            *base = __shfl(incl - v, l, 64);
+            return c0 + l;
+        }
+        carry = __shfl(incl, 63, 64);
+    }
+    return -1;
+}
+
+// kLds: the block's colours (key, count, D^2) stay in LDS for all rounds
+// (R <= kMaxRun); otherwise they are read from global memory every round.
 template <bool kLds>
-__global__ void __launch_bounds__(kCoopThreads) k_init_coop(const JobDev* __restrict__ jobs,
+__global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __restrict__ jobs,
                                                             const int* __restrict__ map, int B)
 {
     __shared__ uint64_t tmp[64];
-    __shared__ uint64_t s_r;
-    __shared__ int s_chunk;
-    __shared__ uint64_t s_before;
+    __shared__ uint64_t s_val[kInitMaxBlocks];
     __shared__ int64_t s_pick;
+    __shared__ uint32_t s_key;
+    __shared__ int s_ok;
     __shared__ uint32_t lkey[kLds ? kCoopLdsCap : 1];
     __shared__ uint32_t lcnt[kLds ? kCoopLdsCap : 1];
     __shared__ uint32_t ld2[kLds ? kCoopLdsCap : 1];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
-    const int G = J.init_blocks;  // team size, <= kCoopMaxSegs * kCoopThreads
+    const int G = J.init_blocks;  // team size, <= kInitMaxBlocks
     const int tb = blockIdx.x - map[jb];
     const uint32_t* __restrict__ keys = gp(J.keys);
     const uint32_t* __restrict__ counts = gp(J.counts);
     const int64_t n = J.n;
     const int K = J.K;
-    const int kpp = J.scheme == CQ_INIT_KMEANSPP;
+    const bool kpp = J.scheme == CQ_INIT_KMEANSPP;
     const int64_t C = J.init_C;
-    uint32_t* __restrict__ d2own = gp(J.d2);
-    uint64_t* __restrict__ vals = gp(J.vals);
+    const int R = int((C + kInitThreads - 1) / kInitThreads);  // run length
+    const int64_t Cb = int64_t(R) * kInitThreads;             // D^2 slots per block
+    uint32_t* __restrict__ d2g = gp(J.d2);                    // [2][G Cb], transposed runs
+    const int64_t dstride = int64_t(G) * Cb;
+    uint64_t* __restrict__ tags = gp(J.vals);                               // [2][kInitMaxBlocks]
+    uint64_t* __restrict__ rsum = gp(J.vals) + 2 * kInitMaxBlocks;          // [2][G kInitThreads]
+    const int64_t rstride = int64_t(G) * kInitThreads;
     Meta* __restrict__ meta = gp(J.meta);
     double* __restrict__ centers = gp(J.centers);
     const int64_t lo = int64_t(tb) * C;
     const int64_t hi = lo + C < n ? lo + C : n;
     const int mine_n = hi > lo ? int(hi - lo) : 0;
-    const int nseg = (G + kCoopThreads - 1) / kCoopThreads;
-    if (kLds) {
-        // all loads issued before the stores (mine_n <= kCoopLdsCap)
-        uint32_t kk[kRun], cc[kRun];
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    const int qlo = t * R;  // this thread's run, block-local colour indices
+    const int qn = mine_n - qlo >= R ? R : (mine_n > qlo ? mine_n - qlo : 0);
+    if constexpr (kLds) {
+        // coalesced loads, transposed stores (R <= kMaxRun)
+        uint32_t kk[kMaxRun], cc[kMaxRun];
 #pragma unroll
-        for (int r = 0; r < kRun; ++r) {
-            const int q = r * kCoopThreads + threadIdx.x;
-            kk[r] = q < mine_n ? keys[lo + q] : 0u;
-            cc[r] = q < mine_n ? counts[lo + q] : 0u;
+        for (int p = 0; p < kMaxRun; ++p) {
+            const int q = p * kInitThreads + t;
+            const bool in = p < R && q < mine_n;
+            kk[p] = in ? keys[lo + q] : 0u;
+            cc[p] = in ? counts[lo + q] : 0u;
         }
 #pragma unroll
-        for (int r = 0; r < kRun; ++r) {
-            const int q = r * kCoopThreads + threadIdx.x;
-            if (q < mine_n) {
-                lkey[q] = kk[r];
-                lcnt[q] = cc[r];
-                ld2[q] = 0xFFFFFFFFu;
+        for (int p = 0; p < kMaxRun; ++p) {
+            const int q = p * kInitThreads + t;
+            if (p < R && q < mine_n) {
+                const int x = (q % R) * kInitThreads + q / R;
+                lkey[x] = kk[p];
+                lcnt[x] = cc[p];
+                ld2[x] = 0xFFFFFFFFu;
             }
         }
     }
-    uint64_t rng = J.seed;  // the stream lives in thread 0 of every block
-    int64_t pick = -1;
+    uint64_t rng = J.seed;  // wave 0 draws; every block draws the same values
     int cr = 0, cg = 0, cb = 0;
     for (int j = 0; j < K; ++j) {
-        __syncthreads();  // the previous round's readers of tmp and s_* are done
         const int par = j & 1;
-        // 1. own chunk
-        uint64_t acc = 0;
-        if (j > 0 || kpp) {
-            // four colours per thread per step, loads first
-            for (int q0 = threadIdx.x; q0 < mine_n; q0 += 4 * kCoopThreads) {
-                uint32_t kq[4], cq[4], oq[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int q = q0 + u * kCoopThreads;
-                    const int64_t i = lo + q;
-                    const bool in = q < mine_n;
-                    kq[u] = in ? (kLds ? lkey[q] : keys[i]) : 0u;
-                    cq[u] = in ? (kLds ? lcnt[q] : counts[i]) : 0u;
-                    oq[u] = (in && j > 1) ? (kLds ? ld2[q] : d2own[i]) : 0xFFFFFFFFu;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int q = q0 + u * kCoopThreads;
-                    if (q >= mine_n) continue;
-                    const int64_t i = lo + q;
-                    if (j == 0) {
-                        acc += cq[u];
-                        continue;
-                    }
-                    int r, g, b;
-                    key_rgb(kq[u], r, g, b);
-                    const uint32_t d = dist_u32(r, g, b, cr, cg, cb);
-                    const uint32_t m = oq[u] < d ? oq[u] : d;
-                    if (kLds)
-                        ld2[q] = m;
-                    else
-                        d2own[i] = m;
-                    if (kpp) {
-                        acc += uint64_t(cq[u]) * m;
-                    } else {
-                        const uint64_t packed = (uint64_t(m) << 32) | uint64_t(0xFFFFFFFFu - uint32_t(i));
-                        acc = packed > acc ? packed : acc;
-                    }
-                }
-            }
-            acc = kpp ? wave_sum(acc) : wave_max(acc);
-            if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = acc;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                uint64_t v = tmp[0];
-                for (int w = 1; w < kCoopThreads / 64; ++w)
-                    v = kpp ? v + tmp[w] : (tmp[w] > v ? tmp[w] : v);
-                vals[int64_t(par) * G + tb] = v;
-            }
-        }
-        // 2. everyone has published
-        if (!grid_barrier(&meta->barrier, uint32_t(j + 1) * uint32_t(G), &meta->sync_error)) return;
-        const uint64_t* v_now = vals + int64_t(par) * G;
-        // 3. the same pick in every block
-        if (!kpp) {
-            if (j == 0) {
-                if (threadIdx.x == 0) s_pick = int64_t(uniform_below(rng, uint64_t(n)));
-                __syncthreads();
-                pick = s_pick;
-            } else {
-                uint64_t best = 0;
-                for (int c = threadIdx.x; c < G; c += kCoopThreads) best = v_now[c] > best ? v_now[c] : best;
-                best = wave_max(best);
-                if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = best;
-                __syncthreads();
-                for (int w = 0; w < kCoopThreads / 64; ++w) best = tmp[w] > best ? tmp[w] : best;
-                pick = int64_t(0xFFFFFFFFu - uint32_t(best & 0xFFFFFFFFull));
-                if (pick >= n) pick = 0;  // unreachable: every colour packs a non-zero value
-            }
+        __syncthreads();  // the previous round's readers of the shared values are done
+        if (!kpp && j == 0) {
+            if (t == 0) s_pick = int64_t(uniform_below(rng, uint64_t(n)));
         } else {
-            // exclusive prefix of the chunk values, one segment of 256 blocks at a time
-            uint64_t ex[kCoopMaxSegs], vv[kCoopMaxSegs];
-            uint64_t carry = 0;
+            // 1. own run
+            uint32_t* __restrict__ d2n = d2g + int64_t(par) * dstride + int64_t(tb) * Cb;
+            const uint32_t* __restrict__ d2o = d2g + int64_t(par ^ 1) * dstride + int64_t(tb) * Cb;
+            uint64_t acc = 0;
+            auto step = [&](int u, uint32_t key, uint32_t cnt, uint32_t old) -> uint32_t {
+                uint32_t m = 1u;  // KPP round 0: the weights are the counts
+                if (j > 0) {
+                    int r, g, b;
+                    key_rgb(key, r, g, b);
+                    const uint32_t d = dist_u32(r, g, b, cr, cg, cb);
+                    m = old < d ? old : d;
+                }
+                if (kpp) {
+                    acc += uint64_t(cnt) * m;
+                } else {
+                    const uint64_t packed = (uint64_t(m) << kIndexBits) |
+                                            uint64_t(((1u << kIndexBits) - 1u) - uint32_t(lo + qlo + u));
+                    acc = packed > acc ? packed : acc;
+                }
+                return m;
+            };
+            if constexpr (kLds) {
+                uint32_t kq[kMaxRun], cq[kMaxRun], oq[kMaxRun];
 #pragma unroll
-            for (int q = 0; q < kCoopMaxSegs; ++q) {
-                ex[q] = vv[q] = 0;
-                if (q >= nseg) continue;
-                const int c = q * kCoopThreads + threadIdx.x;
-                const uint64_t v = c < G ? v_now[c] : 0;
-                uint64_t tot = 0;
-                const uint64_t e = block_exclusive_scan<uint64_t>(v, tmp, &tot);
-                ex[q] = carry + e;
-                vv[q] = v;
-                carry += tot;
-            }
-            if (threadIdx.x == 0) {
-                s_r = carry ? uniform_below(rng, carry) : 0;
-                s_chunk = -1;
-            }
-            __syncthreads();
-            const uint64_t r = s_r;
+                for (int u = 0; u < kMaxRun; ++u) {
+                    const int x = u * kInitThreads + t;
+                    kq[u] = u < qn ? lkey[x] : 0u;
+                    cq[u] = u < qn ? lcnt[x] : 0u;
+                    oq[u] = (u < qn && j > 1) ? ld2[x] : 0xFFFFFFFFu;
+                }
 #pragma unroll
-            for (int q = 0; q < kCoopMaxSegs; ++q) {
-                if (vv[q] != 0 && ex[q] <= r && r < ex[q] + vv[q]) {
-                    s_chunk = q * kCoopThreads + threadIdx.x;
-                    s_before = ex[q];
+                for (int u = 0; u < kMaxRun; ++u) {
+                    if (u < qn) {
+                        const int x = u * kInitThreads + t;
+                        const uint32_t m = step(u, kq[u], cq[u], oq[u]);
+                        if (j > 0) ld2[x] = m;
+                        if (kpp) d2n[x] = m;
+                    }
+                }
+            } else {
+                for (int u = 0; u < qn; ++u) {
+                    const int x = u * kInitThreads + t;
+                    const int64_t i = lo + qlo + u;
+                    const uint32_t m = step(u, keys[i], counts[i], j > 1 ? d2o[x] : 0xFFFFFFFFu);
+                    d2n[x] = m;
                 }
             }
+            if (kpp) rsum[int64_t(par) * rstride + int64_t(tb) * kInitThreads + t] = acc;
+            acc = kpp ? wave_sum(acc) : wave_max(acc);
+            if (lane == 0) tmp[wave] = acc;
             __syncthreads();
-            int c = s_chunk;
-            const uint64_t rr = c >= 0 ? r - s_before : 0;
-            if (c < 0) c = 0;  // unreachable: the chunk values sum to carry > 0
-            if (c == tb) {
-                // the owner finds the colour in its own chunk: each thread takes
-                // a run of kRun consecutive colours per pass, loads first
-                if (threadIdx.x == 0) s_pick = -1;
-                uint64_t before = 0;
-                for (int pbase = 0; pbase < mine_n; pbase += kCoopThreads * kRun) {
-                    const int tlo = pbase + threadIdx.x * kRun;
-                    uint32_t cq[kRun], dq[kRun];
-#pragma unroll
-                    for (int q = 0; q < kRun; ++q) {
-                        const int qq = tlo + q;
-                        const bool in = qq < mine_n;
-                        cq[q] = in ? (kLds ? lcnt[qq] : counts[lo + qq]) : 0u;
-                        dq[q] = (in && j > 0) ? (kLds ? ld2[qq] : d2own[lo + qq]) : 1u;
+            if (t == 0) {
+                uint64_t v = tmp[0];
+                for (int w = 1; w < kInitThreads / 64; ++w) v = kpp ? v + tmp[w] : (tmp[w] > v ? tmp[w] : v);
+                __hip_atomic_store(&tags[par * kInitMaxBlocks + tb], (uint64_t(j + 1) << kTagShift) | v,
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            // 2. wave 0 waits for the team's tags, then (KPP) finds the pick
+            if (wave == 0) {
+                int ok = 1;
+                uint32_t spins = 0;
+                for (int c0 = 0; c0 < G; c0 += 64) {
+                    const int c = c0 + lane;
+                    if (c >= G) continue;
+                    uint64_t v;
+                    for (;;) {
+                        v = __hip_atomic_load(&tags[par * kInitMaxBlocks + c], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                        if ((v >> kTagShift) == uint64_t(j + 1)) break;
+                        if (__hip_atomic_load(&meta->sync_error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                            ++spins > kSpinLimit) {
+                            ok = 0;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
                     }
-                    uint64_t mine = 0;
-#pragma unroll
-                    for (int q = 0; q < kRun; ++q) mine += uint64_t(cq[q]) * dq[q];
-                    uint64_t tot = 0;
-                    const uint64_t off = before + block_exclusive_scan<uint64_t>(mine, tmp, &tot);
-                    if (mine != 0 && off <= rr && rr < off + mine) {
-                        uint64_t acc2 = off;
-#pragma unroll
-                        for (int q = 0; q < kRun; ++q) {
-                            acc2 += uint64_t(cq[q]) * dq[q];
-                            if (acc2 > rr) {
-                                s_pick = lo + tlo + q;
-                                break;
+                    s_val[c] = v & kValMask;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const bool all_ok = __ballot(ok == 0) == 0ull;
+                if (!all_ok && lane == 0)
+                    __hip_atomic_store(&meta->sync_error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0) s_ok = all_ok ? 1 : 0;
+                if (kpp && all_ok) {
+                    // 3. the block, the run and the colour holding r
+                    uint64_t total = 0;
+                    for (int c0 = 0; c0 < G; c0 += 64) total += wave_sum(c0 + lane < G ? s_val[c0 + lane] : 0ull);
+                    const uint64_t r = total ? uniform_below(rng, total) : 0ull;
+                    uint64_t base = 0;
+                    int64_t pk = -1;
+                    const int64_t c = wave_find(G, r, &base, [&](int64_t x) { return s_val[x]; });
+                    if (c >= 0) {
+                        const uint64_t* __restrict__ rs = rsum + int64_t(par) * rstride + c * kInitThreads;
+                        const int64_t tr = wave_find(kInitThreads, r, &base, [&](int64_t x) { return rs[x]; });
+                        if (tr >= 0) {
+                            const int64_t clo = c * C;
+                            const int64_t chi = clo + C < n ? clo + C : n;
+                            const int64_t rlo = clo + tr * R;
+                            const int64_t rn = chi - rlo < R ? chi - rlo : R;
+                            const uint32_t* __restrict__ d2c = d2g + int64_t(par) * dstride + c * Cb;
+                            // the colours of the run: weights and keys in one round trip
+                            uint64_t carry = base;
+                            for (int64_t x0 = 0; x0 < rn && pk < 0; x0 += 64) {
+                                const int64_t x = x0 + lane;
+                                const bool in = x < rn;
+                                const uint64_t w = in ? uint64_t(counts[rlo + x]) *
+                                                            (j == 0 ? 1u : d2c[x * kInitThreads + tr])
+                                                      : 0ull;
+                                const uint32_t kx = in ? keys[rlo + x] : 0u;
+                                const uint64_t incl = carry + wave_incl_scan(w);
+                                const unsigned long long hit = __ballot(in && incl > r);
+                                if (hit) {
+                                    const int l = __ffsll(hit) - 1;
+                                    pk = rlo + x0 + l;
+                                    if (lane == l) s_key = kx;
+                                }
+                                carry = __shfl(incl, 63, 64);
                             }
                         }
                     }
-                    before += tot;
+                    if (pk < 0 && lane == 0) s_key = keys[0];  // unreachable: r < total
+                    if (lane == 0) s_pick = pk >= 0 ? pk : 0;
                 }
+            }
+            __syncthreads();
+            if (!s_ok) return;
+            if (!kpp) {
+                uint64_t best = 0;
+                for (int c = t; c < G; c += kInitThreads) best = s_val[c] > best ? s_val[c] : best;
+                best = wave_max(best);
+                if (lane == 0) tmp[wave] = best;
                 __syncthreads();
-                if (threadIdx.x == 0) {
-                    int64_t pk = s_pick;
-                    if (pk < 0) pk = lo;  // unreachable when the weights are consistent
-                    meta->pick_slot[par] = pk;
-                    __hip_atomic_store(&meta->pick_epoch, uint32_t(j + 1), __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    s_pick = pk;
+                if (t == 0) {
+                    for (int w = 0; w < kInitThreads / 64; ++w) best = tmp[w] > best ? tmp[w] : best;
+                    const int64_t pk =
+                        int64_t(((1u << kIndexBits) - 1u) - uint32_t(best & ((1u << kIndexBits) - 1u)));
+                    s_pick = pk < n ? pk : 0;  // every colour packs a non-zero value, so pk < n
                 }
-                __syncthreads();
-                pick = s_pick;
-            } else {
-                if (!wait_flag(&meta->pick_epoch, uint32_t(j + 1), &meta->sync_error)) return;
-                pick = __hip_atomic_load(&meta->pick_slot[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        const uint32_t pick_key = keys[pick];
-        if (threadIdx.x == 0 && tb == 0) {
+        __syncthreads();
+        // a KPP pick arrives with its key
+        const uint32_t pick_key = kpp ? s_key : keys[s_pick];
+        if (t == 0 && tb == 0) {
             write_center(centers, j, pick_key);
             if (j == K - 1) meta->rng = rng;
         }
@@ -342,7 +391,7 @@ int coop_capacity()
             coop_ok &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(k_init_coop<true>), kCoopThreads, 0) == hipSuccess)
+                &per_cu, reinterpret_cast<const void*>(k_init_coop<true>), kInitThreads, 0) == hipSuccess)
             max_coop = cus * per_cu;
     }
     return max_coop;
@@ -358,11 +407,11 @@ int coop_team_blocks(int64_t n)
     }
     int64_t g = override_blocks > 0 ? override_blocks : (n + kCoopLdsCap - 1) / kCoopLdsCap;
     if (g < 1) g = 1;
-    if (g > kCoopMaxSegs * kCoopThreads) g = kCoopMaxSegs * kCoopThreads;
+    if (g > kInitMaxBlocks) g = kInitMaxBlocks;
     return int(g);
 }
 
-bool coop_fits_lds(int64_t C) { return C <= kCoopLdsCap; }
+bool coop_fits_lds(int64_t C) { return (C + kInitThreads - 1) / kInitThreads <= kMaxRun; }
 
 cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s)
 {
@@ -383,7 +432,7 @@ cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total,
     const void* fn = lds ? reinterpret_cast<const void*>(k_init_coop<true>)
                          : reinterpret_cast<const void*>(k_init_coop<false>);
     timer_begin("k_init_coop", s);
-    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(total), dim3(kCoopThreads), args, 0, s);
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(total), dim3(kInitThreads), args, 0, s);
     timer_end("k_init_coop", s);
     if (e != hipSuccess) {
         set_error("cooperative init launch failed: %s", hipGetErrorString(e));

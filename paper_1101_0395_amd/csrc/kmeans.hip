@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
     if (grouped != kSortMeans) return;
     if (lb == 0 && threadIdx.x == 0) meta->cur_it = it;
     unsigned long long* __restrict__ sums = gp(J.sums) + (it & 1) * kSumStride;
-    uint64_t* __restrict__ grp = gp(J.grp) + (it & 1) * n;
+    uint64_t* __restrict__ grp = gp(J.grp) + record_buffer(it, J.regroup_period) * n;
     for (int t = threadIdx.x; t < 5 * kMaxK; t += blockDim.x) bins[t] = 0ull;
     if (J.prune)
         for (int t = threadIdx.x; t < K * kBuckets; t += blockDim.x) ccount[t] = 0u;
@@ -372,21 +372,6 @@ __device__ __forceinline__ double u128_to_f64(unsigned __int128 v)
     return double(hi) * 18446744073709551616.0 + double(lo);
 }
 
-// acc + v[lane 0] + v[lane 1] + ... + v[lane 63], added one lane at a time in
-// lane order (every lane returns the same value).
-__device__ __forceinline__ double ordered_wave_sum(double acc, double v)
-{
-    const long long bits = __double_as_longlong(v);
-    const int lo = int(bits & 0xffffffffll), hi = int(bits >> 32);
-#pragma unroll
-    for (int l = 0; l < 64; ++l) {
-        const long long b = (long long)(unsigned)__builtin_amdgcn_readlane(lo, l) |
-                            ((long long)__builtin_amdgcn_readlane(hi, l) << 32);
-        acc += __longlong_as_double(b);
-    }
-    return acc;
-}
-
 // Regrouping of a pruned run: this iteration's colour records (new cluster
 // in bits 24-31, distance bucket in bits 60-63) are moved into the other
 // record buffer ordered by (cluster, bucket), a counting sort whose offsets
@@ -399,7 +384,9 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
 {
     constexpr int kPairs = kMaxK * kBuckets;
     constexpr int kPer = kPairs / kMaxK;  // pairs per thread in the scan
-    __shared__ uint32_t start[kPairs];
+    // pair cb lives at cb + cb / kPer: each thread's kPer pairs are consecutive
+    // and the threads' runs start in different LDS banks
+    __shared__ uint32_t start[kPairs + kPairs / kPer];
     __shared__ uint32_t scan_tmp[64];
     const int k = threadIdx.x;
     const int lane = k & 63;
@@ -415,13 +402,14 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
     uint32_t run = block_exclusive_scan<uint32_t>(tsum, scan_tmp, nullptr);
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-        start[k * kPer + u] = run;
+        start[k * (kPer + 1) + u] = run;
         run += c[u];
     }
     __syncthreads();
     const int64_t n = J.n;
-    const uint64_t* __restrict__ src = gp(J.grp) + (it & 1) * n;
-    uint64_t* __restrict__ dst = gp(J.grp) + ((it + 1) & 1) * n;
+    const int rb = record_buffer(it, J.regroup_period);
+    const uint64_t* __restrict__ src = gp(J.grp) + rb * n;
+    uint64_t* __restrict__ dst = gp(J.grp) + (rb ^ 1) * n;
     const int64_t lo = int64_t(s) * kScatterChunk;
     const unsigned long long below = (1ull << lane) - 1ull;
     // every record of the block is loaded and ranked within its wave's group of
@@ -462,7 +450,7 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
 #pragma unroll
     for (int u = 0; u < kPasses; ++u) {
         const unsigned long long base = __shfl(pos[u], lead[u] < 0 ? 0 : lead[u], 64);
-        if (lead[u] >= 0) dst[start[cbv[u]] + base + rank[u]] = g[u];
+        if (lead[u] >= 0) dst[start[cbv[u] + cbv[u] / kPer] + base + rank[u]] = g[u];
     }
 }
 
@@ -493,7 +481,7 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     unsigned long long* __restrict__ cur = gp(J.sums) + (it & 1) * kSumStride;
     unsigned long long* __restrict__ nxt = gp(J.sums) + ((it + 1) & 1) * kSumStride;
     if (a >= K) {
-        regroup(J, a - K, it, cur, cur + kSumCursor);
+        if (regroup_at(it, J.regroup_period)) regroup(J, a - K, it, cur, cur + kSumCursor);
         return;
     }
     double* __restrict__ centers = gp(J.centers);
@@ -548,16 +536,12 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     }
     __syncthreads();
     if (a == 0 && k < 64) {
-        // SSE in ascending cluster order, walked through the registers of one
-        // wave (lane l holds the terms of clusters l, l+64, l+128, l+192)
-        const double t0 = term[k], t1 = term[k + 64], t2 = term[k + 128], t3 = term[k + 192];
         const unsigned long long total = wave_sum(wsum[k] + wsum[k + 64] + wsum[k + 128] + wsum[k + 192]);
-        double sse = 0.0;
-        sse = ordered_wave_sum(sse, t0);
-        sse = ordered_wave_sum(sse, t1);
-        sse = ordered_wave_sum(sse, t2);
-        sse = ordered_wave_sum(sse, t3);
         if (k == 0) {
+            // SSE in ascending cluster order, one addition at a time
+            double sse = 0.0;
+#pragma unroll 16
+            for (int q = 0; q < kMaxK; ++q) sse += term[q];
             unsigned long long pn = 0, pt = 0;
             for (int w = 0; w < kMaxK / 64; ++w) {
                 pn += cnt_red[w];
@@ -587,34 +571,44 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     if (!J.prune) return;
     // row a of the table for the next iteration: the centres ordered by
     // (distance from c_a, index), a itself first (key -1); a bitonic sort of
-    // kMaxK (key, index) pairs in LDS, slots past K keyed +inf
+    // kMaxK (key, index) pairs, slots past K keyed +inf.  Each thread holds
+    // one pair; partners closer than a wave are read with shuffles, the three
+    // stages with stride 64 or 128 go through LDS.
     const int b = k;
     double d = 0.0;
     if (b < K)
         d = dist_f64(c[3 * a], c[3 * a + 1], c[3 * a + 2], c[3 * b], c[3 * b + 1], c[3 * b + 2]);
-    key[b] = b >= K ? __builtin_inf() : (b == a ? -1.0 : d);
-    sidx[b] = b;
     sdist[b] = d;
-    __syncthreads();
+    double mk = b >= K ? __builtin_inf() : (b == a ? -1.0 : d);
+    int mi = b;
     for (int size = 2; size <= kMaxK; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const int partner = b ^ stride;
-            const double mk = key[b], pk = key[partner];
-            const int mi = sidx[b], pi = sidx[partner];
+            double pk;
+            int pi;
+            if (stride >= 64) {
+                __syncthreads();  // earlier readers of key / sidx are done
+                key[b] = mk;
+                sidx[b] = mi;
+                __syncthreads();
+                pk = key[b ^ stride];
+                pi = sidx[b ^ stride];
+            } else {
+                pk = __shfl_xor(mk, stride, 64);
+                pi = __shfl_xor(mi, stride, 64);
+            }
             const bool partner_less = pk < mk || (pk == mk && pi < mi);
             const bool ascending = (b & size) == 0;
-            const bool lower = b < partner;
+            const bool lower = (b & stride) == 0;
             const bool take = (lower == ascending) ? partner_less : !partner_less;
-            __syncthreads();
             if (take) {
-                key[b] = pk;
-                sidx[b] = pi;
+                mk = pk;
+                mi = pi;
             }
-            __syncthreads();
         }
     }
+    __syncthreads();  // sdist complete
     if (b >= K) return;
-    const int src = sidx[b];
+    const int src = mi;
     Rec e;
     e.c0 = c[3 * src];
     e.c1 = c[3 * src + 1];
@@ -636,7 +630,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_unpermute(const JobDev* __re
     const int iters = gp(J.meta)->iters;
     if (!J.prune || iters < 2) return;
     const int64_t n = J.n;
-    const uint64_t* __restrict__ g = gp(J.grp) + (iters & 1) * n;
+    const uint64_t* __restrict__ g = gp(J.grp) + record_buffer(iters, J.regroup_period) * n;
     const uint32_t* __restrict__ keys = gp(J.keys);
     uint8_t* __restrict__ assign = gp(J.assign);
     const int64_t lo = int64_t(lb) * J.chunk;
@@ -729,7 +723,8 @@ cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s)
 // a full search for every job; later ones search fully for the unpruned jobs
 // and walk the sorted table for the pruned ones.
 cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool first, int all_blocks,
-                             int full_blocks, int walk_blocks, int update_blocks, hipStream_t s)
+                             int full_blocks, int walk_blocks, int update_blocks, bool regroup,
+                             int table_blocks, hipStream_t s)
 {
     if (first) {
         CQ_TIMED_LAUNCH("k_assign_full", s, k_assign<false><<<all_blocks, kAssignThreads, 0, s>>>(jobs, maps + kMapAssign * (B + 1), B));
@@ -739,7 +734,10 @@ cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool fi
         if (walk_blocks > 0)
             CQ_TIMED_LAUNCH("k_assign_walk", s, k_assign<true><<<walk_blocks, kAssignThreads, 0, s>>>(jobs, maps + kMapAssignWalk * (B + 1), B));
     }
-    CQ_TIMED_LAUNCH("k_update", s, k_update<<<update_blocks, kMaxK, 0, s>>>(jobs, maps + kMapUpdate * (B + 1), B));
+    if (regroup)
+        CQ_TIMED_LAUNCH("k_update", s, k_update<<<update_blocks, kMaxK, 0, s>>>(jobs, maps + kMapUpdate * (B + 1), B));
+    else
+        CQ_TIMED_LAUNCH("k_update", s, k_update<<<table_blocks, kMaxK, 0, s>>>(jobs, maps + kMapUpdateTable * (B + 1), B));
     return CQ_OK;
 }
 
@@ -750,6 +748,18 @@ cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int block
 }
 
 int64_t regroup_blocks(int64_t n) { return (n + kScatterChunk - 1) / kScatterChunk; }
+
+// Iterations between regroupings of the colour records (after the first
+// four); the environment variable CQ_REGROUP_PERIOD overrides the default.
+int regroup_period()
+{
+    static const int p = [] {
+        const char* e = getenv("CQ_REGROUP_PERIOD");
+        const int v = e ? atoi(e) : 0;
+        return v > 0 ? v : 1;
+    }();
+    return p;
+}
 
 cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s)
 {
