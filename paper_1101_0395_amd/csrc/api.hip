@@ -27,6 +27,7 @@ cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool fi
                              int full_blocks, int walk_blocks, int update_blocks, bool regroup,
                              int table_blocks, hipStream_t s);
 int regroup_period();
+int update_table_blocks(int K, int prune);
 cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s);
 int64_t assign_chunk(int64_t n);
 int64_t regroup_blocks(int64_t n);
@@ -349,11 +350,11 @@ static cq_status run_kmeans(Batch& b)
     const int walk_total = b.set_map(kMapAssignWalk, [&](int j) { return b.h[j].prune ? assign_blocks(j) : 0; });
     const int update_total = b.set_map(kMapUpdate, [&](int j) {
         const JobDev& J = b.h[j];
-        return J.n <= J.K ? 0 : (J.prune ? J.K + int(regroup_blocks(J.n)) : 1);
+        return J.n <= J.K ? 0 : update_table_blocks(J.K, J.prune) + (J.prune ? int(regroup_blocks(J.n)) : 0);
     });
     const int table_total = b.set_map(kMapUpdateTable, [&](int j) {
         const JobDev& J = b.h[j];
-        return J.n <= J.K ? 0 : (J.prune ? J.K : 1);
+        return J.n <= J.K ? 0 : update_table_blocks(J.K, J.prune);
     });
     CQ_TRY(upload(b));
     CQ_TRY(launch_kmeans_begin(b.d_jobs(), b.B, b.s));

@@ -379,15 +379,18 @@ __device__ __forceinline__ double u128_to_f64(unsigned __int128 v)
 // inside a pair is whatever the atomics give; no result depends on it.  Block
 // s of the job's regrouping blocks takes the records
 // [s kScatterChunk, (s + 1) kScatterChunk).
+constexpr int kPairs = kMaxK * kBuckets;
+constexpr int kPairsPer = kPairs / kMaxK;  // pairs per thread in the regrouping scan
+// LDS words of the regrouping offsets: pair cb lives at cb + cb / kPairsPer,
+// so each thread's pairs are consecutive and the threads' runs start in
+// different banks
+constexpr int kStartWords = kPairs + kPairs / kPairsPer;
+
 __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const unsigned long long* __restrict__ cur,
-                                        unsigned long long* __restrict__ cursor)
+                                        unsigned long long* __restrict__ cursor, uint32_t* start,
+                                        uint32_t* scan_tmp)
 {
-    constexpr int kPairs = kMaxK * kBuckets;
-    constexpr int kPer = kPairs / kMaxK;  // pairs per thread in the scan
-    // pair cb lives at cb + cb / kPer: each thread's kPer pairs are consecutive
-    // and the threads' runs start in different LDS banks
-    __shared__ uint32_t start[kPairs + kPairs / kPer];
-    __shared__ uint32_t scan_tmp[64];
+    constexpr int kPer = kPairsPer;
     const int k = threadIdx.x;
     const int lane = k & 63;
     const int npairs = J.K * kBuckets;
@@ -454,23 +457,123 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
     }
 }
 
+// (key, index) order of table entries.
+__device__ __forceinline__ bool entry_less(double k1, int i1, double k2, int i2)
+{
+    return k1 < k2 || (k1 == k2 && i1 < i2);
+}
+
+// Row `a` of the table for the next iteration, built by one block of kMaxK
+// threads: the centres ordered by (distance from c_a, index), a itself first
+// (key -1), slots past K keyed +inf.  The centres move little from one
+// iteration to the next, so the row starts from its previous order
+// (iteration 1: index order): if that is still sorted nothing moves,
+// otherwise up to kFixPasses rounds of odd-even transposition repair it, and
+// a full bitonic sort handles whatever is left.
+constexpr int kFixPasses = 8;
+
+__device__ __forceinline__ void build_row(const JobDev& J, int a, int K, int it, const double* c, double* key,
+                                          int* sidx)
+{
+    const int e = threadIdx.x;
+    Rec* __restrict__ row = gp(J.rec) + a * kRow;
+    int32_t* __restrict__ trow = gp(J.tix) + a * kRow;
+    const int f = (it > 1 && e < K) ? trow[e] : e;  // previous order, read before this block rewrites it
+    double mk = f >= K ? __builtin_inf()
+                       : (f == a ? -1.0 : dist_f64(c[3 * a], c[3 * a + 1], c[3 * a + 2], c[3 * f], c[3 * f + 1], c[3 * f + 2]));
+    int mi = f;
+    key[e] = mk;
+    sidx[e] = mi;
+    __syncthreads();
+    bool unsorted = e + 1 < kMaxK && entry_less(key[e + 1], sidx[e + 1], mk, mi);
+    int pass = 0;
+    while (__syncthreads_or(unsorted) && pass < kFixPasses) {
+        // even pairs (2i, 2i+1), then odd pairs (2i+1, 2i+2)
+#pragma unroll
+        for (int phase = 0; phase < 2; ++phase) {
+            const bool low = ((e - phase) & 1) == 0;  // e is the first of its pair
+            const int partner = low ? e + 1 : e - 1;
+            const bool has = low ? (e + 1 < kMaxK && e >= phase) : (e >= 1 + phase);
+            double pk = mk;
+            int pi = mi;
+            if (has) {
+                pk = key[partner];
+                pi = sidx[partner];
+            }
+            __syncthreads();
+            if (has) {
+                const bool pless = entry_less(pk, pi, mk, mi);
+                if (low ? pless : !pless) {
+                    mk = pk;
+                    mi = pi;
+                }
+            }
+            key[e] = mk;
+            sidx[e] = mi;
+            __syncthreads();
+        }
+        unsorted = e + 1 < kMaxK && entry_less(key[e + 1], sidx[e + 1], mk, mi);
+        ++pass;
+    }
+    if (__syncthreads_or(unsorted)) {
+        // bitonic sort; partners closer than a wave are read with shuffles
+        for (int size = 2; size <= kMaxK; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                double pk;
+                int pi;
+                if (stride >= 64) {
+                    __syncthreads();
+                    key[e] = mk;
+                    sidx[e] = mi;
+                    __syncthreads();
+                    pk = key[e ^ stride];
+                    pi = sidx[e ^ stride];
+                } else {
+                    pk = __shfl_xor(mk, stride, 64);
+                    pi = __shfl_xor(mi, stride, 64);
+                }
+                const bool partner_less = entry_less(pk, pi, mk, mi);
+                const bool ascending = (e & size) == 0;
+                const bool lower = (e & stride) == 0;
+                const bool take = (lower == ascending) ? partner_less : !partner_less;
+                if (take) {
+                    mk = pk;
+                    mi = pi;
+                }
+            }
+        }
+    }
+    if (e >= K) return;
+    Rec r;
+    r.c0 = c[3 * mi];
+    r.c1 = c[3 * mi + 1];
+    r.c2 = c[3 * mi + 2];
+    r.d = mi == a ? 0.0 : mk;
+    row[e] = r;
+    trow[e] = mi;
+}
+
 // Update step, SSE, stopping rule and, in pruned runs, the sorted table and
-// colour order of the next iteration.  A pruned job gets K_j + S_j blocks of
-// kMaxK threads (S_j regrouping blocks), an unpruned one a single block.
-// Every table block derives the new centres from this iteration's cluster sums
-// in LDS; the job's block 0 alone writes the centres, the SSE trace and the
-// control block and clears the statistics of the next iteration.  An empty
-// cluster keeps its centre: its global entry is neither rewritten nor changed,
-// so the other blocks may read it.
+// colour order of the next iteration.  A pruned job gets K_j table blocks
+// (one per row) followed by its regrouping blocks; an unpruned job a single
+// block.  Every table block derives the new
+// centres from this iteration's cluster sums in LDS; the job's block 0 alone
+// writes the centres, the SSE trace and the control block and clears the
+// statistics of the next iteration.  An empty cluster keeps its centre: its
+// global entry is neither rewritten nor changed, so the other blocks may read
+// it.
+__device__ __forceinline__ int table_blocks(const JobDev& J)
+{
+    return J.prune ? J.K : 1;
+}
+
 __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ jobs,
                                                   const int* __restrict__ map, int B)
 {
-    __shared__ double c[3 * kMaxK];
-    __shared__ double term[kMaxK];
-    __shared__ unsigned long long wsum[kMaxK];
-    __shared__ double key[kMaxK];
-    __shared__ double sdist[kMaxK];
-    __shared__ int sidx[kMaxK];
+    // one LDS buffer, used either by a table block or by a regrouping block
+    constexpr int kTableWords = 2 * (3 * kMaxK + kMaxK + kMaxK + 2 * (kMaxK / 64) + kMaxK) + kMaxK;
+    constexpr int kLdsWords = kTableWords > kStartWords + 64 ? kTableWords : kStartWords + 64;
+    __shared__ __attribute__((aligned(16))) uint32_t smem[kLdsWords];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int a = blockIdx.x - map[jb];
@@ -480,10 +583,18 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     const int K = J.K;
     unsigned long long* __restrict__ cur = gp(J.sums) + (it & 1) * kSumStride;
     unsigned long long* __restrict__ nxt = gp(J.sums) + ((it + 1) & 1) * kSumStride;
-    if (a >= K) {
-        if (regroup_at(it, J.regroup_period)) regroup(J, a - K, it, cur, cur + kSumCursor);
+    const int ntab = table_blocks(J);
+    if (a >= ntab) {
+        if (regroup_at(it, J.regroup_period))
+            regroup(J, a - ntab, it, cur, cur + kSumCursor, smem, smem + kStartWords);
         return;
     }
+    double* c = reinterpret_cast<double*>(smem);
+    double* term = c + 3 * kMaxK;
+    unsigned long long* wsum = reinterpret_cast<unsigned long long*>(term + kMaxK);
+    unsigned long long* cnt_red = wsum + kMaxK;
+    double* key = reinterpret_cast<double*>(cnt_red + 2 * (kMaxK / 64));
+    int* sidx = reinterpret_cast<int*>(key + kMaxK);
     double* __restrict__ centers = gp(J.centers);
     const int k = threadIdx.x;
     double t = 0.0;
@@ -516,7 +627,6 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     }
     term[k] = t;  // zero for k >= K and for empty clusters
     wsum[k] = nk;
-    __shared__ unsigned long long cnt_red[2 * (kMaxK / 64)];
     if (a == 0) {
         for (int j = k; j < kSumStride; j += blockDim.x) nxt[j] = 0ull;
         // distance and near-tie counts of this iteration's assignment blocks
@@ -569,53 +679,7 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
         }
     }
     if (!J.prune) return;
-    // row a of the table for the next iteration: the centres ordered by
-    // (distance from c_a, index), a itself first (key -1); a bitonic sort of
-    // kMaxK (key, index) pairs, slots past K keyed +inf.  Each thread holds
-    // one pair; partners closer than a wave are read with shuffles, the three
-    // stages with stride 64 or 128 go through LDS.
-    const int b = k;
-    double d = 0.0;
-    if (b < K)
-        d = dist_f64(c[3 * a], c[3 * a + 1], c[3 * a + 2], c[3 * b], c[3 * b + 1], c[3 * b + 2]);
-    sdist[b] = d;
-    double mk = b >= K ? __builtin_inf() : (b == a ? -1.0 : d);
-    int mi = b;
-    for (int size = 2; size <= kMaxK; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            double pk;
-            int pi;
-            if (stride >= 64) {
-                __syncthreads();  // earlier readers of key / sidx are done
-                key[b] = mk;
-                sidx[b] = mi;
-                __syncthreads();
-                pk = key[b ^ stride];
-                pi = sidx[b ^ stride];
-            } else {
-                pk = __shfl_xor(mk, stride, 64);
-                pi = __shfl_xor(mi, stride, 64);
-            }
-            const bool partner_less = pk < mk || (pk == mk && pi < mi);
-            const bool ascending = (b & size) == 0;
-            const bool lower = (b & stride) == 0;
-            const bool take = (lower == ascending) ? partner_less : !partner_less;
-            if (take) {
-                mk = pk;
-                mi = pi;
-            }
-        }
-    }
-    __syncthreads();  // sdist complete
-    if (b >= K) return;
-    const int src = mi;
-    Rec e;
-    e.c0 = c[3 * src];
-    e.c1 = c[3 * src + 1];
-    e.c2 = c[3 * src + 2];
-    e.d = sdist[src];
-    gp(J.rec)[a * kRow + b] = e;
-    gp(J.tix)[a * kRow + b] = src;
+    build_row(J, a, K, it, c, key, sidx);
 }
 
 // Pruned runs that grouped their colours: the final cluster of every colour
@@ -748,6 +812,9 @@ cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int block
 }
 
 int64_t regroup_blocks(int64_t n) { return (n + kScatterChunk - 1) / kScatterChunk; }
+
+// Update blocks of a job before its regrouping blocks.
+int update_table_blocks(int K, int prune) { return prune ? K : 1; }
 
 // Iterations between regroupings of the colour records (after the first
 // four); the environment variable CQ_REGROUP_PERIOD overrides the default.
