@@ -36,12 +36,68 @@ FLOP_PER_EVAL = 8              # 3 sub, 3 mul, 2 add per FP64 squared distance
 ROOFLINE_KERNEL = "k_assign_walk"  # sort-means nearest-centre passes, FP64 VALU
 
 
+def measure_large(cq, synth, torch, dev, reps=5):
+    """Histogram and pixel-map bandwidth on one 4096 x 4096 stand-in (seed 42),
+    K = 256: each kernel timed with HIP events over `reps` calls; the bytes
+    are the algorithmic ones (image read; colours and counts or index and
+    RGB images written)."""
+    H4 = W4 = 4096
+    img = torch.from_numpy(synth.smooth_field_blobs(H4, W4, 42)).to(dev)
+    ws = cq.Workspace(H4, W4, K, dev)
+    keys, counts = cq.cq_histogram(img, ws)  # warm-up
+    n = int(keys.numel())
+
+    per_kernel = {}
+
+    def timed(names, fn):
+        total = 0.0
+        for name in names:
+            t = cq.KernelTimer(name, reps)
+            t.enable()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            launches, ms = t.read()
+            t.disable()
+            per_kernel[name] = 1e3 * ms / max(1, launches)
+            total += ms / max(1, launches)
+        if total <= 0.0:
+            raise RuntimeError(f"no launches of {names} were timed")
+        return total
+
+    hist_ms = timed(["k_hist_buckets", "k_hist_colscan", "k_hist_scatter", "k_hist_count", "k_hist_emit"],
+                    lambda: cq.cq_histogram(img, ws))
+    centers, _ = cq.cq_init(keys, counts, K, cq.INIT_KMEANSPP, 42, ws)
+    km = cq.cq_kmeans(keys, counts, centers, 3, TOL, True, ws)  # a palette to map to
+    cq.cq_map(img, keys, counts, km.palette, ws)
+    map_ms = timed(["k_map"], lambda: cq.cq_map(img, keys, counts, km.palette, ws))
+    lut_ms = timed(["k_lut"], lambda: cq.cq_map(img, keys, counts, km.palette, ws))
+    hist_bytes = 3 * H4 * W4 + 8 * n
+    map_bytes = 3 * H4 * W4 + H4 * W4 + 3 * H4 * W4
+    hist_gbs = hist_bytes / (hist_ms * 1e-3) / 1e9
+    map_gbs = map_bytes / (map_ms * 1e-3) / 1e9
+    return {
+        "workload": "one 4096x4096 stand-in (seed 42), K=256",
+        "unique_colours": n,
+        "histogram": {"us": 1e3 * hist_ms, "bytes": hist_bytes, "GB/s": hist_gbs,
+                      "frac_of_hbm_peak": hist_gbs / PEAK_HBM_GBS},
+        "pixel_map": {"us": 1e3 * map_ms, "bytes": map_bytes, "GB/s": map_gbs,
+                      "frac_of_hbm_peak": map_gbs / PEAK_HBM_GBS},
+        "colour_table_us": 1e3 * lut_ms,
+        "kernel_us": per_kernel,
+    }
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 4096x4096 histogram/map bandwidth figures")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="finish with plain device-to-device copies of this many MiB (a known-size kernel "
+                         "for scaling memory counters)")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0,
                     help="approximate CPU seconds for the oracle baseline sample")
     return ap.parse_args()
@@ -154,6 +210,9 @@ def main():
         },
     }
 
+    if not args.no_large:
+        line["hbm_bound_steps_4096"] = measure_large(cq, synth, torch, dev)
+
     if not args.no_cpu_baseline:
         import oracle
 
@@ -179,6 +238,13 @@ def main():
         line["mse_rel_err_max"] = max(mse_err)
         line["mse_rel_err_mean"] = float(np.mean(mse_err))
     print(json.dumps(line), flush=True)
+
+    if args.calibration_copy_mib > 0:
+        src = torch.ones(args.calibration_copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -23,8 +23,7 @@
  *    (dx*dx + dy*dy) + dz*dz without contraction.
  *  - Errors: a non-zero cq_status is returned and cq_last_error() describes it.
  *    No call aborts the process and no C++ exception crosses the ABI.  Outputs
- *    are unspecified after an error.  After CQ_EDEVICE the workspace must be
- *    prepared again with cq_workspace_prepare.
+ *    are unspecified after an error.
  *  - Calls that share one workspace must be serialized (same stream or
  *    external synchronization).
  */
@@ -74,18 +73,19 @@ typedef struct {
  * invalid sizes. */
 size_t cq_workspace_bytes(int32_t H, int32_t W, int32_t K);
 
-/* Prepare a fresh workspace: clears the regions that must be zero between
- * calls (the 2^24-entry colour count table and its presence bitmap).  Must be
- * called once before the first use of a workspace and after any CQ_EDEVICE.
- * The library leaves those regions cleared when a call returns CQ_OK or
- * CQ_ECAPACITY.  `ws` must be 256-byte aligned. */
+/* Check a workspace before its first use (size and 256-byte alignment).
+ * No region of the workspace has to hold particular values between calls, so
+ * nothing is written; calling it again, for instance after CQ_EDEVICE, is
+ * harmless. */
 cq_status cq_workspace_prepare(void* ws, size_t ws_bytes, void* stream);
 
 /* Section 2.2 items 1-2: the unique colours of the image with their pixel
  * counts.  Writes keys[0..N') in ascending order and counts[0..N') (the
  * weights before normalization by H W).  *n_unique (host) receives N'; if
  * N' > capacity only the first `capacity` entries are written and
- * CQ_ECAPACITY is returned.  Synchronizes `stream`. */
+ * CQ_ECAPACITY is returned.  The workspace must hold cq_workspace_bytes(H, W,
+ * K) for this image (it stages the pixels partitioned by key range).
+ * Synchronizes `stream`. */
 cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
                        uint32_t* keys, uint32_t* counts, int64_t capacity,
                        int64_t* n_unique /* host */, void* ws, size_t ws_bytes, void* stream);

@@ -13,7 +13,6 @@
 namespace cq {
 
 // kernels launched from the other translation units
-cq_status launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 int hist_blocks(int64_t npix);
 cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_hist_blocks, hipStream_t s);
 int coop_capacity();
@@ -184,19 +183,21 @@ struct Batch {
 // Points the workspace-backed fields of a job at one slot with layout L.
 static void bind_slot(JobDev& J, char* slot, const Layout& L)
 {
-    J.tbl = to_dev(reinterpret_cast<uint32_t*>(slot + L.tbl));
-    J.bitmap = to_dev(reinterpret_cast<uint32_t*>(slot + L.bitmap));
     J.lut = to_dev(reinterpret_cast<uint8_t*>(slot + L.lut));
     J.meta = to_dev(reinterpret_cast<Meta*>(slot + L.meta));
     J.trace = to_dev(reinterpret_cast<double*>(slot + L.trace));
     J.rec = to_dev(reinterpret_cast<Rec*>(slot + L.rec));
     J.tix = to_dev(reinterpret_cast<int32_t*>(slot + L.tix));
     J.sums = to_dev(reinterpret_cast<unsigned long long*>(slot + L.sums));
-    J.blk = to_dev(reinterpret_cast<uint32_t*>(slot + L.blk));
+    J.hkeys = to_dev(reinterpret_cast<uint16_t*>(slot + L.hkeys));
+    J.hcnt = to_dev(reinterpret_cast<uint32_t*>(slot + L.hcnt));
+    J.hmat = to_dev(reinterpret_cast<uint32_t*>(slot + L.hmat));
+    J.hbt = to_dev(reinterpret_cast<uint32_t*>(slot + L.hbt));
+    J.hnu = to_dev(reinterpret_cast<uint32_t*>(slot + L.hnu));
     J.part = to_dev(reinterpret_cast<unsigned long long*>(slot + L.part));
     J.vals = to_dev(reinterpret_cast<uint64_t*>(slot + L.chunks));
-    J.d2 = to_dev(reinterpret_cast<uint32_t*>(slot + L.d2));
-    J.grp = to_dev(reinterpret_cast<uint64_t*>(slot + L.d2));
+    J.d2 = to_dev(reinterpret_cast<uint32_t*>(slot + L.work));
+    J.grp = to_dev(reinterpret_cast<uint64_t*>(slot + L.work));
 }
 
 static void set_image(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride)
@@ -455,7 +456,7 @@ static void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t 
                               uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, char* slot)
 {
     const int64_t npix = int64_t(H) * W;
-    const Layout L = make_layout(npix, true);
+    const Layout L = make_layout(npix, npix, true);
     set_image(J, img, H, W, stride);
     bind_slot(J, slot, L);
     J.keys = to_dev(reinterpret_cast<uint32_t*>(slot + L.keys));
@@ -476,7 +477,7 @@ static void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t 
                (reinterpret_cast<uintptr_t>(out_rgb) & 3u) == 0;
 }
 
-static size_t slot_bytes(const cq_job& j) { return align256(make_layout(int64_t(j.H) * j.W, true).total); }
+static size_t slot_bytes(const cq_job& j) { return align256(make_layout(int64_t(j.H) * j.W, int64_t(j.H) * j.W, true).total); }
 
 static cq_status check_job(const cq_job& j, int idx)
 {
@@ -505,17 +506,15 @@ size_t cq_workspace_bytes(int32_t H, int32_t W, int32_t K)
     if (H <= 0 || W <= 0 || K < 1 || K > kMaxK) return 0;
     const int64_t npix = int64_t(H) * W;
     if (npix > kMaxPixels) return 0;
-    return make_layout(npix, true).total;
+    return make_layout(npix, npix, true).total;
 }
 
 cq_status cq_workspace_prepare(void* ws, size_t ws_bytes, void* stream)
 {
     clear_error();
-    const Layout L = make_layout(0, false);
+    const Layout L = make_layout(0, 0, false);
     CQ_TRY(check_ws(ws, ws_bytes, L.fixed_end));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    // the count table and the bitmap are adjacent: one fill covers both
-    CQ_TRY(launch_fill_zero(at<char>(ws, L.tbl), L.lut - L.tbl, s));
+    (void)stream;  // no region needs clearing between calls
     return CQ_OK;
 }
 
@@ -528,8 +527,8 @@ cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_str
     if (!n_unique) return einval("n_unique is null");
     if (capacity < 0) return einval("capacity is negative");
     if (capacity > 0 && (!keys || !counts)) return einval("keys/counts are null");
-    const Layout L = make_layout(0, false);
-    CQ_TRY(check_ws(ws, ws_bytes, L.fixed_end));
+    const Layout L = make_layout(int64_t(H) * W, 0, false);
+    CQ_TRY(check_ws(ws, ws_bytes, L.total));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
     JobDev& J = b.h[0];
     set_image(J, img, H, W, row_stride_bytes);
@@ -557,7 +556,7 @@ cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique
     if (!keys || !counts || !centers) return einval("keys/counts/centers is null");
     if (n_unique < 1 || n_unique > kMaxPixels) return einval("n_unique = %lld out of range", (long long)n_unique);
     if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_USER) return einval("unknown init scheme %d", int(scheme));
-    const Layout L = make_layout(n_unique, false);
+    const Layout L = make_layout(0, n_unique, false);
     CQ_TRY(check_ws(ws, ws_bytes, L.total));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
     JobDev& J = b.h[0];
@@ -589,7 +588,7 @@ cq_status cq_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n_uniq
     if (n_unique < 1 || n_unique > kMaxPixels) return einval("n_unique = %lld out of range", (long long)n_unique);
     CQ_TRY(check_iters_tol(max_iters, tol));
     // a pruned run keeps two packed records per colour in the workspace
-    const Layout L = make_layout(prune ? n_unique : 0, false);
+    const Layout L = make_layout(0, prune ? n_unique : 0, false);
     CQ_TRY(check_ws(ws, ws_bytes, prune ? L.total : L.fixed_end));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
     JobDev& J = b.h[0];
@@ -627,7 +626,7 @@ cq_status cq_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_by
     if (!keys || !palette) return einval("keys/palette is null");
     if (n_unique < 1 || n_unique > int64_t(H) * W) return einval("n_unique = %lld out of range", (long long)n_unique);
     if (sq_err_sum && !counts) return einval("sq_err_sum needs counts");
-    const Layout L = make_layout(0, false);
+    const Layout L = make_layout(0, 0, false);
     CQ_TRY(check_ws(ws, ws_bytes, L.fixed_end));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
     JobDev& J = b.h[0];
@@ -664,7 +663,7 @@ cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stri
         return einval("cq_quantize needs scheme FORGY, MAXMIN or KMEANSPP");
     CQ_TRY(check_iters_tol(max_iters, tol));
     const int64_t npix = int64_t(H) * W;
-    const Layout L = make_layout(npix, true);
+    const Layout L = make_layout(npix, npix, true);
     CQ_TRY(check_ws(ws, ws_bytes, L.total));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
     fill_quantize_job(b.h[0], img, H, W, row_stride_bytes, K, int(scheme), seed, max_iters, tol, prune, palette,
@@ -690,13 +689,7 @@ cq_status cq_batch_workspace_prepare(const cq_job* jobs, int32_t n_jobs, void* w
     const size_t need = cq_batch_workspace_bytes(jobs, n_jobs);
     if (need == 0) return einval("invalid batch description");
     CQ_TRY(check_ws(ws, ws_bytes, need));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    char* slot = static_cast<char*>(ws) + align256(desc_bytes(n_jobs));
-    const Layout L0 = make_layout(0, false);
-    for (int32_t i = 0; i < n_jobs; ++i) {
-        CQ_TRY(launch_fill_zero(slot + L0.tbl, L0.lut - L0.tbl, s));
-        slot += slot_bytes(jobs[i]);
-    }
+    (void)stream;  // no region needs clearing between calls
     return CQ_OK;
 }
 

@@ -11,18 +11,24 @@
 namespace cq {
 
 constexpr uint32_t kNumKeys = 1u << 24;          // all 24-bit colours
-constexpr uint32_t kBitmapWords = kNumKeys / 32;  // presence bitmap words
 constexpr int kMaxK = 256;
 constexpr int kMaxIters = 100000;
 constexpr int64_t kMaxPixels = int64_t(1) << 28;
 constexpr int kMaxBatch = 4096;
 constexpr int kMaxAssignBlocks = 4096;  // assignment blocks of one job
 
-// Bitmap compaction: each block owns a contiguous run of bitmap words.
-constexpr int kCompactThreads = 256;
-constexpr int kCompactWordsPerThread = 8;
-constexpr int kCompactWordsPerBlock = kCompactThreads * kCompactWordsPerThread;
-constexpr int kCompactBlocks = kBitmapWords / kCompactWordsPerBlock;  // 256
+// Histogram: keys split into kHistBuckets buckets of kHistLow consecutive keys
+// (bucket = key >> kHistLowBits); pixels are taken kHistTile at a time.
+constexpr int kHistLowBits = 13;
+constexpr int kHistLow = 1 << kHistLowBits;
+constexpr int kHistBuckets = 1 << (24 - kHistLowBits);
+constexpr int kHistTile = 32768;
+
+__host__ __device__ __forceinline__ int64_t hist_tiles(int64_t npix)
+{
+    const int64_t t = (npix + kHistTile - 1) / kHistTile;
+    return t > 0 ? t : 1;
+}
 
 // Cooperative initialization: at most kInitMaxBlocks blocks of kInitThreads
 // threads per team.  Thread t of a block owns a run of R consecutive colours;
@@ -107,15 +113,17 @@ struct JobDev {
     uint8_t CQ_GLOBAL* palette;
     uint8_t CQ_GLOBAL* out_idx;
     uint8_t CQ_GLOBAL* out_rgb;
-    uint32_t CQ_GLOBAL* tbl;
-    uint32_t CQ_GLOBAL* bitmap;
+    uint16_t CQ_GLOBAL* hkeys;  // histogram: low key bits of the pixels, partitioned by bucket
+    uint32_t CQ_GLOBAL* hcnt;   // histogram: compacted counts per bucket
+    uint32_t CQ_GLOBAL* hmat;   // histogram: bucket x tile counts, then their prefixes
+    uint32_t CQ_GLOBAL* hbt;    // histogram: pixels per bucket
+    uint32_t CQ_GLOBAL* hnu;    // histogram: unique colours per bucket
     uint8_t CQ_GLOBAL* lut;
     Meta CQ_GLOBAL* meta;
     double CQ_GLOBAL* trace;
     Rec CQ_GLOBAL* rec;   // sorted table rows (kMaxK x kRow)
     int32_t CQ_GLOBAL* tix; // centre index of every table entry (kMaxK x kRow)
     unsigned long long CQ_GLOBAL* sums;
-    uint32_t CQ_GLOBAL* blk;
     unsigned long long CQ_GLOBAL* part;  // per assignment block: distance count, near-tie count
     uint64_t CQ_GLOBAL* vals;  // init: tagged block values, then the run sums
     uint32_t CQ_GLOBAL* d2;
@@ -229,20 +237,21 @@ inline size_t desc_results_off(int B)
 // ---------------------------------------------------------------- layout
 
 struct Layout {
-    size_t tbl, bitmap, lut, meta, trace, rec, tix, sums, centers, palette, blk, part, desc;
-    size_t chunks, d2, keys, counts, assign;
+    size_t lut, meta, trace, rec, tix, sums, centers, palette, part, desc;
+    size_t chunks, work, hkeys, hcnt, hmat, hbt, hnu, keys, counts, assign;
     size_t fixed_end;  // end of the regions every call may use
-    size_t total;      // end including the per-colour regions for n_cap colours
+    size_t total;      // end including the per-pixel and per-colour regions
 };
 
-// n_cap: number of colours the per-colour regions must hold (0 = none).
-// with_colour_arrays: also reserve keys/counts/assign (used by cq_quantize).
-inline Layout make_layout(int64_t n_cap, bool with_colour_arrays)
+// npix: pixels the histogram regions must serve (0 = none); n_cap: colours
+// the per-colour regions must hold (0 = none); with_colour_arrays: also
+// reserve keys / counts / assign (used by cq_quantize).  The histogram's
+// staging and the initialization / k-means buffers share one work region:
+// the histogram is done before either starts.
+inline Layout make_layout(int64_t npix, int64_t n_cap, bool with_colour_arrays)
 {
     Layout L{};
     size_t o = 0;
-    L.tbl = o;      o = align256(o + sizeof(uint32_t) * kNumKeys);
-    L.bitmap = o;   o = align256(o + sizeof(uint32_t) * kBitmapWords);
     L.lut = o;      o = align256(o + kNumKeys);
     L.meta = o;     o = align256(o + 512);
     L.trace = o;    o = align256(o + sizeof(double) * kMaxIters);
@@ -252,19 +261,30 @@ inline Layout make_layout(int64_t n_cap, bool with_colour_arrays)
     L.sums = o;     o = align256(o + sizeof(uint64_t) * 2 * kSumStride);  // two iterations
     L.centers = o;  o = align256(o + sizeof(double) * 3 * kMaxK);
     L.palette = o;  o = align256(o + 3 * kMaxK);
-    L.blk = o;      o = align256(o + sizeof(uint32_t) * 2 * kCompactBlocks);
     L.part = o;     o = align256(o + sizeof(uint64_t) * 2 * kMaxAssignBlocks);
     L.desc = o;     o = align256(o + desc_bytes(1));
     L.fixed_end = o;
     const size_t n = n_cap > 0 ? size_t(n_cap) : 0;
+    const size_t np = npix > 0 ? size_t(npix) : 0;
     // init: tagged block values and per-thread run sums, both for two round parities
     L.chunks = o;   o = align256(o + sizeof(uint64_t) * 2 * kInitMaxBlocks * (1 + kInitThreads));
+    // work region
+    L.work = o;
+    size_t hist = 0;
+    if (np > 0) {
+        L.hkeys = o + hist; hist = align256(hist + sizeof(uint16_t) * np);
+        L.hcnt = o + hist;  hist = align256(hist + sizeof(uint32_t) * np);
+        L.hmat = o + hist;  hist = align256(hist + sizeof(uint32_t) * size_t(kHistBuckets) * size_t(hist_tiles(npix)));
+        L.hbt = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
+        L.hnu = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
+    }
     // init: D^2 for two round parities, kInitThreads R entries per block
-    // (below n + kInitThreads per block); k-means afterwards: two uint64
-    // records per colour
-    const size_t d2_init = sizeof(uint32_t) * 2 * (n + size_t(kInitThreads + 1) * kInitMaxBlocks);
+    // (below n + kInitThreads per block); k-means: two uint64 records per colour
+    const size_t d2_init = n > 0 ? sizeof(uint32_t) * 2 * (n + size_t(kInitThreads + 1) * kInitMaxBlocks) : 0;
     const size_t d2_km = sizeof(uint64_t) * 2 * n;
-    L.d2 = o;       o = align256(o + (d2_init > d2_km ? d2_init : d2_km));
+    size_t work = hist > d2_init ? hist : d2_init;
+    work = work > d2_km ? work : d2_km;
+    o = align256(o + work);
     if (with_colour_arrays) {
         L.keys = o;   o = align256(o + sizeof(uint32_t) * n);
         L.counts = o; o = align256(o + sizeof(uint32_t) * n);

@@ -1,61 +1,29 @@
 // Data reduction of Section 2.2 (items 1 and 2): the unique colours of an image
-// and their pixel counts.
+// and their pixel counts, in ascending key order.
 //
-// The paper hashes colours into a chained table.  Here each block first folds
-// a tile of pixels into a small open-addressing table in LDS, then the 2^24
-// possible colours index a dense uint32 count table directly, and a 2^24-bit
-// presence bitmap records which entries were touched.  Compaction walks the 2 MiB bitmap
-// (not the 64 MiB table), so the unique colours come out in ascending key order
-// with a prefix sum over word popcounts, and only the touched table entries are
-// read and reset.  Both regions are left all-zero for the next call.
+// The paper hashes colours into a chained table.  Here the 2^24 keys are split
+// into kHistBuckets buckets of consecutive keys (the top 11 bits), and the
+// pixels are partitioned by bucket before each bucket is counted in LDS, so no
+// global counter is ever incremented by more than one block:
+//   k_hist_buckets   per tile of pixels: pixels per bucket (LDS), one column
+//                    of the bucket x tile count matrix;
+//   k_hist_colscan   per bucket: exclusive prefix of its row over the tiles,
+//                    and the bucket's pixel total;
+//   k_hist_scatter   per tile: every pixel's low 13 key bits into its bucket's
+//                    range (bucket start + the tile's prefix + rank);
+//   k_hist_count     per bucket: counts of its 8192 keys in LDS, then the
+//                    non-zero ones compacted in ascending order in place;
+//   k_hist_emit      per bucket: the bucket's (key, count) pairs at the
+//                    prefix of the per-bucket unique counts.
+// Every launch covers all jobs of a batch.
 #include "cq_internal.h"
 
 namespace cq {
 
-// Tile aggregation in LDS: each block folds the pixels of a tile into an
-// open-addressing table of (key + 1, count) pairs, then adds every distinct key
-// of the tile to the global table with one atomic (and sets its bitmap bit).
-// Keys that find no free slot within kHashProbes probes go straight to the
-// global table.
-constexpr int kHistThreads = 256;
-constexpr int kHashBits = 12;
-constexpr int kHashSlots = 1 << kHashBits;     // 4096 slots, 32 KiB of LDS
-constexpr int kHistTile = kHashSlots / 2;      // pixels per tile (load <= 1/2)
-constexpr int kHashProbes = 16;
+constexpr int kHistThreads = 512;
+constexpr int kPixPerThread = kHistTile / kHistThreads;  // 64
 
-__device__ __forceinline__ void tile_insert(uint32_t key, uint32_t* hkey, uint32_t* hcnt,
-                                            uint32_t* __restrict__ tbl, uint32_t* __restrict__ bitmap)
-{
-    uint32_t slot = (key * 0x9E3779B1u) >> (32 - kHashBits);
-    const uint32_t tag = key + 1u;
-    for (int probe = 0; probe < kHashProbes; ++probe) {
-        const uint32_t old = atomicCAS(hkey + slot, 0u, tag);
-        if (old == 0u || old == tag) {
-            atomicAdd(hcnt + slot, 1u);
-            return;
-        }
-        slot = (slot + 1u) & (kHashSlots - 1);
-    }
-    atomicAdd(tbl + key, 1u);
-    atomicOr(bitmap + (key >> 5), 1u << (key & 31u));
-}
-
-__device__ __forceinline__ void tile_flush(uint32_t* hkey, uint32_t* hcnt, uint32_t* __restrict__ tbl,
-                                           uint32_t* __restrict__ bitmap)
-{
-    __syncthreads();
-    for (int slot = threadIdx.x; slot < kHashSlots; slot += kHistThreads) {
-        const uint32_t tag = hkey[slot];
-        if (tag == 0u) continue;
-        const uint32_t key = tag - 1u;
-        atomicAdd(tbl + key, hcnt[slot]);
-        atomicOr(bitmap + (key >> 5), 1u << (key & 31u));
-        hkey[slot] = 0u;
-        hcnt[slot] = 0u;
-    }
-    __syncthreads();
-}
-
+// Key of the pixel p (row-major index) of a job image.
 __device__ __forceinline__ uint32_t load_key(const uint8_t* __restrict__ img, int64_t p, int32_t W,
                                              int64_t row_stride, bool packed)
 {
@@ -69,179 +37,267 @@ __device__ __forceinline__ uint32_t load_key(const uint8_t* __restrict__ img, in
     return (uint32_t(q[0]) << 16) | (uint32_t(q[1]) << 8) | uint32_t(q[2]);
 }
 
-// Each block folds up to kTilesPerBlock consecutive tiles of its job.
-// Packed images (row stride 3W, 4-byte aligned) are read four pixels (three
-// dwords) per thread.
-constexpr int kTilesPerBlock = 4;
-
-__global__ void __launch_bounds__(kHistThreads) k_hist_tiles(const JobDev* __restrict__ jobs,
-                                                             const int* __restrict__ map, int B)
+// Keys of the four pixels held in three little-endian dwords:
+// a = R0 G0 B0 R1, b = G1 B1 R2 G2, c = B2 R3 G3 B3.
+__device__ __forceinline__ void unpack4(uint32_t a, uint32_t b, uint32_t c, uint32_t k[4])
 {
-    __shared__ uint32_t hkey[kHashSlots];
-    __shared__ uint32_t hcnt[kHashSlots];
+    k[0] = ((a & 0xffu) << 16) | (a & 0xff00u) | ((a >> 16) & 0xffu);
+    k[1] = ((a >> 24) << 16) | ((b & 0xffu) << 8) | ((b >> 8) & 0xffu);
+    k[2] = (((b >> 16) & 0xffu) << 16) | ((b >> 24) << 8) | (c & 0xffu);
+    k[3] = (((c >> 8) & 0xffu) << 16) | (((c >> 16) & 0xffu) << 8) | (c >> 24);
+}
+
+// Calls f(key, valid) for the pixels of tile `lb`, four pixels per thread per
+// step from three dword loads when the image is packed.
+template <typename F>
+__device__ __forceinline__ void for_tile_pixels(const JobDev& J, int64_t lb, F f)
+{
+    const uint8_t* __restrict__ img = gp(J.img);
+    const int64_t npix = int64_t(J.H) * J.W;
+    const int64_t p0 = lb * kHistTile;
+    const int64_t p1 = p0 + kHistTile < npix ? p0 + kHistTile : npix;
+    if (J.packed) {
+        const uint32_t* __restrict__ w = reinterpret_cast<const uint32_t*>(img);
+        const int64_t g0 = p0 >> 2, g1 = p1 >> 2;  // whole groups of four pixels
+        constexpr int kSteps = kHistTile / 4 / kHistThreads;
+        uint32_t a[kSteps], b[kSteps], c[kSteps];
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {  // all loads first
+            const int64_t g = g0 + s * kHistThreads + threadIdx.x;
+            const bool in = g < g1;
+            a[s] = in ? w[3 * g + 0] : 0u;
+            b[s] = in ? w[3 * g + 1] : 0u;
+            c[s] = in ? w[3 * g + 2] : 0u;
+        }
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            const bool in = g0 + s * kHistThreads + threadIdx.x < g1;
+            uint32_t k[4];
+            unpack4(a[s], b[s], c[s], k);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) f(k[q], in);
+        }
+        // the last tile of an image whose pixel count is not a multiple of 4
+        const int64_t tail = g1 * 4 + threadIdx.x;
+        const bool tin = tail < p1;
+        f(tin ? load_key(img, tail, J.W, J.stride, true) : 0u, tin);
+    } else {
+        for (int64_t p = p0; p < p1; p += kHistThreads) {
+            const int64_t q = p + threadIdx.x;
+            const bool in = q < p1;
+            f(in ? load_key(img, q, J.W, J.stride, false) : 0u, in);
+        }
+    }
+}
+
+// One LDS atomic per distinct bucket among the wave's valid lanes.
+__device__ __forceinline__ void count_bucket(uint32_t* cnt, int bucket, bool valid)
+{
+    const int lane = threadIdx.x & 63;
+    unsigned long long pending = __ballot(valid);
+    while (pending) {
+        const int leader = __ffsll(pending) - 1;
+        const int b = __builtin_amdgcn_readfirstlane(__shfl(bucket, leader, 64));
+        const unsigned long long m = __ballot(valid && bucket == b);
+        if (lane == leader) atomicAdd(&cnt[b], uint32_t(__popcll(m)));
+        pending &= ~m;
+    }
+}
+
+// Exclusive prefix of the kHistBuckets values v[0..) (global), computed by
+// the whole block: thread t gets the prefix up to its first bucket of
+// kPer consecutive ones in *pre, and the block total is returned.
+constexpr int kPerBucketThread = kHistBuckets / kHistThreads;  // 4
+__device__ __forceinline__ uint32_t bucket_prefix(const uint32_t* __restrict__ v, uint32_t vals[kPerBucketThread],
+                                                  uint32_t* pre, uint32_t* tmp)
+{
+    uint32_t sum = 0;
+#pragma unroll
+    for (int u = 0; u < kPerBucketThread; ++u) {
+        vals[u] = v[threadIdx.x * kPerBucketThread + u];
+        sum += vals[u];
+    }
+    uint32_t total = 0;
+    *pre = block_exclusive_scan<uint32_t>(sum, tmp, &total);
+    return total;
+}
+
+// ------------------------------------------------------------------ kernels
+__global__ void __launch_bounds__(kHistThreads) k_hist_buckets(const JobDev* __restrict__ jobs,
+                                                               const int* __restrict__ map, int B)
+{
+    __shared__ uint32_t cnt[kHistBuckets];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
-    const uint8_t* __restrict__ img = gp(J.img);
-    uint32_t* __restrict__ tbl = gp(J.tbl);
-    uint32_t* __restrict__ bitmap = gp(J.bitmap);
-    const int32_t W = J.W;
-    const int64_t row_stride = J.stride;
-    const bool packed = J.packed != 0;
-    for (int t = threadIdx.x; t < kHashSlots; t += kHistThreads) {
-        hkey[t] = 0u;
-        hcnt[t] = 0u;
+    for (int t = threadIdx.x; t < kHistBuckets; t += kHistThreads) cnt[t] = 0u;
+    __syncthreads();
+    for_tile_pixels(J, lb, [&](uint32_t key, bool in) { count_bucket(cnt, int(key >> kHistLowBits), in); });
+    __syncthreads();
+    const int64_t ntiles = hist_tiles(int64_t(J.H) * J.W);
+    uint32_t* __restrict__ mat = gp(J.hmat);
+    for (int t = threadIdx.x; t < kHistBuckets; t += kHistThreads) mat[t * ntiles + lb] = cnt[t];
+}
+
+// One block per (job, bucket): exclusive prefix over the tiles, in place.
+__global__ void __launch_bounds__(256) k_hist_colscan(const JobDev* __restrict__ jobs)
+{
+    __shared__ uint32_t tmp[64];
+    const JobDev& J = jobs[blockIdx.x / kHistBuckets];
+    const int b = blockIdx.x % kHistBuckets;
+    const int64_t ntiles = hist_tiles(int64_t(J.H) * J.W);
+    uint32_t* __restrict__ row = gp(J.hmat) + b * ntiles;
+    uint32_t carry = 0;
+    for (int64_t t0 = 0; t0 < ntiles; t0 += blockDim.x) {
+        const int64_t t = t0 + threadIdx.x;
+        const uint32_t v = t < ntiles ? row[t] : 0u;
+        uint32_t tot = 0;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(v, tmp, &tot);
+        if (t < ntiles) row[t] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) gp(J.hbt)[b] = carry;
+}
+
+__global__ void __launch_bounds__(kHistThreads) k_hist_scatter(const JobDev* __restrict__ jobs,
+                                                               const int* __restrict__ map, int B)
+{
+    __shared__ uint32_t pos[kHistBuckets];
+    __shared__ uint32_t tmp[64];
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int lb = blockIdx.x - map[jb];
+    const int64_t ntiles = hist_tiles(int64_t(J.H) * J.W);
+    const uint32_t* __restrict__ mat = gp(J.hmat);
+    uint32_t vals[kPerBucketThread], pre = 0;
+    bucket_prefix(gp(J.hbt), vals, &pre, tmp);
+#pragma unroll
+    for (int u = 0; u < kPerBucketThread; ++u) {
+        const int b = threadIdx.x * kPerBucketThread + u;
+        pos[b] = pre + mat[b * ntiles + lb];  // bucket start + this tile's prefix
+        pre += vals[u];
     }
     __syncthreads();
-    const int64_t npix = int64_t(J.H) * W;
-    const int64_t ntiles = (npix + kHistTile - 1) / kHistTile;
-    const uint32_t* w = reinterpret_cast<const uint32_t*>(img);
-    for (int64_t tile = int64_t(lb) * kTilesPerBlock; tile < ntiles && tile < int64_t(lb + 1) * kTilesPerBlock; ++tile) {
-        const int64_t p0 = tile * kHistTile;
-        const int64_t p1 = p0 + kHistTile < npix ? p0 + kHistTile : npix;
-        if (packed && p1 - p0 == kHistTile) {
-            // full tile: 4 pixels per thread per step, 12 bytes as three dwords
-            for (int64_t g = (p0 >> 2) + threadIdx.x; g < (p1 >> 2); g += kHistThreads) {
-                const uint32_t a = w[3 * g + 0];
-                const uint32_t b = w[3 * g + 1];
-                const uint32_t c = w[3 * g + 2];
-                // little-endian bytes: a = R0 G0 B0 R1, b = G1 B1 R2 G2, c = B2 R3 G3 B3
-                tile_insert(((a & 0xffu) << 16) | (a & 0xff00u) | ((a >> 16) & 0xffu), hkey, hcnt, tbl, bitmap);
-                tile_insert(((a >> 24) << 16) | ((b & 0xffu) << 8) | ((b >> 8) & 0xffu), hkey, hcnt, tbl, bitmap);
-                tile_insert((((b >> 16) & 0xffu) << 16) | ((b >> 24) << 8) | (c & 0xffu), hkey, hcnt, tbl, bitmap);
-                tile_insert((((c >> 8) & 0xffu) << 16) | (((c >> 16) & 0xffu) << 8) | (c >> 24), hkey, hcnt, tbl, bitmap);
-            }
-        } else {
-            for (int64_t p = p0 + threadIdx.x; p < p1; p += kHistThreads)
-                tile_insert(load_key(img, p, W, row_stride, packed), hkey, hcnt, tbl, bitmap);
+    uint16_t* __restrict__ hk = gp(J.hkeys);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for_tile_pixels(J, lb, [&](uint32_t key, bool in) {
+        const int bucket = int(key >> kHistLowBits);
+        unsigned long long pending = __ballot(in);
+        while (pending) {
+            const int leader = __ffsll(pending) - 1;
+            const int bk = __builtin_amdgcn_readfirstlane(__shfl(bucket, leader, 64));
+            const unsigned long long m = __ballot(in && bucket == bk);
+            uint32_t at = 0;
+            if (lane == leader) at = atomicAdd(&pos[bk], uint32_t(__popcll(m)));
+            at = __shfl(at, leader, 64);
+            if (in && bucket == bk) hk[at + __popcll(m & below)] = uint16_t(key & (kHistLow - 1));
+            pending &= ~m;
         }
-        tile_flush(hkey, hcnt, tbl, bitmap);
-    }
+    });
 }
 
-// Pass 1 of the compaction: popcount of each block's bitmap words.
-__global__ void __launch_bounds__(kCompactThreads) k_bitmap_count(const JobDev* __restrict__ jobs)
+// One block per (job, bucket): the bucket's keys counted in LDS, the
+// non-zero counters compacted in ascending key order over the front of the
+// bucket's own range (its keys are all read before anything is written).
+__global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __restrict__ jobs)
 {
+    __shared__ uint32_t c[kHistLow];
     __shared__ uint32_t tmp[64];
-    const JobDev& J = jobs[blockIdx.x / kCompactBlocks];
-    const uint32_t blk_id = blockIdx.x % kCompactBlocks;
-    const uint32_t* __restrict__ bitmap = gp(J.bitmap);
-    const uint32_t base = blk_id * kCompactWordsPerBlock + threadIdx.x * kCompactWordsPerThread;
-    const uint4* p = reinterpret_cast<const uint4*>(bitmap + base);
-    const uint4 u = p[0], v = p[1];
-    uint32_t c = __popc(u.x) + __popc(u.y) + __popc(u.z) + __popc(u.w) + __popc(v.x) + __popc(v.y) +
-                 __popc(v.z) + __popc(v.w);
-    c = wave_sum(c);
-    if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = c;
+    const JobDev& J = jobs[blockIdx.x / kHistBuckets];
+    const int b = blockIdx.x % kHistBuckets;
+    const uint32_t total = gp(J.hbt)[b];
+    if (total == 0) {
+        if (threadIdx.x == 0) gp(J.hnu)[b] = 0u;
+        return;
+    }
+    uint32_t vals[kPerBucketThread], pre = 0;
+    bucket_prefix(gp(J.hbt), vals, &pre, tmp);
+    // the start of bucket b: the prefix over the buckets before it
+    __shared__ uint32_t s_start;
+    if (threadIdx.x == b / kPerBucketThread) {
+        uint32_t st = pre;
+        for (int u = 0; u < b % kPerBucketThread; ++u) st += vals[u];
+        s_start = st;
+    }
+    for (int t = threadIdx.x; t < kHistLow; t += kHistThreads) c[t] = 0u;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int w = 0; w < kCompactThreads / 64; ++w) s += tmp[w];
-        gp(J.blk)[blk_id] = s;
-    }
-}
-
-// Pass 2: exclusive scan of the per-block counts (one block of 256 threads).
-__global__ void __launch_bounds__(kCompactBlocks) k_bitmap_scan(const JobDev* __restrict__ jobs)
-{
-    __shared__ uint32_t tmp[64];
-    const JobDev& J = jobs[blockIdx.x];
-    uint32_t total = 0;
-    const uint32_t off = block_exclusive_scan<uint32_t>(J.blk[threadIdx.x], tmp, &total);
-    gp(J.blk)[kCompactBlocks + threadIdx.x] = off;
-    if (threadIdx.x == 0) gp(J.meta)->n_unique = int64_t(total);
-}
-
-// Pass 3: emit the keys in ascending order and clear the bitmap words.  Keys
-// past `capacity` are not written; their table entries are reset here.
-__global__ void __launch_bounds__(kCompactThreads) k_bitmap_emit(const JobDev* __restrict__ jobs)
-{
-    __shared__ uint32_t tmp[64];
-    const JobDev& J = jobs[blockIdx.x / kCompactBlocks];
-    const uint32_t blk_id = blockIdx.x % kCompactBlocks;
-    uint32_t* __restrict__ bitmap = gp(J.bitmap);
-    uint32_t* __restrict__ tbl = gp(J.tbl);
-    uint32_t* __restrict__ keys = gp(J.keys);
-    const int64_t capacity = J.capacity;
-    const uint32_t base = blk_id * kCompactWordsPerBlock + threadIdx.x * kCompactWordsPerThread;
-    uint4* p = reinterpret_cast<uint4*>(bitmap + base);
-    const uint4 u = p[0], v = p[1];
-    const uint32_t words[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
-    uint32_t c = 0;
+    const uint32_t start = s_start;
+    uint16_t* __restrict__ hk = gp(J.hkeys) + start;
+    uint32_t* __restrict__ hc = gp(J.hcnt) + start;
+    for (uint32_t i = threadIdx.x; i < total; i += kHistThreads) atomicAdd(&c[hk[i]], 1u);
+    __syncthreads();
+    // thread t owns counters [t R, (t + 1) R)
+    constexpr int R = kHistLow / kHistThreads;  // 16
+    uint32_t nz = 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) c += __popc(words[j]);
-    const uint32_t local = block_exclusive_scan<uint32_t>(c, tmp, nullptr);
-    int64_t o = int64_t(J.blk[kCompactBlocks + blk_id]) + local;
+    for (int u = 0; u < R; ++u) nz += c[threadIdx.x * R + u] != 0u;
+    uint32_t nuniq = 0;
+    uint32_t o = block_exclusive_scan<uint32_t>(nz, tmp, &nuniq);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        uint32_t wbits = words[j];
-        while (wbits) {
-            const uint32_t bit = __ffs(wbits) - 1;
-            wbits &= wbits - 1;
-            const uint32_t key = (base + j) * 32u + bit;
-            if (o < capacity)
-                keys[o] = key;
-            else
-                tbl[key] = 0u;
+    for (int u = 0; u < R; ++u) {
+        const int low = threadIdx.x * R + u;
+        const uint32_t v = c[low];
+        if (v != 0u) {
+            hk[o] = uint16_t(low);
+            hc[o] = v;
             ++o;
         }
     }
-    if (c) {
-        p[0] = make_uint4(0, 0, 0, 0);
-        p[1] = make_uint4(0, 0, 0, 0);
-    }
+    if (threadIdx.x == 0) gp(J.hnu)[b] = nuniq;
 }
 
-// Pass 4: counts[o] = table[keys[o]], and the entry is reset.
-constexpr int kGatherBlocks = 64;  // per job
-
-__global__ void __launch_bounds__(256) k_gather_counts(const JobDev* __restrict__ jobs)
+// One block per (job, bucket): the bucket's pairs into keys / counts at the
+// prefix of the unique counts; entries past `capacity` are not written.
+__global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __restrict__ jobs)
 {
-    const JobDev& J = jobs[blockIdx.x / kGatherBlocks];
-    const int lb = blockIdx.x % kGatherBlocks;
-    const uint32_t* __restrict__ keys = gp(J.keys);
+    __shared__ uint32_t tmp[64];
+    __shared__ uint32_t s_start, s_out;
+    const JobDev& J = jobs[blockIdx.x / kHistBuckets];
+    const int b = blockIdx.x % kHistBuckets;
+    const uint32_t nb = gp(J.hnu)[b];
+    uint32_t tv[kPerBucketThread], tpre = 0;
+    uint32_t uv[kPerBucketThread], upre = 0;
+    if (nb == 0 && b != 0) return;
+    bucket_prefix(gp(J.hbt), tv, &tpre, tmp);
+    const uint32_t nuniq = bucket_prefix(gp(J.hnu), uv, &upre, tmp);
+    if (threadIdx.x == b / kPerBucketThread) {
+        uint32_t st = tpre, ou = upre;
+        for (int u = 0; u < b % kPerBucketThread; ++u) {
+            st += tv[u];
+            ou += uv[u];
+        }
+        s_start = st;
+        s_out = ou;
+    }
+    if (b == 0 && threadIdx.x == 0) gp(J.meta)->n_unique = int64_t(nuniq);
+    __syncthreads();
+    const uint16_t* __restrict__ hk = gp(J.hkeys) + s_start;
+    const uint32_t* __restrict__ hc = gp(J.hcnt) + s_start;
+    const int64_t out = s_out;
+    uint32_t* __restrict__ keys = gp(J.keys);
     uint32_t* __restrict__ counts = gp(J.counts);
-    uint32_t* __restrict__ tbl = gp(J.tbl);
-    const int64_t n = gp(J.meta)->n_unique < J.capacity ? gp(J.meta)->n_unique : J.capacity;
-    const int64_t stride = int64_t(kGatherBlocks) * blockDim.x;
-    for (int64_t o = int64_t(lb) * blockDim.x + threadIdx.x; o < n; o += stride) {
-        const uint32_t key = keys[o];
-        counts[o] = tbl[key];
-        tbl[key] = 0u;
+    const int64_t capacity = J.capacity;
+    for (uint32_t j = threadIdx.x; j < nb; j += kHistThreads) {
+        const int64_t o = out + j;
+        if (o >= capacity) break;
+        keys[o] = (uint32_t(b) << kHistLowBits) | uint32_t(hk[j]);
+        counts[o] = hc[j];
     }
-}
-
-// Workspace preparation: zero the count table and the bitmap with a plain
-// fill kernel.
-__global__ void __launch_bounds__(256) k_fill_zero(uint4* __restrict__ p, int64_t n16)
-{
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride)
-        p[i] = make_uint4(0, 0, 0, 0);
 }
 
 // ------------------------------------------------------------------ host
-cq_status launch_fill_zero(void* p, size_t bytes, hipStream_t s)
-{
-    const int64_t n16 = int64_t(bytes / 16);
-    CQ_TIMED_LAUNCH("k_fill_zero", s, k_fill_zero<<<2048, 256, 0, s>>>(reinterpret_cast<uint4*>(p), n16));
-    return CQ_OK;
-}
+int hist_blocks(int64_t npix) { return int(hist_tiles(npix)); }
 
-int hist_blocks(int64_t npix)
+// Histogram of every job; N' is left in each job's meta.
+cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_tiles, hipStream_t s)
 {
-    const int64_t tiles = (npix + kHistTile - 1) / kHistTile;
-    return int((tiles + kTilesPerBlock - 1) / kTilesPerBlock);
-}
-
-// Histogram and compaction of every job; N' is left in each job's meta.
-cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_hist_blocks, hipStream_t s)
-{
-    CQ_TIMED_LAUNCH("k_hist_tiles", s, k_hist_tiles<<<total_hist_blocks, kHistThreads, 0, s>>>(jobs, maps + kMapHist * (B + 1), B));
-    CQ_TIMED_LAUNCH("k_bitmap_count", s, k_bitmap_count<<<kCompactBlocks * B, kCompactThreads, 0, s>>>(jobs));
-    CQ_TIMED_LAUNCH("k_bitmap_scan", s, k_bitmap_scan<<<B, kCompactBlocks, 0, s>>>(jobs));
-    CQ_TIMED_LAUNCH("k_bitmap_emit", s, k_bitmap_emit<<<kCompactBlocks * B, kCompactThreads, 0, s>>>(jobs));
-    CQ_TIMED_LAUNCH("k_gather_counts", s, k_gather_counts<<<kGatherBlocks * B, 256, 0, s>>>(jobs));
+    const int* tmap = maps + kMapHist * (B + 1);
+    CQ_TIMED_LAUNCH("k_hist_buckets", s, k_hist_buckets<<<total_tiles, kHistThreads, 0, s>>>(jobs, tmap, B));
+    CQ_TIMED_LAUNCH("k_hist_colscan", s, k_hist_colscan<<<kHistBuckets * B, 256, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_hist_scatter", s, k_hist_scatter<<<total_tiles, kHistThreads, 0, s>>>(jobs, tmap, B));
+    CQ_TIMED_LAUNCH("k_hist_count", s, k_hist_count<<<kHistBuckets * B, kHistThreads, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_hist_emit", s, k_hist_emit<<<kHistBuckets * B, kHistThreads, 0, s>>>(jobs));
     return CQ_OK;
 }
 

@@ -30,9 +30,11 @@ def test_workspace_bytes():
     L = cq.lib()
     small = L.cq_workspace_bytes(64, 64, 16)
     big = L.cq_workspace_bytes(4096, 4096, 256)
-    assert small > (1 << 24) * 5  # count table + byte LUT
+    assert small > (1 << 24)  # the 2^24-entry byte colour table
     assert big > small
-    assert big - small >= 9 * (4096 * 4096 - 64 * 64)  # per-colour arrays
+    # per pixel: a work region of two 8-byte records per colour (it also holds
+    # the histogram's 6 bytes per pixel) plus keys, counts and memberships (9)
+    assert big - small >= 24 * (4096 * 4096 - 64 * 64)
     for bad in [(0, 5, 16), (5, 0, 16), (5, 5, 0), (5, 5, 257), (1 << 15, 1 << 14, 16)]:
         assert L.cq_workspace_bytes(*bad) == 0
 
