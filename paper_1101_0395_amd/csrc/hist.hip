@@ -90,20 +90,6 @@ __device__ __forceinline__ void for_tile_pixels(const JobDev& J, int64_t lb, F f
     }
 }
 
-// One LDS atomic per distinct bucket among the wave's valid lanes.
-__device__ __forceinline__ void count_bucket(uint32_t* cnt, int bucket, bool valid)
-{
-    const int lane = threadIdx.x & 63;
-    unsigned long long pending = __ballot(valid);
-    while (pending) {
-        const int leader = __ffsll(pending) - 1;
-        const int b = __builtin_amdgcn_readfirstlane(__shfl(bucket, leader, 64));
-        const unsigned long long m = __ballot(valid && bucket == b);
-        if (lane == leader) atomicAdd(&cnt[b], uint32_t(__popcll(m)));
-        pending &= ~m;
-    }
-}
-
 // Exclusive prefix of the kHistBuckets values v[0..) (global), computed by
 // the whole block: thread t gets the prefix up to its first bucket of
 // kPer consecutive ones in *pre, and the block total is returned.
@@ -132,7 +118,11 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_buckets(const JobDev* __r
     const int lb = blockIdx.x - map[jb];
     for (int t = threadIdx.x; t < kHistBuckets; t += kHistThreads) cnt[t] = 0u;
     __syncthreads();
-    for_tile_pixels(J, lb, [&](uint32_t key, bool in) { count_bucket(cnt, int(key >> kHistLowBits), in); });
+    // one LDS atomic per pixel: lanes with different buckets proceed together,
+    // lanes that share one are serialized by the LDS unit
+    for_tile_pixels(J, lb, [&](uint32_t key, bool in) {
+        if (in) atomicAdd(&cnt[key >> kHistLowBits], 1u);
+    });
     __syncthreads();
     const int64_t ntiles = hist_tiles(int64_t(J.H) * J.W);
     uint32_t* __restrict__ mat = gp(J.hmat);
@@ -179,21 +169,8 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_scatter(const JobDev* __r
     }
     __syncthreads();
     uint16_t* __restrict__ hk = gp(J.hkeys);
-    const int lane = threadIdx.x & 63;
-    const unsigned long long below = (1ull << lane) - 1ull;
     for_tile_pixels(J, lb, [&](uint32_t key, bool in) {
-        const int bucket = int(key >> kHistLowBits);
-        unsigned long long pending = __ballot(in);
-        while (pending) {
-            const int leader = __ffsll(pending) - 1;
-            const int bk = __builtin_amdgcn_readfirstlane(__shfl(bucket, leader, 64));
-            const unsigned long long m = __ballot(in && bucket == bk);
-            uint32_t at = 0;
-            if (lane == leader) at = atomicAdd(&pos[bk], uint32_t(__popcll(m)));
-            at = __shfl(at, leader, 64);
-            if (in && bucket == bk) hk[at + __popcll(m & below)] = uint16_t(key & (kHistLow - 1));
-            pending &= ~m;
-        }
+        if (in) hk[atomicAdd(&pos[key >> kHistLowBits], 1u)] = uint16_t(key & (kHistLow - 1));
     });
 }
 

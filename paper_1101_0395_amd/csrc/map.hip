@@ -66,18 +66,24 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ 
 // Pixel map: index and/or palette colour of every pixel through the table.
 // Block b of job j takes kMapGroupsPerBlock groups of 4 pixels.  Packed jobs
 // (contiguous rows, 4-byte aligned image and outputs) read 12 bytes and write
-// one dword of indices and three of colours per group; other jobs go pixel by
-// pixel.  The palette sits in LDS with all 256 entries (zero past K), so any
-// table byte indexes in bounds.
+// one dword of indices and three of colours per group, a thread issuing the
+// loads of all its groups before any table lookup; other jobs go pixel by
+// pixel.  The palette sits in LDS as one dword per entry (R | G << 8 | B << 16)
+// with all 256 entries (zero past K), so any table byte indexes in bounds.
+constexpr int kMapGroupsPerThread = kMapGroupsPerBlock / kMapThreads;
+
 __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ jobs,
                                                      const int* __restrict__ map, int B)
 {
-    __shared__ uint8_t pal[3 * kMaxK];
+    __shared__ uint32_t pal[kMaxK];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
     const int K = J.map_k;
-    for (int t = threadIdx.x; t < 3 * kMaxK; t += blockDim.x) pal[t] = t < 3 * K ? gp(J.palette)[t] : 0;
+    for (int t = threadIdx.x; t < kMaxK; t += blockDim.x) {
+        const uint8_t* q = gp(J.palette) + 3 * t;
+        pal[t] = t < K ? (uint32_t(q[0]) | (uint32_t(q[1]) << 8) | (uint32_t(q[2]) << 16)) : 0u;
+    }
     __syncthreads();
     const uint8_t* __restrict__ img = gp(J.img);
     const uint8_t* __restrict__ lut = gp(J.lut);
@@ -89,26 +95,40 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
     if (J.packed) {
         const int64_t ngroups = npix >> 2;
         const uint32_t* w = reinterpret_cast<const uint32_t*>(img);
-        for (int64_t g = g0 + threadIdx.x; g < g1 && g < ngroups; g += kMapThreads) {
-            const uint32_t a = w[3 * g + 0];
-            const uint32_t b = w[3 * g + 1];
-            const uint32_t c = w[3 * g + 2];
-            const uint32_t k0 = ((a & 0xffu) << 16) | (a & 0xff00u) | ((a >> 16) & 0xffu);
-            const uint32_t k1 = ((a >> 24) << 16) | ((b & 0xffu) << 8) | ((b >> 8) & 0xffu);
-            const uint32_t k2 = (((b >> 16) & 0xffu) << 16) | ((b >> 24) << 8) | (c & 0xffu);
-            const uint32_t k3 = (((c >> 8) & 0xffu) << 16) | (((c >> 16) & 0xffu) << 8) | (c >> 24);
-            const uint32_t i0 = lut[k0], i1 = lut[k1], i2 = lut[k2], i3 = lut[k3];
+        uint32_t a[kMapGroupsPerThread], b[kMapGroupsPerThread], c[kMapGroupsPerThread];
+#pragma unroll
+        for (int s = 0; s < kMapGroupsPerThread; ++s) {
+            const int64_t g = g0 + s * kMapThreads + threadIdx.x;
+            const bool in = g < ngroups;
+            a[s] = in ? w[3 * g + 0] : 0u;
+            b[s] = in ? w[3 * g + 1] : 0u;
+            c[s] = in ? w[3 * g + 2] : 0u;
+        }
+        uint32_t ix[kMapGroupsPerThread][4];
+#pragma unroll
+        for (int s = 0; s < kMapGroupsPerThread; ++s) {
+            const uint32_t k0 = ((a[s] & 0xffu) << 16) | (a[s] & 0xff00u) | ((a[s] >> 16) & 0xffu);
+            const uint32_t k1 = ((a[s] >> 24) << 16) | ((b[s] & 0xffu) << 8) | ((b[s] >> 8) & 0xffu);
+            const uint32_t k2 = (((b[s] >> 16) & 0xffu) << 16) | ((b[s] >> 24) << 8) | (c[s] & 0xffu);
+            const uint32_t k3 = (((c[s] >> 8) & 0xffu) << 16) | (((c[s] >> 16) & 0xffu) << 8) | (c[s] >> 24);
+            ix[s][0] = lut[k0];
+            ix[s][1] = lut[k1];
+            ix[s][2] = lut[k2];
+            ix[s][3] = lut[k3];
+        }
+#pragma unroll
+        for (int s = 0; s < kMapGroupsPerThread; ++s) {
+            const int64_t g = g0 + s * kMapThreads + threadIdx.x;
+            if (g >= ngroups) continue;
+            const uint32_t i0 = ix[s][0], i1 = ix[s][1], i2 = ix[s][2], i3 = ix[s][3];
             if (out_idx)
                 reinterpret_cast<uint32_t*>(out_idx)[g] = i0 | (i1 << 8) | (i2 << 16) | (i3 << 24);
             if (out_rgb) {
-                const uint8_t* p0 = pal + 3 * i0;
-                const uint8_t* p1 = pal + 3 * i1;
-                const uint8_t* p2 = pal + 3 * i2;
-                const uint8_t* p3 = pal + 3 * i3;
+                const uint32_t q0 = pal[i0], q1 = pal[i1], q2 = pal[i2], q3 = pal[i3];
                 uint32_t* o = reinterpret_cast<uint32_t*>(out_rgb) + 3 * g;
-                o[0] = uint32_t(p0[0]) | (uint32_t(p0[1]) << 8) | (uint32_t(p0[2]) << 16) | (uint32_t(p1[0]) << 24);
-                o[1] = uint32_t(p1[1]) | (uint32_t(p1[2]) << 8) | (uint32_t(p2[0]) << 16) | (uint32_t(p2[1]) << 24);
-                o[2] = uint32_t(p2[2]) | (uint32_t(p3[0]) << 8) | (uint32_t(p3[1]) << 16) | (uint32_t(p3[2]) << 24);
+                o[0] = q0 | (q1 << 24);
+                o[1] = (q1 >> 8) | (q2 << 16);
+                o[2] = (q2 >> 16) | (q3 << 8);
             }
         }
         // the last npix % 4 pixels belong to the block holding group ngroups
@@ -119,9 +139,9 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
             const uint32_t idx = lut[(uint32_t(p[0]) << 16) | (uint32_t(p[1]) << 8) | uint32_t(p[2])];
             if (out_idx) out_idx[px] = uint8_t(idx);
             if (out_rgb) {
-                out_rgb[3 * px + 0] = pal[3 * idx + 0];
-                out_rgb[3 * px + 1] = pal[3 * idx + 1];
-                out_rgb[3 * px + 2] = pal[3 * idx + 2];
+                out_rgb[3 * px + 0] = uint8_t(pal[idx]);
+                out_rgb[3 * px + 1] = uint8_t(pal[idx] >> 8);
+                out_rgb[3 * px + 2] = uint8_t(pal[idx] >> 16);
             }
         }
     } else {
@@ -133,9 +153,9 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
             const uint32_t idx = lut[(uint32_t(q[0]) << 16) | (uint32_t(q[1]) << 8) | uint32_t(q[2])];
             if (out_idx) out_idx[p] = uint8_t(idx);
             if (out_rgb) {
-                out_rgb[3 * p + 0] = pal[3 * idx + 0];
-                out_rgb[3 * p + 1] = pal[3 * idx + 1];
-                out_rgb[3 * p + 2] = pal[3 * idx + 2];
+                out_rgb[3 * p + 0] = uint8_t(pal[idx]);
+                out_rgb[3 * p + 1] = uint8_t(pal[idx] >> 8);
+                out_rgb[3 * p + 2] = uint8_t(pal[idx] >> 16);
             }
         }
     }
