@@ -202,7 +202,19 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __res
     const uint32_t start = s_start;
     uint16_t* __restrict__ hk = gp(J.hkeys) + start;
     uint32_t* __restrict__ hc = gp(J.hcnt) + start;
-    for (uint32_t i = threadIdx.x; i < total; i += kHistThreads) atomicAdd(&c[hk[i]], 1u);
+    // eight keys in flight per thread before their LDS atomics
+    constexpr int kUnroll = 8;
+    for (uint32_t i0 = 0; i0 < total; i0 += kUnroll * kHistThreads) {
+        uint32_t kq[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t i = i0 + u * kHistThreads + threadIdx.x;
+            kq[u] = i < total ? uint32_t(hk[i]) : 0xffffffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (kq[u] != 0xffffffffu) atomicAdd(&c[kq[u]], 1u);
+    }
     __syncthreads();
     // thread t owns counters [t R, (t + 1) R)
     constexpr int R = kHistLow / kHistThreads;  // 16
@@ -255,11 +267,24 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __rest
     uint32_t* __restrict__ keys = gp(J.keys);
     uint32_t* __restrict__ counts = gp(J.counts);
     const int64_t capacity = J.capacity;
-    for (uint32_t j = threadIdx.x; j < nb; j += kHistThreads) {
-        const int64_t o = out + j;
-        if (o >= capacity) break;
-        keys[o] = (uint32_t(b) << kHistLowBits) | uint32_t(hk[j]);
-        counts[o] = hc[j];
+    constexpr int kUnroll = 4;
+    for (uint32_t j0 = 0; j0 < nb; j0 += kUnroll * kHistThreads) {
+        uint32_t kq[kUnroll], cq[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t j = j0 + u * kHistThreads + threadIdx.x;
+            kq[u] = j < nb ? uint32_t(hk[j]) : 0u;
+            cq[u] = j < nb ? hc[j] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t j = j0 + u * kHistThreads + threadIdx.x;
+            const int64_t o = out + j;
+            if (j < nb && o < capacity) {
+                keys[o] = (uint32_t(b) << kHistLowBits) | kq[u];
+                counts[o] = cq[u];
+            }
+        }
     }
 }
 

@@ -319,8 +319,39 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
                     int64_t pk = -1;
                     const int64_t c = wave_find(G, r, &base, [&](int64_t x) { return s_val[x]; });
                     if (c >= 0) {
+                        // the block's kInitThreads run sums, all loaded in one round trip:
+                        // lane l holds runs [l S, (l + 1) S)
+                        constexpr int S = kInitThreads / 64;
                         const uint64_t* __restrict__ rs = rsum + int64_t(par) * rstride + c * kInitThreads;
-                        const int64_t tr = wave_find(kInitThreads, r, &base, [&](int64_t x) { return rs[x]; });
+                        uint64_t rv[S];
+                        uint64_t lsum = 0;
+#pragma unroll
+                        for (int u = 0; u < S; ++u) {
+                            rv[u] = rs[lane * S + u];
+                            lsum += rv[u];
+                        }
+                        const uint64_t lincl = base + wave_incl_scan(lsum);
+                        const unsigned long long hitl = __ballot(lincl > r);
+                        int64_t tr = -1;
+                        if (hitl) {
+                            const int l = __ffsll(hitl) - 1;
+                            uint64_t acc2 = __shfl(lincl - lsum, l, 64);  // sum before lane l's runs
+                            int found = -1;
+                            uint64_t before = acc2;
+#pragma unroll
+                            for (int u = 0; u < S; ++u) {
+                                const uint64_t v = __shfl(rv[u], l, 64);
+                                if (found < 0 && acc2 + v > r) {
+                                    found = u;
+                                    before = acc2;
+                                }
+                                acc2 += v;
+                            }
+                            if (found >= 0) {
+                                tr = int64_t(l) * S + found;
+                                base = before;
+                            }
+                        }
                         if (tr >= 0) {
                             const int64_t clo = c * C;
                             const int64_t chi = clo + C < n ? clo + C : n;

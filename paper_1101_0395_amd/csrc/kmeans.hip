@@ -356,7 +356,16 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 acc_add(acc, bins, v.best, w, r, g, b);
             }
         }
-        bin_add_vals(bins, acc.k >= 0, acc.k, acc.n, acc.s0, acc.s1, acc.s2, acc.q);
+        // each lane's last cluster straight into LDS: lanes that share a
+        // cluster are serialized by the LDS unit, cheaper than reducing
+        // five 64-bit values across the wave
+        if (acc.k >= 0) {
+            atomicAdd(&bins[kSumN + acc.k], acc.n);
+            atomicAdd(&bins[kSumS + 3 * acc.k + 0], acc.s0);
+            atomicAdd(&bins[kSumS + 3 * acc.k + 1], acc.s1);
+            atomicAdd(&bins[kSumS + 3 * acc.k + 2], acc.s2);
+            atomicAdd(&bins[kSumQ + acc.k], acc.q);
+        }
     }
     __syncthreads();
     flush_counters(ndc, ties, red, gp(J.part) + 2 * lb);
