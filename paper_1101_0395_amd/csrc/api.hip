@@ -14,7 +14,9 @@ namespace cq {
 
 // kernels launched from the other translation units
 int hist_blocks(int64_t npix);
-cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_hist_blocks, hipStream_t s);
+int hist_count_blocks(int64_t npix);
+cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_hist_blocks, int total_count,
+                           hipStream_t s);
 int coop_capacity();
 int coop_team_blocks(int64_t n);
 bool coop_fits_lds(int64_t C);
@@ -194,6 +196,8 @@ static void bind_slot(JobDev& J, char* slot, const Layout& L)
     J.hmat = to_dev(reinterpret_cast<uint32_t*>(slot + L.hmat));
     J.hbt = to_dev(reinterpret_cast<uint32_t*>(slot + L.hbt));
     J.hnu = to_dev(reinterpret_cast<uint32_t*>(slot + L.hnu));
+    J.hbs = to_dev(reinterpret_cast<uint32_t*>(slot + L.hbs));
+    J.hus = to_dev(reinterpret_cast<uint32_t*>(slot + L.hus));
     J.part = to_dev(reinterpret_cast<unsigned long long*>(slot + L.part));
     J.vals = to_dev(reinterpret_cast<uint64_t*>(slot + L.chunks));
     J.d2 = to_dev(reinterpret_cast<uint32_t*>(slot + L.work));
@@ -263,8 +267,9 @@ static cq_status collect(Batch& b)
 static cq_status run_histogram(Batch& b)
 {
     const int total = b.set_map(kMapHist, [&](int j) { return hist_blocks(int64_t(b.h[j].H) * b.h[j].W); });
+    const int count = b.set_map(kMapHistCount, [&](int j) { return hist_count_blocks(int64_t(b.h[j].H) * b.h[j].W); });
     CQ_TRY(upload(b));
-    return launch_histogram(b.d_jobs(), b.d_maps(), b.B, total, b.s);
+    return launch_histogram(b.d_jobs(), b.d_maps(), b.B, total, count, b.s);
 }
 
 // Once N' is known (from the histogram or from the caller).

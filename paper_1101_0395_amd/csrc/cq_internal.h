@@ -118,6 +118,8 @@ struct JobDev {
     uint32_t CQ_GLOBAL* hmat;   // histogram: bucket x tile counts, then their prefixes
     uint32_t CQ_GLOBAL* hbt;    // histogram: pixels per bucket
     uint32_t CQ_GLOBAL* hnu;    // histogram: unique colours per bucket
+    uint32_t CQ_GLOBAL* hbs;    // histogram: first pixel slot of each bucket
+    uint32_t CQ_GLOBAL* hus;    // histogram: first output entry of each bucket
     uint8_t CQ_GLOBAL* lut;
     Meta CQ_GLOBAL* meta;
     double CQ_GLOBAL* trace;
@@ -201,6 +203,7 @@ struct JobResult {
 
 enum MapId {
     kMapHist = 0,
+    kMapHistCount,   // histogram counting blocks
     kMapAssign,      // every job with iterations (first iteration, final pass)
     kMapAssignFull,  // unpruned jobs (full searches after the first iteration)
     kMapAssignWalk,  // pruned jobs (sort-means passes)
@@ -238,7 +241,7 @@ inline size_t desc_results_off(int B)
 
 struct Layout {
     size_t lut, meta, trace, rec, tix, sums, centers, palette, part, desc;
-    size_t chunks, work, hkeys, hcnt, hmat, hbt, hnu, keys, counts, assign;
+    size_t chunks, work, hkeys, hcnt, hmat, hbt, hnu, hbs, hus, keys, counts, assign;
     size_t fixed_end;  // end of the regions every call may use
     size_t total;      // end including the per-pixel and per-colour regions
 };
@@ -277,6 +280,8 @@ inline Layout make_layout(int64_t npix, int64_t n_cap, bool with_colour_arrays)
         L.hmat = o + hist;  hist = align256(hist + sizeof(uint32_t) * size_t(kHistBuckets) * size_t(hist_tiles(npix)));
         L.hbt = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
         L.hnu = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
+        L.hbs = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
+        L.hus = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
     }
     // init: D^2 for two round parities, kInitThreads R entries per block
     // (below n + kInitThreads per block); k-means: two uint64 records per colour

@@ -9,19 +9,20 @@
 //                    of the bucket x tile count matrix;
 //   k_hist_colscan   per bucket: exclusive prefix of its row over the tiles,
 //                    and the bucket's pixel total;
+//   k_hist_starts    per job: the first pixel slot of every bucket;
 //   k_hist_scatter   per tile: every pixel's low 13 key bits into its bucket's
 //                    range (bucket start + the tile's prefix + rank);
-//   k_hist_count     per bucket: counts of its 8192 keys in LDS, then the
-//                    non-zero ones compacted in ascending order in place;
-//   k_hist_emit      per bucket: the bucket's (key, count) pairs at the
-//                    prefix of the per-bucket unique counts.
+//   k_hist_count     per bucket (a fixed number of blocks per job): counts of
+//                    its 8192 keys in LDS, then the non-zero ones compacted in
+//                    ascending order in place;
+//   k_hist_ustarts   per job: the first output entry of every bucket and N';
+//   k_hist_emit      per bucket: the bucket's (key, count) pairs from there.
 // Every launch covers all jobs of a batch.
 #include "cq_internal.h"
 
 namespace cq {
 
 constexpr int kHistThreads = 512;
-constexpr int kPixPerThread = kHistTile / kHistThreads;  // 64
 
 // Key of the pixel p (row-major index) of a job image.
 __device__ __forceinline__ uint32_t load_key(const uint8_t* __restrict__ img, int64_t p, int32_t W,
@@ -90,21 +91,26 @@ __device__ __forceinline__ void for_tile_pixels(const JobDev& J, int64_t lb, F f
     }
 }
 
-// Exclusive prefix of the kHistBuckets values v[0..) (global), computed by
-// the whole block: thread t gets the prefix up to its first bucket of
-// kPer consecutive ones in *pre, and the block total is returned.
+// Exclusive prefix of kHistBuckets values (one block of kHistThreads
+// threads, kHistBuckets / kHistThreads consecutive values per thread);
+// returns the total.
 constexpr int kPerBucketThread = kHistBuckets / kHistThreads;  // 4
-__device__ __forceinline__ uint32_t bucket_prefix(const uint32_t* __restrict__ v, uint32_t vals[kPerBucketThread],
-                                                  uint32_t* pre, uint32_t* tmp)
+__device__ __forceinline__ uint32_t bucket_scan(const uint32_t* __restrict__ v, uint32_t* __restrict__ out,
+                                                uint32_t* tmp)
 {
-    uint32_t sum = 0;
+    uint32_t vals[kPerBucketThread], sum = 0;
 #pragma unroll
     for (int u = 0; u < kPerBucketThread; ++u) {
         vals[u] = v[threadIdx.x * kPerBucketThread + u];
         sum += vals[u];
     }
     uint32_t total = 0;
-    *pre = block_exclusive_scan<uint32_t>(sum, tmp, &total);
+    uint32_t pre = block_exclusive_scan<uint32_t>(sum, tmp, &total);
+#pragma unroll
+    for (int u = 0; u < kPerBucketThread; ++u) {
+        out[threadIdx.x * kPerBucketThread + u] = pre;
+        pre += vals[u];
+    }
     return total;
 }
 
@@ -149,24 +155,35 @@ __global__ void __launch_bounds__(256) k_hist_colscan(const JobDev* __restrict__
     if (threadIdx.x == 0) gp(J.hbt)[b] = carry;
 }
 
+// One block per job: first pixel slot of every bucket.
+__global__ void __launch_bounds__(kHistThreads) k_hist_starts(const JobDev* __restrict__ jobs)
+{
+    __shared__ uint32_t tmp[64];
+    const JobDev& J = jobs[blockIdx.x];
+    bucket_scan(gp(J.hbt), gp(J.hbs), tmp);
+}
+
+// One block per job: first output entry of every bucket, and N'.
+__global__ void __launch_bounds__(kHistThreads) k_hist_ustarts(const JobDev* __restrict__ jobs)
+{
+    __shared__ uint32_t tmp[64];
+    const JobDev& J = jobs[blockIdx.x];
+    const uint32_t total = bucket_scan(gp(J.hnu), gp(J.hus), tmp);
+    if (threadIdx.x == 0) gp(J.meta)->n_unique = int64_t(total);
+}
+
 __global__ void __launch_bounds__(kHistThreads) k_hist_scatter(const JobDev* __restrict__ jobs,
                                                                const int* __restrict__ map, int B)
 {
     __shared__ uint32_t pos[kHistBuckets];
-    __shared__ uint32_t tmp[64];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
     const int64_t ntiles = hist_tiles(int64_t(J.H) * J.W);
     const uint32_t* __restrict__ mat = gp(J.hmat);
-    uint32_t vals[kPerBucketThread], pre = 0;
-    bucket_prefix(gp(J.hbt), vals, &pre, tmp);
-#pragma unroll
-    for (int u = 0; u < kPerBucketThread; ++u) {
-        const int b = threadIdx.x * kPerBucketThread + u;
-        pos[b] = pre + mat[b * ntiles + lb];  // bucket start + this tile's prefix
-        pre += vals[u];
-    }
+    const uint32_t* __restrict__ bs = gp(J.hbs);
+    for (int b = threadIdx.x; b < kHistBuckets; b += kHistThreads)
+        pos[b] = bs[b] + mat[b * ntiles + lb];  // bucket start + this tile's prefix
     __syncthreads();
     uint16_t* __restrict__ hk = gp(J.hkeys);
     for_tile_pixels(J, lb, [&](uint32_t key, bool in) {
@@ -174,96 +191,97 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_scatter(const JobDev* __r
     });
 }
 
-// One block per (job, bucket): the bucket's keys counted in LDS, the
-// non-zero counters compacted in ascending key order over the front of the
-// bucket's own range (its keys are all read before anything is written).
-__global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __restrict__ jobs)
+// Per job, hist_count_blocks(npix) blocks (a power of two up to one per
+// bucket), block c of C taking the buckets c, c + C, ...: each bucket's keys
+// are counted in LDS, then the non-zero
+// counters are compacted in ascending key order over the front of the
+// bucket's own range (its keys are all read before anything is written).  The
+// 8192 counters are cleared once; a bucket marks the groups of 64 counters it
+// touches, and only those are read back and cleared again, so a bucket costs
+// in proportion to its contents.
+constexpr int kGroups = kHistLow / 64;  // 128 groups of 64 counters
+
+__global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __restrict__ jobs,
+                                                             const int* __restrict__ map, int B)
 {
     __shared__ uint32_t c[kHistLow];
+    __shared__ uint32_t touched[kGroups / 32];
     __shared__ uint32_t tmp[64];
-    const JobDev& J = jobs[blockIdx.x / kHistBuckets];
-    const int b = blockIdx.x % kHistBuckets;
-    const uint32_t total = gp(J.hbt)[b];
-    if (total == 0) {
-        if (threadIdx.x == 0) gp(J.hnu)[b] = 0u;
-        return;
-    }
-    uint32_t vals[kPerBucketThread], pre = 0;
-    bucket_prefix(gp(J.hbt), vals, &pre, tmp);
-    // the start of bucket b: the prefix over the buckets before it
-    __shared__ uint32_t s_start;
-    if (threadIdx.x == b / kPerBucketThread) {
-        uint32_t st = pre;
-        for (int u = 0; u < b % kPerBucketThread; ++u) st += vals[u];
-        s_start = st;
-    }
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int cb0 = blockIdx.x - map[jb];
+    const int kCountBlocks = map[jb + 1] - map[jb];
     for (int t = threadIdx.x; t < kHistLow; t += kHistThreads) c[t] = 0u;
+    if (threadIdx.x < kGroups / 32) touched[threadIdx.x] = 0u;
     __syncthreads();
-    const uint32_t start = s_start;
-    uint16_t* __restrict__ hk = gp(J.hkeys) + start;
-    uint32_t* __restrict__ hc = gp(J.hcnt) + start;
-    // eight keys in flight per thread before their LDS atomics
+    constexpr int R = kHistLow / kHistThreads;  // 16 counters per thread in the compaction
     constexpr int kUnroll = 8;
-    for (uint32_t i0 = 0; i0 < total; i0 += kUnroll * kHistThreads) {
-        uint32_t kq[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint32_t i = i0 + u * kHistThreads + threadIdx.x;
-            kq[u] = i < total ? uint32_t(hk[i]) : 0xffffffffu;
+    for (int b = cb0; b < kHistBuckets; b += kCountBlocks) {
+        const uint32_t total = gp(J.hbt)[b];
+        if (total == 0) {
+            if (threadIdx.x == 0) gp(J.hnu)[b] = 0u;
+            continue;
         }
+        const uint32_t start = gp(J.hbs)[b];
+        uint16_t* __restrict__ hk = gp(J.hkeys) + start;
+        uint32_t* __restrict__ hc = gp(J.hcnt) + start;
+        // eight keys in flight per thread before their LDS atomics
+        for (uint32_t i0 = 0; i0 < total; i0 += kUnroll * kHistThreads) {
+            uint32_t kq[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-            if (kq[u] != 0xffffffffu) atomicAdd(&c[kq[u]], 1u);
-    }
-    __syncthreads();
-    // thread t owns counters [t R, (t + 1) R)
-    constexpr int R = kHistLow / kHistThreads;  // 16
-    uint32_t nz = 0;
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t i = i0 + u * kHistThreads + threadIdx.x;
+                kq[u] = i < total ? uint32_t(hk[i]) : 0xffffffffu;
+            }
 #pragma unroll
-    for (int u = 0; u < R; ++u) nz += c[threadIdx.x * R + u] != 0u;
-    uint32_t nuniq = 0;
-    uint32_t o = block_exclusive_scan<uint32_t>(nz, tmp, &nuniq);
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-        const int low = threadIdx.x * R + u;
-        const uint32_t v = c[low];
-        if (v != 0u) {
-            hk[o] = uint16_t(low);
-            hc[o] = v;
-            ++o;
+            for (int u = 0; u < kUnroll; ++u) {
+                if (kq[u] == 0xffffffffu) continue;
+                if (atomicAdd(&c[kq[u]], 1u) == 0u) atomicOr(&touched[kq[u] >> 11], 1u << ((kq[u] >> 6) & 31u));
+            }
         }
+        __syncthreads();
+        // thread t owns counters [t R, (t + 1) R), inside group t R / 64
+        const int g = threadIdx.x * R / 64;
+        const bool hit = (touched[g >> 5] >> (g & 31)) & 1u;
+        uint32_t v[R];
+        uint32_t nz = 0;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            v[u] = hit ? c[threadIdx.x * R + u] : 0u;
+            nz += v[u] != 0u;
+        }
+        uint32_t nuniq = 0;
+        uint32_t o = block_exclusive_scan<uint32_t>(nz, tmp, &nuniq);
+        if (hit) {
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                if (v[u] != 0u) {
+                    hk[o] = uint16_t(threadIdx.x * R + u);
+                    hc[o] = v[u];
+                    ++o;
+                    c[threadIdx.x * R + u] = 0u;
+                }
+            }
+        }
+        if (threadIdx.x == 0) gp(J.hnu)[b] = nuniq;
+        __syncthreads();  // every touched counter is cleared and the mask was read
+        if (threadIdx.x < kGroups / 32) touched[threadIdx.x] = 0u;
+        __syncthreads();
     }
-    if (threadIdx.x == 0) gp(J.hnu)[b] = nuniq;
 }
 
 // One block per (job, bucket): the bucket's pairs into keys / counts at the
 // prefix of the unique counts; entries past `capacity` are not written.
 __global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __restrict__ jobs)
 {
-    __shared__ uint32_t tmp[64];
-    __shared__ uint32_t s_start, s_out;
     const JobDev& J = jobs[blockIdx.x / kHistBuckets];
     const int b = blockIdx.x % kHistBuckets;
     const uint32_t nb = gp(J.hnu)[b];
-    uint32_t tv[kPerBucketThread], tpre = 0;
-    uint32_t uv[kPerBucketThread], upre = 0;
-    if (nb == 0 && b != 0) return;
-    bucket_prefix(gp(J.hbt), tv, &tpre, tmp);
-    const uint32_t nuniq = bucket_prefix(gp(J.hnu), uv, &upre, tmp);
-    if (threadIdx.x == b / kPerBucketThread) {
-        uint32_t st = tpre, ou = upre;
-        for (int u = 0; u < b % kPerBucketThread; ++u) {
-            st += tv[u];
-            ou += uv[u];
-        }
-        s_start = st;
-        s_out = ou;
-    }
-    if (b == 0 && threadIdx.x == 0) gp(J.meta)->n_unique = int64_t(nuniq);
-    __syncthreads();
-    const uint16_t* __restrict__ hk = gp(J.hkeys) + s_start;
-    const uint32_t* __restrict__ hc = gp(J.hcnt) + s_start;
-    const int64_t out = s_out;
+    if (nb == 0) return;
+    const uint32_t start = gp(J.hbs)[b];
+    const uint16_t* __restrict__ hk = gp(J.hkeys) + start;
+    const uint32_t* __restrict__ hc = gp(J.hcnt) + start;
+    const int64_t out = gp(J.hus)[b];
     uint32_t* __restrict__ keys = gp(J.keys);
     uint32_t* __restrict__ counts = gp(J.counts);
     const int64_t capacity = J.capacity;
@@ -291,14 +309,27 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __rest
 // ------------------------------------------------------------------ host
 int hist_blocks(int64_t npix) { return int(hist_tiles(npix)); }
 
+// Counting blocks of a job: about one per 4096 pixels, a power of two
+// between 256 and one per bucket.
+int hist_count_blocks(int64_t npix)
+{
+    int c = 256;
+    while (c < kHistBuckets && int64_t(c) * 4096 < npix) c <<= 1;
+    return c;
+}
+
 // Histogram of every job; N' is left in each job's meta.
-cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_tiles, hipStream_t s)
+cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_tiles, int total_count,
+                           hipStream_t s)
 {
     const int* tmap = maps + kMapHist * (B + 1);
+    const int* cmap = maps + kMapHistCount * (B + 1);
     CQ_TIMED_LAUNCH("k_hist_buckets", s, k_hist_buckets<<<total_tiles, kHistThreads, 0, s>>>(jobs, tmap, B));
     CQ_TIMED_LAUNCH("k_hist_colscan", s, k_hist_colscan<<<kHistBuckets * B, 256, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_hist_starts", s, k_hist_starts<<<B, kHistThreads, 0, s>>>(jobs));
     CQ_TIMED_LAUNCH("k_hist_scatter", s, k_hist_scatter<<<total_tiles, kHistThreads, 0, s>>>(jobs, tmap, B));
-    CQ_TIMED_LAUNCH("k_hist_count", s, k_hist_count<<<kHistBuckets * B, kHistThreads, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_hist_count", s, k_hist_count<<<total_count, kHistThreads, 0, s>>>(jobs, cmap, B));
+    CQ_TIMED_LAUNCH("k_hist_ustarts", s, k_hist_ustarts<<<B, kHistThreads, 0, s>>>(jobs));
     CQ_TIMED_LAUNCH("k_hist_emit", s, k_hist_emit<<<kHistBuckets * B, kHistThreads, 0, s>>>(jobs));
     return CQ_OK;
 }
