@@ -88,6 +88,23 @@ def measure_large(cq, synth, torch, dev, reps=5):
     }
 
 
+def recorded_traffic():
+    """HBM bytes per launch of the sort-means pass from the committed counter
+    summary, if it was measured on the kernel source as it is now; else None."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_assign_walk_traffic_8x512.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        src = open(os.path.join(ROOT, "paper_1101_0395_amd", "csrc", "kmeans.hip"), "rb").read()
+    except (OSError, AttributeError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,7 +221,7 @@ def main():
             "peak": PEAK_FP64_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP64_VALU_TFLOPS,
-            "traffic": None,
+            "traffic": recorded_traffic(),
             "launches": launches,
             "avg_launch_us": 1e3 * kern_ms / max(1, launches),
         },
