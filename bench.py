@@ -88,6 +88,30 @@ def measure_large(cq, synth, torch, dev, reps=5):
     }
 
 
+def measure_serving(cq, torch, imgs, dev, n_req=96, rate=500.0, max_jobs=16, iters_per_step=8):
+    """Continuous batching under Poisson arrivals: n_req requests for the
+    eight 512 x 512 stand-ins in turn (request r uses k-means++ seed 1000 + r),
+    K = 256, same settings as the batched step, offered at `rate` requests/s
+    to an engine with room for max_jobs jobs in flight."""
+    from paper_1101_0395_amd import serve
+
+    eng = cq.Engine(max_jobs, max_jobs * cq.engine_job_bytes(H, W), dev)
+    arrivals = serve.poisson_arrivals(n_req, rate, seed=7)
+
+    def requests():
+        return [serve.Request(float(t), cq.BatchJob(imgs[r % len(imgs)], K, cq.INIT_KMEANSPP, 1000 + r,
+                                                   MAX_ITERS, TOL, True))
+                for r, t in enumerate(arrivals)]
+
+    serve.run(eng, requests()[:max_jobs], iters_per_step)  # warm-up
+    out = serve.run(eng, requests(), iters_per_step)
+    eng.close()
+    out["workload"] = (f"{n_req} requests, Poisson arrivals at {rate:g}/s, 512x512 stand-ins, K=256, "
+                       f"k-means++, sort-means, tol 1e-4, max 100 iters, full map; engine with "
+                       f"{max_jobs} jobs in flight, {iters_per_step} iterations per step")
+    return out
+
+
 def recorded_traffic():
     """HBM bytes per launch of the sort-means pass from the committed counter
     summary, if it was measured on the kernel source as it is now; else None."""
@@ -112,6 +136,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 4096x4096 histogram/map bandwidth figures")
+    ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching latency figures")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="finish with plain device-to-device copies of this many MiB (a known-size kernel "
                          "for scaling memory counters)")
@@ -229,6 +254,8 @@ def main():
 
     if not args.no_large:
         line["hbm_bound_steps_4096"] = measure_large(cq, synth, torch, dev)
+    if not args.no_serving:
+        line["serving"] = measure_serving(cq, torch, imgs, dev)
 
     if not args.no_cpu_baseline:
         import oracle

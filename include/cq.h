@@ -176,8 +176,8 @@ typedef struct {
  * invalid description.  At most 4096 jobs. */
 size_t cq_batch_workspace_bytes(const cq_job* jobs /* host */, int32_t n_jobs);
 
-/* Clears the zero-between-calls regions of every slot (once per workspace, and
- * after CQ_EDEVICE).  The same job sizes must be used with the workspace. */
+/* Checks that the workspace is large enough and aligned for the batch; no
+ * region of it needs clearing between calls, so no device work is done. */
 cq_status cq_batch_workspace_prepare(const cq_job* jobs /* host */, int32_t n_jobs, void* ws,
                                      size_t ws_bytes, void* stream);
 
@@ -186,9 +186,78 @@ cq_status cq_batch_workspace_prepare(const cq_job* jobs /* host */, int32_t n_jo
 cq_status cq_quantize_batch(const cq_job* jobs /* host */, int32_t n_jobs, cq_stats* stats /* host */,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving engine: continuous batching of whole-quantizer jobs (cq_job, as in
+ * cq_quantize) that arrive over time.  Each job's results are identical to
+ * cq_quantize on that image alone, whatever else is in flight.
+ *
+ * The engine owns host bookkeeping only; its device memory is one
+ * caller-owned workspace: a descriptor region for up to max_jobs jobs in
+ * flight, followed by a pool from which every admitted job takes a slot of
+ * cq_engine_job_bytes(job) bytes (its histogram, records, sums and lookup
+ * table) until it finishes.  Jobs wait in submission order; the oldest is
+ * admitted at the start of a step when fewer than max_jobs are in flight and
+ * a free range of the pool fits its slot (first fit).  A step then
+ *   1. runs the histogram and initialization of the jobs just admitted
+ *      (their "prefill"),
+ *   2. runs `iters` Lloyd iterations of every job in flight, each at its own
+ *      iteration count (the first one a full search, sort-means after that),
+ *   3. for every job that has stopped: palette, pixel map and statistics; its
+ *      slot returns to the pool.
+ * Nothing is in flight on `stream` between calls.  An engine is used from one
+ * host thread at a time; the caller keeps each job's image and output buffers
+ * alive until the job is reported done.
+ * ---------------------------------------------------------------------- */
+typedef struct cq_engine cq_engine;
+
+/* One finished job, as reported by cq_engine_step. */
+typedef struct {
+    int64_t ticket;     /* from cq_engine_submit                                   */
+    cq_status status;   /* CQ_OK, or CQ_EDEVICE if its initialization barrier timed out */
+    int32_t reserved_;
+    cq_stats stats;     /* as cq_quantize reports them (includes mse_img)          */
+} cq_engine_done;
+
+/* Pool bytes one job occupies while in flight; 0 for an invalid size. */
+size_t cq_engine_job_bytes(int32_t H, int32_t W);
+
+/* Workspace bytes for max_jobs (1..4096) jobs in flight and a pool of
+ * pool_bytes; 0 for invalid arguments. */
+size_t cq_engine_workspace_bytes(int32_t max_jobs, size_t pool_bytes);
+
+/* Creates an engine over `ws` (device, 256-byte aligned, at least
+ * cq_engine_workspace_bytes(max_jobs, 0) bytes; everything past the
+ * descriptor region is the pool).  *engine (host) receives the handle.  No
+ * device work. */
+cq_status cq_engine_create(int32_t max_jobs, void* ws, size_t ws_bytes, void* stream,
+                           cq_engine** engine /* host */);
+
+/* Queues a job (validated as in cq_quantize_batch); *ticket (host) receives
+ * its number, increasing from 1.  CQ_ECAPACITY if its slot is larger than
+ * the whole pool (it could never be admitted).  No device work. */
+cq_status cq_engine_submit(cq_engine* engine, const cq_job* job /* host */, int64_t* ticket /* host */);
+
+/* One step (admission, prefill, `iters` iterations (0..100000), completion).
+ * done (host) has room for `capacity` >= max_jobs entries; *n_done (host)
+ * receives how many jobs finished in this step, in their admission order.
+ * Synchronizes `stream`.  After an error other than an invalid argument
+ * (CQ_EINVAL for iters, capacity or a null pointer) the engine accepts only
+ * cq_engine_destroy. */
+cq_status cq_engine_step(cq_engine* engine, int32_t iters, cq_engine_done* done /* host */, int32_t capacity,
+                         int32_t* n_done /* host */);
+
+/* Jobs waiting for admission, jobs in flight and pool bytes in use (each
+ * output nullable, host). */
+cq_status cq_engine_pending(const cq_engine* engine, int32_t* queued, int32_t* running, size_t* pool_used);
+
+/* Frees the host bookkeeping (the workspace stays the caller's).  Jobs still
+ * queued or in flight are dropped; after a failed step it first waits for
+ * `stream`.  NULL is accepted. */
+void cq_engine_destroy(cq_engine* engine);
+
 /* Kernel timing for measurement harnesses (not needed for quantization).
  * While enabled, every launch of the kernel named `kernel` (for example
- * "k_assign", "k_hist_packed", "k_map_packed") is bracketed by a pair of HIP
+ * "k_assign_walk", "k_hist_count", "k_map") is bracketed by a pair of HIP
  * events recorded on the stream it is launched on, for at most max_launches
  * launches.  cq_timer_read waits for those events and returns the number of
  * bracketed launches and the sum of their durations in milliseconds.

@@ -20,8 +20,9 @@ CQ_OK, CQ_EINVAL, CQ_ECAPACITY, CQ_EWORKSPACE, CQ_EDEVICE = 0, 1, 2, 3, 4
 INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER = 0, 1, 2, 3
 EXPORTS = ("cq_workspace_bytes", "cq_workspace_prepare", "cq_histogram", "cq_init", "cq_kmeans",
            "cq_map", "cq_quantize", "cq_batch_workspace_bytes", "cq_batch_workspace_prepare",
-           "cq_quantize_batch", "cq_timer_enable", "cq_timer_read", "cq_timer_disable",
-           "cq_last_error")
+           "cq_quantize_batch", "cq_engine_job_bytes", "cq_engine_workspace_bytes", "cq_engine_create",
+           "cq_engine_submit", "cq_engine_step", "cq_engine_pending", "cq_engine_destroy",
+           "cq_timer_enable", "cq_timer_read", "cq_timer_disable", "cq_last_error")
 
 
 class CqStats(ctypes.Structure):
@@ -57,6 +58,15 @@ class CqJob(ctypes.Structure):
         ("palette", ctypes.c_void_p),
         ("out_idx", ctypes.c_void_p),
         ("out_rgb", ctypes.c_void_p),
+    ]
+
+
+class CqEngineDone(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_int64),
+        ("status", ctypes.c_int),
+        ("reserved_", ctypes.c_int32),
+        ("stats", CqStats),
     ]
 
 
@@ -98,6 +108,18 @@ def lib() -> ctypes.CDLL:
         L.cq_batch_workspace_prepare.restype = ctypes.c_int
         L.cq_quantize_batch.argtypes = [ctypes.POINTER(CqJob), i32, ctypes.POINTER(CqStats), P, sz, P]
         L.cq_quantize_batch.restype = ctypes.c_int
+        L.cq_engine_job_bytes.argtypes = [i32, i32]
+        L.cq_engine_job_bytes.restype = sz
+        L.cq_engine_workspace_bytes.argtypes = [i32, sz]
+        L.cq_engine_workspace_bytes.restype = sz
+        L.cq_engine_create.argtypes = [i32, P, sz, P, ctypes.POINTER(P)]
+        L.cq_engine_submit.argtypes = [P, ctypes.POINTER(CqJob), ctypes.POINTER(i64)]
+        L.cq_engine_step.argtypes = [P, i32, ctypes.POINTER(CqEngineDone), i32, ctypes.POINTER(i32)]
+        L.cq_engine_pending.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(sz)]
+        for f in ("cq_engine_create", "cq_engine_submit", "cq_engine_step", "cq_engine_pending"):
+            getattr(L, f).restype = ctypes.c_int
+        L.cq_engine_destroy.argtypes = [P]
+        L.cq_engine_destroy.restype = None
         L.cq_timer_enable.argtypes = [ctypes.c_char_p, i32]
         L.cq_timer_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(f64)]
         L.cq_timer_disable.argtypes = []
@@ -303,3 +325,71 @@ def cq_quantize_batch(jobs: list[BatchJob], ws: BatchWorkspace) -> list[dict]:
     rc = lib().cq_quantize_batch(arr, len(jobs), stats, ws.ptr, ws.nbytes, _stream(ws.device))
     _check("cq_quantize_batch", rc)
     return [st.as_dict() for st in stats]
+
+
+def engine_job_bytes(H: int, W: int) -> int:
+    """Pool bytes one H x W job holds while it is in flight."""
+    n = lib().cq_engine_job_bytes(H, W)
+    if n == 0:
+        raise ValueError(f"invalid image size {H}x{W}")
+    return n
+
+
+class Engine:
+    """Continuous-batching serving engine (cq_engine_*): jobs are submitted at
+    any time, admitted in submission order when their slot fits the pool, and
+    reported by step() once they finish.  The engine keeps each job's tensors
+    alive until then."""
+
+    def __init__(self, max_jobs: int, pool_bytes: int, device="cuda"):
+        self.device = torch.device(device)
+        self.max_jobs = max_jobs
+        self.nbytes = lib().cq_engine_workspace_bytes(max_jobs, pool_bytes)
+        if self.nbytes == 0:
+            raise ValueError("invalid engine size")
+        self._buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._buf.data_ptr()
+        self.ptr = ctypes.c_void_p(base + (-base) % 256)
+        h = ctypes.c_void_p()
+        _check("cq_engine_create", lib().cq_engine_create(max_jobs, self.ptr, self.nbytes,
+                                                          _stream(self.device), ctypes.byref(h)))
+        self._h = h
+        self._jobs: dict[int, BatchJob] = {}
+        self._done = (CqEngineDone * max_jobs)()
+
+    def submit(self, job: BatchJob) -> int:
+        t = ctypes.c_int64()
+        _check("cq_engine_submit", lib().cq_engine_submit(self._h, ctypes.byref(job.c), ctypes.byref(t)))
+        self._jobs[t.value] = job
+        return t.value
+
+    def step(self, iters: int = 8) -> list[tuple[int, BatchJob, dict]]:
+        """One engine step; returns (ticket, job, stats) of the jobs that finished
+        (stats["status"] is the job's own status)."""
+        n = ctypes.c_int32()
+        _check("cq_engine_step", lib().cq_engine_step(self._h, iters, self._done, self.max_jobs,
+                                                      ctypes.byref(n)))
+        out = []
+        for d in self._done[:n.value]:
+            st = d.stats.as_dict()
+            st["status"] = d.status  # CQ_OK, or the job's own device-side failure
+            out.append((d.ticket, self._jobs.pop(d.ticket), st))
+        return out
+
+    def pending(self) -> tuple[int, int, int]:
+        """(queued, running, pool bytes in use)."""
+        q, r, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        _check("cq_engine_pending", lib().cq_engine_pending(self._h, ctypes.byref(q), ctypes.byref(r),
+                                                            ctypes.byref(u)))
+        return q.value, r.value, u.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().cq_engine_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

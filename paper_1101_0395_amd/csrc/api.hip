@@ -8,34 +8,9 @@
 #include <deque>
 #include <vector>
 
-#include "cq_internal.h"
+#include "batch.h"
 
 namespace cq {
-
-// kernels launched from the other translation units
-int hist_blocks(int64_t npix);
-int hist_count_blocks(int64_t npix);
-cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_hist_blocks, int total_count,
-                           hipStream_t s);
-int coop_capacity();
-int coop_team_blocks(int64_t n);
-bool coop_fits_lds(int64_t C);
-cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s);
-cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s);
-cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, bool lds, hipStream_t s);
-cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s);
-cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool first, int all_blocks,
-                             int full_blocks, int walk_blocks, int update_blocks, bool regroup,
-                             int table_blocks, hipStream_t s);
-int regroup_period();
-int update_table_blocks(int K, int prune);
-cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s);
-int64_t assign_chunk(int64_t n);
-int64_t regroup_blocks(int64_t n);
-cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int blocks, hipStream_t s);
-int map_blocks(int64_t npix);
-cq_status launch_lut(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s);
-cq_status launch_map(const JobDev* jobs, const int* maps, int B, int total, hipStream_t s);
 
 // ---------------------------------------------------------------- errors
 static thread_local char g_error[512];
@@ -60,7 +35,7 @@ cq_status check_launch(const char* what)
     return CQ_OK;
 }
 
-static cq_status einval(const char* fmt, ...)
+cq_status einval(const char* fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
@@ -68,12 +43,6 @@ static cq_status einval(const char* fmt, ...)
     va_end(ap);
     return CQ_EINVAL;
 }
-
-#define CQ_TRY(expr)                     \
-    do {                                 \
-        cq_status st_ = (expr);          \
-        if (st_ != CQ_OK) return st_;    \
-    } while (0)
 
 // ---------------------------------------------------------------- kernel timer
 struct KernelTimer {
@@ -120,7 +89,7 @@ static cq_status check_image(const uint8_t* img, int32_t H, int32_t W, int64_t r
     return CQ_OK;
 }
 
-static cq_status check_ws(const void* ws, size_t ws_bytes, size_t need)
+cq_status check_ws(const void* ws, size_t ws_bytes, size_t need)
 {
     if (!ws) {
         set_error("workspace is null");
@@ -151,37 +120,6 @@ static cq_status check_iters_tol(int32_t max_iters, double tol)
 }
 
 // ---------------------------------------------------------------- batches
-// Host view of one launch sequence: job descriptors, block maps, and the
-// device descriptor region they are copied to.
-struct Batch {
-    int B = 0;
-    char* desc = nullptr;
-    hipStream_t s = nullptr;
-    std::vector<JobDev> h;
-    std::vector<int> maps;
-    std::vector<JobResult> res;
-    std::deque<std::vector<char>> staged;  // host copies behind every upload, kept until the call ends
-
-    Batch(int nb, char* d, hipStream_t st)
-        : B(nb), desc(d), s(st), h(size_t(nb)), maps(size_t(kNumMaps) * (nb + 1), 0), res(size_t(nb))
-    {
-        memset(static_cast<void*>(h.data()), 0, sizeof(JobDev) * h.size());
-    }
-    JobDev* d_jobs() const { return reinterpret_cast<JobDev*>(desc); }
-    int* d_maps() const { return reinterpret_cast<int*>(desc + desc_maps_off(B)); }
-    JobResult* d_results() const { return reinterpret_cast<JobResult*>(desc + desc_results_off(B)); }
-
-    // map `id` from per-job block counts; returns the total
-    template <typename F>
-    int set_map(int id, F blocks_of)
-    {
-        int* m = maps.data() + size_t(id) * (B + 1);
-        m[0] = 0;
-        for (int j = 0; j < B; ++j) m[j + 1] = m[j] + blocks_of(j);
-        return m[B];
-    }
-};
-
 // Points the workspace-backed fields of a job at one slot with layout L.
 static void bind_slot(JobDev& J, char* slot, const Layout& L)
 {
@@ -215,7 +153,7 @@ static void set_image(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64
 
 // Copies the job descriptors and block maps to the device.  Each upload reads
 // its own host snapshot, which outlives the asynchronous copy.
-static cq_status upload(Batch& b)
+cq_status upload(Batch& b)
 {
     const size_t jb = sizeof(JobDev) * size_t(b.B), mb = sizeof(int) * b.maps.size();
     b.staged.emplace_back(jb + mb);
@@ -255,16 +193,17 @@ __global__ void k_zero_sq_err(const JobDev* __restrict__ jobs, int B)
 }
 
 // Gathers every job's control block into b.res (synchronizes the stream).
-static cq_status collect(Batch& b)
+cq_status collect(Batch& b)
 {
     CQ_TIMED_LAUNCH("k_collect", b.s, k_collect<<<(b.B + 63) / 64, 64, 0, b.s>>>(b.d_jobs(), b.B, b.d_results()));
     CQ_HIP_TRY(hipMemcpyAsync(b.res.data(), b.d_results(), sizeof(JobResult) * size_t(b.B), hipMemcpyDeviceToHost, b.s));
     CQ_HIP_TRY(hipStreamSynchronize(b.s));
+    b.staged.clear();  // every upload before this point has completed
     return CQ_OK;
 }
 
 // ---------------------------------------------------------------- phases
-static cq_status run_histogram(Batch& b)
+cq_status run_histogram(Batch& b)
 {
     const int total = b.set_map(kMapHist, [&](int j) { return hist_blocks(int64_t(b.h[j].H) * b.h[j].W); });
     const int count = b.set_map(kMapHistCount, [&](int j) { return hist_count_blocks(int64_t(b.h[j].H) * b.h[j].W); });
@@ -273,7 +212,7 @@ static cq_status run_histogram(Batch& b)
 }
 
 // Once N' is known (from the histogram or from the caller).
-static void set_counts(Batch& b, const std::vector<int64_t>& n)
+void set_counts(Batch& b, const std::vector<int64_t>& n)
 {
     for (int j = 0; j < b.B; ++j) {
         JobDev& J = b.h[j];
@@ -283,7 +222,7 @@ static void set_counts(Batch& b, const std::vector<int64_t>& n)
     }
 }
 
-static cq_status run_init(Batch& b)
+cq_status run_init(Batch& b)
 {
     CQ_TRY(upload(b));
     CQ_TRY(launch_init_begin(b.d_jobs(), b.B, b.s));
@@ -339,7 +278,7 @@ static cq_status run_init(Batch& b)
 // Iterations of every job until all have stopped.  Iterations are enqueued
 // in groups; a stopped job's blocks return at once, so one readback per group
 // suffices.
-static cq_status run_kmeans(Batch& b)
+cq_status run_kmeans(Batch& b)
 {
     // every job iterates in step with the launches, so the host knows which
     // iterations regroup (the same rule as on the device)
@@ -383,7 +322,7 @@ static cq_status run_kmeans(Batch& b)
     return CQ_OK;
 }
 
-static cq_status run_map(Batch& b, bool with_err)
+cq_status run_map(Batch& b, bool with_err)
 {
     const int lut_total = b.set_map(kMapLut, [&](int j) {
         const JobDev& J = b.h[j];
@@ -400,7 +339,7 @@ static cq_status run_map(Batch& b, bool with_err)
     return CQ_OK;
 }
 
-static void fill_stats(const JobDev& J, const JobResult& r, cq_stats& st, bool with_img)
+void fill_stats(const JobDev& J, const JobResult& r, cq_stats& st, bool with_img)
 {
     memset(&st, 0, sizeof st);
     st.iters = r.iters;
@@ -416,7 +355,7 @@ static void fill_stats(const JobDev& J, const JobResult& r, cq_stats& st, bool w
 }
 
 // After the initialization: a team barrier that gave up is a device error.
-static cq_status check_init(const Batch& b)
+cq_status check_init(const Batch& b)
 {
     for (int j = 0; j < b.B; ++j) {
         if (b.res[j].sync_error) {
@@ -428,7 +367,7 @@ static cq_status check_init(const Batch& b)
 }
 
 // After the iterations (fields written by the k-means begin kernel).
-static cq_status check_kmeans(const Batch& b)
+cq_status check_kmeans(const Batch& b)
 {
     for (int j = 0; j < b.B; ++j)
         if (b.res[j].bad_input) return einval("job %d: initial centres contain a non-finite value", j);
@@ -456,7 +395,7 @@ static cq_status run_quantize(Batch& b, cq_stats* stats)
     return CQ_OK;
 }
 
-static void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride, int32_t K,
+void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride, int32_t K,
                               int scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
                               uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, char* slot)
 {
@@ -482,9 +421,9 @@ static void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t 
                (reinterpret_cast<uintptr_t>(out_rgb) & 3u) == 0;
 }
 
-static size_t slot_bytes(const cq_job& j) { return align256(make_layout(int64_t(j.H) * j.W, int64_t(j.H) * j.W, true).total); }
+size_t slot_bytes(const cq_job& j) { return align256(make_layout(int64_t(j.H) * j.W, int64_t(j.H) * j.W, true).total); }
 
-static cq_status check_job(const cq_job& j, int idx)
+cq_status check_job(const cq_job& j, int idx)
 {
     cq_status s = check_image(j.img, j.H, j.W, j.row_stride_bytes);
     if (s == CQ_OK) s = check_k(j.K);

@@ -1,0 +1,101 @@
+// Host side of a batch: the job descriptors and block maps of one launch
+// sequence, and the phases of the quantizer over a batch (defined in
+// api.hip; the serving engine in engine.hip drives the same phases over the
+// jobs it has in flight).
+#pragma once
+
+#include <string.h>
+
+#include <deque>
+#include <vector>
+
+#include "cq_internal.h"
+
+namespace cq {
+
+// Host view of one launch sequence: job descriptors, block maps, and the
+// device descriptor region they are copied to.
+struct Batch {
+    int B = 0;
+    char* desc = nullptr;
+    hipStream_t s = nullptr;
+    std::vector<JobDev> h;
+    std::vector<int> maps;
+    std::vector<JobResult> res;
+    std::deque<std::vector<char>> staged;  // host copies behind the uploads, kept until the stream is synchronized
+
+    Batch(int nb, char* d, hipStream_t st)
+        : B(nb), desc(d), s(st), h(size_t(nb)), maps(size_t(kNumMaps) * (nb + 1), 0), res(size_t(nb))
+    {
+        memset(static_cast<void*>(h.data()), 0, sizeof(JobDev) * h.size());
+    }
+    JobDev* d_jobs() const { return reinterpret_cast<JobDev*>(desc); }
+    int* d_maps() const { return reinterpret_cast<int*>(desc + desc_maps_off(B)); }
+    JobResult* d_results() const { return reinterpret_cast<JobResult*>(desc + desc_results_off(B)); }
+
+    // map `id` from per-job block counts; returns the total
+    template <typename F>
+    int set_map(int id, F blocks_of)
+    {
+        int* m = maps.data() + size_t(id) * (B + 1);
+        m[0] = 0;
+        for (int j = 0; j < B; ++j) m[j + 1] = m[j] + blocks_of(j);
+        return m[B];
+    }
+};
+
+// kernels launched from the other translation units
+int hist_blocks(int64_t npix);
+int hist_count_blocks(int64_t npix);
+cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_hist_blocks, int total_count,
+                           hipStream_t s);
+int coop_capacity();
+int coop_team_blocks(int64_t n);
+bool coop_fits_lds(int64_t C);
+cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s);
+cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s);
+cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, bool lds, hipStream_t s);
+cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s);
+cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool first, int all_blocks,
+                             int full_blocks, int walk_blocks, int update_blocks, bool regroup,
+                             int table_blocks, hipStream_t s);
+int regroup_period();
+int update_table_blocks(int K, int prune);
+cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s);
+int64_t assign_chunk(int64_t n);
+int64_t regroup_blocks(int64_t n);
+cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int blocks, hipStream_t s);
+int map_blocks(int64_t npix);
+cq_status launch_lut(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s);
+cq_status launch_map(const JobDev* jobs, const int* maps, int B, int total, hipStream_t s);
+
+// argument checks (set the thread's error text)
+cq_status einval(const char* fmt, ...);
+cq_status check_ws(const void* ws, size_t ws_bytes, size_t need);
+cq_status check_job(const cq_job& j, int idx);
+
+// phases over a filled batch
+cq_status upload(Batch& b);
+cq_status collect(Batch& b);  // every job's control block into b.res; synchronizes the stream
+cq_status run_histogram(Batch& b);
+void set_counts(Batch& b, const std::vector<int64_t>& n);
+cq_status run_init(Batch& b);
+cq_status run_kmeans(Batch& b);
+cq_status run_map(Batch& b, bool with_err);
+cq_status check_init(const Batch& b);
+cq_status check_kmeans(const Batch& b);
+void fill_stats(const JobDev& J, const JobResult& r, cq_stats& st, bool with_img);
+
+// one whole-quantizer job in a slot of slot_bytes(j) bytes
+size_t slot_bytes(const cq_job& j);
+void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride, int32_t K,
+                       int scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
+                       uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, char* slot);
+
+#define CQ_TRY(expr)                     \
+    do {                                 \
+        cq_status st_ = (expr);          \
+        if (st_ != CQ_OK) return st_;    \
+    } while (0)
+
+}  // namespace cq

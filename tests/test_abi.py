@@ -107,3 +107,51 @@ def test_product_package_does_not_import_the_oracle():
                     text = fh.read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "cqref" not in text, f
+
+
+def test_engine_sizes_and_argument_checks_without_a_device():
+    """Engine calls that do no device work: sizing, creation over a workspace
+    that is never dereferenced, submission checks, step argument checks."""
+    L = cq.lib()
+    job_small = L.cq_engine_job_bytes(64, 64)
+    job_big = L.cq_engine_job_bytes(512, 512)
+    assert job_small % 256 == 0 and job_big > job_small > (1 << 24)
+    assert L.cq_engine_job_bytes(0, 4) == 0 and L.cq_engine_job_bytes(1 << 15, 1 << 14) == 0
+    head = L.cq_engine_workspace_bytes(4, 0)
+    assert head > 0 and L.cq_engine_workspace_bytes(4, 1000) == head + 1024
+    assert L.cq_engine_workspace_bytes(0, 0) == 0 and L.cq_engine_workspace_bytes(4097, 0) == 0
+
+    ws = ctypes.c_void_p(1 << 40)  # aligned, never dereferenced by these calls
+    h = ctypes.c_void_p()
+    rc, msg = _status(L.cq_engine_create, 4, ws, head - 1, None, ctypes.byref(h))
+    assert rc == cq.CQ_EWORKSPACE
+    rc, msg = _status(L.cq_engine_create, 0, ws, head, None, ctypes.byref(h))
+    assert rc == cq.CQ_EINVAL
+    pool = 2 * job_small + job_small // 2  # room for two 64x64 jobs
+    rc, msg = _status(L.cq_engine_create, 4, ws, head + pool, None, ctypes.byref(h))
+    assert rc == cq.CQ_OK and h.value
+    try:
+        fake = ctypes.c_void_p(0x10000)
+        job = cq.CqJob(fake, 64, 64, 192, 16, cq.INIT_KMEANSPP, 1, 10, 1e-4, 1, fake, None, None)
+        t = ctypes.c_int64()
+        for expect in (1, 2, 3):
+            assert L.cq_engine_submit(h, ctypes.byref(job), ctypes.byref(t)) == cq.CQ_OK
+            assert t.value == expect
+        big = cq.CqJob(fake, 2048, 2048, 6144, 16, cq.INIT_KMEANSPP, 1, 10, 1e-4, 1, fake, None, None)
+        rc, msg = _status(L.cq_engine_submit, h, ctypes.byref(big), ctypes.byref(t))
+        assert rc == cq.CQ_ECAPACITY and "pool" in msg
+        bad = cq.CqJob(fake, 64, 64, 192, 300, cq.INIT_KMEANSPP, 1, 10, 1e-4, 1, fake, None, None)
+        rc, msg = _status(L.cq_engine_submit, h, ctypes.byref(bad), ctypes.byref(t))
+        assert rc == cq.CQ_EINVAL and "K" in msg
+        q, r, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        assert L.cq_engine_pending(h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(u)) == cq.CQ_OK
+        assert (q.value, r.value, u.value) == (3, 0, 0)  # admission happens in a step
+        done = (cq.CqEngineDone * 4)()
+        n = ctypes.c_int32()
+        rc, msg = _status(L.cq_engine_step, h, 8, done, 3, ctypes.byref(n))
+        assert rc == cq.CQ_EINVAL and "capacity" in msg
+        rc, msg = _status(L.cq_engine_step, h, -1, done, 4, ctypes.byref(n))
+        assert rc == cq.CQ_EINVAL and "iters" in msg
+    finally:
+        L.cq_engine_destroy(h)
+    L.cq_engine_destroy(None)

@@ -20,3 +20,14 @@ def test_mod_u64_matches_integer_remainder(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "0 mismatches" in out.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_engine_pool_allocator_matches_byte_map_model(tmp_path):
+    exe = tmp_path / "pool_check"
+    src = os.path.join(ROOT, "tests", "host", "pool_check.cpp")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-I", CSRC, src, "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert " 0 mismatches" in out.stdout
