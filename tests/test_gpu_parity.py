@@ -247,6 +247,10 @@ def test_full_size_4096(cqm, dev):
     c0, _ = oracle.init(rk, rc, 256, oracle.INIT_KMEANSPP, 42)
     g0, _ = cqm.cq_init(keys, counts, 256, oracle.INIT_KMEANSPP, 42, ws)
     assert np.array_equal(g0.cpu().numpy(), c0)
+    # more colours than the blocks of a team keep in LDS: runs read from memory
+    m0, _ = oracle.init(rk, rc, 64, oracle.INIT_MAXMIN, 5)
+    gm, _ = cqm.cq_init(keys, counts, 64, oracle.INIT_MAXMIN, 5, ws)
+    assert np.array_equal(gm.cpu().numpy(), m0)
     r = oracle.kmeans(rk, rc, c0, 3, 1e-4, True)
     g = cqm.cq_kmeans(keys, counts, _to_dev(c0, dev), 3, 1e-4, True, ws)
     _compare_kmeans(g, r)
