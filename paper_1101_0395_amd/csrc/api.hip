@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <deque>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "batch.h"
@@ -202,6 +204,58 @@ cq_status collect(Batch& b)
     return CQ_OK;
 }
 
+// Stream (one per device, default priority, never destroyed) for readbacks
+// that must not queue behind later work on the caller's stream.
+static cq_status side_stream(hipStream_t* out)
+{
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    int dev = 0;
+    CQ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = streams.find(dev);
+    if (it == streams.end()) {
+        hipStream_t st = nullptr;
+        CQ_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        it = streams.emplace(dev, st).first;
+    }
+    *out = it->second;
+    return CQ_OK;
+}
+
+cq_status collect_async(Batch& b, int slot, hipEvent_t done)
+{
+    CQ_TIMED_LAUNCH("k_collect", b.s, k_collect<<<(b.B + 63) / 64, 64, 0, b.s>>>(b.d_jobs(), b.B, b.d_results(slot)));
+    CQ_HIP_TRY(hipEventRecord(done, b.s));
+    return CQ_OK;
+}
+
+cq_status read_results(Batch& b, int slot, hipEvent_t done)
+{
+    hipStream_t side = nullptr;
+    CQ_TRY(side_stream(&side));
+    CQ_HIP_TRY(hipStreamWaitEvent(side, done, 0));
+    CQ_HIP_TRY(hipMemcpyAsync(b.res.data(), b.d_results(slot), sizeof(JobResult) * size_t(b.B), hipMemcpyDeviceToHost,
+                              side));
+    CQ_HIP_TRY(hipStreamSynchronize(side));
+    return CQ_OK;
+}
+
+// Two events without timing, destroyed with the object.
+struct EventPair {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    cq_status create()
+    {
+        for (auto& e : ev) CQ_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        return CQ_OK;
+    }
+    ~EventPair()
+    {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
 // ---------------------------------------------------------------- phases
 cq_status run_histogram(Batch& b)
 {
@@ -306,18 +360,27 @@ cq_status run_kmeans(Batch& b)
     CQ_TRY(upload(b));
     CQ_TRY(launch_kmeans_begin(b.d_jobs(), b.B, b.s));
     if (assign_total == 0) return collect(b);
+    // The status of group g is read while group g + 1 runs: the device never
+    // waits for the host, and the group enqueued after the last job stopped
+    // costs only early returns.
+    EventPair ev;
+    CQ_TRY(ev.create());
     const int group = 8;
-    for (int it = 1; it <= max_iters; it += group) {
+    bool all_done = false;
+    for (int it = 1, g = 0; it <= max_iters; it += group, ++g) {
         const int n_it = it + group - 1 <= max_iters ? group : max_iters - it + 1;
         for (int q = 0; q < n_it; ++q)
             CQ_TRY(launch_kmeans_iter(b.d_jobs(), b.d_maps(), b.B, it + q == 1, assign_total, full_total,
                                       walk_total, update_total, regroup_at(it + q, period), table_total,
                                       b.s));
-        CQ_TRY(collect(b));
-        bool all_done = true;
+        CQ_TRY(collect_async(b, g & 1, ev.ev[g & 1]));
+        if (g == 0) continue;
+        CQ_TRY(read_results(b, (g - 1) & 1, ev.ev[(g - 1) & 1]));
+        all_done = true;
         for (const JobResult& r : b.res) all_done = all_done && r.done;
         if (all_done) break;
     }
+    if (!all_done) CQ_TRY(collect(b));  // the state after the last group
     bool grouped = false;
     for (const JobDev& J : b.h) grouped = grouped || (J.prune && J.n > J.K);
     if (grouped) CQ_TRY(launch_unpermute(b.d_jobs(), b.d_maps(), b.B, assign_total, b.s));

@@ -31,7 +31,10 @@ struct Batch {
     }
     JobDev* d_jobs() const { return reinterpret_cast<JobDev*>(desc); }
     int* d_maps() const { return reinterpret_cast<int*>(desc + desc_maps_off(B)); }
-    JobResult* d_results() const { return reinterpret_cast<JobResult*>(desc + desc_results_off(B)); }
+    JobResult* d_results(int slot = 0) const
+    {
+        return reinterpret_cast<JobResult*>(desc + desc_results_off(B) + size_t(slot) * align256(sizeof(JobResult) * size_t(B)));
+    }
 
     // map `id` from per-job block counts; returns the total
     template <typename F>
@@ -77,6 +80,11 @@ cq_status check_job(const cq_job& j, int idx);
 // phases over a filled batch
 cq_status upload(Batch& b);
 cq_status collect(Batch& b);  // every job's control block into b.res; synchronizes the stream
+// Copies every job's control block to result slot `slot` and records `done`
+// on the batch stream; read_results waits for that event only (not for work
+// enqueued after it) and fills b.res from the slot.
+cq_status collect_async(Batch& b, int slot, hipEvent_t done);
+cq_status read_results(Batch& b, int slot, hipEvent_t done);
 cq_status run_histogram(Batch& b);
 void set_counts(Batch& b, const std::vector<int64_t>& n);
 cq_status run_init(Batch& b);

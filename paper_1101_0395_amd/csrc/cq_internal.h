@@ -226,10 +226,12 @@ __device__ __forceinline__ int find_job(const int* __restrict__ map, int B, int 
 }
 
 // Descriptor region: jobs, block maps, gathered results.
+// Descriptor region of a batch: job descriptors, block maps, and two slots of
+// control-block copies (read back alternately while iterations continue).
 inline size_t desc_bytes(int B)
 {
     return align256(sizeof(JobDev) * size_t(B)) + align256(sizeof(int) * size_t(kNumMaps) * size_t(B + 1)) +
-           align256(sizeof(JobResult) * size_t(B));
+           2 * align256(sizeof(JobResult) * size_t(B));
 }
 inline size_t desc_maps_off(int B) { return align256(sizeof(JobDev) * size_t(B)); }
 inline size_t desc_results_off(int B)

@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
             unsigned long long pending = __ballot(valid);
             while (pending) {
                 const int leader = __ffsll(pending) - 1;
-                const int ps = __builtin_amdgcn_readfirstlane(__shfl(p, leader, 64));
+                const int ps = __builtin_amdgcn_readlane(p, leader);
                 const bool mine = valid && p == ps;
                 const Rec CQ_CONST* row = rec + ps * kRow;
                 const int32_t CQ_CONST* trow = tix + ps * kRow;
@@ -403,12 +403,33 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
     const int k = threadIdx.x;
     const int lane = k & 63;
     const int npairs = J.K * kBuckets;
+    const int64_t n = J.n;
+    const int rb = record_buffer(it, J.regroup_period);
+    const uint64_t* __restrict__ src = gp(J.grp) + rb * n;
+    uint64_t* __restrict__ dst = gp(J.grp) + (rb ^ 1) * n;
+    const int64_t lo = int64_t(s) * kScatterChunk;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // the block's records first, in flight while the offsets are computed
+    constexpr int kPasses = kScatterChunk / kMaxK;
+    uint64_t g[kPasses];
+#pragma unroll
+    for (int u = 0; u < kPasses; ++u) {
+        const int64_t i = lo + u * kMaxK + k;
+        g[u] = i < n ? src[i] : 0ull;
+    }
+    // pair counts: coalesced loads into LDS, then each thread scans its run
+    // of kPer consecutive pairs
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int cb = u * kMaxK + k;
+        start[cb + cb / kPer] = cb < npairs ? uint32_t(cur[kSumColours + cb]) : 0u;
+    }
+    __syncthreads();
     uint32_t c[kPer];
     uint32_t tsum = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-        const int cb = k * kPer + u;
-        c[u] = cb < npairs ? uint32_t(cur[kSumColours + cb]) : 0u;
+        c[u] = start[k * (kPer + 1) + u];
         tsum += c[u];
     }
     uint32_t run = block_exclusive_scan<uint32_t>(tsum, scan_tmp, nullptr);
@@ -418,24 +439,11 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
         run += c[u];
     }
     __syncthreads();
-    const int64_t n = J.n;
-    const int rb = record_buffer(it, J.regroup_period);
-    const uint64_t* __restrict__ src = gp(J.grp) + rb * n;
-    uint64_t* __restrict__ dst = gp(J.grp) + (rb ^ 1) * n;
-    const int64_t lo = int64_t(s) * kScatterChunk;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    // every record of the block is loaded and ranked within its wave's group of
-    // equal (cluster, bucket) first; the group leaders then reserve their
-    // places with atomics that are all in flight together
-    constexpr int kPasses = kScatterChunk / kMaxK;
-    uint64_t g[kPasses];
+    // every record of the block is ranked within its wave's group of equal
+    // (cluster, bucket) first; the group leaders then reserve their places
+    // with atomics that are all in flight together
     int cbv[kPasses], lead[kPasses], rank[kPasses];
     unsigned long long pos[kPasses];
-#pragma unroll
-    for (int u = 0; u < kPasses; ++u) {
-        const int64_t i = lo + u * kMaxK + k;
-        g[u] = i < n ? src[i] : 0ull;
-    }
 #pragma unroll
     for (int u = 0; u < kPasses; ++u) {
         const bool valid = lo + u * kMaxK + k < n;
@@ -446,7 +454,7 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
         unsigned long long pending = __ballot(valid);
         while (pending) {
             const int leader = __ffsll(pending) - 1;
-            const int cs = __builtin_amdgcn_readfirstlane(__shfl(cbv[u], leader, 64));
+            const int cs = __builtin_amdgcn_readlane(cbv[u], leader);
             const bool mine = valid && cbv[u] == cs;
             const unsigned long long mask = __ballot(mine);
             if (mine) {
@@ -472,115 +480,148 @@ __device__ __forceinline__ bool entry_less(double k1, int i1, double k2, int i2)
     return k1 < k2 || (k1 == k2 && i1 < i2);
 }
 
-// Row `a` of the table for the next iteration, built by one block of kMaxK
-// threads: the centres ordered by (distance from c_a, index), a itself first
-// (key -1), slots past K keyed +inf.  The centres move little from one
-// iteration to the next, so the row starts from its previous order
-// (iteration 1: index order): if that is still sorted nothing moves,
-// otherwise up to kFixPasses rounds of odd-even transposition repair it, and
-// a full bitonic sort handles whatever is left.
+// Row `a` of the table for the next iteration, built by one wave: the
+// centres ordered by (distance from c_a, index), a itself first (key -1),
+// slots past K keyed +inf.  Lane l holds the four consecutive entries 4 l ..
+// 4 l + 3 in registers.  The centres move little from one iteration to the
+// next, so the row starts from its previous order (iteration 1: index
+// order): if that is still sorted nothing moves, otherwise up to kFixPasses
+// rounds of odd-even transposition repair it (the pairs inside a lane in
+// registers, the pair across two lanes with one shuffle), and a bitonic sort
+// of the whole row handles whatever is left.
 constexpr int kFixPasses = 8;
+constexpr int kRowsPerBlock = kMaxK / 64;  // one wave per row
+constexpr int kPerLane = kRow / 64;        // entries per lane
 
-__device__ __forceinline__ void build_row(const JobDev& J, int a, int K, int it, const double* c, double* key,
-                                          int* sidx)
+__device__ __forceinline__ void cmp_swap(double& k0, int& i0, double& k1, int& i1)
 {
-    const int e = threadIdx.x;
+    if (entry_less(k1, i1, k0, i0)) {
+        const double tk = k0;
+        const int ti = i0;
+        k0 = k1;
+        i0 = i1;
+        k1 = tk;
+        i1 = ti;
+    }
+}
+
+__device__ __forceinline__ void build_row(const JobDev& J, int a, int K, int it, const double* c)
+{
+    const int lane = threadIdx.x & 63;
     Rec* __restrict__ row = gp(J.rec) + a * kRow;
     int32_t* __restrict__ trow = gp(J.tix) + a * kRow;
-    const int f = (it > 1 && e < K) ? trow[e] : e;  // previous order, read before this block rewrites it
-    double mk = f >= K ? __builtin_inf()
-                       : (f == a ? -1.0 : dist_f64(c[3 * a], c[3 * a + 1], c[3 * a + 2], c[3 * f], c[3 * f + 1], c[3 * f + 2]));
-    int mi = f;
-    key[e] = mk;
-    sidx[e] = mi;
-    __syncthreads();
-    bool unsorted = e + 1 < kMaxK && entry_less(key[e + 1], sidx[e + 1], mk, mi);
-    int pass = 0;
-    while (__syncthreads_or(unsorted) && pass < kFixPasses) {
-        // even pairs (2i, 2i+1), then odd pairs (2i+1, 2i+2)
+    const double a0 = c[3 * a], a1 = c[3 * a + 1], a2 = c[3 * a + 2];
+    double k[kPerLane];
+    int x[kPerLane];
 #pragma unroll
-        for (int phase = 0; phase < 2; ++phase) {
-            const bool low = ((e - phase) & 1) == 0;  // e is the first of its pair
-            const int partner = low ? e + 1 : e - 1;
-            const bool has = low ? (e + 1 < kMaxK && e >= phase) : (e >= 1 + phase);
-            double pk = mk;
-            int pi = mi;
-            if (has) {
-                pk = key[partner];
-                pi = sidx[partner];
-            }
-            __syncthreads();
-            if (has) {
-                const bool pless = entry_less(pk, pi, mk, mi);
-                if (low ? pless : !pless) {
-                    mk = pk;
-                    mi = pi;
-                }
-            }
-            key[e] = mk;
-            sidx[e] = mi;
-            __syncthreads();
-        }
-        unsorted = e + 1 < kMaxK && entry_less(key[e + 1], sidx[e + 1], mk, mi);
-        ++pass;
+    for (int i = 0; i < kPerLane; ++i) {
+        const int e = kPerLane * lane + i;
+        const int f = (it > 1 && e < K) ? trow[e] : e;  // previous order, read before the wave rewrites it
+        x[i] = f;
+        k[i] = f >= K ? __builtin_inf()
+                      : (f == a ? -1.0 : dist_f64(a0, a1, a2, c[3 * f], c[3 * f + 1], c[3 * f + 2]));
     }
-    if (__syncthreads_or(unsorted)) {
-        // bitonic sort; partners closer than a wave are read with shuffles
-        for (int size = 2; size <= kMaxK; size <<= 1) {
+    auto unsorted = [&]() {
+        bool u = false;
+#pragma unroll
+        for (int i = 0; i + 1 < kPerLane; ++i) u = u || entry_less(k[i + 1], x[i + 1], k[i], x[i]);
+        const double nk = __shfl_down(k[0], 1, 64);
+        const int nx = __shfl_down(x[0], 1, 64);
+        if (lane < 63) u = u || entry_less(nk, nx, k[kPerLane - 1], x[kPerLane - 1]);
+        return __ballot(u) != 0ull;
+    };
+    bool uns = unsorted();
+    for (int pass = 0; uns && pass < kFixPasses; ++pass) {
+        // even pairs (2m, 2m+1): inside the lane
+#pragma unroll
+        for (int i = 0; i + 1 < kPerLane; i += 2) cmp_swap(k[i], x[i], k[i + 1], x[i + 1]);
+        // odd pairs (2m+1, 2m+2): inside the lane, and the lane's last entry
+        // with the next lane's first (each side keeps its half of the pair)
+#pragma unroll
+        for (int i = 1; i + 1 < kPerLane; i += 2) cmp_swap(k[i], x[i], k[i + 1], x[i + 1]);
+        const double nk = __shfl_down(k[0], 1, 64);
+        const int nx = __shfl_down(x[0], 1, 64);
+        const double pk = __shfl_up(k[kPerLane - 1], 1, 64);
+        const int px = __shfl_up(x[kPerLane - 1], 1, 64);
+        if (lane < 63 && entry_less(nk, nx, k[kPerLane - 1], x[kPerLane - 1])) {
+            k[kPerLane - 1] = nk;
+            x[kPerLane - 1] = nx;
+        }
+        if (lane > 0 && entry_less(k[0], x[0], pk, px)) {
+            k[0] = pk;
+            x[0] = px;
+        }
+        uns = unsorted();
+    }
+    if (uns) {
+        // bitonic sort over entry e = kPerLane lane + i: partners kPerLane or
+        // more apart sit in other lanes (same register), closer ones in this lane
+        for (int size = 2; size <= kRow; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                double pk;
-                int pi;
-                if (stride >= 64) {
-                    __syncthreads();
-                    key[e] = mk;
-                    sidx[e] = mi;
-                    __syncthreads();
-                    pk = key[e ^ stride];
-                    pi = sidx[e ^ stride];
+                if (stride >= kPerLane) {
+                    const int ls = stride / kPerLane;
+#pragma unroll
+                    for (int i = 0; i < kPerLane; ++i) {
+                        const double pk = __shfl_xor(k[i], ls, 64);
+                        const int px = __shfl_xor(x[i], ls, 64);
+                        const int e = kPerLane * lane + i;
+                        const bool ascending = (e & size) == 0;
+                        const bool lower = (e & stride) == 0;
+                        const bool partner_less = entry_less(pk, px, k[i], x[i]);
+                        if ((lower == ascending) ? partner_less : !partner_less) {
+                            k[i] = pk;
+                            x[i] = px;
+                        }
+                    }
                 } else {
-                    pk = __shfl_xor(mk, stride, 64);
-                    pi = __shfl_xor(mi, stride, 64);
-                }
-                const bool partner_less = entry_less(pk, pi, mk, mi);
-                const bool ascending = (e & size) == 0;
-                const bool lower = (e & stride) == 0;
-                const bool take = (lower == ascending) ? partner_less : !partner_less;
-                if (take) {
-                    mk = pk;
-                    mi = pi;
+#pragma unroll
+                    for (int i = 0; i < kPerLane; ++i) {
+                        if (i & stride) continue;
+                        const int j = i | stride;
+                        const bool ascending = ((kPerLane * lane + i) & size) == 0;
+                        if (ascending)
+                            cmp_swap(k[i], x[i], k[j], x[j]);
+                        else
+                            cmp_swap(k[j], x[j], k[i], x[i]);
+                    }
                 }
             }
         }
     }
-    if (e >= K) return;
-    Rec r;
-    r.c0 = c[3 * mi];
-    r.c1 = c[3 * mi + 1];
-    r.c2 = c[3 * mi + 2];
-    r.d = mi == a ? 0.0 : mk;
-    row[e] = r;
-    trow[e] = mi;
+#pragma unroll
+    for (int i = 0; i < kPerLane; ++i) {
+        const int e = kPerLane * lane + i;
+        if (e >= K) continue;
+        Rec r;
+        r.c0 = c[3 * x[i]];
+        r.c1 = c[3 * x[i] + 1];
+        r.c2 = c[3 * x[i] + 2];
+        r.d = x[i] == a ? 0.0 : k[i];
+        row[e] = r;
+        trow[e] = x[i];
+    }
 }
 
 // Update step, SSE, stopping rule and, in pruned runs, the sorted table and
-// colour order of the next iteration.  A pruned job gets K_j table blocks
-// (one per row) followed by its regrouping blocks; an unpruned job a single
-// block.  Every table block derives the new
-// centres from this iteration's cluster sums in LDS; the job's block 0 alone
-// writes the centres, the SSE trace and the control block and clears the
-// statistics of the next iteration.  An empty cluster keeps its centre: its
-// global entry is neither rewritten nor changed, so the other blocks may read
-// it.
-__device__ __forceinline__ int table_blocks(const JobDev& J)
+// colour order of the next iteration.  A pruned job gets ceil(K_j / 4) table
+// blocks (one wave per row) followed by its regrouping blocks; an unpruned
+// job a single block.  Every table block derives the new centres from this
+// iteration's cluster sums in LDS; the job's block 0 alone writes the
+// centres, the SSE trace and the control block and clears the statistics of
+// the next iteration.  An empty cluster keeps its centre: its global entry is
+// neither rewritten nor changed, so the other blocks may read it.
+__host__ __device__ __forceinline__ int table_blocks_of(int K, int prune)
 {
-    return J.prune ? J.K : 1;
+    return prune ? (K + kRowsPerBlock - 1) / kRowsPerBlock : 1;
 }
+
+__device__ __forceinline__ int table_blocks(const JobDev& J) { return table_blocks_of(J.K, J.prune); }
 
 __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ jobs,
                                                   const int* __restrict__ map, int B)
 {
     // one LDS buffer, used either by a table block or by a regrouping block
-    constexpr int kTableWords = 2 * (3 * kMaxK + kMaxK + kMaxK + 2 * (kMaxK / 64) + kMaxK) + kMaxK;
+    constexpr int kTableWords = 2 * (3 * kMaxK + kMaxK + kMaxK + 2 * (kMaxK / 64));
     constexpr int kLdsWords = kTableWords > kStartWords + 64 ? kTableWords : kStartWords + 64;
     __shared__ __attribute__((aligned(16))) uint32_t smem[kLdsWords];
     const int jb = find_job(map, B, blockIdx.x);
@@ -602,8 +643,6 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     double* term = c + 3 * kMaxK;
     unsigned long long* wsum = reinterpret_cast<unsigned long long*>(term + kMaxK);
     unsigned long long* cnt_red = wsum + kMaxK;
-    double* key = reinterpret_cast<double*>(cnt_red + 2 * (kMaxK / 64));
-    int* sidx = reinterpret_cast<int*>(key + kMaxK);
     double* __restrict__ centers = gp(J.centers);
     const int k = threadIdx.x;
     double t = 0.0;
@@ -688,7 +727,8 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
         }
     }
     if (!J.prune) return;
-    build_row(J, a, K, it, c, key, sidx);
+    const int r = a * kRowsPerBlock + int(threadIdx.x >> 6);
+    if (r < K) build_row(J, r, K, it, c);
 }
 
 // Pruned runs that grouped their colours: the final cluster of every colour
@@ -823,7 +863,7 @@ cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int block
 int64_t regroup_blocks(int64_t n) { return (n + kScatterChunk - 1) / kScatterChunk; }
 
 // Update blocks of a job before its regrouping blocks.
-int update_table_blocks(int K, int prune) { return prune ? K : 1; }
+int update_table_blocks(int K, int prune) { return table_blocks_of(K, prune); }
 
 // Iterations between regroupings of the colour records (after the first
 // four); the environment variable CQ_REGROUP_PERIOD overrides the default.
