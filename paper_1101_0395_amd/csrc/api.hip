@@ -279,19 +279,20 @@ void set_counts(Batch& b, const std::vector<int64_t>& n)
 cq_status run_init(Batch& b)
 {
     bool any_forgy = false;
-    std::vector<int> want(size_t(b.B), 0);
+    std::vector<int64_t> coop_n(size_t(b.B), 0);
     for (int j = 0; j < b.B; ++j) {
         JobDev& J = b.h[j];
         J.init_blocks = 0;
         if (J.n <= J.K) continue;
         if (J.scheme == CQ_INIT_FORGY) any_forgy = true;
-        if (J.scheme == CQ_INIT_MAXMIN || J.scheme == CQ_INIT_KMEANSPP) want[j] = coop_team_blocks(J.n);
-        J.init_blocks = want[j];  // the begin kernel clears this many blocks' published values
+        if (J.scheme == CQ_INIT_MAXMIN || J.scheme == CQ_INIT_KMEANSPP) coop_n[j] = J.n;
     }
+    const int cap = coop_capacity();
+    std::vector<int> want(size_t(b.B), 0);
+    coop_team_sizes(coop_n.data(), want.data(), b.B, cap);
     CQ_TRY(upload(b));
     CQ_TRY(launch_init_begin(b.d_jobs(), b.B, b.s));
     if (any_forgy) CQ_TRY(launch_forgy(b.d_jobs(), b.B, b.s));
-    const int cap = coop_capacity();
     int next = 0;
     while (true) {
         while (next < b.B && want[next] == 0) ++next;

@@ -54,6 +54,7 @@ cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total
                            hipStream_t s);
 int coop_capacity();
 int coop_team_blocks(int64_t n);
+void coop_team_sizes(const int64_t* n, int* want, int B, int cap);
 bool coop_fits_lds(int64_t C);
 cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s);
 cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s);

@@ -85,12 +85,9 @@ __global__ void __launch_bounds__(kMaxK) k_init_begin(const JobDev* __restrict__
         gp(J.meta)->pick_epoch = 0;
     }
     // round tags of the cooperative initialization start below round 1: the
-    // block slots and the run sums of the team (init_blocks is an upper bound
-    // of its size here)
+    // block slots and the pick slots
     uint64_t* __restrict__ vals = gp(J.vals);
-    for (int t = k; t < 2 * kInitMaxBlocks; t += blockDim.x) vals[t] = 0ull;
-    const int64_t nrs = int64_t(2) * J.init_blocks * kInitThreads;
-    for (int64_t t = k; t < nrs; t += blockDim.x) vals[2 * kInitMaxBlocks + t] = 0ull;
+    for (int t = k; t < 2 * kInitMaxBlocks + 2; t += blockDim.x) vals[t] = 0ull;
     if (J.n > J.K || k >= J.K) return;
     if (k < J.n) {
         write_center(J.centers, k, gp(J.keys)[k]);
@@ -103,37 +100,33 @@ __global__ void __launch_bounds__(kMaxK) k_init_begin(const JobDev* __restrict__
 // Cooperative MMX / KPP: one launch runs all K rounds of every job, each job
 // with its own team of G co-resident blocks.  Block b of a team owns the
 // colours [b C, (b+1) C); thread t of a block owns the run of R = C / 512
-// (rounded up) consecutive colours from t R on.  Round j (its pick is the same
-// in every block):
+// (rounded up) consecutive colours from t R on.  Round j:
 //   1. every thread lowers D^2 of its run with the colour picked in round j-1;
-//      KPP: it publishes the sum of n D^2 over its run (the counts alone in
-//      round 0), and the block publishes the sum over its colours in its own
+//      KPP: it keeps the sum of n D^2 over its run (the counts alone in round
+//      0) in LDS, and the block publishes the sum over its colours in its own
 //      slot; MMX: the block publishes the largest (D^2, -index) packed into 46
-//      bits.  Every published value carries the tag j + 1 (bits 46-63);
+//      bits.  A published value carries the tag j + 1 (bits 46-63);
 //   2. every block waits until all G slots carry the tag j + 1 (a shared
 //      arrival counter would serialize G atomics on one address);
-//   3. MMX: the largest value names the colour.  KPP: r = U(total) from the
-//      block's own copy of the splitmix64 stream, then the block and the run
-//      whose inclusive prefix of n D^2 first exceeds r, read from what was
-//      published, and the colour within the run, whose weights the block
-//      recomputes from the colours picked so far (the smallest squared
-//      distance to any of them): every block finds the same colour, so no
-//      block waits for another to announce it.
+//   3. MMX: the largest value names the colour, the same in every block.
+//      KPP: r = U(total) from the block's own copy of the splitmix64 stream
+//      (every block draws the same values), and the block whose inclusive
+//      prefix of block sums first exceeds r.  That block alone finds the run
+//      and the colour holding r from its own LDS and publishes the colour's
+//      key, tagged, in the team's pick slot; the others wait for it.
 // Published values are written and read with agent-scope relaxed atomics and
-// each reader checks the tag of every value it uses, so no fence (and no
+// each reader checks the tag of the value it uses, so no fence (and no
 // write-back or invalidation of the L2) is needed: a value that is not there
 // yet is read again.  They are double-buffered by round parity: a block
 // writes a parity again only after every block has published the next round,
-// that is after all of them have finished reading it.  The run sums start
-// cleared (k_init_begin), so no value left by an earlier launch carries a
-// round tag.  Runs are stored transposed (entry u of thread t at u 512 + t),
-// so the threads of a wave touch consecutive words.
+// that is after all of them have finished reading it.  Runs are stored
+// transposed (entry u of thread t at u 512 + t), so the threads of a wave
+// touch consecutive words.
 constexpr int kCoopLdsCap = 8192;                    // colours per block kept in LDS (96 KiB)
 constexpr int kMaxRun = kCoopLdsCap / kInitThreads;  // run length when the colours fit in LDS
 constexpr int kTagShift = 46;      // KPP sums stay below 2^46 (2^28 pixels x 3 x 255^2)
 constexpr uint64_t kValMask = (1ull << kTagShift) - 1ull;
 constexpr uint32_t kIndexBits = 28;  // MMX: colour index below 2^28, D^2 below 2^18
-constexpr int kPickCols = 16;        // run colours whose weights are recomputed together
 
 // Wave-wide inclusive prefix sum.
 __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v)
@@ -189,13 +182,10 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
 {
     __shared__ uint64_t tmp[64];
     __shared__ uint64_t s_val[kInitMaxBlocks];
-    __shared__ uint32_t s_picks[kMaxK];        // keys of the colours picked so far
-    __shared__ uint32_t s_part[kInitThreads];  // partial minima of the recomputed D^2
+    __shared__ uint64_t s_run[kInitThreads];  // KPP: the threads' run sums of n D^2
     __shared__ int64_t s_pick;
-    __shared__ int64_t s_run_lo, s_run_n;      // KPP: the run holding r (s_run_n 0: none)
-    __shared__ uint64_t s_r, s_base;
     __shared__ uint32_t s_key;
-    __shared__ int s_ok, s_found;
+    __shared__ int s_ok;
     __shared__ uint32_t lkey[kLds ? kCoopLdsCap : 1];
     __shared__ uint32_t lcnt[kLds ? kCoopLdsCap : 1];
     __shared__ uint32_t ld2[kLds ? kCoopLdsCap : 1];
@@ -213,8 +203,7 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
     const int64_t Cb = int64_t(R) * kInitThreads;             // D^2 slots per block
     uint32_t* __restrict__ d2own = gp(J.d2) + int64_t(tb) * Cb;             // [G Cb], transposed runs
     uint64_t* __restrict__ tags = gp(J.vals);                               // [2][kInitMaxBlocks]
-    uint64_t* __restrict__ rsum = gp(J.vals) + 2 * kInitMaxBlocks;          // [2][G kInitThreads]
-    const int64_t rstride = int64_t(G) * kInitThreads;
+    uint64_t* __restrict__ pick = gp(J.vals) + 2 * kInitMaxBlocks;          // [2]: KPP picked key
     Meta* __restrict__ meta = gp(J.meta);
     double* __restrict__ centers = gp(J.centers);
     const int64_t lo = int64_t(tb) * C;
@@ -297,7 +286,7 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
                     if (j > 0) d2own[x] = m;
                 }
             }
-            if (kpp) store_tagged(&rsum[int64_t(par) * rstride + int64_t(tb) * kInitThreads + t], tag | acc);
+            if (kpp) s_run[t] = acc;
             acc = kpp ? wave_sum(acc) : wave_max(acc);
             if (lane == 0) tmp[wave] = acc;
             __syncthreads();
@@ -306,7 +295,7 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
                 for (int w = 1; w < kInitThreads / 64; ++w) v = kpp ? v + tmp[w] : (tmp[w] > v ? tmp[w] : v);
                 store_tagged(&tags[par * kInitMaxBlocks + tb], tag | v);
             }
-            // 2. wave 0 waits for the team's tags, then (KPP) finds the block and the run
+            // 2. wave 0 waits for the team's tags
             if (wave == 0) {
                 int ok = 1;
                 uint32_t spins = 0;
@@ -331,142 +320,93 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
                     }
                     s_val[c] = v & kValMask;
                 }
-                int64_t run_lo = 0, run_n = 0;
-                uint64_t r = 0, base = 0;
                 if (kpp && __ballot(ok == 0) == 0ull) {
-                    // 3. the block and the run holding r
+                    // 3. the block holding r
                     uint64_t total = 0;
                     for (int c0 = 0; c0 < G; c0 += 64) total += wave_sum(c0 + lane < G ? s_val[c0 + lane] : 0ull);
-                    r = total ? uniform_below(rng, total) : 0ull;
+                    const uint64_t r = total ? uniform_below(rng, total) : 0ull;
+                    uint64_t base = 0;
                     const int64_t c = wave_find(G, r, &base, [&](int64_t x) { return s_val[x]; });
-                    if (c >= 0) {
-                        // the block's kInitThreads run sums, all loaded in one round trip
-                        // (again while any is from an earlier round): lane l holds runs
-                        // [l S, (l + 1) S)
+                    uint32_t key = 0u;
+                    if (c == tb) {
+                        // this block: the run (lane l holds runs [l S, (l + 1) S)) and
+                        // the colour in it, both from its own data
                         constexpr int S = kInitThreads / 64;
-                        const uint64_t* __restrict__ rs = rsum + int64_t(par) * rstride + c * kInitThreads;
                         uint64_t rv[S];
-                        for (;;) {
-                            bool fresh = true;
+                        uint64_t lsum = 0;
+#pragma unroll
+                        for (int u = 0; u < S; ++u) {
+                            rv[u] = s_run[lane * S + u];
+                            lsum += rv[u];
+                        }
+                        const uint64_t lincl = base + wave_incl_scan(lsum);
+                        const unsigned long long hitl = __ballot(lincl > r);
+                        int64_t pk = -1;
+                        if (hitl) {
+                            const int l = __ffsll(hitl) - 1;
+                            uint64_t acc2 = __shfl(lincl - lsum, l, 64);  // sum before lane l's runs
+                            int tr = -1;
 #pragma unroll
                             for (int u = 0; u < S; ++u) {
-                                rv[u] = load_tagged(&rs[lane * S + u]);
-                                fresh = fresh && (rv[u] & ~kValMask) == tag;
+                                const uint64_t v = __shfl(rv[u], l, 64);
+                                if (tr < 0 && acc2 + v > r) tr = l * S + u;
+                                else if (tr < 0) acc2 += v;
                             }
-                            if (__ballot(!fresh) == 0ull) break;
+                            if (tr >= 0) {
+                                const int rn = mine_n - tr * R < R ? mine_n - tr * R : R;
+                                uint64_t carry = acc2;
+                                for (int x0 = 0; x0 < rn && pk < 0; x0 += 64) {
+                                    const int u = x0 + lane;
+                                    const bool in = u < rn;
+                                    uint64_t w = 0;
+                                    uint32_t kx = 0;
+                                    if (in) {
+                                        const int x = u * kInitThreads + tr;
+                                        if constexpr (kLds) {
+                                            kx = lkey[x];
+                                            w = uint64_t(lcnt[x]) * (j == 0 ? 1u : ld2[x]);
+                                        } else {
+                                            const int64_t i = lo + int64_t(tr) * R + u;
+                                            kx = keys[i];
+                                            w = uint64_t(counts[i]) * (j == 0 ? 1u : d2own[x]);
+                                        }
+                                    }
+                                    const uint64_t incl = carry + wave_incl_scan(w);
+                                    const unsigned long long hit = __ballot(in && incl > r);
+                                    if (hit) {
+                                        const int hl = __ffsll(hit) - 1;
+                                        pk = lo + int64_t(tr) * R + x0 + hl;
+                                        key = __builtin_amdgcn_readlane(kx, hl);
+                                    }
+                                    carry = __shfl(incl, 63, 64);
+                                }
+                            }
+                        }
+                        if (pk < 0) key = keys[0];  // unreachable: r < total
+                        if (lane == 0) store_tagged(&pick[par], tag | key);
+                    } else {
+                        // another block holds r: wait for its pick
+                        uint64_t v = 0;
+                        for (;;) {
+                            v = load_tagged(&pick[par]);
+                            if ((v & ~kValMask) == tag) break;
                             if (!keep_waiting()) {
                                 ok = 0;
                                 break;
                             }
                         }
-                        uint64_t lsum = 0;
-#pragma unroll
-                        for (int u = 0; u < S; ++u) {
-                            rv[u] &= kValMask;
-                            lsum += rv[u];
-                        }
-                        const uint64_t lincl = base + wave_incl_scan(lsum);
-                        const unsigned long long hitl = __ballot(lincl > r);
-                        if (hitl && __ballot(ok == 0) == 0ull) {
-                            const int l = __ffsll(hitl) - 1;
-                            uint64_t acc2 = __shfl(lincl - lsum, l, 64);  // sum before lane l's runs
-                            int found = -1;
-                            uint64_t before = acc2;
-#pragma unroll
-                            for (int u = 0; u < S; ++u) {
-                                const uint64_t v = __shfl(rv[u], l, 64);
-                                if (found < 0 && acc2 + v > r) {
-                                    found = u;
-                                    before = acc2;
-                                }
-                                acc2 += v;
-                            }
-                            if (found >= 0) {
-                                const int64_t tr = int64_t(l) * S + found;
-                                const int64_t clo = c * C;
-                                const int64_t chi = clo + C < n ? clo + C : n;
-                                run_lo = clo + tr * R;
-                                run_n = chi - run_lo < R ? chi - run_lo : R;
-                                base = before;
-                            }
-                        }
+                        key = uint32_t(v) & 0xffffffu;
                     }
+                    if (lane == 0) s_key = key;
                 }
                 const bool all_ok = __ballot(ok == 0) == 0ull;
                 if (!all_ok && lane == 0)
                     __hip_atomic_store(&meta->sync_error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (lane == 0) {
-                    s_ok = all_ok ? 1 : 0;
-                    s_run_lo = run_lo;
-                    s_run_n = all_ok ? run_n : 0;
-                    s_r = r;
-                    s_base = base;
-                    s_found = 0;
-                }
+                if (lane == 0) s_ok = all_ok ? 1 : 0;
             }
             __syncthreads();
             if (!s_ok) return;
-            if (kpp) {
-                // 4. the colour within the run: its weight is n D^2, with D^2 the
-                // smallest squared distance to the j colours picked so far
-                // (recomputed by the whole block, kPickCols colours at a time)
-                const int64_t run_lo = s_run_lo, run_n = s_run_n;
-                const uint64_t r = s_r;
-                uint64_t carry = s_base;
-                const int u = t % kPickCols, sub = t / kPickCols;
-                constexpr int kSubs = kInitThreads / kPickCols;
-                for (int64_t x0 = 0; x0 < run_n; x0 += kPickCols) {
-                    const int64_t x = x0 + u;
-                    const uint32_t kx = x < run_n ? keys[run_lo + x] : 0u;
-                    if (j > 0) {
-                        int r0, g0, b0;
-                        key_rgb(kx, r0, g0, b0);
-                        uint32_t d2 = 0xFFFFFFFFu;
-                        for (int i = sub; i < j; i += kSubs) {
-                            int r1, g1, b1;
-                            key_rgb(s_picks[i], r1, g1, b1);
-                            const uint32_t d = dist_u32(r0, g0, b0, r1, g1, b1);
-                            d2 = d < d2 ? d : d2;
-                        }
-                        s_part[t] = d2;
-                    }
-                    __syncthreads();
-                    if (wave == 0) {
-                        uint64_t w = 0;
-                        uint32_t kl = 0;
-                        if (lane < kPickCols && x0 + lane < run_n) {
-                            uint32_t d2 = 1u;  // round 0: the weights are the counts
-                            if (j > 0) {
-                                d2 = 0xFFFFFFFFu;
-#pragma unroll 8
-                                for (int q = 0; q < kSubs; ++q) {
-                                    const uint32_t v = s_part[q * kPickCols + lane];
-                                    d2 = v < d2 ? v : d2;
-                                }
-                            }
-                            w = uint64_t(counts[run_lo + x0 + lane]) * d2;
-                            kl = keys[run_lo + x0 + lane];
-                        }
-                        const uint64_t incl = carry + wave_incl_scan(w);
-                        const unsigned long long hit = __ballot(lane < kPickCols && x0 + lane < run_n && incl > r);
-                        if (hit) {
-                            const int l = __ffsll(hit) - 1;
-                            if (lane == l) {
-                                s_key = kl;
-                                s_pick = run_lo + x0 + l;
-                                s_found = 1;
-                            }
-                        }
-                        carry = __shfl(incl, 63, 64);
-                    }
-                    __syncthreads();
-                    if (s_found) break;  // carry: wave 0 holds it; the other waves do not use it
-                }
-                if (t == 0 && !s_found) {  // unreachable: r < total
-                    s_key = keys[0];
-                    s_pick = 0;
-                }
-            } else {
+            if (!kpp) {
                 uint64_t best = 0;
                 for (int c = t; c < G; c += kInitThreads) best = s_val[c] > best ? s_val[c] : best;
                 best = wave_max(best);
@@ -483,12 +423,9 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
         __syncthreads();
         // a KPP pick arrives with its key
         const uint32_t pick_key = kpp ? s_key : keys[s_pick];
-        if (t == 0) {
-            s_picks[j] = pick_key;
-            if (tb == 0) {
-                write_center(centers, j, pick_key);
-                if (j == K - 1) meta->rng = rng;
-            }
+        if (t == 0 && tb == 0) {
+            write_center(centers, j, pick_key);
+            if (j == K - 1) meta->rng = rng;
         }
         key_rgb(pick_key, cr, cg, cb);
     }
@@ -525,6 +462,33 @@ int coop_team_blocks(int64_t n)
     if (g < 1) g = 1;
     if (g > kInitMaxBlocks) g = kInitMaxBlocks;
     return int(g);
+}
+
+// Team sizes of the cooperative jobs of a batch (n[j] colours; 0: no team).
+// Each job needs at least the blocks whose LDS holds its colours; when all
+// of those fit the co-resident capacity together, the spare blocks are shared
+// out in proportion to the colours (a smaller share of every round's update
+// per block), keeping at least one colour per thread.  CQ_INIT_BLOCKS forces
+// a fixed size.
+void coop_team_sizes(const int64_t* n, int* want, int B, int cap)
+{
+    int need = 0;
+    int64_t ncol = 0;
+    for (int j = 0; j < B; ++j) {
+        want[j] = n[j] > 0 ? coop_team_blocks(n[j]) : 0;
+        need += want[j];
+        ncol += n[j] > 0 ? n[j] : 0;
+    }
+    const char* env = getenv("CQ_INIT_BLOCKS");
+    if ((env && atoi(env) > 0) || cap <= 0 || need > cap || ncol == 0) return;
+    const int64_t spare = cap - need;
+    for (int j = 0; j < B; ++j) {
+        if (want[j] == 0) continue;
+        int64_t g = want[j] + spare * n[j] / ncol;
+        const int64_t most = n[j] / kInitThreads > want[j] ? n[j] / kInitThreads : want[j];
+        g = g < most ? g : most;
+        want[j] = int(g < kInitMaxBlocks ? g : kInitMaxBlocks);
+    }
 }
 
 bool coop_fits_lds(int64_t C) { return (C + kInitThreads - 1) / kInitThreads <= kMaxRun; }
