@@ -374,6 +374,90 @@ __device__ __forceinline__ uint64_t uniform_below(uint64_t& s, uint64_t T)
     }
 }
 
+// ---------------------------------------------------------------- wave-wide
+// Scans and reductions over the 64 lanes of a wave with DPP moves (register
+// to register, no LDS round trip): an inclusive scan inside each row of 16
+// lanes by shifts of 1, 2, 4 and 8 lanes, then the last lane of a row added to
+// the rows after it (row_bcast:15, row_bcast:31).  Every lane of the wave must
+// be active.  A lane with no source lane, or in a row that a move skips,
+// receives `old`.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+template <int kCtrl, int kRowMask, typename T>
+__device__ __forceinline__ T dpp_move(T old, T v)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        const int r = __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v), kCtrl,
+                                                  kRowMask, 0xf, false);
+        return __builtin_bit_cast(T, r);
+    } else {
+        const uint64_t o = __builtin_bit_cast(uint64_t, old), x = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(o)), int(uint32_t(x)), kCtrl,
+                                                                 kRowMask, 0xf, false));
+        const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(o >> 32)), int(uint32_t(x >> 32)),
+                                                                 kCtrl, kRowMask, 0xf, false));
+        return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int lane)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+    } else {
+        const uint64_t x = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x)), lane));
+        const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x >> 32)), lane));
+        return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
+    }
+}
+
+// Inclusive prefix sum over the lanes.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x)
+{
+    const T z = T(0);
+    x += dpp_move<kDppRowShr1, 0xf>(z, x);
+    x += dpp_move<kDppRowShr2, 0xf>(z, x);
+    x += dpp_move<kDppRowShr4, 0xf>(z, x);
+    x += dpp_move<kDppRowShr8, 0xf>(z, x);
+    x += dpp_move<kDppRowBcast15, 0xa>(z, x);
+    x += dpp_move<kDppRowBcast31, 0xc>(z, x);
+    return x;
+}
+
+// Inclusive prefix maximum over the lanes (a lane without a source keeps its
+// own value, so any ordered type works).
+template <typename T>
+__device__ __forceinline__ T wave_incl_max(T x)
+{
+    auto mx = [](T a, T b) { return b > a ? b : a; };
+    x = mx(x, dpp_move<kDppRowShr1, 0xf>(x, x));
+    x = mx(x, dpp_move<kDppRowShr2, 0xf>(x, x));
+    x = mx(x, dpp_move<kDppRowShr4, 0xf>(x, x));
+    x = mx(x, dpp_move<kDppRowShr8, 0xf>(x, x));
+    x = mx(x, dpp_move<kDppRowBcast15, 0xa>(x, x));
+    x = mx(x, dpp_move<kDppRowBcast31, 0xc>(x, x));
+    return x;
+}
+
+// Sum and maximum over the lanes, the same value in every lane.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    return read_lane(wave_incl_scan(v), 63);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+    return read_lane(wave_incl_max(v), 63);
+}
+
 // Block-wide exclusive scan of one value per thread (blockDim.x <= 1024,
 // multiple of 64).  `tmp` must hold 64 entries.  Returns the
 // exclusive prefix; *total receives the block sum.
@@ -383,22 +467,12 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* tmp, T* total)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
-    T incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const T up = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += up;
-    }
+    const T incl = wave_incl_scan(v);
     if (lane == 63) tmp[wave] = incl;
     __syncthreads();
     if (wave == 0) {
-        T w = lane < nwaves ? tmp[lane] : T(0);
-        T wi = w;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const T up = __shfl_up(wi, d, 64);
-            if (lane >= d) wi += up;
-        }
+        const T w = lane < nwaves ? tmp[lane] : T(0);
+        const T wi = wave_incl_scan(w);
         if (lane < nwaves) tmp[lane] = wi - w;  // exclusive wave offsets
         if (lane == nwaves - 1) tmp[63] = wi;   // block total (slot 63 is free)
     }
@@ -468,24 +542,7 @@ __device__ __forceinline__ bool wait_flag(uint32_t* flag, uint32_t target, int32
     return s_ok2 != 0;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
 
-template <typename T>
-__device__ __forceinline__ T wave_max(T v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const T o = __shfl_xor(v, d, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
 
 }  // namespace cq
 

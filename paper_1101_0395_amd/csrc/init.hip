@@ -128,18 +128,6 @@ constexpr int kTagShift = 46;      // KPP sums stay below 2^46 (2^28 pixels x 3 
 constexpr uint64_t kValMask = (1ull << kTagShift) - 1ull;
 constexpr uint32_t kIndexBits = 28;  // MMX: colour index below 2^28, D^2 below 2^18
 
-// Wave-wide inclusive prefix sum.
-__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint64_t up = __shfl_up(v, d, 64);
-        if (lane >= d) v += up;
-    }
-    return v;
-}
-
 // One wave: the first of `cnt` weights (read through `get`) whose running
 // sum, started at *base, exceeds r; *base becomes the sum before it.  Returns
 // -1 if there is none.
