@@ -15,7 +15,7 @@ constexpr int kMaxK = 256;
 constexpr int kMaxIters = 100000;
 constexpr int64_t kMaxPixels = int64_t(1) << 28;
 constexpr int kMaxBatch = 4096;
-constexpr int kMaxAssignBlocks = 4096;  // assignment blocks of one job
+constexpr int kMaxAssignBlocks = 8192;  // assignment blocks of one job (so a block has at most 32768 colours)
 
 // Histogram: keys split into kHistBuckets buckets of kHistLow consecutive keys
 // (bucket = key >> kHistLowBits); pixels are taken kHistTile at a time.

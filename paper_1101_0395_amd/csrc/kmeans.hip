@@ -174,10 +174,17 @@ __device__ __forceinline__ void flush_bins(const unsigned long long* bins, const
         atomicAdd(&sums[kSumQ + k], bins[kSumQ + k]);
     }
     if (!ccount) return;
-    for (int cb = threadIdx.x; cb < K * kBuckets; cb += blockDim.x) {
-        const uint32_t c = ccount[cb];
-        if (c != 0) atomicAdd(&sums[kSumColours + cb], (unsigned long long)c);
+    for (int w = threadIdx.x; w < K * kBuckets / 2; w += blockDim.x) {
+        const uint32_t c = ccount[w];
+        if (c & 0xffffu) atomicAdd(&sums[kSumColours + 2 * w], (unsigned long long)(c & 0xffffu));
+        if (c >> 16) atomicAdd(&sums[kSumColours + 2 * w + 1], (unsigned long long)(c >> 16));
     }
+}
+
+// One more colour of (cluster, bucket) pair cb in the block's packed counters.
+__device__ __forceinline__ void count_pair(uint32_t* ccount, int cb)
+{
+    atomicAdd(&ccount[cb >> 1], 1u << ((cb & 1) << 4));
 }
 
 __device__ __forceinline__ bool near_tie(const Best& v)
@@ -235,7 +242,9 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                                                            const int* __restrict__ map, int B)
 {
     __shared__ unsigned long long bins[5 * kMaxK];     // n, S0, S1, S2, Q per cluster
-    __shared__ uint32_t ccount[kMaxK * kBuckets];     // colours per (cluster, bucket), pruned runs
+    // colours per (cluster, bucket) in pruned runs, two 16-bit counters per
+    // word (a block holds at most 32768 colours)
+    __shared__ uint32_t ccount[kMaxK * kBuckets / 2];
     __shared__ unsigned long long red[2 * (kAssignThreads / 64)];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
@@ -255,7 +264,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
     uint64_t* __restrict__ grp = gp(J.grp) + record_buffer(it, J.regroup_period) * n;
     for (int t = threadIdx.x; t < 5 * kMaxK; t += blockDim.x) bins[t] = 0ull;
     if (J.prune)
-        for (int t = threadIdx.x; t < K * kBuckets; t += blockDim.x) ccount[t] = 0u;
+        for (int t = threadIdx.x; t < K * kBuckets / 2; t += blockDim.x) ccount[t] = 0u;
     __syncthreads();
 
     unsigned long long ndc = 0, ties = 0;
@@ -279,7 +288,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 if (J.prune) {
                     const int bk = dist_bucket(v.bd);
                     grp[i] = pack_colour(key, v.best, w, bk);
-                    atomicAdd(&ccount[v.best * kBuckets + bk], 1u);
+                    count_pair(ccount, v.best * kBuckets + bk);
                 }
             }
             bin_add(bins, valid, v.best, w, r, g, b);
@@ -352,7 +361,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 ties += near_tie(v) ? 1 : 0;
                 const int bk = dist_bucket(v.bd);
                 grp[i] = pack_colour(key, v.best, w, bk);
-                atomicAdd(&ccount[v.best * kBuckets + bk], 1u);
+                count_pair(ccount, v.best * kBuckets + bk);
                 acc_add(acc, bins, v.best, w, r, g, b);
             }
         }
