@@ -48,8 +48,8 @@ struct alignas(32) Rec {
 
 // Entries a row walk reads per round, and the padding past the last row that
 // lets the final round of any row read whole rounds.
-constexpr int kWalk = 8;
-constexpr int kTablePad = kWalk;
+constexpr int kWalk = 4;      // table entries per round of a sort-means walk
+constexpr int kTablePad = 8;  // entries after the last row: a walk's last round (and the one loaded ahead) may reach past its row
 
 // Cluster statistics of one iteration (uint64 each): n_k, S_k (3 per
 // cluster), Q_k, then the number of unique colours and the counting-sort

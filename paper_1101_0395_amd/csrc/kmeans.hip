@@ -318,7 +318,23 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 const bool mine = valid && p == ps;
                 const Rec CQ_CONST* row = rec + ps * kRow;
                 const int32_t CQ_CONST* trow = tix + ps * kRow;
+                // the own entry and the first round in one round trip; each
+                // round's evaluation overlaps the loads of the next
                 const Rec own = row[0];
+                Rec q[kWalk];
+                int tq[kWalk];
+#pragma unroll
+                for (int u = 0; u < kWalk; ++u) {
+                    q[u] = row[1 + u];
+                    tq[u] = trow[1 + u];
+                }
+                // an empty statement that needs both: the loads are issued
+                // here, and waited for together, not one after the other
+                static_assert(kWalk == 4, "the statement below names every entry of a round");
+                asm volatile("" ::"s"(own.c0), "s"(own.c1), "s"(own.c2), "s"(q[0].c0), "s"(q[0].c1), "s"(q[0].c2),
+                             "s"(q[0].d), "s"(q[1].c0), "s"(q[1].c1), "s"(q[1].c2), "s"(q[1].d), "s"(q[2].c0),
+                             "s"(q[2].c1), "s"(q[2].c2), "s"(q[2].d), "s"(q[3].c0), "s"(q[3].c1), "s"(q[3].c2),
+                             "s"(q[3].d), "s"(tq[0]), "s"(tq[1]), "s"(tq[2]), "s"(tq[3]));
                 const double prev = dist_f64(x0, x1, x2, own.c0, own.c1, own.c2);
                 const double limit = 4.0 * prev * (1.0 + 1e-12);
                 const double reach = wave_max(mine ? limit : -1.0);  // same value in every lane
@@ -329,14 +345,18 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                     evals = 1;
                 }
                 // entries j .. j + kWalk - 1 per round; the table is padded so
-                // that the last round of a row stays inside the allocation
+                // that the last round of a row, and the round loaded ahead of
+                // it, stay inside the allocation
                 for (int j = 1; j < K; j += kWalk) {
-                    Rec q[kWalk];
-                    int tq[kWalk];
+                    Rec qn[kWalk];
+                    int tqn[kWalk];
+                    const bool ahead = j + kWalk < K && q[kWalk - 1].d <= reach;
+                    if (ahead) {
 #pragma unroll
-                    for (int u = 0; u < kWalk; ++u) {
-                        q[u] = row[j + u];
-                        tq[u] = trow[j + u];
+                        for (int u = 0; u < kWalk; ++u) {
+                            qn[u] = row[j + kWalk + u];
+                            tqn[u] = trow[j + kWalk + u];
+                        }
                     }
 #pragma unroll
                     for (int u = 0; u < kWalk; ++u) {
@@ -352,7 +372,12 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                         // one entry at a time: fewer registers, more waves per SIMD
                         __builtin_amdgcn_sched_barrier(0);
                     }
-                    if (j + kWalk >= K || q[kWalk - 1].d > reach) break;
+                    if (!ahead) break;
+#pragma unroll
+                    for (int u = 0; u < kWalk; ++u) {
+                        q[u] = qn[u];
+                        tq[u] = tqn[u];
+                    }
                 }
                 pending &= ~__ballot(mine);
             }
