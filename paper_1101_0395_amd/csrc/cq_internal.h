@@ -35,7 +35,7 @@ __host__ __device__ __forceinline__ int64_t hist_tiles(int64_t npix)
 // every round the block publishes a tagged value and each thread the sum of
 // its run (both for two round parities).
 constexpr int kInitMaxBlocks = 256;
-constexpr int kInitThreads = 512;
+constexpr int kInitThreads = 1024;
 
 // Sorted centre table: row stride (entries) independent of K.
 constexpr int kRow = kMaxK;
@@ -59,9 +59,11 @@ constexpr int kBuckets = 16;
 constexpr int kSumN = 0;
 constexpr int kSumS = kMaxK;
 constexpr int kSumQ = 4 * kMaxK;
+// (u64 slot offsets) the colour counts and the regrouping cursors per
+// (cluster, bucket) pair are uint32 (a count is below 2^28), two per slot
 constexpr int kSumColours = 5 * kMaxK;
-constexpr int kSumCursor = kSumColours + kMaxK * kBuckets;
-constexpr int kSumStride = kSumCursor + kMaxK * kBuckets;
+constexpr int kSumCursor = kSumColours + kMaxK * kBuckets / 2;
+constexpr int kSumStride = kSumCursor + kMaxK * kBuckets / 2;
 
 // Device-side control block, one per workspace.
 struct Meta {
@@ -271,8 +273,8 @@ inline Layout make_layout(int64_t npix, int64_t n_cap, bool with_colour_arrays)
     L.fixed_end = o;
     const size_t n = n_cap > 0 ? size_t(n_cap) : 0;
     const size_t np = npix > 0 ? size_t(npix) : 0;
-    // init: tagged block values and per-thread run sums, both for two round parities
-    L.chunks = o;   o = align256(o + sizeof(uint64_t) * 2 * kInitMaxBlocks * (1 + kInitThreads));
+    // init: tagged block values and picks, both for two round parities
+    L.chunks = o;   o = align256(o + sizeof(uint64_t) * 2 * (kInitMaxBlocks + 1));
     // work region
     L.work = o;
     size_t hist = 0;
@@ -285,9 +287,10 @@ inline Layout make_layout(int64_t npix, int64_t n_cap, bool with_colour_arrays)
         L.hbs = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
         L.hus = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
     }
-    // init: D^2 for two round parities, kInitThreads R entries per block
-    // (below n + kInitThreads per block); k-means: two uint64 records per colour
-    const size_t d2_init = n > 0 ? sizeof(uint32_t) * 2 * (n + size_t(kInitThreads + 1) * kInitMaxBlocks) : 0;
+    // init (colours beyond what LDS holds): D^2, kInitThreads R entries per
+    // block (below n + kInitThreads per block); k-means: two uint64 records
+    // per colour
+    const size_t d2_init = n > 0 ? sizeof(uint32_t) * (n + size_t(kInitThreads + 1) * kInitMaxBlocks) : 0;
     const size_t d2_km = sizeof(uint64_t) * 2 * n;
     size_t work = hist > d2_init ? hist : d2_init;
     work = work > d2_km ? work : d2_km;

@@ -99,8 +99,8 @@ __global__ void __launch_bounds__(kMaxK) k_init_begin(const JobDev* __restrict__
 // ------------------------------------------------------------------------
 // Cooperative MMX / KPP: one launch runs all K rounds of every job, each job
 // with its own team of G co-resident blocks.  Block b of a team owns the
-// colours [b C, (b+1) C); thread t of a block owns the run of R = C / 512
-// (rounded up) consecutive colours from t R on.  Round j:
+// colours [b C, (b+1) C); thread t of a block owns the run of R = C / T
+// (rounded up, T threads per block) consecutive colours from t R on.  Round j:
 //   1. every thread lowers D^2 of its run with the colour picked in round j-1;
 //      KPP: it keeps the sum of n D^2 over its run (the counts alone in round
 //      0) in LDS, and the block publishes the sum over its colours in its own
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kMaxK) k_init_begin(const JobDev* __restrict__
 // yet is read again.  They are double-buffered by round parity: a block
 // writes a parity again only after every block has published the next round,
 // that is after all of them have finished reading it.  Runs are stored
-// transposed (entry u of thread t at u 512 + t), so the threads of a wave
+// transposed (entry u of thread t at u T + t), so the threads of a wave
 // touch consecutive words.
 constexpr int kCoopLdsCap = 8192;                    // colours per block kept in LDS (96 KiB)
 constexpr int kMaxRun = kCoopLdsCap / kInitThreads;  // run length when the colours fit in LDS

@@ -176,8 +176,9 @@ __device__ __forceinline__ void flush_bins(const unsigned long long* bins, const
     if (!ccount) return;
     for (int w = threadIdx.x; w < K * kBuckets / 2; w += blockDim.x) {
         const uint32_t c = ccount[w];
-        if (c & 0xffffu) atomicAdd(&sums[kSumColours + 2 * w], (unsigned long long)(c & 0xffffu));
-        if (c >> 16) atomicAdd(&sums[kSumColours + 2 * w + 1], (unsigned long long)(c >> 16));
+        uint32_t* colours = reinterpret_cast<uint32_t*>(sums + kSumColours);
+        if (c & 0xffffu) atomicAdd(&colours[2 * w], c & 0xffffu);
+        if (c >> 16) atomicAdd(&colours[2 * w + 1], c >> 16);
     }
 }
 
@@ -429,9 +430,8 @@ constexpr int kPairsPer = kPairs / kMaxK;  // pairs per thread in the regrouping
 // different banks
 constexpr int kStartWords = kPairs + kPairs / kPairsPer;
 
-__device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const unsigned long long* __restrict__ cur,
-                                        unsigned long long* __restrict__ cursor, uint32_t* start,
-                                        uint32_t* scan_tmp)
+__device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const uint32_t* __restrict__ colours,
+                                        uint32_t* __restrict__ cursor, uint32_t* start, uint32_t* scan_tmp)
 {
     constexpr int kPer = kPairsPer;
     const int k = threadIdx.x;
@@ -441,11 +441,11 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
     const int rb = record_buffer(it, J.regroup_period);
     const uint64_t* __restrict__ src = gp(J.grp) + rb * n;
     uint64_t* __restrict__ dst = gp(J.grp) + (rb ^ 1) * n;
-    const int64_t lo = int64_t(s) * kScatterChunk;
     const unsigned long long below = (1ull << lane) - 1ull;
-    // the block's records first, in flight while the offsets are computed
     constexpr int kPasses = kScatterChunk / kMaxK;
+    // the block's records first, in flight while the offsets are computed
     uint64_t g[kPasses];
+    const int64_t lo = int64_t(s) * kScatterChunk;
 #pragma unroll
     for (int u = 0; u < kPasses; ++u) {
         const int64_t i = lo + u * kMaxK + k;
@@ -456,7 +456,7 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int cb = u * kMaxK + k;
-        start[cb + cb / kPer] = cb < npairs ? uint32_t(cur[kSumColours + cb]) : 0u;
+        start[cb + cb / kPer] = cb < npairs ? colours[cb] : 0u;
     }
     __syncthreads();
     uint32_t c[kPer];
@@ -477,7 +477,7 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
     // (cluster, bucket) first; the group leaders then reserve their places
     // with atomics that are all in flight together
     int cbv[kPasses], lead[kPasses], rank[kPasses];
-    unsigned long long pos[kPasses];
+    uint32_t pos[kPasses];
 #pragma unroll
     for (int u = 0; u < kPasses; ++u) {
         const bool valid = lo + u * kMaxK + k < n;
@@ -499,11 +499,11 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const un
             pending &= ~mask;
         }
         pos[u] = 0;
-        if (gsize > 0) pos[u] = atomicAdd(&cursor[cbv[u]], (unsigned long long)gsize);
+        if (gsize > 0) pos[u] = atomicAdd(&cursor[cbv[u]], uint32_t(gsize));
     }
 #pragma unroll
     for (int u = 0; u < kPasses; ++u) {
-        const unsigned long long base = __shfl(pos[u], lead[u] < 0 ? 0 : lead[u], 64);
+        const uint32_t base = __shfl(pos[u], lead[u] < 0 ? 0 : lead[u], 64);
         if (lead[u] >= 0) dst[start[cbv[u] + cbv[u] / kPer] + base + rank[u]] = g[u];
     }
 }
@@ -670,7 +670,8 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     const int ntab = table_blocks(J);
     if (a >= ntab) {
         if (regroup_at(it, J.regroup_period))
-            regroup(J, a - ntab, it, cur, cur + kSumCursor, smem, smem + kStartWords);
+            regroup(J, a - ntab, it, reinterpret_cast<const uint32_t*>(cur + kSumColours),
+                    reinterpret_cast<uint32_t*>(cur + kSumCursor), smem, smem + kStartWords);
         return;
     }
     double* c = reinterpret_cast<double*>(smem);
