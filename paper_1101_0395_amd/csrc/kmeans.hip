@@ -247,6 +247,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
     // word (a block holds at most 32768 colours)
     __shared__ uint32_t ccount[kMaxK * kBuckets / 2];
     __shared__ unsigned long long red[2 * (kAssignThreads / 64)];
+    __shared__ int s_slice;  // sort-means passes: the block's next slice of 64 colours
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
@@ -266,6 +267,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
     for (int t = threadIdx.x; t < 5 * kMaxK; t += blockDim.x) bins[t] = 0ull;
     if (J.prune)
         for (int t = threadIdx.x; t < K * kBuckets / 2; t += blockDim.x) ccount[t] = 0u;
+    if (threadIdx.x == 0) s_slice = 0;
     __syncthreads();
 
     unsigned long long ndc = 0, ties = 0;
@@ -298,12 +300,21 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
         const Rec CQ_CONST* rec = cp(J.rec);
         const int32_t CQ_CONST* tix = cp(J.tix);
         Acc acc{-1, 0ull, 0ull, 0ull, 0ull, 0ull};
-        uint64_t g_next = lo + threadIdx.x < hi ? grp[lo + threadIdx.x] : 0ull;
-        for (int64_t base = lo; base < hi; base += blockDim.x) {
-            const int64_t i = base + threadIdx.x;
+        // the waves take the block's slices of 64 colours in order from an LDS
+        // counter, so a wave that finishes early takes more of them; each wave
+        // takes its next slice, and starts loading it, before working on the
+        // current one
+        const int lane = threadIdx.x & 63;
+        const int nslices = int((hi - lo + 63) / 64);
+        auto take = [&]() { return __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(&s_slice, 1) : 0); };
+        int sl = take();
+        uint64_t g_next = sl < nslices && lo + sl * 64 + lane < hi ? grp[lo + sl * 64 + lane] : 0ull;
+        while (sl < nslices) {
+            const int64_t i = lo + int64_t(sl) * 64 + lane;
             const bool valid = i < hi;
             const uint64_t g0 = g_next;
-            g_next = i + blockDim.x < hi ? grp[i + blockDim.x] : 0ull;  // next pass, in flight
+            sl = take();
+            g_next = sl < nslices && lo + sl * 64 + lane < hi ? grp[lo + sl * 64 + lane] : 0ull;  // in flight
             const uint32_t key = uint32_t(g0) & 0xffffffu;
             const int p = int((uint32_t(g0) >> 24) & 255u);
             const uint32_t w = uint32_t(g0 >> 32) & 0x0fffffffu;
