@@ -550,7 +550,20 @@ __device__ __forceinline__ void cmp_swap(double& k0, int& i0, double& k1, int& i
     }
 }
 
-__device__ __forceinline__ void build_row(const JobDev& J, int a, int K, int it, const double* c)
+// The row's previous order (iteration 1: index order), one entry per
+// register: loaded before the centres are derived so the two overlap.
+__device__ __forceinline__ void load_row_order(const JobDev& J, int a, int K, int it, int* prev)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t* __restrict__ trow = gp(J.tix) + a * kRow;
+#pragma unroll
+    for (int i = 0; i < kPerLane; ++i) {
+        const int e = kPerLane * lane + i;
+        prev[i] = (it > 1 && e < K && a < K) ? trow[e] : e;
+    }
+}
+
+__device__ __forceinline__ void build_row(const JobDev& J, int a, int K, const double* c, const int* prev)
 {
     const int lane = threadIdx.x & 63;
     Rec* __restrict__ row = gp(J.rec) + a * kRow;
@@ -560,8 +573,7 @@ __device__ __forceinline__ void build_row(const JobDev& J, int a, int K, int it,
     int x[kPerLane];
 #pragma unroll
     for (int i = 0; i < kPerLane; ++i) {
-        const int e = kPerLane * lane + i;
-        const int f = (it > 1 && e < K) ? trow[e] : e;  // previous order, read before the wave rewrites it
+        const int f = prev[i];
         x[i] = f;
         k[i] = f >= K ? __builtin_inf()
                       : (f == a ? -1.0 : dist_f64(a0, a1, a2, c[3 * f], c[3 * f + 1], c[3 * f + 2]));
@@ -691,6 +703,9 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
     unsigned long long* cnt_red = wsum + kMaxK;
     double* __restrict__ centers = gp(J.centers);
     const int k = threadIdx.x;
+    const int r = a * kRowsPerBlock + int(threadIdx.x >> 6);  // this wave's table row
+    int prev[kPerLane];
+    if (J.prune) load_row_order(J, r, K, it, prev);
     double t = 0.0;
     unsigned long long nk = 0;
     if (k < K) {
@@ -704,11 +719,12 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
             c[3 * k + 0] = double(s0) / dn;
             c[3 * k + 1] = double(s1) / dn;
             c[3 * k + 2] = double(s2) / dn;
-            const unsigned __int128 nq = (unsigned __int128)nk * q;
-            const unsigned __int128 ss = (unsigned __int128)s0 * s0 + (unsigned __int128)s1 * s1 +
-                                         (unsigned __int128)s2 * s2;
-            t = u128_to_f64(nq - ss) / dn;
             if (a == 0) {
+                // the cluster's SSE term, exactly from the integer sums
+                const unsigned __int128 nq = (unsigned __int128)nk * q;
+                const unsigned __int128 ss = (unsigned __int128)s0 * s0 + (unsigned __int128)s1 * s1 +
+                                             (unsigned __int128)s2 * s2;
+                t = u128_to_f64(nq - ss) / dn;
                 centers[3 * k + 0] = c[3 * k + 0];
                 centers[3 * k + 1] = c[3 * k + 1];
                 centers[3 * k + 2] = c[3 * k + 2];
@@ -719,10 +735,16 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
             c[3 * k + 2] = centers[3 * k + 2];
         }
     }
-    term[k] = t;  // zero for k >= K and for empty clusters
+    term[k] = t;  // zero for k >= K, for empty clusters and outside block 0
     wsum[k] = nk;
+    {
+        // the next iteration's statistics start at zero; the job's table
+        // blocks clear a slice each
+        const int per = (kSumStride + ntab - 1) / ntab;
+        const int end = (a + 1) * per < kSumStride ? (a + 1) * per : kSumStride;
+        for (int j = a * per + k; j < end; j += blockDim.x) nxt[j] = 0ull;
+    }
     if (a == 0) {
-        for (int j = k; j < kSumStride; j += blockDim.x) nxt[j] = 0ull;
         // distance and near-tie counts of this iteration's assignment blocks
         const int nblk = int((J.n + J.chunk - 1) / J.chunk);
         const unsigned long long* __restrict__ part = gp(J.part);
@@ -773,8 +795,7 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
         }
     }
     if (!J.prune) return;
-    const int r = a * kRowsPerBlock + int(threadIdx.x >> 6);
-    if (r < K) build_row(J, r, K, it, c);
+    if (r < K) build_row(J, r, K, c, prev);
 }
 
 // Pruned runs that grouped their colours: the final cluster of every colour
