@@ -34,6 +34,7 @@ PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 FLOP_PER_EVAL = 8              # 3 sub, 3 mul, 2 add per FP64 squared distance
 ROOFLINE_KERNEL = "k_assign_walk"  # sort-means nearest-centre passes, FP64 VALU
+TIMER_EVERY = 8                    # HIP-event bracket on every 8th launch of it
 
 
 def measure_large(cq, synth, torch, dev, reps=5):
@@ -209,7 +210,9 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    timer = cq.KernelTimer(ROOFLINE_KERNEL, max_launches=args.steps * (MAX_ITERS + 8))
+    # every TIMER_EVERY-th launch of the roofline kernel is bracketed with HIP
+    # events on its stream (bracketing all of them would slow the step itself)
+    timer = cq.KernelTimer(ROOFLINE_KERNEL, max_launches=args.steps * (MAX_ITERS + 16), every=TIMER_EVERY)
     timer.enable()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -218,8 +221,13 @@ def main():
         stats.extend(step())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    launches, kern_ms = timer.read()
+    timed, timed_ms = timer.read()
+    launches = timer.seen
     timer.disable()
+    if timed == 0:
+        raise RuntimeError(f"no launch of {ROOFLINE_KERNEL} was timed")
+    avg_launch_ms = timed_ms / timed
+    kern_ms = avg_launch_ms * launches  # all launches of the kernel in the timed region
     elapsed = t1 - t0
 
     # the plain path: one image per call, same images and settings
@@ -283,7 +291,8 @@ def main():
             "frac": achieved_tflops / PEAK_FP64_VALU_TFLOPS,
             "traffic": recorded_traffic(),
             "launches": launches,
-            "avg_launch_us": 1e3 * kern_ms / max(1, launches),
+            "timed_launches": timed,
+            "avg_launch_us": 1e3 * avg_launch_ms,
         },
     }
 

@@ -256,14 +256,17 @@ cq_status cq_engine_pending(const cq_engine* engine, int32_t* queued, int32_t* r
 void cq_engine_destroy(cq_engine* engine);
 
 /* Kernel timing for measurement harnesses (not needed for quantization).
- * While enabled, every launch of the kernel named `kernel` (for example
- * "k_assign_walk", "k_hist_count", "k_map") is bracketed by a pair of HIP
- * events recorded on the stream it is launched on, for at most max_launches
- * launches.  cq_timer_read waits for those events and returns the number of
- * bracketed launches and the sum of their durations in milliseconds.
+ * While enabled, launches of the kernel named `kernel` (for example
+ * "k_assign_walk", "k_hist_count", "k_map") are counted, and every
+ * `every`-th of them (the 1st, the (every+1)-th, ...; every >= 1) is
+ * bracketed by a pair of HIP events recorded on the stream it is launched
+ * on, for at most max_launches bracketed launches.  Sampling keeps the
+ * events' own cost out of the work being timed.  cq_timer_read waits for
+ * those events and returns the number of bracketed launches, the sum of their
+ * durations in milliseconds and the number of launches seen (nullable).
  * Process-global state: enable, run and read from one host thread. */
-cq_status cq_timer_enable(const char* kernel, int32_t max_launches);
-cq_status cq_timer_read(int64_t* launches /* host */, double* total_ms /* host */);
+cq_status cq_timer_enable(const char* kernel, int32_t max_launches, int32_t every);
+cq_status cq_timer_read(int64_t* launches /* host */, double* total_ms /* host */, int64_t* seen /* host */);
 cq_status cq_timer_disable(void);
 
 /* Thread-local description of the last error on this thread ("" if none);

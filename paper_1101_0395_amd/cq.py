@@ -120,8 +120,8 @@ def lib() -> ctypes.CDLL:
             getattr(L, f).restype = ctypes.c_int
         L.cq_engine_destroy.argtypes = [P]
         L.cq_engine_destroy.restype = None
-        L.cq_timer_enable.argtypes = [ctypes.c_char_p, i32]
-        L.cq_timer_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(f64)]
+        L.cq_timer_enable.argtypes = [ctypes.c_char_p, i32, i32]
+        L.cq_timer_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(i64)]
         L.cq_timer_disable.argtypes = []
         for f in ("cq_timer_enable", "cq_timer_read", "cq_timer_disable"):
             getattr(L, f).restype = ctypes.c_int
@@ -132,19 +132,25 @@ def lib() -> ctypes.CDLL:
 
 
 class KernelTimer:
-    """HIP-event timing of every launch of one named kernel (library-side)."""
+    """HIP-event timing of the launches of one named kernel (library-side):
+    every `every`-th launch is bracketed; all are counted."""
 
-    def __init__(self, kernel: str, max_launches: int):
+    def __init__(self, kernel: str, max_launches: int, every: int = 1):
         self.kernel = kernel
         self.max_launches = int(max_launches)
+        self.every = int(every)
+        self.seen = 0
 
     def enable(self):
-        _check("cq_timer_enable", lib().cq_timer_enable(self.kernel.encode(), self.max_launches))
+        _check("cq_timer_enable", lib().cq_timer_enable(self.kernel.encode(), self.max_launches, self.every))
 
     def read(self):
+        """(bracketed launches, their total ms); `seen` holds all launches counted."""
         n = ctypes.c_int64(0)
         ms = ctypes.c_double(0.0)
-        _check("cq_timer_read", lib().cq_timer_read(ctypes.byref(n), ctypes.byref(ms)))
+        seen = ctypes.c_int64(0)
+        _check("cq_timer_read", lib().cq_timer_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(seen)))
+        self.seen = seen.value
         return n.value, ms.value
 
     def disable(self):

@@ -49,9 +49,12 @@ cq_status einval(const char* fmt, ...)
 // ---------------------------------------------------------------- kernel timer
 struct KernelTimer {
     bool enabled = false;
+    bool armed = false;  // the current launch is bracketed
     char name[64] = {0};
     int32_t capacity = 0;
     int32_t used = 0;
+    int32_t every = 1;
+    int64_t seen = 0;
     hipEvent_t* start = nullptr;
     hipEvent_t* stop = nullptr;
 };
@@ -59,15 +62,17 @@ static KernelTimer g_timer;
 
 void timer_begin(const char* kernel, hipStream_t s)
 {
-    if (!g_timer.enabled || g_timer.used >= g_timer.capacity || strcmp(kernel, g_timer.name) != 0) return;
-    (void)hipEventRecord(g_timer.start[g_timer.used], s);
+    if (!g_timer.enabled || strcmp(kernel, g_timer.name) != 0) return;
+    g_timer.armed = g_timer.seen++ % g_timer.every == 0 && g_timer.used < g_timer.capacity;
+    if (g_timer.armed) (void)hipEventRecord(g_timer.start[g_timer.used], s);
 }
 
 void timer_end(const char* kernel, hipStream_t s)
 {
-    if (!g_timer.enabled || g_timer.used >= g_timer.capacity || strcmp(kernel, g_timer.name) != 0) return;
+    if (!g_timer.enabled || !g_timer.armed || strcmp(kernel, g_timer.name) != 0) return;
     (void)hipEventRecord(g_timer.stop[g_timer.used], s);
     ++g_timer.used;
+    g_timer.armed = false;
 }
 
 static void timer_release()
@@ -722,11 +727,12 @@ cq_status cq_quantize_batch(const cq_job* jobs, int32_t n_jobs, cq_stats* stats,
     return run_quantize(b, stats);
 }
 
-cq_status cq_timer_enable(const char* kernel, int32_t max_launches)
+cq_status cq_timer_enable(const char* kernel, int32_t max_launches, int32_t every)
 {
     clear_error();
     if (!kernel || !kernel[0] || strlen(kernel) >= sizeof g_timer.name) return einval("bad kernel name");
     if (max_launches < 1 || max_launches > (1 << 22)) return einval("max_launches out of range");
+    if (every < 1) return einval("every must be at least 1");
     timer_release();
     g_timer.start = new hipEvent_t[max_launches];
     g_timer.stop = new hipEvent_t[max_launches];
@@ -741,11 +747,14 @@ cq_status cq_timer_enable(const char* kernel, int32_t max_launches)
     }
     strncpy(g_timer.name, kernel, sizeof g_timer.name - 1);
     g_timer.used = 0;
+    g_timer.every = every;
+    g_timer.seen = 0;
+    g_timer.armed = false;
     g_timer.enabled = true;
     return CQ_OK;
 }
 
-cq_status cq_timer_read(int64_t* launches, double* total_ms)
+cq_status cq_timer_read(int64_t* launches, double* total_ms, int64_t* seen)
 {
     clear_error();
     if (!launches || !total_ms) return einval("null output");
@@ -758,6 +767,7 @@ cq_status cq_timer_read(int64_t* launches, double* total_ms)
     }
     *launches = g_timer.used;
     *total_ms = total;
+    if (seen) *seen = g_timer.seen;
     return CQ_OK;
 }
 
