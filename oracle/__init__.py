@@ -18,11 +18,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcqref.so")
 SRC_PATH = os.path.join(_HERE, "cqref.c")
 
-INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER = 0, 1, 2, 3
+INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF = 0, 1, 2, 3, 4, 5
 OK, EINVAL, ECAPACITY, ENOMEM = 0, 1, 2, 5
 
 BUILD_CMD = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra",
-             "-fPIC", "-shared", "-o", LIB_PATH, SRC_PATH]
+             "-fPIC", "-shared", "-o", LIB_PATH, SRC_PATH, "-lm"]
 
 
 def build() -> str:
@@ -66,6 +66,8 @@ def lib():
         L.cqref_uniform_below.restype = u64
         L.cqref_histogram.argtypes = [P, i32, i32, i64, P, P, i64, ctypes.POINTER(i64)]
         L.cqref_init.argtypes = [P, P, i64, i32, i32, u64, P, ctypes.POINTER(i32)]
+        L.cqref_sff_subset.argtypes = [i32, i64]
+        L.cqref_sff_subset.restype = i64
         L.cqref_kmeans.argtypes = [P, P, i64, i32, P, i32, f64, i32, P, P, P, ctypes.POINTER(Stats)]
         L.cqref_map.argtypes = [P, i32, i32, i64, P, i32, P, P, ctypes.POINTER(u64)]
         L.cqref_quantize.argtypes = [P, i32, i32, i64, i32, i32, u64, i32, f64, i32, P, P, P,
@@ -183,3 +185,8 @@ def quantize(img: np.ndarray, K: int, scheme: int, seed: int, max_iters: int, to
                                                   max_iters, tol, int(bool(prune)), _ptr(palette),
                                                   _ptr(idx), _ptr(rgb), ctypes.byref(st)))
     return palette, idx, rgb, st.as_dict()
+
+
+def sff_subset(K: int, n: int) -> int:
+    """Size of the SFF subset: max(K, ceil(2 K ln K)), at most n."""
+    return int(lib().cqref_sff_subset(K, n))

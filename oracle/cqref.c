@@ -26,6 +26,7 @@
  */
 #include "cqref.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -157,12 +158,129 @@ static void update_min_d2(const uint32_t* keys, int64_t n, uint32_t chosen_key, 
     }
 }
 
+/* VAR (Section 2.3, maximum variance), read on the pixel data set: colour i
+ * stands for counts[i] identical pixels.  The channel is the one whose pixel
+ * variance is largest (compared exactly as N S2 - S1^2; ties to the lower
+ * channel, R before G before B).  The N pixels in ascending order of
+ * (channel value, key) are cut into K groups [floor(g N / K), floor((g+1) N / K));
+ * centre g is the pixel at the group's lower median position. */
+static int init_var(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K, double* centers)
+{
+    unsigned __int128 best = 0;
+    int ch = 0;
+    uint64_t N = 0;
+    for (int64_t i = 0; i < n; ++i)
+        N += counts[i];
+    for (int c = 0; c < 3; ++c) {
+        uint64_t s1 = 0;
+        unsigned __int128 s2 = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const uint64_t x = (keys[i] >> (16 - 8 * c)) & 255u;
+            s1 += (uint64_t)counts[i] * x;
+            s2 += (unsigned __int128)counts[i] * x * x;
+        }
+        const unsigned __int128 v = (unsigned __int128)N * s2 - (unsigned __int128)s1 * s1;
+        if (c == 0 || v > best) {
+            best = v;
+            ch = c;
+        }
+    }
+    /* the colours in ascending (channel value, key): a stable counting sort of
+       the key-ordered colours by the channel value */
+    int64_t* order = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    if (!order)
+        return CQREF_ENOMEM;
+    int64_t start[257] = {0};
+    for (int64_t i = 0; i < n; ++i)
+        ++start[((keys[i] >> (16 - 8 * ch)) & 255u) + 1];
+    for (int v = 0; v < 256; ++v)
+        start[v + 1] += start[v];
+    for (int64_t i = 0; i < n; ++i)
+        order[start[(keys[i] >> (16 - 8 * ch)) & 255u]++] = i;
+    /* walk the pixels in that order */
+    int64_t pos = 0;  /* first pixel of order[q] */
+    int64_t q = 0;
+    for (int32_t g = 0; g < K; ++g) {
+        const uint64_t lo = (uint64_t)(((unsigned __int128)g * N) / (unsigned)K);
+        const uint64_t hi = (uint64_t)(((unsigned __int128)(g + 1) * N) / (unsigned)K);
+        const uint64_t m = lo + (hi - lo - 1) / 2;
+        while ((uint64_t)(pos + counts[order[q]]) <= m) {
+            pos += counts[order[q]];
+            ++q;
+        }
+        set_center_from_key(centers + 3 * g, keys[order[q]]);
+    }
+    free(order);
+    return CQREF_OK;
+}
+
+int64_t cqref_sff_subset(int32_t K, int64_t n)
+{
+    int64_t L = (int64_t)ceil(2.0 * (double)K * log((double)K));
+    if (L < K)
+        L = K;
+    return L < n ? L : n;
+}
+
+/* SFF (Section 2.3, subset farthest first): a uniform subset of L =
+ * cqref_sff_subset(K, n) distinct colours, the first L positions of a partial
+ * Fisher-Yates shuffle (the draws of FGY), then MMX on the subset in draw
+ * order: the first centre is subset[U(L)], then K-1 farthest-first picks by
+ * integer D^2 over the subset, ties to the lowest subset position. */
+static int init_sff(const uint32_t* keys, int64_t n, int32_t K, uint64_t* rng, double* centers)
+{
+    const int64_t L = cqref_sff_subset(K, n);
+    int64_t* perm = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    int64_t* d2 = (int64_t*)malloc((size_t)L * sizeof(int64_t));
+    if (!perm || !d2) {
+        free(perm);
+        free(d2);
+        return CQREF_ENOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        perm[i] = i;
+    for (int64_t j = 0; j < L; ++j) {
+        const int64_t r = j + (int64_t)cqref_uniform_below(rng, (uint64_t)(n - j));
+        const int64_t t = perm[j];
+        perm[j] = perm[r];
+        perm[r] = t;
+    }
+    for (int64_t s = 0; s < L; ++s)
+        d2[s] = INT64_MAX;
+    int64_t pick = (int64_t)cqref_uniform_below(rng, (uint64_t)L);
+    for (int32_t j = 0; j < K; ++j) {
+        if (j > 0) {
+            int64_t best = -1;
+            for (int64_t s = 0; s < L; ++s) {
+                if (d2[s] > best) {
+                    best = d2[s];
+                    pick = s;
+                }
+            }
+        }
+        const uint32_t key = keys[perm[pick]];
+        set_center_from_key(centers + 3 * j, key);
+        int cr, cg, cb;
+        key_rgb(key, &cr, &cg, &cb);
+        for (int64_t s = 0; s < L; ++s) {
+            int r, g, b;
+            key_rgb(keys[perm[s]], &r, &g, &b);
+            const int64_t d = dist_int(r, g, b, cr, cg, cb);
+            if (d < d2[s])
+                d2[s] = d;
+        }
+    }
+    free(perm);
+    free(d2);
+    return CQREF_OK;
+}
+
 int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K,
                int32_t scheme, uint64_t seed, double* centers, int32_t* k_used)
 {
     if (!keys || !counts || !centers || n < 1 || K < 1 || K > 256)
         return CQREF_EINVAL;
-    if (scheme < CQREF_INIT_FORGY || scheme > CQREF_INIT_USER)
+    if (scheme < CQREF_INIT_FORGY || scheme > CQREF_INIT_SFF)
         return CQREF_EINVAL;
     if (n <= K) {
         /* Fewer colours than palette entries: every colour is a centre. */
@@ -182,6 +300,10 @@ int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t 
         return CQREF_OK;
 
     uint64_t rng = seed;
+    if (scheme == CQREF_INIT_VAR)
+        return init_var(keys, counts, n, K, centers);
+    if (scheme == CQREF_INIT_SFF)
+        return init_sff(keys, n, K, &rng, centers);
     if (scheme == CQREF_INIT_FORGY) {
         int64_t* perm = (int64_t*)malloc((size_t)n * sizeof(int64_t));
         if (!perm)

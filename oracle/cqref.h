@@ -19,7 +19,8 @@ extern "C" {
 #endif
 
 enum { CQREF_OK = 0, CQREF_EINVAL = 1, CQREF_ECAPACITY = 2, CQREF_ENOMEM = 5 };
-enum { CQREF_INIT_FORGY = 0, CQREF_INIT_MAXMIN = 1, CQREF_INIT_KMEANSPP = 2, CQREF_INIT_USER = 3 };
+enum { CQREF_INIT_FORGY = 0, CQREF_INIT_MAXMIN = 1, CQREF_INIT_KMEANSPP = 2, CQREF_INIT_USER = 3,
+       CQREF_INIT_VAR = 4, CQREF_INIT_SFF = 5 };
 
 typedef struct {
     int32_t iters;      /* Lloyd iterations run                                  */
@@ -35,6 +36,9 @@ typedef struct {
     double mse_img;     /* filled by cqref_quantize: MSE of the mapped image    */
 } cqref_stats;
 
+/* SFF subset size: max(K, ceil(2 K ln K)), at most n. */
+int64_t cqref_sff_subset(int32_t K, int64_t n);
+
 /* splitmix64 (Steele, Lea & Flood 2014): next output for state *s. */
 uint64_t cqref_splitmix64_next(uint64_t* s);
 /* Uniform integer in [0, T) by rejection on splitmix64 outputs (T >= 1). */
@@ -45,7 +49,8 @@ uint64_t cqref_uniform_below(uint64_t* s, uint64_t T);
 int cqref_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride,
                     uint32_t* keys, uint32_t* counts, int64_t capacity, int64_t* n_unique);
 
-/* Initialization schemes of Section 2.3 (FGY, MMX, KPP) on the unique colours. */
+/* Initialization schemes of Section 2.3 (FGY, MMX, KPP, VAR, SFF) on the
+ * unique colours. */
 int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K,
                int32_t scheme, uint64_t seed, double* centers, int32_t* k_used);
 

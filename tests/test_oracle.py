@@ -387,3 +387,135 @@ def test_quantize_end_to_end_small_config():
     assert 10 < psnr < 60
     again = oracle.quantize(img, 16, oracle.INIT_MAXMIN, 0, 50, 1e-4, prune=True)
     assert np.array_equal(again[0], pal) and again[3]["sse_final"] == st["sse_final"]
+
+
+# ---------------------------------------------------------------- VAR and SFF
+def _rand_colours(rng, n, max_count=5):
+    keys = np.sort(rng.choice(1 << 24, size=n, replace=False)).astype(np.uint32)
+    counts = rng.integers(1, max_count + 1, size=n).astype(np.uint32)
+    return keys, counts
+
+
+def _var_brute(keys, counts, K):
+    """VAR of Section 2.3 on the expanded pixel list, in plain Python."""
+    px = np.repeat(keys.astype(np.int64), counts.astype(np.int64))
+    ch = [(px >> 16) & 255, (px >> 8) & 255, px & 255]
+    N = len(px)
+    scores = [N * int((c * c).sum()) - int(c.sum()) ** 2 for c in ch]
+    c = max(range(3), key=lambda i: (scores[i], -i))  # largest; ties to the lower channel
+    order = np.lexsort((px, ch[c]))  # by channel value, then key
+    out = []
+    for g in range(K):
+        lo, hi = g * N // K, (g + 1) * N // K
+        k = int(px[order[lo + (hi - lo - 1) // 2]])
+        out.append([(k >> 16) & 255, (k >> 8) & 255, k & 255])
+    return np.array(out, dtype=np.float64)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_var_matches_pixel_brute_force(seed):
+    rng = np.random.default_rng(1000 + seed)
+    keys, counts = _rand_colours(rng, 60)
+    for K in (1, 2, 5, 7, 16, 59):
+        got, used = oracle.init(keys, counts, K, oracle.INIT_VAR, 0)
+        assert used == K
+        assert np.array_equal(got, _var_brute(keys, counts, K)), K
+
+
+def test_var_closed_form_single_channel():
+    # R = 0..99 once each, G = B = 0: the groups of 25 pixels have lower
+    # medians at R = 12, 37, 62, 87
+    keys = (np.arange(100, dtype=np.uint32) << 16)
+    counts = np.ones(100, dtype=np.uint32)
+    got, _ = oracle.init(keys, counts, 4, oracle.INIT_VAR, 0)
+    assert got[:, 0].tolist() == [12, 37, 62, 87] and not got[:, 1:].any()
+    # weights move the medians: R = 0 holding 300 of 399 pixels takes 3 groups
+    counts2 = counts.copy()
+    counts2[0] = 300
+    got2, _ = oracle.init(keys, counts2, 4, oracle.INIT_VAR, 0)
+    assert got2[:, 0].tolist() == [0, 0, 0, 49]
+
+
+def test_var_picks_the_widest_channel():
+    rng = np.random.default_rng(5)
+    r = rng.integers(0, 256, 200)
+    g = rng.integers(100, 110, 200)
+    b = rng.integers(50, 60, 200)
+    keys, counts = np.unique((r << 16) | (g << 8) | b, return_counts=True)
+    got, _ = oracle.init(keys.astype(np.uint32), counts.astype(np.uint32), 8, oracle.INIT_VAR, 0)
+    assert np.all(np.diff(got[:, 0]) >= 0)  # the centres ascend along R
+
+
+def test_sff_subset_size():
+    for K in range(1, 257):
+        want = max(K, math.ceil(2 * K * math.log(K)))
+        assert oracle.sff_subset(K, 1 << 28) == want
+        assert oracle.sff_subset(K, 50) == min(want, 50)
+        # no 2 K ln K lies near an integer, so the ceiling does not depend on
+        # the last bit of the logarithm
+        v = 2 * K * math.log(K)
+        assert K == 1 or abs(v - round(v)) > 1e-9
+
+
+class _Stream:
+    """The oracle's splitmix64 stream (pinned to the published sequence)."""
+
+    def __init__(self, seed):
+        import ctypes
+        self.s = ctypes.c_uint64(seed)
+        self.ctypes = ctypes
+
+    def below(self, T):
+        return int(oracle.lib().cqref_uniform_below(self.ctypes.byref(self.s), T))
+
+
+def _sff_brute(keys, K, seed):
+    n = len(keys)
+    L = min(max(K, math.ceil(2 * K * math.log(K))), n)
+    st = _Stream(seed)
+    perm = list(range(n))
+    for j in range(L):
+        r = j + st.below(n - j)
+        perm[j], perm[r] = perm[r], perm[j]
+    sub = [int(keys[perm[s]]) for s in range(L)]
+    rgb = [((k >> 16) & 255, (k >> 8) & 255, k & 255) for k in sub]
+    d2 = [None] * L
+    pick = st.below(L)
+    out = []
+    for j in range(K):
+        if j > 0:
+            best = max(d2)
+            pick = d2.index(best)  # lowest subset position among the farthest
+        out.append(list(rgb[pick]))
+        for s in range(L):
+            d = sum((a - b) ** 2 for a, b in zip(rgb[s], rgb[pick]))
+            d2[s] = d if d2[s] is None else min(d2[s], d)
+    return np.array(out, dtype=np.float64)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_sff_matches_brute_force(seed):
+    rng = np.random.default_rng(2000 + seed)
+    keys, counts = _rand_colours(rng, 300)
+    for K in (1, 2, 3, 8, 20):  # subsets of 1, 4, 7, 34 and 120 colours
+        got, _ = oracle.init(keys, counts, K, oracle.INIT_SFF, 77 + seed)
+        assert np.array_equal(got, _sff_brute(keys, K, 77 + seed)), K
+
+
+def test_sff_centres_are_distinct_subset_colours():
+    rng = np.random.default_rng(9)
+    keys, counts = _rand_colours(rng, 5000)
+    got, _ = oracle.init(keys, counts, 64, oracle.INIT_SFF, 3)
+    ks = (got[:, 0].astype(np.int64) << 16) | (got[:, 1].astype(np.int64) << 8) | got[:, 2].astype(np.int64)
+    assert len(set(ks.tolist())) == 64 and set(ks.tolist()) <= set(keys.tolist())
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_sff_ties_go_to_the_lowest_subset_position(seed):
+    # a 3 x 3 x 3 lattice: farthest-first meets equal distances at every step
+    v = np.array([0, 100, 200])
+    keys = np.sort(((v[:, None, None] << 16) | (v[None, :, None] << 8) | v[None, None, :]).ravel()).astype(np.uint32)
+    counts = np.ones(len(keys), dtype=np.uint32)
+    for K in (4, 6):  # subsets of 12 and 22 of the 27 colours
+        got, _ = oracle.init(keys, counts, K, oracle.INIT_SFF, seed)
+        assert np.array_equal(got, _sff_brute(keys, K, seed)), K
