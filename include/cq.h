@@ -50,7 +50,9 @@ typedef enum {
     CQ_INIT_FORGY = 0,     /* K distinct colours drawn uniformly (FGY)              */
     CQ_INIT_MAXMIN = 1,    /* farthest-first after a uniform first colour (MMX)     */
     CQ_INIT_KMEANSPP = 2,  /* D^2 sampling, weighted by pixel counts (KPP)          */
-    CQ_INIT_USER = 3       /* centres supplied by the caller (WSM-X warm start)     */
+    CQ_INIT_USER = 3,      /* centres supplied by the caller (WSM-X warm start)     */
+    CQ_INIT_VAR = 4,       /* maximum variance: medians along the widest channel    */
+    CQ_INIT_SFF = 5        /* farthest first on a random subset (SFF)              */
 } cq_init_t;
 
 /* Run statistics (host structure). */
@@ -96,8 +98,15 @@ cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_str
  * from one splitmix64 stream seeded with `seed`: FGY does a partial
  * Fisher-Yates shuffle (draw j uniform in [j, N')); MMX draws the first colour
  * uniformly; KPP draws the first colour with probability proportional to its
- * count and colour j with probability proportional to count * D^2.  With
- * CQ_INIT_USER the centres are left as given.  Synchronizes only if k_used is
+ * count and colour j with probability proportional to count * D^2.  VAR takes
+ * the pixel data set (colour i repeated count_i times): the channel with the
+ * largest pixel variance (ties: R, then G, then B), the pixels ordered by
+ * (that channel's value, key), K groups [floor(g N / K), floor((g+1) N / K)) of
+ * the N pixels, and each group's lower-median pixel; no draws.  SFF draws a
+ * subset of L = max(K, ceil(2 K ln K)) colours (at most N') as FGY draws, then
+ * runs MMX on the subset in draw order (first centre subset[U(L)], ties to
+ * the lowest subset position).  With CQ_INIT_USER the centres are left as
+ * given.  Synchronizes only if k_used is
  * non-null; a device-side failure of the initialization is reported by that
  * synchronization or by the next synchronizing call on the workspace. */
 cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique, int32_t K,
@@ -162,7 +171,7 @@ typedef struct {
     int32_t H, W;
     int64_t row_stride_bytes;
     int32_t K;                  /* palette size, 1..256                                 */
-    cq_init_t scheme;           /* CQ_INIT_FORGY, CQ_INIT_MAXMIN or CQ_INIT_KMEANSPP    */
+    cq_init_t scheme;           /* any cq_init_t but CQ_INIT_USER                       */
     uint64_t seed;
     int32_t max_iters;          /* 1..100000                                            */
     double tol;                 /* >= 0                                                 */

@@ -283,7 +283,7 @@ void set_counts(Batch& b, const std::vector<int64_t>& n)
 
 cq_status run_init(Batch& b)
 {
-    bool any_forgy = false;
+    bool any_forgy = false, any_sff = false;
     std::vector<int64_t> coop_n(size_t(b.B), 0);
     for (int j = 0; j < b.B; ++j) {
         JobDev& J = b.h[j];
@@ -291,13 +291,22 @@ cq_status run_init(Batch& b)
         if (J.n <= J.K) continue;
         if (J.scheme == CQ_INIT_FORGY) any_forgy = true;
         if (J.scheme == CQ_INIT_MAXMIN || J.scheme == CQ_INIT_KMEANSPP) coop_n[j] = J.n;
+        if (J.scheme == CQ_INIT_SFF) {
+            any_sff = true;
+            J.init_C = sff_subset(J.K, J.n);
+        }
     }
+    auto var_job = [&](int j) { return b.h[j].scheme == CQ_INIT_VAR && b.h[j].n > b.h[j].K; };
+    const int var_tiles = b.set_map(kMapVarTiles, [&](int j) { return var_job(j) ? var_tile_count(b.h[j].n) : 0; });
+    const int var_groups = b.set_map(kMapVarGroups, [&](int j) { return var_job(j) ? b.h[j].K : 0; });
     const int cap = coop_capacity();
     std::vector<int> want(size_t(b.B), 0);
     coop_team_sizes(coop_n.data(), want.data(), b.B, cap);
     CQ_TRY(upload(b));
     CQ_TRY(launch_init_begin(b.d_jobs(), b.B, b.s));
     if (any_forgy) CQ_TRY(launch_forgy(b.d_jobs(), b.B, b.s));
+    if (var_tiles > 0) CQ_TRY(launch_var(b.d_jobs(), b.d_maps(), b.B, var_tiles, var_groups, b.s));
+    if (any_sff) CQ_TRY(launch_sff(b.d_jobs(), b.B, b.s));
     int next = 0;
     while (true) {
         while (next < b.B && want[next] == 0) ++next;
@@ -499,8 +508,8 @@ cq_status check_job(const cq_job& j, int idx)
     cq_status s = check_image(j.img, j.H, j.W, j.row_stride_bytes);
     if (s == CQ_OK) s = check_k(j.K);
     if (s == CQ_OK && !j.palette) s = einval("palette is null");
-    if (s == CQ_OK && (int(j.scheme) < CQ_INIT_FORGY || int(j.scheme) > CQ_INIT_KMEANSPP))
-        s = einval("scheme must be FORGY, MAXMIN or KMEANSPP");
+    if (s == CQ_OK && (int(j.scheme) < CQ_INIT_FORGY || int(j.scheme) > CQ_INIT_SFF || j.scheme == CQ_INIT_USER))
+        s = einval("scheme must be FORGY, MAXMIN, KMEANSPP, VAR or SFF");
     if (s == CQ_OK) s = check_iters_tol(j.max_iters, j.tol);
     if (s != CQ_OK) {
         char msg[512];
@@ -570,7 +579,7 @@ cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique
     CQ_TRY(check_k(K));
     if (!keys || !counts || !centers) return einval("keys/counts/centers is null");
     if (n_unique < 1 || n_unique > kMaxPixels) return einval("n_unique = %lld out of range", (long long)n_unique);
-    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_USER) return einval("unknown init scheme %d", int(scheme));
+    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_SFF) return einval("unknown init scheme %d", int(scheme));
     const Layout L = make_layout(0, n_unique, false);
     CQ_TRY(check_ws(ws, ws_bytes, L.total));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
@@ -674,8 +683,8 @@ cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stri
     CQ_TRY(check_image(img, H, W, row_stride_bytes));
     CQ_TRY(check_k(K));
     if (!palette) return einval("palette is null");
-    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_KMEANSPP)
-        return einval("cq_quantize needs scheme FORGY, MAXMIN or KMEANSPP");
+    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_SFF || scheme == CQ_INIT_USER)
+        return einval("cq_quantize needs scheme FORGY, MAXMIN, KMEANSPP, VAR or SFF");
     CQ_TRY(check_iters_tol(max_iters, tol));
     const int64_t npix = int64_t(H) * W;
     const Layout L = make_layout(npix, npix, true);

@@ -58,6 +58,10 @@ void coop_team_sizes(const int64_t* n, int* want, int B, int cap);
 bool coop_fits_lds(int64_t C);
 cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s);
 cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s);
+cq_status launch_var(const JobDev* jobs, const int* maps, int B, int tiles, int groups, hipStream_t s);
+int var_tile_count(int64_t n);
+cq_status launch_sff(const JobDev* jobs, int B, hipStream_t s);
+int64_t sff_subset(int32_t K, int64_t n);
 cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, bool lds, hipStream_t s);
 cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s);
 cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool first, int all_blocks,

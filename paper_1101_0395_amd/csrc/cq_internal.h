@@ -214,6 +214,8 @@ enum MapId {
     kMapLut,
     kMapPix,
     kMapInit,
+    kMapVarTiles,    // VAR: colour tiles
+    kMapVarGroups,   // VAR: one block per centre
     kNumMaps
 };
 

@@ -8,6 +8,8 @@
 // documented for cq_init in cq.h.
 #include <stdlib.h>
 
+#include <math.h>
+
 #include "cq_internal.h"
 
 namespace cq {
@@ -70,6 +72,289 @@ __global__ void __launch_bounds__(64) k_forgy(const JobDev* __restrict__ jobs)
         __syncthreads();
     }
     if (lane == 0) meta->rng = rng;
+}
+
+// ------------------------------------------------------------------------
+// VAR (maximum variance), read on the pixel data set: colour i stands for
+// counts[i] identical pixels.  The channel is the one with the largest pixel
+// variance (N S2 - S1^2, exact; ties to the lower channel, R before G before
+// B); the pixels in ascending (channel value, key) order are cut into K groups
+// [floor(g N / K), floor((g+1) N / K)) and centre g is the pixel at the
+// group's lower median.  The colours are in key order, so within one channel
+// value they are already in key order: a tile of kVarTile colours keeps the
+// pixel count of every value of every channel, and the pixel at a given
+// position is found by value, then tile, then colour.
+constexpr int kVarTile = 1024;
+constexpr int kVarThreads = 1024;
+constexpr int kVarStats = 7;  // per tile: pixels, then n x and n x^2 for R, G, B
+
+__host__ __device__ __forceinline__ int64_t var_tiles(int64_t n) { return (n + kVarTile - 1) / kVarTile; }
+
+// Per-tile statistics in the work region: pixel counts per (channel, value)
+// as uint32 [T][3][256], then the sums as uint64 [T][kVarStats].
+__device__ __forceinline__ uint32_t* var_hist(const JobDev& J) { return gp(J.d2); }
+__device__ __forceinline__ unsigned long long* var_sums(const JobDev& J)
+{
+    return reinterpret_cast<unsigned long long*>(gp(J.d2) + var_tiles(J.n) * 3 * 256);  // 3 KiB per tile: aligned
+}
+
+__device__ __forceinline__ int key_channel(uint32_t key, int c) { return int((key >> (16 - 8 * c)) & 255u); }
+
+__global__ void __launch_bounds__(kVarThreads) k_var_tiles(const JobDev* __restrict__ jobs, const int* __restrict__ map,
+                                                          int B)
+{
+    __shared__ uint32_t h[3 * 256];
+    __shared__ unsigned long long red[kVarStats][kVarThreads / 64];
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int64_t t = blockIdx.x - map[jb];
+    const int k = threadIdx.x, lane = k & 63, wave = k >> 6;
+    for (int i = k; i < 3 * 256; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    const int64_t i = t * kVarTile + k;
+    unsigned long long st[kVarStats] = {0, 0, 0, 0, 0, 0, 0};
+    if (i < J.n) {
+        const uint32_t key = gp(J.keys)[i];
+        const uint32_t cnt = gp(J.counts)[i];
+        st[0] = cnt;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const unsigned x = unsigned(key_channel(key, c));
+            atomicAdd(&h[c * 256 + int(x)], cnt);
+            st[1 + 2 * c] = (unsigned long long)cnt * x;
+            st[2 + 2 * c] = (unsigned long long)cnt * (x * x);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kVarStats; ++q) {
+        const unsigned long long v = wave_sum(st[q]);
+        if (lane == 0) red[q][wave] = v;
+    }
+    __syncthreads();
+    uint32_t* __restrict__ out = var_hist(J) + t * 3 * 256;
+    for (int q = k; q < 3 * 256; q += blockDim.x) out[q] = h[q];
+    if (k < kVarStats) {
+        unsigned long long v = 0;
+        for (int w = 0; w < kVarThreads / 64; ++w) v += red[k][w];
+        var_sums(J)[t * kVarStats + k] = v;
+    }
+}
+
+// One block per job: the channel, then each group's median pixel as (value,
+// position among the pixels of that value), packed for k_var_find as
+// channel << 48 | value << 32 | position.
+__global__ void __launch_bounds__(kVarThreads) k_var_pick(const JobDev* __restrict__ jobs)
+{
+    const JobDev& J = jobs[blockIdx.x];
+    if (J.scheme != CQ_INIT_VAR || J.n <= J.K) return;
+    __shared__ unsigned long long red[kVarStats][kVarThreads / 64];
+    __shared__ unsigned long long tot[kVarStats];
+    __shared__ int s_ch;
+    __shared__ uint32_t part[kVarThreads / 256][256];
+    __shared__ unsigned long long start[257];
+    const int k = threadIdx.x, lane = k & 63, wave = k >> 6;
+    const int64_t T = var_tiles(J.n);
+    const unsigned long long* __restrict__ sums = var_sums(J);
+    unsigned long long st[kVarStats] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t t = k; t < T; t += blockDim.x)
+#pragma unroll
+        for (int q = 0; q < kVarStats; ++q) st[q] += sums[t * kVarStats + q];
+#pragma unroll
+    for (int q = 0; q < kVarStats; ++q) {
+        const unsigned long long v = wave_sum(st[q]);
+        if (lane == 0) red[q][wave] = v;
+    }
+    __syncthreads();
+    if (k < kVarStats) {
+        unsigned long long v = 0;
+        for (int w = 0; w < kVarThreads / 64; ++w) v += red[k][w];
+        tot[k] = v;
+    }
+    __syncthreads();
+    const unsigned long long N = tot[0];
+    if (k == 0) {
+        int ch = 0;
+        unsigned __int128 best = 0;
+        for (int c = 0; c < 3; ++c) {
+            const unsigned __int128 v = (unsigned __int128)N * tot[2 + 2 * c] -
+                                        (unsigned __int128)tot[1 + 2 * c] * tot[1 + 2 * c];
+            if (c == 0 || v > best) {
+                best = v;
+                ch = c;
+            }
+        }
+        s_ch = ch;
+    }
+    __syncthreads();
+    const int ch = s_ch;
+    // pixels per value of the channel: thread k sums value k % 256 over every
+    // (kVarThreads / 256)-th tile
+    {
+        const int v = k & 255, q = k >> 8;
+        const uint32_t* __restrict__ h = var_hist(J);
+        uint32_t c = 0;
+        for (int64_t t = q; t < T; t += kVarThreads / 256) c += h[t * 3 * 256 + ch * 256 + v];
+        part[q][v] = c;
+    }
+    __syncthreads();
+    if (k < 256) {
+        unsigned long long c = 0;
+        for (int q = 0; q < kVarThreads / 256; ++q) c += part[q][k];
+        start[k + 1] = c;  // pixels of value k; a prefix sum below
+    }
+    __syncthreads();
+    if (k == 0) {
+        start[0] = 0;
+        for (int v = 0; v < 256; ++v) start[v + 1] += start[v];
+    }
+    __syncthreads();
+    if (k < J.K) {
+        const unsigned long long lo = (unsigned long long)(((unsigned __int128)k * N) / unsigned(J.K));
+        const unsigned long long hi = (unsigned long long)(((unsigned __int128)(k + 1) * N) / unsigned(J.K));
+        const unsigned long long m = lo + (hi - lo - 1) / 2;
+        int l = 0, r = 256;  // last value whose first pixel is at or before m
+        while (r - l > 1) {
+            const int mid = (l + r) >> 1;
+            if (start[mid] <= m) l = mid; else r = mid;
+        }
+        gp(J.vals)[k] = (uint64_t(ch) << 48) | (uint64_t(l) << 32) | (m - start[l]);
+    }
+}
+
+// One block per centre: the tile holding the group's median pixel (a scan of
+// the tiles' counts of that value), then the colour in the tile.
+__global__ void __launch_bounds__(kVarThreads) k_var_find(const JobDev* __restrict__ jobs, const int* __restrict__ map,
+                                                         int B)
+{
+    __shared__ uint32_t tmp[64];
+    __shared__ int64_t s_tile;
+    __shared__ uint32_t s_off;
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int g = blockIdx.x - map[jb];
+    const int k = threadIdx.x;
+    const uint64_t target = gp(J.vals)[g];
+    const int ch = int(target >> 48), v = int((target >> 32) & 255u);
+    const uint32_t pos = uint32_t(target);
+    const int64_t T = var_tiles(J.n);
+    const uint32_t* __restrict__ h = var_hist(J);
+    if (k == 0) s_tile = -1;
+    __syncthreads();
+    uint32_t carry = 0;
+    for (int64_t t0 = 0; t0 < T; t0 += blockDim.x) {
+        const int64_t t = t0 + k;
+        const uint32_t c = t < T ? h[t * 3 * 256 + ch * 256 + v] : 0u;
+        uint32_t total = 0;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(c, tmp, &total);
+        if (c > 0 && carry + ex <= pos && pos < carry + ex + c) {
+            s_tile = t;
+            s_off = pos - (carry + ex);
+        }
+        __syncthreads();
+        if (s_tile >= 0) break;
+        carry += total;
+    }
+    const int64_t t = s_tile;
+    if (t < 0) return;  // unreachable: the position lies below the value's pixel count
+    const uint32_t off = s_off;
+    const int64_t i = t * kVarTile + k;
+    uint32_t key = 0, w = 0;
+    if (i < J.n) {
+        key = gp(J.keys)[i];
+        w = key_channel(key, ch) == v ? gp(J.counts)[i] : 0u;
+    }
+    const uint32_t ex = block_exclusive_scan<uint32_t>(w, tmp, nullptr);
+    if (w > 0 && ex <= off && off < ex + w) write_center(gp(J.centers), g, key);
+}
+
+// ------------------------------------------------------------------------
+// SFF (subset farthest first): the first L = max(K, ceil(2 K ln K)) positions
+// (at most N') of a partial Fisher-Yates shuffle of the colours, drawn as FGY
+// draws them, then MMX on that subset in draw order: the first centre is
+// subset[U(L)], then K - 1 farthest-first picks by integer D^2, ties to the
+// lowest subset position.  One block per job.  The draws are sequential
+// (thread 0); the positions that a swap displaced are kept in an LDS hash map
+// (open addressing) from position to colour index.
+constexpr int kSffMax = 2840;         // L at K = 256
+constexpr int kSffHash = 8192;        // slots, more than twice the 2 L entries
+constexpr int kSffThreads = 1024;
+
+__device__ __forceinline__ int sff_slot(const int32_t* hk, int32_t pos)
+{
+    uint32_t h = (uint32_t(pos) * 2654435761u) >> (32 - 13);
+    while (hk[h] != -1 && hk[h] != pos) h = (h + 1) & (kSffHash - 1);
+    return int(h);
+}
+
+__global__ void __launch_bounds__(kSffThreads) k_sff(const JobDev* __restrict__ jobs)
+{
+    const JobDev& J = jobs[blockIdx.x];
+    if (J.scheme != CQ_INIT_SFF || J.n <= J.K) return;
+    __shared__ int32_t hk[kSffHash];
+    __shared__ int32_t hv[kSffHash];
+    __shared__ uint32_t sub[kSffMax];  // subset keys, in draw order
+    __shared__ uint32_t d2[kSffMax];
+    __shared__ unsigned long long wbest[kSffThreads / 64];
+    __shared__ int s_pick;
+    const int k = threadIdx.x, lane = k & 63, wave = k >> 6;
+    const uint32_t* __restrict__ keys = gp(J.keys);
+    const int64_t n = J.n;
+    const int K = J.K;
+    const int L = J.init_C;  // subset size, set by the host
+    Meta* __restrict__ meta = gp(J.meta);
+    for (int i = k; i < kSffHash; i += blockDim.x) hk[i] = -1;
+    __syncthreads();
+    if (k == 0) {
+        uint64_t rng = meta->rng;
+        auto value_at = [&](int32_t p) {
+            const int h = sff_slot(hk, p);
+            return hk[h] == p ? hv[h] : p;
+        };
+        auto set_at = [&](int32_t p, int32_t val) {
+            const int h = sff_slot(hk, p);
+            hk[h] = p;
+            hv[h] = val;
+        };
+        for (int j = 0; j < L; ++j) {
+            const int32_t r = int32_t(j + int64_t(uniform_below(rng, uint64_t(n - j))));
+            const int32_t vj = value_at(j), vr = value_at(r);
+            set_at(j, vr);
+            set_at(r, vj);
+            sub[j] = keys[vr];
+        }
+        s_pick = int(uniform_below(rng, uint64_t(L)));
+        meta->rng = rng;
+    }
+    for (int s2 = k; s2 < L; s2 += blockDim.x) d2[s2] = 0xFFFFFFFFu;
+    __syncthreads();
+    double* __restrict__ centers = gp(J.centers);
+    for (int j = 0; j < K; ++j) {
+        const uint32_t pk = sub[s_pick];
+        if (k == 0) write_center(centers, j, pk);
+        int cr, cg, cb;
+        key_rgb(pk, cr, cg, cb);
+        // lower D^2 with the new centre; the farthest subset colour, lowest
+        // position on ties, packed as D^2 << 32 | (2^32 - 1 - position)
+        unsigned long long best = 0;
+        for (int q = k; q < L; q += blockDim.x) {
+            int r, g, b;
+            key_rgb(sub[q], r, g, b);
+            const uint32_t d = dist_u32(r, g, b, cr, cg, cb);
+            const uint32_t m = d < d2[q] ? d : d2[q];
+            d2[q] = m;
+            const unsigned long long packed = (uint64_t(m) << 32) | uint64_t(0xFFFFFFFFu - uint32_t(q));
+            best = packed > best ? packed : best;
+        }
+        best = wave_max(best);
+        if (lane == 0) wbest[wave] = best;
+        __syncthreads();
+        if (k == 0) {
+            unsigned long long b = 0;
+            for (int w = 0; w < kSffThreads / 64; ++w) b = wbest[w] > b ? wbest[w] : b;
+            s_pick = int(0xFFFFFFFFu - uint32_t(b));
+        }
+        __syncthreads();
+    }
 }
 
 // Per job: seed the stream and reset the team barrier; for N' <= K the
@@ -485,6 +770,30 @@ cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s)
 {
     CQ_TIMED_LAUNCH("k_init_begin", s, k_init_begin<<<B, kMaxK, 0, s>>>(jobs));
     return CQ_OK;
+}
+
+cq_status launch_var(const JobDev* jobs, const int* maps, int B, int tiles, int groups, hipStream_t s)
+{
+    CQ_TIMED_LAUNCH("k_var_tiles", s, k_var_tiles<<<tiles, kVarThreads, 0, s>>>(jobs, maps + kMapVarTiles * (B + 1), B));
+    CQ_TIMED_LAUNCH("k_var_pick", s, k_var_pick<<<B, kVarThreads, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_var_find", s, k_var_find<<<groups, kVarThreads, 0, s>>>(jobs, maps + kMapVarGroups * (B + 1), B));
+    return CQ_OK;
+}
+
+int var_tile_count(int64_t n) { return int(var_tiles(n)); }
+
+cq_status launch_sff(const JobDev* jobs, int B, hipStream_t s)
+{
+    CQ_TIMED_LAUNCH("k_sff", s, k_sff<<<B, kSffThreads, 0, s>>>(jobs));
+    return CQ_OK;
+}
+
+// SFF subset size: max(K, ceil(2 K ln K)), at most n (at most kSffMax).
+int64_t sff_subset(int32_t K, int64_t n)
+{
+    int64_t L = int64_t(ceil(2.0 * double(K) * log(double(K))));
+    if (L < K) L = K;
+    return L < n ? L : n;
 }
 
 cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s)

@@ -44,6 +44,9 @@ MIXED = [
     (200, 301, 128, oracle.INIT_MAXMIN, 7, True, 5, 1e-4),
     (5, 3, 8, oracle.INIT_KMEANSPP, 8, True, 20, 1e-4),
     (257, 129, 256, oracle.INIT_KMEANSPP, 9, False, 15, 1e-4),
+    (240, 180, 64, oracle.INIT_VAR, 10, True, 100, 1e-4),
+    (150, 90, 32, oracle.INIT_SFF, 11, True, 100, 1e-4),
+    (6, 6, 16, oracle.INIT_VAR, 12, True, 10, 1e-4),  # N' <= K
 ]
 
 

@@ -97,7 +97,8 @@ def _hist_pair(img, cqm, dev, ws):
     return rk, rc, _to_dev(rk.view(np.int32), dev), _to_dev(rc.view(np.int32), dev)
 
 
-@pytest.mark.parametrize("scheme", [oracle.INIT_FORGY, oracle.INIT_MAXMIN, oracle.INIT_KMEANSPP])
+@pytest.mark.parametrize("scheme", [oracle.INIT_FORGY, oracle.INIT_MAXMIN, oracle.INIT_KMEANSPP, oracle.INIT_VAR,
+                                    oracle.INIT_SFF])
 @pytest.mark.parametrize("K,seed", [(16, 0), (64, 3), (256, 1)])
 def test_init_parity(cqm, dev, ws_small, scheme, K, seed):
     _say(f"init scheme={scheme} K={K} seed={seed}")
@@ -107,6 +108,27 @@ def test_init_parity(cqm, dev, ws_small, scheme, K, seed):
     got, used = cqm.cq_init(dk, dc, K, scheme, seed, ws_small)
     assert used == ref_used
     assert np.array_equal(got.cpu().numpy(), ref)
+
+
+def test_var_weighted_duplicates_and_sff_small_sets(cqm, dev, ws_small):
+    """VAR where one colour's pixels span several groups (repeated centres),
+    and SFF on sets smaller than its subset size (the subset is every colour)."""
+    _say("init VAR heavy colour / SFF small set")
+    rng = np.random.default_rng(31)
+    img = rng.integers(0, 256, (64, 96, 3)).astype(np.uint8)
+    img[:40] = (200, 10, 90)  # 2560 of 6144 pixels share one colour
+    rk, rc, dk, dc = _hist_pair(img, cqm, dev, ws_small)
+    for K in (5, 16, 64):
+        ref, _ = oracle.init(rk, rc, K, oracle.INIT_VAR, 0)
+        got, _ = cqm.cq_init(dk, dc, K, oracle.INIT_VAR, 0, ws_small)
+        assert np.array_equal(got.cpu().numpy(), ref), K
+    small = rng.integers(0, 256, (10, 12, 3)).astype(np.uint8)
+    rk, rc, dk, dc = _hist_pair(small, cqm, dev, ws_small)
+    for K in (8, 40, 100):  # subsets 34, 296 and 921 capped at the ~120 colours
+        for seed in (1, 2):
+            ref, _ = oracle.init(rk, rc, K, oracle.INIT_SFF, seed)
+            got, _ = cqm.cq_init(dk, dc, K, oracle.INIT_SFF, seed, ws_small)
+            assert np.array_equal(got.cpu().numpy(), ref), (K, seed)
 
 
 def test_init_fewer_colours_than_k(cqm, dev, ws_small):
@@ -251,6 +273,13 @@ def test_full_size_4096(cqm, dev):
     m0, _ = oracle.init(rk, rc, 64, oracle.INIT_MAXMIN, 5)
     gm, _ = cqm.cq_init(keys, counts, 64, oracle.INIT_MAXMIN, 5, ws)
     assert np.array_equal(gm.cpu().numpy(), m0)
+    # VAR over thousands of tiles (several rounds of the tile scan), and SFF
+    v0, _ = oracle.init(rk, rc, 256, oracle.INIT_VAR, 0)
+    gv, _ = cqm.cq_init(keys, counts, 256, oracle.INIT_VAR, 0, ws)
+    assert np.array_equal(gv.cpu().numpy(), v0)
+    f0, _ = oracle.init(rk, rc, 256, oracle.INIT_SFF, 9)
+    gf, _ = cqm.cq_init(keys, counts, 256, oracle.INIT_SFF, 9, ws)
+    assert np.array_equal(gf.cpu().numpy(), f0)
     r = oracle.kmeans(rk, rc, c0, 3, 1e-4, True)
     g = cqm.cq_kmeans(keys, counts, _to_dev(c0, dev), 3, 1e-4, True, ws)
     _compare_kmeans(g, r)
