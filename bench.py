@@ -148,6 +148,44 @@ def measure_serving(cq, torch, synth, imgs, dev):
     return out
 
 
+def measure_init_schemes(cq, torch, imgs, dev, reps=3):
+    """The headline batch (eight 512 x 512 stand-ins, K = 256, sort-means, tol
+    1e-4) with each initialization scheme: step time, the time of the scheme's
+    own kernels (HIP events), mean iterations and mean MSE of the mapped
+    images."""
+    import numpy as np
+
+    kernels = {cq.INIT_FORGY: ["k_forgy"], cq.INIT_MAXMIN: ["k_init_coop"], cq.INIT_KMEANSPP: ["k_init_coop"],
+               cq.INIT_VAR: ["k_var_tiles", "k_var_pick", "k_var_find"], cq.INIT_SFF: ["k_sff"]}
+    names = {cq.INIT_FORGY: "FGY", cq.INIT_MAXMIN: "MMX", cq.INIT_KMEANSPP: "KPP", cq.INIT_VAR: "VAR",
+             cq.INIT_SFF: "SFF"}
+    out = {}
+    for scheme, kern in kernels.items():
+        jobs = [cq.BatchJob(img, K, scheme, SEEDS[i], MAX_ITERS, TOL, True) for i, img in enumerate(imgs)]
+        bws = cq.BatchWorkspace(jobs, dev)
+        cq.cq_quantize_batch(jobs, bws)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = cq.cq_quantize_batch(jobs, bws)
+        torch.cuda.synchronize()
+        step_ms = 1e3 * (time.perf_counter() - t0) / reps
+        init_ms = 0.0
+        for name in kern:
+            t = cq.KernelTimer(name, reps * 4)
+            t.enable()
+            for _ in range(reps):
+                cq.cq_quantize_batch(jobs, bws)
+            torch.cuda.synchronize()
+            launches, ms = t.read()
+            t.disable()
+            init_ms += ms / reps
+        out[names[scheme]] = {"step_ms": step_ms, "init_ms": init_ms,
+                              "mean_iters": float(np.mean([x["iters"] for x in st])),
+                              "mean_mse": float(np.mean([x["mse_img"] for x in st]))}
+    return out
+
+
 def recorded_traffic():
     """HBM bytes per launch of the sort-means pass from the committed counter
     summary, if it was measured on the kernel source as it is now; else None."""
@@ -173,6 +211,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 4096x4096 histogram/map bandwidth figures")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching latency figures")
+    ap.add_argument("--no-init-schemes", action="store_true", help="skip the per-initialization figures")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="finish with plain device-to-device copies of this many MiB (a known-size kernel "
                          "for scaling memory counters)")
@@ -300,6 +339,8 @@ def main():
         line["hbm_bound_steps_4096"] = measure_large(cq, synth, torch, dev)
     if not args.no_serving:
         line["serving"] = measure_serving(cq, torch, synth, imgs, dev)
+    if not args.no_init_schemes:
+        line["init_schemes_8x512"] = measure_init_schemes(cq, torch, imgs, dev)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -294,6 +294,10 @@ cq_status run_init(Batch& b)
         if (J.scheme == CQ_INIT_SFF) {
             any_sff = true;
             J.init_C = sff_subset(J.K, J.n);
+            // CQ_SFF_SEQUENTIAL=1 takes the draws one at a time (the path for a
+            // rejected draw), for tests; read on every call
+            const char* e = getenv("CQ_SFF_SEQUENTIAL");
+            J.init_blocks = (e && atoi(e) > 0) ? 1 : 0;
         }
     }
     auto var_job = [&](int j) { return b.h[j].scheme == CQ_INIT_VAR && b.h[j].n > b.h[j].K; };

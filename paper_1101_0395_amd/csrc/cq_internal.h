@@ -348,6 +348,14 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t& s)
     return z ^ (z >> 31);
 }
 
+// splitmix64 is counter-based: the i-th output (0-based) of the stream whose
+// state starts at s0 is the finalizer applied to s0 + (i + 1) gamma.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t s0, uint64_t i)
+{
+    uint64_t s = s0 + i * 0x9E3779B97F4A7C15ull;
+    return splitmix64(s);
+}
+
 // r mod T (T >= 1), exactly.  The quotient is estimated in FP64 twice (the
 // first estimate is within 2^12 / T + 1 of r / T, so the remainder left by it
 // has magnitude below 2^12 + 2 T, which the second estimate resolves to within

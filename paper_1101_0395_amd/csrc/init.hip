@@ -272,11 +272,22 @@ __global__ void __launch_bounds__(kVarThreads) k_var_find(const JobDev* __restri
 // (at most N') of a partial Fisher-Yates shuffle of the colours, drawn as FGY
 // draws them, then MMX on that subset in draw order: the first centre is
 // subset[U(L)], then K - 1 farthest-first picks by integer D^2, ties to the
-// lowest subset position.  One block per job.  The draws are sequential
-// (thread 0); the positions that a swap displaced are kept in an LDS hash map
-// (open addressing) from position to colour index.
-constexpr int kSffMax = 2840;         // L at K = 256
-constexpr int kSffHash = 8192;        // slots, more than twice the 2 L entries
+// lowest subset position.  One block per job.
+//
+// The draws are taken in parallel: the stream is counter-based, and a draw
+// uses the next output unless it falls below U's rejection threshold (about
+// T / 2^64, T < 2^28), so draw j uses output j unless an earlier draw was
+// rejected; if any draw would be, the block falls back to drawing one at a
+// time.  Position j of the shuffle then holds the colour index that was at
+// position r_j just before step j: the value W of the last earlier step k
+// with r_k = r_j, or r_j itself if there is none, where W(k), the value at
+// position k before step k, is in turn W of the last earlier step that wrote
+// position k, or k.  Those last-writer links come from one sort of the
+// (r_j, j) pairs.  The sequential fallback keeps the displaced positions in
+// an LDS hash map (open addressing) from position to colour index.
+constexpr int kSffMax = 2840;    // L at K = 256
+constexpr int kSffSort = 4096;   // sort width, a power of two >= kSffMax
+constexpr int kSffHash = 8192;   // fallback slots, more than twice the 2 L entries
 constexpr int kSffThreads = 1024;
 
 __device__ __forceinline__ int sff_slot(const int32_t* hk, int32_t pos)
@@ -290,22 +301,91 @@ __global__ void __launch_bounds__(kSffThreads) k_sff(const JobDev* __restrict__ 
 {
     const JobDev& J = jobs[blockIdx.x];
     if (J.scheme != CQ_INIT_SFF || J.n <= J.K) return;
-    __shared__ int32_t hk[kSffHash];
-    __shared__ int32_t hv[kSffHash];
+    // the sort (fast path) and the hash map (fallback) share one buffer
+    __shared__ __attribute__((aligned(16))) uint64_t buf[kSffHash];  // 64 KiB
+    __shared__ int32_t rr[kSffMax];    // r_j
+    __shared__ int32_t hit[kSffMax];   // the last step before k that wrote position k
     __shared__ uint32_t sub[kSffMax];  // subset keys, in draw order
     __shared__ uint32_t d2[kSffMax];
     __shared__ unsigned long long wbest[kSffThreads / 64];
-    __shared__ int s_pick;
+    __shared__ int s_pick, s_rejected;
     const int k = threadIdx.x, lane = k & 63, wave = k >> 6;
     const uint32_t* __restrict__ keys = gp(J.keys);
     const int64_t n = J.n;
     const int K = J.K;
-    const int L = J.init_C;  // subset size, set by the host
+    const int L = int(J.init_C);  // subset size, set by the host
     Meta* __restrict__ meta = gp(J.meta);
-    for (int i = k; i < kSffHash; i += blockDim.x) hk[i] = -1;
+    const uint64_t s0 = meta->rng;
+    if (k == 0) s_rejected = J.init_blocks;  // nonzero: the host asks for the draws one at a time
     __syncthreads();
-    if (k == 0) {
-        uint64_t rng = meta->rng;
+    // every draw, assuming no rejection: r_j = j + (output_j mod (N' - j)); the
+    // first pick, output_L mod L
+    for (int j = k; j <= L; j += blockDim.x) {
+        const uint64_t T = j < L ? uint64_t(n - j) : uint64_t(L);
+        const uint64_t out = splitmix64_at(s0, uint64_t(j));
+        if (out < mod_u64(0ull - T, T)) s_rejected = 1;
+        const uint64_t v = mod_u64(out, T);
+        if (j < L) rr[j] = int32_t(j + int64_t(v));
+        else s_pick = int(v);
+    }
+    __syncthreads();
+    if (!s_rejected) {
+        for (int i = k; i < kSffSort; i += blockDim.x)
+            buf[i] = i < L ? (uint64_t(uint32_t(rr[i])) << 12) | uint64_t(i) : ~0ull;
+        __syncthreads();
+        // bitonic sort of the (r, step) pairs
+        for (int size = 2; size <= kSffSort; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = k; i < kSffSort / 2; i += blockDim.x) {
+                    const int lo = 2 * i - (i & (stride - 1));
+                    const int hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint64_t a = buf[lo], b = buf[hi];
+                    if ((a > b) == up) {
+                        buf[lo] = b;
+                        buf[hi] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // the links (no array is both read and written between two barriers):
+        // d2[j] <- the last earlier step with r = r_j (its sorted predecessor
+        // with the same r), hit[k] <- the last step before k with r = k (binary
+        // search for (k, k)); ~0 / -1 for none
+        for (int q = k; q < L; q += blockDim.x) {
+            const uint64_t e = buf[q];
+            const bool same = q > 0 && (buf[q - 1] >> 12) == (e >> 12);
+            d2[e & 4095u] = same ? uint32_t(buf[q - 1] & 4095u) : 0xFFFFFFFFu;
+        }
+        for (int j = k; j < L; j += blockDim.x) {
+            const uint64_t probe = (uint64_t(uint32_t(j)) << 12) | uint64_t(j);
+            int l = 0, r = L;  // first sorted entry >= probe
+            while (l < r) {
+                const int m = (l + r) >> 1;
+                if (buf[m] < probe) l = m + 1; else r = m;
+            }
+            hit[j] = (l > 0 && (buf[l - 1] >> 12) == uint64_t(j)) ? int(buf[l - 1] & 4095u) : -1;
+        }
+        __syncthreads();
+        // position j's colour index: W(last) if a step before j drew r_j, else
+        // r_j; W follows the last-writer links down to a position never written
+        for (int j = k; j < L; j += blockDim.x) {
+            int v = rr[j];
+            if (d2[j] != 0xFFFFFFFFu) {
+                int c = int(d2[j]);
+                while (hit[c] >= 0) c = hit[c];
+                v = c;
+            }
+            sub[j] = keys[v];
+        }
+        __syncthreads();  // d2 is cleared below
+        if (k == 0) meta->rng = s0 + uint64_t(L + 1) * 0x9E3779B97F4A7C15ull;
+    } else if (k == 0) {
+        int32_t* hk = reinterpret_cast<int32_t*>(buf);
+        int32_t* hv = hk + kSffHash;
+        for (int i = 0; i < kSffHash; ++i) hk[i] = -1;
+        uint64_t rng = s0;
         auto value_at = [&](int32_t p) {
             const int h = sff_slot(hk, p);
             return hk[h] == p ? hv[h] : p;
@@ -325,7 +405,7 @@ __global__ void __launch_bounds__(kSffThreads) k_sff(const JobDev* __restrict__ 
         s_pick = int(uniform_below(rng, uint64_t(L)));
         meta->rng = rng;
     }
-    for (int s2 = k; s2 < L; s2 += blockDim.x) d2[s2] = 0xFFFFFFFFu;
+    for (int q = k; q < L; q += blockDim.x) d2[q] = 0xFFFFFFFFu;
     __syncthreads();
     double* __restrict__ centers = gp(J.centers);
     for (int j = 0; j < K; ++j) {

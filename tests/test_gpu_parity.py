@@ -131,6 +131,21 @@ def test_var_weighted_duplicates_and_sff_small_sets(cqm, dev, ws_small):
             assert np.array_equal(got.cpu().numpy(), ref), (K, seed)
 
 
+def test_sff_sequential_draws_match(cqm, dev, ws_small, monkeypatch):
+    """The one-at-a-time draws SFF falls back to when a draw is rejected give
+    the same centres as the parallel draws (forced by CQ_SFF_SEQUENTIAL)."""
+    _say("init SFF sequential draws")
+    img = synth.smooth_field_blobs(200, 300, 4)
+    rk, rc, dk, dc = _hist_pair(img, cqm, dev, ws_small)
+    for K in (16, 256):
+        ref, _ = oracle.init(rk, rc, K, oracle.INIT_SFF, K)
+        monkeypatch.setenv("CQ_SFF_SEQUENTIAL", "1")
+        seq, _ = cqm.cq_init(dk, dc, K, oracle.INIT_SFF, K, ws_small)
+        monkeypatch.delenv("CQ_SFF_SEQUENTIAL")
+        par, _ = cqm.cq_init(dk, dc, K, oracle.INIT_SFF, K, ws_small)
+        assert np.array_equal(seq.cpu().numpy(), ref) and np.array_equal(par.cpu().numpy(), ref), K
+
+
 def test_init_fewer_colours_than_k(cqm, dev, ws_small):
     _say("init N' <= K")
     img = np.array([[[1, 2, 3], [1, 2, 3], [9, 9, 9]]], np.uint8)
