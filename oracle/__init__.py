@@ -64,13 +64,13 @@ def lib():
         L.cqref_splitmix64_next.restype = u64
         L.cqref_uniform_below.argtypes = [ctypes.POINTER(u64), u64]
         L.cqref_uniform_below.restype = u64
-        L.cqref_histogram.argtypes = [P, i32, i32, i64, P, P, i64, ctypes.POINTER(i64)]
+        L.cqref_histogram.argtypes = [P, i32, i32, i64, i32, P, P, i64, ctypes.POINTER(i64)]
         L.cqref_init.argtypes = [P, P, i64, i32, i32, u64, P, ctypes.POINTER(i32)]
         L.cqref_sff_subset.argtypes = [i32, i64]
         L.cqref_sff_subset.restype = i64
         L.cqref_kmeans.argtypes = [P, P, i64, i32, P, i32, f64, i32, P, P, P, ctypes.POINTER(Stats)]
         L.cqref_map.argtypes = [P, i32, i32, i64, P, i32, P, P, ctypes.POINTER(u64)]
-        L.cqref_quantize.argtypes = [P, i32, i32, i64, i32, i32, u64, i32, f64, i32, P, P, P,
+        L.cqref_quantize.argtypes = [P, i32, i32, i64, i32, i32, i32, u64, i32, f64, i32, P, P, P,
                                      ctypes.POINTER(Stats)]
         for f in ("cqref_histogram", "cqref_init", "cqref_kmeans", "cqref_map", "cqref_quantize"):
             getattr(L, f).restype = ctypes.c_int
@@ -111,14 +111,15 @@ def _img_args(img: np.ndarray):
     return img, img.shape[0], img.shape[1], img.strides[0]
 
 
-def histogram(img: np.ndarray, capacity: int | None = None):
-    """Unique colours (ascending 0xRRGGBB keys) and their pixel counts."""
+def histogram(img: np.ndarray, capacity: int | None = None, subsample: bool = False):
+    """Unique colours (ascending 0xRRGGBB keys) and their pixel counts
+    (optionally of the 2:1-subsampled image)."""
     img, H, W, stride = _img_args(img)
     cap = H * W if capacity is None else capacity
     keys = np.zeros(max(cap, 1), np.uint32)
     counts = np.zeros(max(cap, 1), np.uint32)
     n = ctypes.c_int64(0)
-    rc = lib().cqref_histogram(_ptr(img), H, W, stride, _ptr(keys), _ptr(counts), cap,
+    rc = lib().cqref_histogram(_ptr(img), H, W, stride, int(bool(subsample)), _ptr(keys), _ptr(counts), cap,
                                ctypes.byref(n))
     if rc == ECAPACITY:
         raise OracleError("cqref_histogram", rc)
@@ -175,13 +176,13 @@ def map_image(img: np.ndarray, palette: np.ndarray):
 
 
 def quantize(img: np.ndarray, K: int, scheme: int, seed: int, max_iters: int, tol: float,
-             prune: bool = True, want_images: bool = True):
+             prune: bool = True, want_images: bool = True, subsample: bool = False):
     img, H, W, stride = _img_args(img)
     palette = np.zeros((K, 3), np.uint8)
     idx = np.zeros((H, W), np.uint8) if want_images else None
     rgb = np.zeros((H, W, 3), np.uint8) if want_images else None
     st = Stats()
-    _check("cqref_quantize", lib().cqref_quantize(_ptr(img), H, W, stride, K, scheme, seed,
+    _check("cqref_quantize", lib().cqref_quantize(_ptr(img), H, W, stride, int(bool(subsample)), K, scheme, seed,
                                                   max_iters, tol, int(bool(prune)), _ptr(palette),
                                                   _ptr(idx), _ptr(rgb), ctypes.byref(st)))
     return palette, idx, rgb, st.as_dict()

@@ -90,19 +90,22 @@ static double dist_f64(double x0, double x1, double x2, const double* c)
 /* the set of distinct colours with their frequencies, which a dense count    */
 /* over all 2^24 colours yields directly, in ascending key order.            */
 /* ------------------------------------------------------------------------- */
-int cqref_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride,
+int cqref_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, int32_t subsample,
                     uint32_t* keys, uint32_t* counts, int64_t capacity, int64_t* n_unique)
 {
     if (!img || H <= 0 || W <= 0 || row_stride < 3 * (int64_t)W || !n_unique || capacity < 0)
         return CQREF_EINVAL;
+    /* Section 2.2 item 1, first method: 2:1 subsampling in both directions
+       keeps the pixels at even row and even column */
+    const int32_t step = subsample ? 2 : 1;
     if (capacity > 0 && (!keys || !counts))
         return CQREF_EINVAL;
     uint32_t* cnt = (uint32_t*)calloc(NKEYS, sizeof(uint32_t));
     if (!cnt)
         return CQREF_ENOMEM;
-    for (int32_t y = 0; y < H; ++y) {
+    for (int32_t y = 0; y < H; y += step) {
         const uint8_t* row = img + (int64_t)y * row_stride;
-        for (int32_t x = 0; x < W; ++x) {
+        for (int32_t x = 0; x < W; x += step) {
             const uint8_t* p = row + 3 * (int64_t)x;
             uint32_t key = ((uint32_t)p[0] << 16) | ((uint32_t)p[1] << 8) | (uint32_t)p[2];
             cnt[key] += 1u;
@@ -643,8 +646,8 @@ int cqref_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride,
     return CQREF_OK;
 }
 
-int cqref_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, int32_t K,
-                   int32_t scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
+int cqref_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, int32_t subsample,
+                   int32_t K, int32_t scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
                    uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, cqref_stats* stats)
 {
     if (!img || !palette || H <= 0 || W <= 0 || K < 1 || K > 256 || scheme == CQREF_INIT_USER)
@@ -657,7 +660,7 @@ int cqref_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride,
     int rc = CQREF_ENOMEM;
     if (!keys || !counts || !assign)
         goto out;
-    rc = cqref_histogram(img, H, W, row_stride, keys, counts, cap, &n);
+    rc = cqref_histogram(img, H, W, row_stride, subsample, keys, counts, cap, &n);
     if (rc)
         goto out;
     rc = cqref_init(keys, counts, n, K, scheme, seed, centers, NULL);

@@ -45,8 +45,10 @@ uint64_t cqref_splitmix64_next(uint64_t* s);
 uint64_t cqref_uniform_below(uint64_t* s, uint64_t T);
 
 /* Data reduction of Section 2.2 item 1 (unique colours) and item 2 (weights):
- * key = R<<16 | G<<8 | B, emitted in ascending key order with pixel counts. */
-int cqref_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride,
+ * key = R<<16 | G<<8 | B, emitted in ascending key order with pixel counts.
+ * subsample != 0 first applies the 2:1 subsampling of item 1 (the pixels at
+ * even row and even column). */
+int cqref_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, int32_t subsample,
                     uint32_t* keys, uint32_t* counts, int64_t capacity, int64_t* n_unique);
 
 /* Initialization schemes of Section 2.3 (FGY, MMX, KPP, VAR, SFF) on the
@@ -67,8 +69,8 @@ int cqref_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride,
               uint64_t* sq_err_sum);
 
 /* Whole quantizer: histogram -> init -> k-means -> map. */
-int cqref_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, int32_t K,
-                   int32_t scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
+int cqref_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, int32_t subsample,
+                   int32_t K, int32_t scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
                    uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, cqref_stats* stats);
 
 #ifdef __cplusplus

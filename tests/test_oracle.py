@@ -519,3 +519,31 @@ def test_sff_ties_go_to_the_lowest_subset_position(seed):
     for K in (4, 6):  # subsets of 12 and 22 of the 27 colours
         got, _ = oracle.init(keys, counts, K, oracle.INIT_SFF, seed)
         assert np.array_equal(got, _sff_brute(keys, K, seed)), K
+
+
+# ---------------------------------------------------------------- 2:1 subsampling
+@pytest.mark.parametrize("shape", [(7, 9), (8, 10), (1, 5), (33, 2)])
+def test_subsampled_histogram_is_the_even_pixels(shape):
+    rng = np.random.default_rng(sum(shape))
+    img = rng.integers(0, 4, (shape[0], shape[1] + 3, 3)).astype(np.uint8) * 60  # padded rows
+    view = img[:, : shape[1]]
+    keys, counts = oracle.histogram(view, subsample=True)
+    sub = view[::2, ::2].reshape(-1, 3).astype(np.int64)
+    uk, uc = np.unique((sub[:, 0] << 16) | (sub[:, 1] << 8) | sub[:, 2], return_counts=True)
+    assert np.array_equal(keys, uk) and np.array_equal(counts, uc)
+
+
+def test_subsampled_quantize_clusters_the_even_pixels_and_maps_all():
+    img = synth.blobs_on_gradient(41, 37, 2)
+    pal, idx, rgb, st = oracle.quantize(img, 16, oracle.INIT_KMEANSPP, 5, 50, 1e-4, subsample=True)
+    # the same clustering from the even pixels taken by slicing
+    k2, c2 = oracle.histogram(np.ascontiguousarray(img[::2, ::2]))
+    cen, _ = oracle.init(k2, c2, 16, oracle.INIT_KMEANSPP, 5)
+    km = oracle.kmeans(k2, c2, cen, 50, 1e-4, True)
+    assert np.array_equal(pal, km.palette)
+    assert st["n_unique"] == len(k2) and st["iters"] == km.stats["iters"]
+    # every pixel of the full image is mapped to its nearest palette entry
+    X = img.reshape(-1, 3).astype(np.int64)
+    D = ((X[:, None, :] - pal.astype(np.int64)[None, :, :]) ** 2).sum(-1)
+    assert np.array_equal(idx.reshape(-1), np.argmin(D, axis=1))
+    assert st["mse_img"] == pytest.approx(D.min(axis=1).mean(), rel=1e-12)
