@@ -66,8 +66,14 @@ def measure_large(cq, synth, torch, dev, reps=5):
             raise RuntimeError(f"no launches of {names} were timed")
         return total
 
-    hist_ms = timed(["k_hist_buckets", "k_hist_colscan", "k_hist_scatter", "k_hist_count", "k_hist_emit"],
-                    lambda: cq.cq_histogram(img, ws))
+    hist_names = ["k_hist_buckets", "k_hist_colscan", "k_hist_scatter", "k_hist_count", "k_hist_emit"]
+    hist_ms = timed(hist_names, lambda: cq.cq_histogram(img, ws))
+    full_kernels = dict(per_kernel)
+    keys_s, _ = cq.cq_histogram(img, ws, subsample=True)
+    n_sub = int(keys_s.numel())
+    sub_ms = timed(hist_names, lambda: cq.cq_histogram(img, ws, subsample=True))
+    sub_kernels = {k: per_kernel[k] for k in hist_names}
+    per_kernel.update(full_kernels)
     centers, _ = cq.cq_init(keys, counts, K, cq.INIT_KMEANSPP, 42, ws)
     km = cq.cq_kmeans(keys, counts, centers, 3, TOL, True, ws)  # a palette to map to
     cq.cq_map(img, keys, counts, km.palette, ws)
@@ -86,6 +92,13 @@ def measure_large(cq, synth, torch, dev, reps=5):
                       "frac_of_hbm_peak": map_gbs / PEAK_HBM_GBS},
         "colour_table_us": 1e3 * lut_ms,
         "kernel_us": per_kernel,
+        # 2:1 subsampling: a quarter of the pixels are counted; the even rows
+        # are still read whole, so the bytes are those rows plus the output
+        "histogram_subsampled": {"us": 1e3 * sub_ms, "unique_colours": n_sub,
+                                 "bytes_even_rows": 3 * ((H4 + 1) // 2) * W4 + 8 * n_sub,
+                                 "GB/s_even_rows": (3 * ((H4 + 1) // 2) * W4 + 8 * n_sub) / (sub_ms * 1e-3) / 1e9,
+                                 "speedup_vs_full": hist_ms / sub_ms,
+                                 "kernel_us": sub_kernels},
     }
 
 
@@ -186,6 +199,32 @@ def measure_init_schemes(cq, torch, imgs, dev, reps=3):
     return out
 
 
+def measure_subsample(cq, torch, imgs, dev, reps=3):
+    """The headline batch with the 2:1 subsampling of Section 2.2 (item 1)
+    before the histogram, against the same batch without it: step time, mean
+    unique colours and iterations, and mean MSE of the mapped (full) images."""
+    import numpy as np
+
+    out = {}
+    for label, sub in (("full", False), ("subsampled", True)):
+        jobs = [cq.BatchJob(img, K, cq.INIT_KMEANSPP, SEEDS[i], MAX_ITERS, TOL, True, subsample=sub)
+                for i, img in enumerate(imgs)]
+        bws = cq.BatchWorkspace(jobs, dev)
+        cq.cq_quantize_batch(jobs, bws)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = cq.cq_quantize_batch(jobs, bws)
+        torch.cuda.synchronize()
+        out[label] = {"step_ms": 1e3 * (time.perf_counter() - t0) / reps,
+                      "mean_unique_colours": float(np.mean([x["n_unique"] for x in st])),
+                      "mean_iters": float(np.mean([x["iters"] for x in st])),
+                      "mean_mse": float(np.mean([x["mse_img"] for x in st]))}
+    out["speedup"] = out["full"]["step_ms"] / out["subsampled"]["step_ms"]
+    out["mse_ratio"] = out["subsampled"]["mean_mse"] / out["full"]["mean_mse"]
+    return out
+
+
 def recorded_traffic():
     """HBM bytes per launch of the sort-means pass from the committed counter
     summary, if it was measured on the kernel source as it is now; else None."""
@@ -212,6 +251,7 @@ def parse():
     ap.add_argument("--no-large", action="store_true", help="skip the 4096x4096 histogram/map bandwidth figures")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching latency figures")
     ap.add_argument("--no-init-schemes", action="store_true", help="skip the per-initialization figures")
+    ap.add_argument("--no-subsample", action="store_true", help="skip the 2:1 subsampling figures")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="finish with plain device-to-device copies of this many MiB (a known-size kernel "
                          "for scaling memory counters)")
@@ -341,6 +381,8 @@ def main():
         line["serving"] = measure_serving(cq, torch, synth, imgs, dev)
     if not args.no_init_schemes:
         line["init_schemes_8x512"] = measure_init_schemes(cq, torch, imgs, dev)
+    if not args.no_subsample:
+        line["subsample_8x512"] = measure_subsample(cq, torch, imgs, dev)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -82,14 +82,16 @@ size_t cq_workspace_bytes(int32_t H, int32_t W, int32_t K);
 cq_status cq_workspace_prepare(void* ws, size_t ws_bytes, void* stream);
 
 /* Section 2.2 items 1-2: the unique colours of the image with their pixel
- * counts.  Writes keys[0..N') in ascending order and counts[0..N') (the
- * weights before normalization by H W).  *n_unique (host) receives N'; if
- * N' > capacity only the first `capacity` entries are written and
- * CQ_ECAPACITY is returned.  The workspace must hold cq_workspace_bytes(H, W,
- * K) for this image (it stages the pixels partitioned by key range).
- * Synchronizes `stream`. */
+ * counts.  subsample != 0 first applies the optional 2:1 subsampling of item
+ * 1: only the pixels at even row and even column (ceil(H/2) x ceil(W/2) of
+ * them) are counted.  Writes keys[0..N') in ascending order and
+ * counts[0..N') (the weights before normalization by the number of pixels
+ * counted).  *n_unique (host) receives N'; if N' > capacity only the first
+ * `capacity` entries are written and CQ_ECAPACITY is returned.  The workspace
+ * must hold cq_workspace_bytes(H, W, K) for this image (it stages the pixels
+ * partitioned by key range).  Synchronizes `stream`. */
 cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
-                       uint32_t* keys, uint32_t* counts, int64_t capacity,
+                       int32_t subsample, uint32_t* keys, uint32_t* counts, int64_t capacity,
                        int64_t* n_unique /* host */, void* ws, size_t ws_bytes, void* stream);
 
 /* Section 2.3: initial centres from the N' unique colours.  centers is a
@@ -150,13 +152,15 @@ cq_status cq_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_by
                  const uint8_t* palette, int32_t K, uint8_t* out_idx, uint8_t* out_rgb,
                  uint64_t* sq_err_sum /* host */, void* ws, size_t ws_bytes, void* stream);
 
-/* The whole quantizer: histogram -> init (FGY, MMX or KPP) -> weighted
+/* The whole quantizer: histogram (of the 2:1-subsampled image if subsample
+ * != 0, as in cq_histogram) -> init (any scheme but CQ_INIT_USER) -> weighted
  * sort-means (prune = 1) or plain weighted Lloyd (prune = 0) -> palette ->
- * map.  palette is device uint8[K][3] (entries past k_used are zero); out_idx
- * and out_rgb as in cq_map (nullable).  stats (host, nullable) includes
- * mse_img.  Synchronizes `stream`. */
+ * map of every pixel of the image.  palette is device uint8[K][3] (entries
+ * past k_used are zero); out_idx and out_rgb as in cq_map (nullable).  stats
+ * (host, nullable) includes mse_img, over all H W pixels; mse_float divides
+ * the final SSE by the pixels the histogram counted.  Synchronizes `stream`. */
 cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
-                      int32_t K, cq_init_t scheme, uint64_t seed, int32_t max_iters, double tol,
+                      int32_t subsample, int32_t K, cq_init_t scheme, uint64_t seed, int32_t max_iters, double tol,
                       int32_t prune, uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb,
                       cq_stats* stats /* host */, void* ws, size_t ws_bytes, void* stream);
 
@@ -179,6 +183,7 @@ typedef struct {
     uint8_t* palette;           /* device uint8 [K][3] (entries past k_used are zero)   */
     uint8_t* out_idx;           /* device uint8 [H][W], nullable                         */
     uint8_t* out_rgb;           /* device uint8 [H][W][3], nullable                      */
+    int32_t subsample;          /* 1: histogram of the pixels at even row and column    */
 } cq_job;
 
 /* Workspace bytes for a batch (one slot per job plus descriptors); 0 for an

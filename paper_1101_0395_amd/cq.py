@@ -58,6 +58,7 @@ class CqJob(ctypes.Structure):
         ("palette", ctypes.c_void_p),
         ("out_idx", ctypes.c_void_p),
         ("out_rgb", ctypes.c_void_p),
+        ("subsample", ctypes.c_int32),
     ]
 
 
@@ -92,12 +93,12 @@ def lib() -> ctypes.CDLL:
         L.cq_workspace_bytes.argtypes = [i32, i32, i32]
         L.cq_workspace_bytes.restype = sz
         L.cq_workspace_prepare.argtypes = [P, sz, P]
-        L.cq_histogram.argtypes = [P, i32, i32, i64, P, P, i64, ctypes.POINTER(i64), P, sz, P]
+        L.cq_histogram.argtypes = [P, i32, i32, i64, i32, P, P, i64, ctypes.POINTER(i64), P, sz, P]
         L.cq_init.argtypes = [P, P, i64, i32, ctypes.c_int, u64, P, ctypes.POINTER(i32), P, sz, P]
         L.cq_kmeans.argtypes = [P, P, i64, i32, P, i32, f64, i32, P, P, P, ctypes.POINTER(CqStats),
                                 P, sz, P]
         L.cq_map.argtypes = [P, i32, i32, i64, P, P, i64, P, i32, P, P, ctypes.POINTER(u64), P, sz, P]
-        L.cq_quantize.argtypes = [P, i32, i32, i64, i32, ctypes.c_int, u64, i32, f64, i32, P, P, P,
+        L.cq_quantize.argtypes = [P, i32, i32, i64, i32, i32, ctypes.c_int, u64, i32, f64, i32, P, P, P,
                                   ctypes.POINTER(CqStats), P, sz, P]
         for f in ("cq_workspace_prepare", "cq_histogram", "cq_init", "cq_kmeans", "cq_map",
                   "cq_quantize"):
@@ -203,15 +204,16 @@ class Workspace:
                lib().cq_workspace_prepare(self.ptr, self.nbytes, _stream(self.device)))
 
 
-def cq_histogram(img: torch.Tensor, ws: Workspace, capacity: int | None = None):
-    """Unique colour keys (ascending) and pixel counts, as device uint32 tensors."""
+def cq_histogram(img: torch.Tensor, ws: Workspace, capacity: int | None = None, subsample: bool = False):
+    """Unique colour keys (ascending) and pixel counts, as device uint32
+    tensors; with subsample, of the pixels at even row and column only."""
     H, W, stride = _image_args(img)
     cap = H * W if capacity is None else capacity
     keys = torch.empty(max(cap, 1), dtype=torch.int32, device=img.device)
     counts = torch.empty(max(cap, 1), dtype=torch.int32, device=img.device)
     n = ctypes.c_int64(0)
-    rc = lib().cq_histogram(_ptr(img), H, W, stride, _ptr(keys), _ptr(counts), cap, ctypes.byref(n),
-                            ws.ptr, ws.nbytes, _stream(img.device))
+    rc = lib().cq_histogram(_ptr(img), H, W, stride, int(bool(subsample)), _ptr(keys), _ptr(counts), cap,
+                            ctypes.byref(n), ws.ptr, ws.nbytes, _stream(img.device))
     _check("cq_histogram", rc)
     return keys[: n.value], counts[: n.value]
 
@@ -273,8 +275,9 @@ def cq_map(img: torch.Tensor, keys: torch.Tensor, counts: torch.Tensor | None, p
 def cq_quantize(img: torch.Tensor, K: int, scheme: int, seed: int, max_iters: int, tol: float,
                 prune: bool, ws: Workspace, want_idx: bool = True, want_rgb: bool = True,
                 palette: torch.Tensor | None = None, out_idx: torch.Tensor | None = None,
-                out_rgb: torch.Tensor | None = None):
-    """Whole quantizer on one image; returns (palette, idx, rgb, stats)."""
+                out_rgb: torch.Tensor | None = None, subsample: bool = False):
+    """Whole quantizer on one image (its histogram 2:1-subsampled if
+    subsample); returns (palette, idx, rgb, stats)."""
     H, W, stride = _image_args(img)
     dev = img.device
     if palette is None:
@@ -284,9 +287,9 @@ def cq_quantize(img: torch.Tensor, K: int, scheme: int, seed: int, max_iters: in
     if out_rgb is None and want_rgb:
         out_rgb = torch.empty((H, W, 3), dtype=torch.uint8, device=dev)
     st = CqStats()
-    rc = lib().cq_quantize(_ptr(img), H, W, stride, K, scheme, seed, max_iters, tol, int(bool(prune)),
-                           _ptr(palette), _ptr(out_idx), _ptr(out_rgb), ctypes.byref(st), ws.ptr,
-                           ws.nbytes, _stream(dev))
+    rc = lib().cq_quantize(_ptr(img), H, W, stride, int(bool(subsample)), K, scheme, seed, max_iters, tol,
+                           int(bool(prune)), _ptr(palette), _ptr(out_idx), _ptr(out_rgb), ctypes.byref(st),
+                           ws.ptr, ws.nbytes, _stream(dev))
     _check("cq_quantize", rc)
     return palette, out_idx, out_rgb, st.as_dict()
 
@@ -295,7 +298,7 @@ class BatchJob:
     """One image of a batch with its outputs (device tensors)."""
 
     def __init__(self, img: torch.Tensor, K: int, scheme: int, seed: int, max_iters: int, tol: float,
-                 prune: bool = True, want_idx: bool = True, want_rgb: bool = True):
+                 prune: bool = True, want_idx: bool = True, want_rgb: bool = True, subsample: bool = False):
         H, W, stride = _image_args(img)
         dev = img.device
         self.img = img
@@ -305,7 +308,7 @@ class BatchJob:
         self.c = CqJob(ctypes.c_void_p(img.data_ptr()), H, W, stride, K, scheme, seed, max_iters, tol,
                        int(bool(prune)), ctypes.c_void_p(self.palette.data_ptr()),
                        ctypes.c_void_p(self.idx.data_ptr()) if want_idx else None,
-                       ctypes.c_void_p(self.rgb.data_ptr()) if want_rgb else None)
+                       ctypes.c_void_p(self.rgb.data_ptr()) if want_rgb else None, int(bool(subsample)))
 
 
 class BatchWorkspace:

@@ -96,6 +96,12 @@ static cq_status check_image(const uint8_t* img, int32_t H, int32_t W, int64_t r
     return CQ_OK;
 }
 
+static cq_status check_subsample(int32_t subsample)
+{
+    if (subsample != 0 && subsample != 1) return einval("subsample = %d is not 0 or 1", subsample);
+    return CQ_OK;
+}
+
 cq_status check_ws(const void* ws, size_t ws_bytes, size_t need)
 {
     if (!ws) {
@@ -149,13 +155,22 @@ static void bind_slot(JobDev& J, char* slot, const Layout& L)
     J.grp = to_dev(reinterpret_cast<uint64_t*>(slot + L.work));
 }
 
-static void set_image(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride)
+// The image, and the view of it that the histogram counts: all of it, or with
+// subsampling its pixels at even row and column (ceil(H/2) x ceil(W/2) pixels,
+// twice the row and pixel steps).
+static void set_image(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride, bool subsample)
 {
     J.img = to_dev(img);
     J.H = H;
     J.W = W;
     J.stride = stride;
     J.packed = (stride == 3 * int64_t(W) && (reinterpret_cast<uintptr_t>(img) & 3u) == 0) ? 1 : 0;
+    J.hH = subsample ? (H + 1) / 2 : H;
+    J.hW = subsample ? (W + 1) / 2 : W;
+    J.hstride = subsample ? 2 * stride : stride;
+    J.hpitch = subsample ? 6 : 3;
+    J.hpacked = subsample ? 0 : J.packed;
+    J.map_direct = subsample ? 1 : 0;
 }
 
 // Copies the job descriptors and block maps to the device.  Each upload reads
@@ -264,8 +279,8 @@ struct EventPair {
 // ---------------------------------------------------------------- phases
 cq_status run_histogram(Batch& b)
 {
-    const int total = b.set_map(kMapHist, [&](int j) { return hist_blocks(int64_t(b.h[j].H) * b.h[j].W); });
-    const int count = b.set_map(kMapHistCount, [&](int j) { return hist_count_blocks(int64_t(b.h[j].H) * b.h[j].W); });
+    const int total = b.set_map(kMapHist, [&](int j) { return hist_blocks(hist_pixels(b.h[j])); });
+    const int count = b.set_map(kMapHistCount, [&](int j) { return hist_count_blocks(hist_pixels(b.h[j])); });
     CQ_TRY(upload(b));
     return launch_histogram(b.d_jobs(), b.d_maps(), b.B, total, count, b.s);
 }
@@ -408,18 +423,22 @@ cq_status run_kmeans(Batch& b)
 
 cq_status run_map(Batch& b, bool with_err)
 {
+    // a job whose table covers every colour of its image maps through it and
+    // sums the squared error over the colours; one that searches the palette
+    // per pixel sums it over the pixels in the map kernel
     const int lut_total = b.set_map(kMapLut, [&](int j) {
         const JobDev& J = b.h[j];
-        return int((J.n + J.chunk - 1) / J.chunk);
+        return J.map_direct ? 0 : int((J.n + J.chunk - 1) / J.chunk);
     });
     const int pix_total = b.set_map(kMapPix, [&](int j) {
         const JobDev& J = b.h[j];
-        return (J.out_idx || J.out_rgb) ? map_blocks(int64_t(J.H) * J.W) : 0;
+        const bool pass = J.out_idx || J.out_rgb || (with_err && J.map_direct);
+        return pass ? map_blocks(int64_t(J.H) * J.W) : 0;
     });
     CQ_TRY(upload(b));
     if (with_err) CQ_TIMED_LAUNCH("k_zero_sq_err", b.s, k_zero_sq_err<<<(b.B + 63) / 64, 64, 0, b.s>>>(b.d_jobs(), b.B));
     if (lut_total > 0) CQ_TRY(launch_lut(b.d_jobs(), b.d_maps(), b.B, lut_total, with_err ? 1 : 0, b.s));
-    if (pix_total > 0) CQ_TRY(launch_map(b.d_jobs(), b.d_maps(), b.B, pix_total, b.s));
+    if (pix_total > 0) CQ_TRY(launch_map(b.d_jobs(), b.d_maps(), b.B, pix_total, with_err ? 1 : 0, b.s));
     return CQ_OK;
 }
 
@@ -479,13 +498,13 @@ static cq_status run_quantize(Batch& b, cq_stats* stats)
     return CQ_OK;
 }
 
-void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride, int32_t K,
-                              int scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
-                              uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, char* slot)
+void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride, int32_t subsample,
+                       int32_t K, int scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
+                       uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, char* slot)
 {
     const int64_t npix = int64_t(H) * W;
     const Layout L = make_layout(npix, npix, true);
-    set_image(J, img, H, W, stride);
+    set_image(J, img, H, W, stride, subsample != 0);
     bind_slot(J, slot, L);
     J.keys = to_dev(reinterpret_cast<uint32_t*>(slot + L.keys));
     J.counts = to_dev(reinterpret_cast<uint32_t*>(slot + L.counts));
@@ -510,6 +529,7 @@ size_t slot_bytes(const cq_job& j) { return align256(make_layout(int64_t(j.H) * 
 cq_status check_job(const cq_job& j, int idx)
 {
     cq_status s = check_image(j.img, j.H, j.W, j.row_stride_bytes);
+    if (s == CQ_OK) s = check_subsample(j.subsample);
     if (s == CQ_OK) s = check_k(j.K);
     if (s == CQ_OK && !j.palette) s = einval("palette is null");
     if (s == CQ_OK && (int(j.scheme) < CQ_INIT_FORGY || int(j.scheme) > CQ_INIT_SFF || j.scheme == CQ_INIT_USER))
@@ -547,11 +567,12 @@ cq_status cq_workspace_prepare(void* ws, size_t ws_bytes, void* stream)
 }
 
 cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
-                       uint32_t* keys, uint32_t* counts, int64_t capacity, int64_t* n_unique,
+                       int32_t subsample, uint32_t* keys, uint32_t* counts, int64_t capacity, int64_t* n_unique,
                        void* ws, size_t ws_bytes, void* stream)
 {
     clear_error();
     CQ_TRY(check_image(img, H, W, row_stride_bytes));
+    CQ_TRY(check_subsample(subsample));
     if (!n_unique) return einval("n_unique is null");
     if (capacity < 0) return einval("capacity is negative");
     if (capacity > 0 && (!keys || !counts)) return einval("keys/counts are null");
@@ -559,7 +580,7 @@ cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_str
     CQ_TRY(check_ws(ws, ws_bytes, L.total));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
     JobDev& J = b.h[0];
-    set_image(J, img, H, W, row_stride_bytes);
+    set_image(J, img, H, W, row_stride_bytes, subsample != 0);
     bind_slot(J, static_cast<char*>(ws), L);
     J.keys = to_dev(keys);
     J.counts = to_dev(counts);
@@ -658,7 +679,7 @@ cq_status cq_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_by
     CQ_TRY(check_ws(ws, ws_bytes, L.fixed_end));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
     JobDev& J = b.h[0];
-    set_image(J, img, H, W, row_stride_bytes);
+    set_image(J, img, H, W, row_stride_bytes, false);
     bind_slot(J, static_cast<char*>(ws), L);
     J.keys = to_dev(const_cast<uint32_t*>(keys));
     J.counts = to_dev(const_cast<uint32_t*>(counts));
@@ -678,13 +699,14 @@ cq_status cq_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_by
     return CQ_OK;
 }
 
-cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes, int32_t K,
-                      cq_init_t scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
+cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes, int32_t subsample,
+                      int32_t K, cq_init_t scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
                       uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, cq_stats* stats, void* ws,
                       size_t ws_bytes, void* stream)
 {
     clear_error();
     CQ_TRY(check_image(img, H, W, row_stride_bytes));
+    CQ_TRY(check_subsample(subsample));
     CQ_TRY(check_k(K));
     if (!palette) return einval("palette is null");
     if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_SFF || scheme == CQ_INIT_USER)
@@ -694,8 +716,8 @@ cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stri
     const Layout L = make_layout(npix, npix, true);
     CQ_TRY(check_ws(ws, ws_bytes, L.total));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
-    fill_quantize_job(b.h[0], img, H, W, row_stride_bytes, K, int(scheme), seed, max_iters, tol, prune, palette,
-                      out_idx, out_rgb, static_cast<char*>(ws));
+    fill_quantize_job(b.h[0], img, H, W, row_stride_bytes, subsample, K, int(scheme), seed, max_iters, tol, prune,
+                      palette, out_idx, out_rgb, static_cast<char*>(ws));
     return run_quantize(b, stats);
 }
 
@@ -733,7 +755,7 @@ cq_status cq_quantize_batch(const cq_job* jobs, int32_t n_jobs, cq_stats* stats,
     char* slot = static_cast<char*>(ws) + align256(desc_bytes(n_jobs));
     for (int32_t i = 0; i < n_jobs; ++i) {
         const cq_job& j = jobs[i];
-        fill_quantize_job(b.h[i], j.img, j.H, j.W, j.row_stride_bytes, j.K, int(j.scheme), j.seed, j.max_iters,
+        fill_quantize_job(b.h[i], j.img, j.H, j.W, j.row_stride_bytes, j.subsample, j.K, int(j.scheme), j.seed, j.max_iters,
                           j.tol, j.prune, j.palette, j.out_idx, j.out_rgb, slot);
         slot += slot_bytes(j);
     }

@@ -75,7 +75,7 @@ int64_t regroup_blocks(int64_t n);
 cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int blocks, hipStream_t s);
 int map_blocks(int64_t npix);
 cq_status launch_lut(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s);
-cq_status launch_map(const JobDev* jobs, const int* maps, int B, int total, hipStream_t s);
+cq_status launch_map(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s);
 
 // argument checks (set the thread's error text)
 cq_status einval(const char* fmt, ...);
@@ -101,8 +101,8 @@ void fill_stats(const JobDev& J, const JobResult& r, cq_stats& st, bool with_img
 
 // one whole-quantizer job in a slot of slot_bytes(j) bytes
 size_t slot_bytes(const cq_job& j);
-void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride, int32_t K,
-                       int scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
+void fill_quantize_job(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64_t stride, int32_t subsample,
+                       int32_t K, int scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
                        uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, char* slot);
 
 #define CQ_TRY(expr)                     \

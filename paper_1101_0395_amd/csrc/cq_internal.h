@@ -146,7 +146,19 @@ struct JobDev {
     int32_t map_k;       // palette entries the pixel map searches
     int32_t regroup_period;  // pruned runs: regroup the colours at iterations 1-4 and every this many
     int32_t pad_;
+    // the pixels the histogram counts: the whole image, or after 2:1
+    // subsampling its pixels at even row and column
+    int64_t hstride;     // bytes between rows of the view
+    int32_t hH, hW;      // rows and columns of the view
+    int32_t hpitch;      // bytes between pixels of a view row (3 or 6)
+    int32_t hpacked;     // the view is the whole image, its rows contiguous and 4-byte aligned
+    int32_t map_direct;  // the map searches the palette per pixel: the colour table only
+                         // covers the colours the histogram counted
+    int32_t pad2_;
 };
+
+// Pixels the histogram of a job counts.
+__host__ __device__ __forceinline__ int64_t hist_pixels(const JobDev& J) { return int64_t(J.hH) * J.hW; }
 
 // Pruned runs regroup their colour records (a counting sort by cluster and
 // distance bucket) in the update step of iterations 1-4 and of every

@@ -57,7 +57,7 @@ static std::vector<int> engine_admit(cq_engine* e)
         if (!e->pool.alloc(q.bytes, &off)) break;
         q.off = off;
         const cq_job& j = q.spec;
-        fill_quantize_job(q.dev, j.img, j.H, j.W, j.row_stride_bytes, j.K, int(j.scheme), j.seed, j.max_iters,
+        fill_quantize_job(q.dev, j.img, j.H, j.W, j.row_stride_bytes, j.subsample, j.K, int(j.scheme), j.seed, j.max_iters,
                           j.tol, j.prune, j.palette, j.out_idx, j.out_rgb, e->pool_base + off);
         q.dev.regroup_period = e->period;
         q.it = 0;

@@ -24,16 +24,16 @@ namespace cq {
 
 constexpr int kHistThreads = 512;
 
-// Key of the pixel p (row-major index) of a job image.
+// Key of the pixel p (row-major index) of a job's histogram view.
 __device__ __forceinline__ uint32_t load_key(const uint8_t* __restrict__ img, int64_t p, int32_t W,
-                                             int64_t row_stride, bool packed)
+                                             int64_t row_stride, int32_t pitch, bool packed)
 {
     const uint8_t* q;
     if (packed) {
         q = img + 3 * p;
     } else {
         const int64_t y = p / W, x = p - y * W;
-        q = img + y * row_stride + 3 * x;
+        q = img + y * row_stride + pitch * x;
     }
     return (uint32_t(q[0]) << 16) | (uint32_t(q[1]) << 8) | uint32_t(q[2]);
 }
@@ -48,16 +48,16 @@ __device__ __forceinline__ void unpack4(uint32_t a, uint32_t b, uint32_t c, uint
     k[3] = (((c >> 8) & 0xffu) << 16) | (((c >> 16) & 0xffu) << 8) | (c >> 24);
 }
 
-// Calls f(key, valid) for the pixels of tile `lb`, four pixels per thread per
-// step from three dword loads when the image is packed.
+// Calls f(key, valid) for the pixels of tile `lb` of the histogram view, four
+// pixels per thread per step from three dword loads when the view is packed.
 template <typename F>
 __device__ __forceinline__ void for_tile_pixels(const JobDev& J, int64_t lb, F f)
 {
     const uint8_t* __restrict__ img = gp(J.img);
-    const int64_t npix = int64_t(J.H) * J.W;
+    const int64_t npix = hist_pixels(J);
     const int64_t p0 = lb * kHistTile;
     const int64_t p1 = p0 + kHistTile < npix ? p0 + kHistTile : npix;
-    if (J.packed) {
+    if (J.hpacked) {
         const uint32_t* __restrict__ w = reinterpret_cast<const uint32_t*>(img);
         const int64_t g0 = p0 >> 2, g1 = p1 >> 2;  // whole groups of four pixels
         constexpr int kSteps = kHistTile / 4 / kHistThreads;
@@ -81,12 +81,12 @@ __device__ __forceinline__ void for_tile_pixels(const JobDev& J, int64_t lb, F f
         // the last tile of an image whose pixel count is not a multiple of 4
         const int64_t tail = g1 * 4 + threadIdx.x;
         const bool tin = tail < p1;
-        f(tin ? load_key(img, tail, J.W, J.stride, true) : 0u, tin);
+        f(tin ? load_key(img, tail, J.hW, J.hstride, 3, true) : 0u, tin);
     } else {
         for (int64_t p = p0; p < p1; p += kHistThreads) {
             const int64_t q = p + threadIdx.x;
             const bool in = q < p1;
-            f(in ? load_key(img, q, J.W, J.stride, false) : 0u, in);
+            f(in ? load_key(img, q, J.hW, J.hstride, J.hpitch, false) : 0u, in);
         }
     }
 }
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_buckets(const JobDev* __r
         if (in) atomicAdd(&cnt[key >> kHistLowBits], 1u);
     });
     __syncthreads();
-    const int64_t ntiles = hist_tiles(int64_t(J.H) * J.W);
+    const int64_t ntiles = hist_tiles(hist_pixels(J));
     uint32_t* __restrict__ mat = gp(J.hmat);
     for (int t = threadIdx.x; t < kHistBuckets; t += kHistThreads) mat[t * ntiles + lb] = cnt[t];
 }
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_hist_colscan(const JobDev* __restrict__
     __shared__ uint32_t tmp[64];
     const JobDev& J = jobs[blockIdx.x / kHistBuckets];
     const int b = blockIdx.x % kHistBuckets;
-    const int64_t ntiles = hist_tiles(int64_t(J.H) * J.W);
+    const int64_t ntiles = hist_tiles(hist_pixels(J));
     uint32_t* __restrict__ row = gp(J.hmat) + b * ntiles;
     uint32_t carry = 0;
     for (int64_t t0 = 0; t0 < ntiles; t0 += blockDim.x) {
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_scatter(const JobDev* __r
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
-    const int64_t ntiles = hist_tiles(int64_t(J.H) * J.W);
+    const int64_t ntiles = hist_tiles(hist_pixels(J));
     const uint32_t* __restrict__ mat = gp(J.hmat);
     const uint32_t* __restrict__ bs = gp(J.hbs);
     for (int b = threadIdx.x; b < kHistBuckets; b += kHistThreads)

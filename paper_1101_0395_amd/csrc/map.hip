@@ -7,6 +7,10 @@
 // looks its key up and writes the index and/or the palette colour.  The squared
 // error of every pixel is n_i |x_i - P_lut|^2 summed over the unique colours,
 // an exact uint64.
+//
+// With 2:1 subsampling the unique colours are those of a quarter of the
+// pixels, so the table does not cover the others: such a job searches the
+// palette for every pixel instead and sums the squared error over the pixels.
 #include "cq_internal.h"
 
 namespace cq {
@@ -72,10 +76,69 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ 
 // with all 256 entries (zero past K), so any table byte indexes in bounds.
 constexpr int kMapGroupsPerThread = kMapGroupsPerBlock / kMapThreads;
 
+// Per-pixel search of a job with map_direct: block b takes the pixels
+// [4 b G, 4 (b + 1) G) (G = kMapGroupsPerBlock), one per thread per step.
+// Since |x - p|^2 = |x|^2 + (|p|^2 - 2 x.p), the entry with the least
+// |p|^2 - 2 x.p (exact in 32-bit integers, x.p from one four-byte dot
+// product) is the nearest, lowest index on ties.  `ent` holds (packed entry,
+// |p|^2) pairs, entries past K with |p|^2 too large to be chosen, up to an
+// even count.  Adds the pixels' squared errors to the job's sum if with_err.
+__device__ __forceinline__ void map_direct_pixels(const JobDev& J, int64_t g0, int64_t g1, const uint32_t* pal,
+                                                  const uint2* ent, int with_err)
+{
+    const int K2 = (J.map_k + 1) & ~1;
+    const uint8_t* __restrict__ img = gp(J.img);
+    uint8_t* __restrict__ out_idx = gp(J.out_idx);
+    uint8_t* __restrict__ out_rgb = gp(J.out_rgb);
+    const int64_t npix = int64_t(J.H) * J.W;
+    const int64_t p0 = g0 * 4, p1 = g1 * 4 < npix ? g1 * 4 : npix;
+    const int32_t W = J.W;
+    unsigned long long err = 0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kMapThreads) {
+        const int64_t y = p / W, x = p - y * W;
+        const uint8_t* q = img + y * J.stride + 3 * x;
+        const int r = q[0], g = q[1], b = q[2];
+        const uint32_t xv = uint32_t(r) | (uint32_t(g) << 8) | (uint32_t(b) << 16);
+        int best_s = 0x7fffffff, best = 0;
+#pragma unroll 4
+        for (int k = 0; k < K2; k += 2) {
+            const uint4 e = *reinterpret_cast<const uint4*>(ent + k);  // entries k and k + 1
+            const int s0 = int(e.y) - 2 * int(__builtin_amdgcn_udot4(xv, e.x, 0u, false));
+            const int s1 = int(e.w) - 2 * int(__builtin_amdgcn_udot4(xv, e.z, 0u, false));
+            if (s0 < best_s) {
+                best_s = s0;
+                best = k;
+            }
+            if (s1 < best_s) {
+                best_s = s1;
+                best = k + 1;
+            }
+        }
+        if (with_err) err += uint32_t(r * r + g * g + b * b + best_s);
+        if (out_idx) out_idx[p] = uint8_t(best);
+        if (out_rgb) {
+            out_rgb[3 * p + 0] = uint8_t(pal[best]);
+            out_rgb[3 * p + 1] = uint8_t(pal[best] >> 8);
+            out_rgb[3 * p + 2] = uint8_t(pal[best] >> 16);
+        }
+    }
+    if (!with_err) return;
+    __shared__ unsigned long long red[kMapThreads / 64];
+    err = wave_sum(err);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = err;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kMapThreads / 64; ++w) t += red[w];
+        atomicAdd(reinterpret_cast<unsigned long long*>(&gp(J.meta)->sq_err), t);
+    }
+}
+
 __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ jobs,
-                                                     const int* __restrict__ map, int B)
+                                                     const int* __restrict__ map, int B, int with_err)
 {
     __shared__ uint32_t pal[kMaxK];
+    __shared__ __align__(16) uint2 ent[kMaxK];  // read two entries at a time
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
@@ -84,14 +147,25 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
         const uint8_t* q = gp(J.palette) + 3 * t;
         pal[t] = t < K ? (uint32_t(q[0]) | (uint32_t(q[1]) << 8) | (uint32_t(q[2]) << 16)) : 0u;
     }
+    const int64_t g0 = int64_t(lb) * kMapGroupsPerBlock;
+    const int64_t g1 = g0 + kMapGroupsPerBlock;
+    if (J.map_direct) {  // uniform over the block
+        for (int t = threadIdx.x; t < kMaxK; t += blockDim.x) {
+            const uint8_t* q = gp(J.palette) + 3 * t;
+            const int r = t < K ? q[0] : 0, g = t < K ? q[1] : 0, b = t < K ? q[2] : 0;
+            const uint32_t packed = uint32_t(r) | (uint32_t(g) << 8) | (uint32_t(b) << 16);
+            ent[t] = make_uint2(packed, t < K ? uint32_t(r * r + g * g + b * b) : 0x3fffffffu);
+        }
+        __syncthreads();
+        map_direct_pixels(J, g0, g1, pal, ent, with_err);
+        return;
+    }
     __syncthreads();
     const uint8_t* __restrict__ img = gp(J.img);
     const uint8_t* __restrict__ lut = gp(J.lut);
     uint8_t* __restrict__ out_idx = gp(J.out_idx);
     uint8_t* __restrict__ out_rgb = gp(J.out_rgb);
     const int64_t npix = int64_t(J.H) * J.W;
-    const int64_t g0 = int64_t(lb) * kMapGroupsPerBlock;
-    const int64_t g1 = g0 + kMapGroupsPerBlock;
     if (J.packed) {
         const int64_t ngroups = npix >> 2;
         const uint32_t* w = reinterpret_cast<const uint32_t*>(img);
@@ -176,9 +250,9 @@ cq_status launch_lut(const JobDev* jobs, const int* maps, int B, int total, int 
     return CQ_OK;
 }
 
-cq_status launch_map(const JobDev* jobs, const int* maps, int B, int total, hipStream_t s)
+cq_status launch_map(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s)
 {
-    CQ_TIMED_LAUNCH("k_map", s, k_map<<<total, kMapThreads, 0, s>>>(jobs, maps + kMapPix * (B + 1), B));
+    CQ_TIMED_LAUNCH("k_map", s, k_map<<<total, kMapThreads, 0, s>>>(jobs, maps + kMapPix * (B + 1), B, with_err));
     return CQ_OK;
 }
 

@@ -49,17 +49,20 @@ def test_invalid_arguments_are_rejected_without_a_device():
     fake = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
     n = ctypes.c_int64(0)
     # null image
-    rc, msg = _status(L.cq_histogram, None, 4, 4, 12, fake, fake, 16, ctypes.byref(n), fake, 1 << 30, None)
+    rc, msg = _status(L.cq_histogram, None, 4, 4, 12, 0, fake, fake, 16, ctypes.byref(n), fake, 1 << 30, None)
     assert rc == cq.CQ_EINVAL and "img" in msg
     # stride below 3 W
-    rc, msg = _status(L.cq_histogram, fake, 4, 4, 11, fake, fake, 16, ctypes.byref(n), fake, 1 << 30, None)
+    rc, msg = _status(L.cq_histogram, fake, 4, 4, 11, 0, fake, fake, 16, ctypes.byref(n), fake, 1 << 30, None)
     assert rc == cq.CQ_EINVAL and "stride" in msg
     # workspace too small / misaligned / null
-    rc, msg = _status(L.cq_histogram, fake, 4, 4, 12, fake, fake, 16, ctypes.byref(n), fake, 1024, None)
+    rc, msg = _status(L.cq_histogram, fake, 4, 4, 12, 0, fake, fake, 16, ctypes.byref(n), fake, 1024, None)
     assert rc == cq.CQ_EWORKSPACE
-    rc, msg = _status(L.cq_histogram, fake, 4, 4, 12, fake, fake, 16, ctypes.byref(n),
+    rc, msg = _status(L.cq_histogram, fake, 4, 4, 12, 0, fake, fake, 16, ctypes.byref(n),
                       ctypes.c_void_p(0x10001), 1 << 30, None)
     assert rc == cq.CQ_EWORKSPACE and "aligned" in msg
+    # subsample flag other than 0 or 1
+    rc, msg = _status(L.cq_histogram, fake, 4, 4, 12, 2, fake, fake, 16, ctypes.byref(n), fake, 1 << 30, None)
+    assert rc == cq.CQ_EINVAL and "subsample" in msg
     rc, msg = _status(L.cq_workspace_prepare, None, 1 << 30, None)
     assert rc == cq.CQ_EWORKSPACE
     # K out of range
@@ -90,10 +93,10 @@ def test_invalid_arguments_are_rejected_without_a_device():
                       fake, 1 << 30, None)
     assert rc == cq.CQ_EINVAL and "counts" in msg
     # quantize: user init is not a quantize scheme; oversize image
-    rc, _ = _status(L.cq_quantize, fake, 4, 4, 12, 4, 3, 0, 10, 1e-4, 1, fake, None, None,
+    rc, _ = _status(L.cq_quantize, fake, 4, 4, 12, 0, 4, 3, 0, 10, 1e-4, 1, fake, None, None,
                     ctypes.byref(st), fake, 1 << 30, None)
     assert rc == cq.CQ_EINVAL
-    rc, _ = _status(L.cq_quantize, fake, 1 << 15, 1 << 14, 3 << 14, 4, 2, 0, 10, 1e-4, 1, fake, None,
+    rc, _ = _status(L.cq_quantize, fake, 1 << 15, 1 << 14, 3 << 14, 0, 4, 2, 0, 10, 1e-4, 1, fake, None,
                     None, ctypes.byref(st), fake, 1 << 30, None)
     assert rc == cq.CQ_EINVAL
 
@@ -143,6 +146,9 @@ def test_engine_sizes_and_argument_checks_without_a_device():
         bad = cq.CqJob(fake, 64, 64, 192, 300, cq.INIT_KMEANSPP, 1, 10, 1e-4, 1, fake, None, None)
         rc, msg = _status(L.cq_engine_submit, h, ctypes.byref(bad), ctypes.byref(t))
         assert rc == cq.CQ_EINVAL and "K" in msg
+        bad = cq.CqJob(fake, 64, 64, 192, 16, cq.INIT_KMEANSPP, 1, 10, 1e-4, 1, fake, None, None, -1)
+        rc, msg = _status(L.cq_engine_submit, h, ctypes.byref(bad), ctypes.byref(t))
+        assert rc == cq.CQ_EINVAL and "subsample" in msg
         q, r, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
         assert L.cq_engine_pending(h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(u)) == cq.CQ_OK
         assert (q.value, r.value, u.value) == (3, 0, 0)  # admission happens in a step

@@ -31,3 +31,24 @@ def test_engine_pool_allocator_matches_byte_map_model(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
     assert " 0 mismatches" in out.stdout
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_public_structs_match_binding_layout(tmp_path):
+    import ctypes
+
+    from paper_1101_0395_amd import cq
+
+    exe = tmp_path / "struct_layout"
+    src = os.path.join(ROOT, "tests", "host", "struct_layout.c")
+    subprocess.run(["gcc", "-std=c11", "-O0", "-I", os.path.join(ROOT, "include"), src, "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60, check=True).stdout
+    py = {"cq_job": cq.CqJob, "cq_stats": cq.CqStats, "cq_engine_done": cq.CqEngineDone}
+    seen = 0
+    for line in out.splitlines():
+        name, field, value = line.split()
+        want = ctypes.sizeof(py[name]) if field == "size" else getattr(py[name], field).offset
+        assert int(value) == want, line
+        seen += 1
+    assert seen == 20
