@@ -216,10 +216,22 @@ def measure_subsample(cq, torch, imgs, dev, reps=3):
         for _ in range(reps):
             st = cq.cq_quantize_batch(jobs, bws)
         torch.cuda.synchronize()
-        out[label] = {"step_ms": 1e3 * (time.perf_counter() - t0) / reps,
+        step_ms = 1e3 * (time.perf_counter() - t0) / reps
+        kern_us = {}
+        for name in ("k_hist_buckets", "k_hist_scatter", "k_hist_count", "k_lut", "k_map"):
+            t = cq.KernelTimer(name, reps)
+            t.enable()
+            for _ in range(reps):
+                cq.cq_quantize_batch(jobs, bws)
+            torch.cuda.synchronize()
+            launches, ms = t.read()
+            t.disable()
+            kern_us[name] = 1e3 * ms / launches if launches else 0.0
+        out[label] = {"step_ms": step_ms,
                       "mean_unique_colours": float(np.mean([x["n_unique"] for x in st])),
                       "mean_iters": float(np.mean([x["iters"] for x in st])),
-                      "mean_mse": float(np.mean([x["mse_img"] for x in st]))}
+                      "mean_mse": float(np.mean([x["mse_img"] for x in st])),
+                      "kernel_us_per_launch": kern_us}
     out["speedup"] = out["full"]["step_ms"] / out["subsampled"]["step_ms"]
     out["mse_ratio"] = out["subsampled"]["mean_mse"] / out["full"]["mean_mse"]
     return out

@@ -32,8 +32,8 @@ __device__ __forceinline__ uint32_t load_key(const uint8_t* __restrict__ img, in
     if (packed) {
         q = img + 3 * p;
     } else {
-        const int64_t y = p / W, x = p - y * W;
-        q = img + y * row_stride + pitch * x;
+        const uint32_t y = uint32_t(p) / uint32_t(W), x = uint32_t(p) - y * uint32_t(W);  // p < 2^28
+        q = img + int64_t(y) * row_stride + pitch * x;
     }
     return (uint32_t(q[0]) << 16) | (uint32_t(q[1]) << 8) | uint32_t(q[2]);
 }

@@ -95,8 +95,8 @@ __device__ __forceinline__ void map_direct_pixels(const JobDev& J, int64_t g0, i
     const int32_t W = J.W;
     unsigned long long err = 0;
     for (int64_t p = p0 + threadIdx.x; p < p1; p += kMapThreads) {
-        const int64_t y = p / W, x = p - y * W;
-        const uint8_t* q = img + y * J.stride + 3 * x;
+        const uint32_t y = uint32_t(p) / uint32_t(W), x = uint32_t(p) - y * uint32_t(W);  // p < 2^28
+        const uint8_t* q = img + int64_t(y) * J.stride + 3 * x;
         const int r = q[0], g = q[1], b = q[2];
         const uint32_t xv = uint32_t(r) | (uint32_t(g) << 8) | (uint32_t(b) << 16);
         int best_s = 0x7fffffff, best = 0;
@@ -222,8 +222,8 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
         const int32_t W = J.W;
         const int64_t p0 = g0 * 4, p1 = g1 * 4 < npix ? g1 * 4 : npix;
         for (int64_t p = p0 + threadIdx.x; p < p1; p += kMapThreads) {
-            const int64_t y = p / W, x = p - y * W;
-            const uint8_t* q = img + y * J.stride + 3 * x;
+            const uint32_t y = uint32_t(p) / uint32_t(W), x = uint32_t(p) - y * uint32_t(W);  // p < 2^28
+            const uint8_t* q = img + int64_t(y) * J.stride + 3 * x;
             const uint32_t idx = lut[(uint32_t(q[0]) << 16) | (uint32_t(q[1]) << 8) | uint32_t(q[2])];
             if (out_idx) out_idx[p] = uint8_t(idx);
             if (out_rgb) {
