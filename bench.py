@@ -237,6 +237,50 @@ def measure_subsample(cq, torch, imgs, dev, reps=3):
     return out
 
 
+def measure_km_vs_wsm(cq, torch, imgs, dev, Ks=(32, 64, 128, 256), iters=20):
+    """The comparison of Section 3.2 on the eight stand-ins: plain KM (full
+    search over every pixel) against WSM (sort-means on the weighted
+    histogram), both from the same FGY centres and run for at most 20
+    iterations (tol 0: a run ends early only once its SSE stops falling, and
+    then both end together).  Per K: distance calculations per point and
+    iteration (KM: K; WSM: over the unique colours), and the k-means time of
+    each (one call per image, mean over the images)."""
+    import numpy as np
+
+    ws = cq.Workspace(H, W, max(Ks), dev)
+    data = []
+    for i, img in enumerate(imgs):
+        hk, hc = cq.cq_histogram(img, ws)
+        hk, hc = hk.clone(), hc.clone()
+        pk, pc = cq.cq_pixel_keys(img)
+        data.append((hk, hc, pk, pc))
+    out = {}
+    for K in Ks:
+        km_ms, wsm_ms, km_ndc, wsm_ndc, same = [], [], [], [], True
+        for i, (hk, hc, pk, pc) in enumerate(data):
+            c0, _ = cq.cq_init(hk, hc, K, cq.INIT_FORGY, SEEDS[i], ws)
+            c0 = c0.clone()
+            res = {}
+            for label, keys, counts, prune, acc in (("wsm", hk, hc, True, wsm_ms), ("km", pk, pc, False, km_ms)):
+                cq.cq_kmeans(keys, counts, c0.clone(), iters, 0.0, prune, ws)  # warm-up
+                c = c0.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = cq.cq_kmeans(keys, counts, c, iters, 0.0, prune, ws)
+                acc.append(1e3 * (time.perf_counter() - t0))
+                res[label] = r
+            w, k = res["wsm"], res["km"]
+            same = same and torch.equal(w.centers, k.centers) and w.sse_trace == k.sse_trace
+            wsm_ndc.append(w.stats["ndc_total"] / (w.stats["n_unique"] * max(1, w.stats["iters"])))
+            km_ndc.append(k.stats["ndc_total"] / (k.stats["n_unique"] * max(1, k.stats["iters"])))
+        out[str(K)] = {"ndc_per_point_iter": {"km": float(np.mean(km_ndc)), "wsm": float(np.mean(wsm_ndc)),
+                                              "km_over_wsm": float(np.mean(km_ndc) / np.mean(wsm_ndc))},
+                       "kmeans_ms_per_image": {"km": float(np.mean(km_ms)), "wsm": float(np.mean(wsm_ms)),
+                                               "km_over_wsm": float(np.mean(km_ms) / np.mean(wsm_ms))},
+                       "identical_results": bool(same)}
+    return out
+
+
 def recorded_traffic():
     """HBM bytes per launch of the sort-means pass from the committed counter
     summary, if it was measured on the kernel source as it is now; else None."""
@@ -264,6 +308,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching latency figures")
     ap.add_argument("--no-init-schemes", action="store_true", help="skip the per-initialization figures")
     ap.add_argument("--no-subsample", action="store_true", help="skip the 2:1 subsampling figures")
+    ap.add_argument("--no-km-vs-wsm", action="store_true", help="skip the KM against WSM comparison")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="finish with plain device-to-device copies of this many MiB (a known-size kernel "
                          "for scaling memory counters)")
@@ -395,6 +440,8 @@ def main():
         line["init_schemes_8x512"] = measure_init_schemes(cq, torch, imgs, dev)
     if not args.no_subsample:
         line["subsample_8x512"] = measure_subsample(cq, torch, imgs, dev)
+    if not args.no_km_vs_wsm:
+        line["km_vs_wsm_8x512"] = measure_km_vs_wsm(cq, torch, imgs, dev)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -94,6 +94,17 @@ cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_str
                        int32_t subsample, uint32_t* keys, uint32_t* counts, int64_t capacity,
                        int64_t* n_unique /* host */, void* ws, size_t ws_bytes, void* stream);
 
+/* The data set of plain KM (Algo. 1, the baseline of the comparison in
+ * Section 3.2): one record per pixel, in row-major order, keys[p] the pixel's
+ * colour key and counts[p] = 1.  keys and counts are device uint32[H W].
+ * Passed to cq_kmeans with prune = 0 they make it run KM over the pixels: a
+ * full search of the K centres for every pixel in every iteration.  The same
+ * starting centres give the same centres, SSE trace and palette as the
+ * weighted run on the histogram (the cluster sums are exact integers).  Does
+ * not synchronize. */
+cq_status cq_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
+                        uint32_t* keys, uint32_t* counts, void* stream);
+
 /* Section 2.3: initial centres from the N' unique colours.  centers is a
  * device double[K][3].  For N' <= K the centres are the colours in key order
  * followed by zeros and *k_used (host, nullable) is N'.  Random draws come
@@ -116,7 +127,9 @@ cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique
                   void* ws, size_t ws_bytes, void* stream);
 
 /* Algo. 1 / Algo. 2: weighted Lloyd iterations on the unique colours starting
- * from centers (device double[K][3], updated in place).
+ * from centers (device double[K][3], updated in place).  keys/counts are the
+ * ascending unique colours of cq_histogram; with prune = 0 any records will
+ * do (unsorted, repeated keys: cq_pixel_keys gives plain KM).
  *  - prune = 0: full nearest-centre search every iteration (Algo. 1).
  *  - prune = 1: sort-means (Algo. 2): iteration 1 is a full search; later
  *    iterations scan the centres in increasing distance from the previous

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcq.so")
 
 CQ_OK, CQ_EINVAL, CQ_ECAPACITY, CQ_EWORKSPACE, CQ_EDEVICE = 0, 1, 2, 3, 4
 INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF = 0, 1, 2, 3, 4, 5
-EXPORTS = ("cq_workspace_bytes", "cq_workspace_prepare", "cq_histogram", "cq_init", "cq_kmeans",
+EXPORTS = ("cq_workspace_bytes", "cq_workspace_prepare", "cq_histogram", "cq_pixel_keys", "cq_init", "cq_kmeans",
            "cq_map", "cq_quantize", "cq_batch_workspace_bytes", "cq_batch_workspace_prepare",
            "cq_quantize_batch", "cq_engine_job_bytes", "cq_engine_workspace_bytes", "cq_engine_create",
            "cq_engine_submit", "cq_engine_step", "cq_engine_pending", "cq_engine_destroy",
@@ -94,6 +94,8 @@ def lib() -> ctypes.CDLL:
         L.cq_workspace_bytes.restype = sz
         L.cq_workspace_prepare.argtypes = [P, sz, P]
         L.cq_histogram.argtypes = [P, i32, i32, i64, i32, P, P, i64, ctypes.POINTER(i64), P, sz, P]
+        L.cq_pixel_keys.argtypes = [P, i32, i32, i64, P, P, P]
+        L.cq_pixel_keys.restype = ctypes.c_int
         L.cq_init.argtypes = [P, P, i64, i32, ctypes.c_int, u64, P, ctypes.POINTER(i32), P, sz, P]
         L.cq_kmeans.argtypes = [P, P, i64, i32, P, i32, f64, i32, P, P, P, ctypes.POINTER(CqStats),
                                 P, sz, P]
@@ -216,6 +218,17 @@ def cq_histogram(img: torch.Tensor, ws: Workspace, capacity: int | None = None, 
                             ctypes.byref(n), ws.ptr, ws.nbytes, _stream(img.device))
     _check("cq_histogram", rc)
     return keys[: n.value], counts[: n.value]
+
+
+def cq_pixel_keys(img: torch.Tensor):
+    """One (key, count 1) record per pixel, row-major, as device uint32
+    tensors: the data set of plain KM for cq_kmeans with prune=False."""
+    H, W, stride = _image_args(img)
+    keys = torch.empty(H * W, dtype=torch.int32, device=img.device)
+    counts = torch.empty(H * W, dtype=torch.int32, device=img.device)
+    _check("cq_pixel_keys", lib().cq_pixel_keys(_ptr(img), H, W, stride, _ptr(keys), _ptr(counts),
+                                                _stream(img.device)))
+    return keys, counts
 
 
 def cq_init(keys: torch.Tensor, counts: torch.Tensor, K: int, scheme: int, seed: int, ws: Workspace,

@@ -596,6 +596,15 @@ cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_str
     return CQ_OK;
 }
 
+cq_status cq_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes, uint32_t* keys,
+                        uint32_t* counts, void* stream)
+{
+    clear_error();
+    CQ_TRY(check_image(img, H, W, row_stride_bytes));
+    if (!keys || !counts) return einval("keys/counts are null");
+    return launch_pixel_keys(img, H, W, row_stride_bytes, keys, counts, static_cast<hipStream_t>(stream));
+}
+
 cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique, int32_t K,
                   cq_init_t scheme, uint64_t seed, double* centers, int32_t* k_used, void* ws,
                   size_t ws_bytes, void* stream)

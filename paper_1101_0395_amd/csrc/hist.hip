@@ -319,6 +319,30 @@ int hist_count_blocks(int64_t npix)
 }
 
 // Histogram of every job; N' is left in each job's meta.
+// The unreduced data set of Algo. 1: one (key, count 1) record per pixel, in
+// row-major order.
+constexpr int kPixelKeyThreads = 256;
+__global__ void __launch_bounds__(kPixelKeyThreads) k_pixel_keys(const uint8_t* __restrict__ img, int32_t W,
+                                                                 int64_t row_stride, int64_t npix,
+                                                                 uint32_t* __restrict__ keys,
+                                                                 uint32_t* __restrict__ counts)
+{
+    const int64_t p = int64_t(blockIdx.x) * kPixelKeyThreads + threadIdx.x;
+    if (p >= npix) return;
+    keys[p] = load_key(img, p, W, row_stride, 3, false);
+    counts[p] = 1u;
+}
+
+cq_status launch_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, uint32_t* keys,
+                            uint32_t* counts, hipStream_t s)
+{
+    const int64_t npix = int64_t(H) * W;  // at most 2^28
+    const int blocks = int((npix + kPixelKeyThreads - 1) / kPixelKeyThreads);
+    CQ_TIMED_LAUNCH("k_pixel_keys", s,
+                    k_pixel_keys<<<blocks, kPixelKeyThreads, 0, s>>>(img, W, row_stride, npix, keys, counts));
+    return CQ_OK;
+}
+
 cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_tiles, int total_count,
                            hipStream_t s)
 {

@@ -19,6 +19,44 @@ constexpr int kLutThreads = 256;
 constexpr int kMapThreads = 256;
 constexpr int kMapGroupsPerBlock = 1024;  // 4-pixel groups per map block
 
+// Nearest-entry search.  Since |x - p|^2 = |x|^2 - (2 x.p - |p|^2), the
+// nearest entry has the largest 2 x.p - |p|^2, an exact integer (x.p is one
+// four-byte dot product of the colours packed in key order, R << 16 | G << 8
+// | B).  Entry t is stored with (255 - t) - (|p|^2 << 8), so a colour's value
+// for it, (x.p << 9) plus that, is ((2 x.p - |p|^2) << 8) | (255 - t): the
+// largest value belongs to the nearest entry and, among equal distances, to
+// the lowest index.
+//
+// The palette table in LDS holds (packed entry, stored value) per entry; the
+// entries from K up to kMaxK have a value too small ever to be the largest,
+// so a search may run to an even count and read two entries at a time.
+__device__ __forceinline__ void load_search_palette(const uint8_t* __restrict__ palette, int K, uint2* ent)
+{
+    for (int t = threadIdx.x; t < kMaxK; t += blockDim.x) {
+        const uint8_t* q = palette + 3 * t;
+        const int r = t < K ? q[0] : 0, g = t < K ? q[1] : 0, b = t < K ? q[2] : 0;
+        const uint32_t packed = (uint32_t(r) << 16) | (uint32_t(g) << 8) | uint32_t(b);
+        const int pp = t < K ? r * r + g * g + b * b : 0x3fffff;
+        ent[t] = make_uint2(packed, uint32_t((255 - t) - (pp << 8)));
+    }
+}
+
+// Index of the entry nearest to colour x (key order) among the first K2 (even)
+// of `ent`, lowest index on ties; *d receives the squared distance.
+__device__ __forceinline__ int nearest_entry(uint32_t x, const uint2* ent, int K2, uint32_t* d)
+{
+    int best = -0x7fffffff - 1;
+#pragma unroll 4
+    for (int k = 0; k < K2; k += 2) {
+        const uint4 e = *reinterpret_cast<const uint4*>(ent + k);  // entries k and k + 1
+        const int v0 = int((__builtin_amdgcn_udot4(x, e.x, 0u, false) << 9) + e.y);
+        const int v1 = int((__builtin_amdgcn_udot4(x, e.z, 0u, false) << 9) + e.w);
+        best = max(best, max(v0, v1));
+    }
+    *d = uint32_t(int(__builtin_amdgcn_udot4(x, x, 0u, false)) - (best >> 8));
+    return 255 - (best & 255);
+}
+
 // Nearest rounded palette entry of every unique colour (exact integer
 // distances, lowest index on ties) into the job's byte table; adds
 // n_i |x_i - P|^2 to the job's squared-error sum.  Block b of job j takes the
@@ -26,35 +64,25 @@ constexpr int kMapGroupsPerBlock = 1024;  // 4-pixel groups per map block
 __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ jobs,
                                                      const int* __restrict__ map, int B, int with_err)
 {
-    __shared__ int pal[3 * kMaxK];
+    __shared__ __align__(16) uint2 ent[kMaxK];
     __shared__ unsigned long long red[kLutThreads / 64];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
-    const int K = J.map_k;
+    const int K2 = (J.map_k + 1) & ~1;
     const uint32_t* __restrict__ keys = gp(J.keys);
     const uint32_t* __restrict__ counts = gp(J.counts);
     uint8_t* __restrict__ lut = gp(J.lut);
-    for (int t = threadIdx.x; t < 3 * K; t += blockDim.x) pal[t] = gp(J.palette)[t];
+    load_search_palette(gp(J.palette), J.map_k, ent);
     __syncthreads();
     const int64_t lo = int64_t(lb) * J.chunk;
     const int64_t hi = lo + J.chunk < J.n ? lo + J.chunk : J.n;
     unsigned long long err = 0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         const uint32_t key = keys[i];
-        int r, g, b;
-        key_rgb(key, r, g, b);
-        uint32_t bd = dist_u32(r, g, b, pal[0], pal[1], pal[2]);
-        int best = 0;
-        for (int k = 1; k < K; ++k) {
-            const uint32_t d = dist_u32(r, g, b, pal[3 * k], pal[3 * k + 1], pal[3 * k + 2]);
-            if (d < bd) {
-                bd = d;
-                best = k;
-            }
-        }
-        lut[key] = uint8_t(best);
-        if (with_err) err += (unsigned long long)counts[i] * bd;
+        uint32_t d;
+        lut[key] = uint8_t(nearest_entry(key, ent, K2, &d));
+        if (with_err) err += (unsigned long long)counts[i] * d;
     }
     if (!with_err) return;
     err = wave_sum(err);
@@ -78,11 +106,7 @@ constexpr int kMapGroupsPerThread = kMapGroupsPerBlock / kMapThreads;
 
 // Per-pixel search of a job with map_direct: block b takes the pixels
 // [4 b G, 4 (b + 1) G) (G = kMapGroupsPerBlock), one per thread per step.
-// Since |x - p|^2 = |x|^2 + (|p|^2 - 2 x.p), the entry with the least
-// |p|^2 - 2 x.p (exact in 32-bit integers, x.p from one four-byte dot
-// product) is the nearest, lowest index on ties.  `ent` holds (packed entry,
-// |p|^2) pairs, entries past K with |p|^2 too large to be chosen, up to an
-// even count.  Adds the pixels' squared errors to the job's sum if with_err.
+// Adds the pixels' squared errors to the job's sum if with_err.
 __device__ __forceinline__ void map_direct_pixels(const JobDev& J, int64_t g0, int64_t g1, const uint32_t* pal,
                                                   const uint2* ent, int with_err)
 {
@@ -97,24 +121,10 @@ __device__ __forceinline__ void map_direct_pixels(const JobDev& J, int64_t g0, i
     for (int64_t p = p0 + threadIdx.x; p < p1; p += kMapThreads) {
         const uint32_t y = uint32_t(p) / uint32_t(W), x = uint32_t(p) - y * uint32_t(W);  // p < 2^28
         const uint8_t* q = img + int64_t(y) * J.stride + 3 * x;
-        const int r = q[0], g = q[1], b = q[2];
-        const uint32_t xv = uint32_t(r) | (uint32_t(g) << 8) | (uint32_t(b) << 16);
-        int best_s = 0x7fffffff, best = 0;
-#pragma unroll 4
-        for (int k = 0; k < K2; k += 2) {
-            const uint4 e = *reinterpret_cast<const uint4*>(ent + k);  // entries k and k + 1
-            const int s0 = int(e.y) - 2 * int(__builtin_amdgcn_udot4(xv, e.x, 0u, false));
-            const int s1 = int(e.w) - 2 * int(__builtin_amdgcn_udot4(xv, e.z, 0u, false));
-            if (s0 < best_s) {
-                best_s = s0;
-                best = k;
-            }
-            if (s1 < best_s) {
-                best_s = s1;
-                best = k + 1;
-            }
-        }
-        if (with_err) err += uint32_t(r * r + g * g + b * b + best_s);
+        const uint32_t key = (uint32_t(q[0]) << 16) | (uint32_t(q[1]) << 8) | uint32_t(q[2]);
+        uint32_t d;
+        const int best = nearest_entry(key, ent, K2, &d);
+        if (with_err) err += d;
         if (out_idx) out_idx[p] = uint8_t(best);
         if (out_rgb) {
             out_rgb[3 * p + 0] = uint8_t(pal[best]);
@@ -150,12 +160,7 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
     const int64_t g0 = int64_t(lb) * kMapGroupsPerBlock;
     const int64_t g1 = g0 + kMapGroupsPerBlock;
     if (J.map_direct) {  // uniform over the block
-        for (int t = threadIdx.x; t < kMaxK; t += blockDim.x) {
-            const uint8_t* q = gp(J.palette) + 3 * t;
-            const int r = t < K ? q[0] : 0, g = t < K ? q[1] : 0, b = t < K ? q[2] : 0;
-            const uint32_t packed = uint32_t(r) | (uint32_t(g) << 8) | (uint32_t(b) << 16);
-            ent[t] = make_uint2(packed, t < K ? uint32_t(r * r + g * g + b * b) : 0x3fffffffu);
-        }
+        load_search_palette(gp(J.palette), K, ent);
         __syncthreads();
         map_direct_pixels(J, g0, g1, pal, ent, with_err);
         return;
