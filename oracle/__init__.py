@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcqref.so")
 SRC_PATH = os.path.join(_HERE, "cqref.c")
 
-INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF = 0, 1, 2, 3, 4, 5
+INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF, INIT_WU = 0, 1, 2, 3, 4, 5, 6
 OK, EINVAL, ECAPACITY, ENOMEM = 0, 1, 2, 5
 
 BUILD_CMD = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra",
@@ -66,13 +66,14 @@ def lib():
         L.cqref_uniform_below.restype = u64
         L.cqref_histogram.argtypes = [P, i32, i32, i64, i32, P, P, i64, ctypes.POINTER(i64)]
         L.cqref_init.argtypes = [P, P, i64, i32, i32, u64, P, ctypes.POINTER(i32)]
+        L.cqref_wu_boxes.argtypes = [P, P, i64, i32, P, ctypes.POINTER(i32)]
         L.cqref_sff_subset.argtypes = [i32, i64]
         L.cqref_sff_subset.restype = i64
         L.cqref_kmeans.argtypes = [P, P, i64, i32, P, i32, f64, i32, P, P, P, ctypes.POINTER(Stats)]
         L.cqref_map.argtypes = [P, i32, i32, i64, P, i32, P, P, ctypes.POINTER(u64)]
         L.cqref_quantize.argtypes = [P, i32, i32, i64, i32, i32, i32, u64, i32, f64, i32, P, P, P,
                                      ctypes.POINTER(Stats)]
-        for f in ("cqref_histogram", "cqref_init", "cqref_kmeans", "cqref_map", "cqref_quantize"):
+        for f in ("cqref_histogram", "cqref_init", "cqref_kmeans", "cqref_map", "cqref_quantize", "cqref_wu_boxes"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -191,3 +192,15 @@ def quantize(img: np.ndarray, K: int, scheme: int, seed: int, max_iters: int, to
 def sff_subset(K: int, n: int) -> int:
     """Size of the SFF subset: max(K, ceil(2 K ln K)), at most n."""
     return int(lib().cqref_sff_subset(K, n))
+
+
+def wu_boxes(keys: np.ndarray, counts: np.ndarray, K: int) -> np.ndarray:
+    """WU's boxes for K, in box index order: rows (lo_r, lo_g, lo_b, hi_r,
+    hi_g, hi_b) over the 32 levels value >> 3, inclusive."""
+    keys = np.ascontiguousarray(keys, np.uint32)
+    counts = np.ascontiguousarray(counts, np.uint32)
+    boxes = np.zeros((K, 6), np.int32)
+    nb = ctypes.c_int32(0)
+    _check("cqref_wu_boxes", lib().cqref_wu_boxes(_ptr(keys), _ptr(counts), len(keys), K, _ptr(boxes),
+                                                  ctypes.byref(nb)))
+    return boxes[: nb.value].copy()

@@ -278,12 +278,223 @@ static int init_sff(const uint32_t* keys, int64_t n, int32_t K, uint64_t* rng, d
     return CQREF_OK;
 }
 
+/* ------------------------------------------------------------------------- */
+/* WU as an initializer (Section 3.3, WSM-WU): Wu's greedy orthogonal        */
+/* bipartitioning of the colour space (X. Wu, "Efficient statistical         */
+/* computations for optimal color quantization", Graphics Gems II, 1991).    */
+/* ------------------------------------------------------------------------- */
+/* Each channel is cut into 32 levels (value >> 3), giving 32^3 cells.  A box
+ * is an inclusive range [lo, hi] of cells per channel.  The statistics of a
+ * set of pixels are five exact integers: w (pixels), the channel sums
+ * sr, sg, sb, and s2 = the sum of r^2 + g^2 + b^2. */
+#define WU_LEVELS 32
+#define WU_CELLS (WU_LEVELS * WU_LEVELS * WU_LEVELS)
+
+typedef struct {
+    uint64_t m[5]; /* w, sr, sg, sb, s2 */
+} wu_mom;
+
+typedef struct {
+    int lo[3], hi[3];
+} wu_box;
+
+/* |m|^2 / w in FP64, evaluated as ((sr^2 + sg^2) + sb^2) / w. */
+static double wu_spread(const wu_mom* a)
+{
+    const double r = (double)a->m[1], g = (double)a->m[2], b = (double)a->m[3];
+    return (r * r + g * g + b * b) / (double)a->m[0];
+}
+
+/* Weighted variance (sum of squared deviations from the mean) of a box, in
+ * FP64: s2 - |m|^2 / w.  A box of one cell cannot be split and counts 0; a
+ * value below zero by rounding also counts 0. */
+static double wu_var(const wu_box* b, const wu_mom* tot)
+{
+    const int vol = (b->hi[0] - b->lo[0] + 1) * (b->hi[1] - b->lo[1] + 1) * (b->hi[2] - b->lo[2] + 1);
+    if (vol <= 1 || tot->m[0] == 0)
+        return 0.0;
+    const double v = (double)tot->m[4] - wu_spread(tot);
+    return v > 0.0 ? v : 0.0;
+}
+
+/* Statistics of box b summed directly over its cells. */
+static void wu_box_moments(const wu_mom* cells, const wu_box* b, wu_mom* out)
+{
+    memset(out, 0, sizeof *out);
+    for (int r = b->lo[0]; r <= b->hi[0]; ++r)
+        for (int g = b->lo[1]; g <= b->hi[1]; ++g)
+            for (int bl = b->lo[2]; bl <= b->hi[2]; ++bl)
+                for (int q = 0; q < 5; ++q)
+                    out->m[q] += cells[(r * WU_LEVELS + g) * WU_LEVELS + bl].m[q];
+}
+
+/* The best cut of box b: along each channel a, every plane c in
+ * [lo_a, hi_a - 1] splits b into [lo_a, c] and [c + 1, hi_a]; a cut leaving
+ * either part without pixels is not allowed.  A cut's value is the sum of
+ * wu_spread over the two parts (the larger, the smaller their summed squared
+ * error); the best cut of a channel is its first one of largest value, and the
+ * channel chosen is the one whose best value is largest, ties to R, then G,
+ * then B.  Returns 0 if no channel has an allowed cut. */
+static int wu_best_cut(const wu_mom* cells, const wu_box* b, const wu_mom* whole, int* axis, int* plane,
+                       wu_mom* lower)
+{
+    double best_v[3] = {0.0, 0.0, 0.0};
+    int best_c[3] = {-1, -1, -1};
+    wu_mom best_low[3];
+    for (int a = 0; a < 3; ++a) {
+        /* the box's statistics plane by plane along channel a */
+        wu_mom marg[WU_LEVELS];
+        memset(marg, 0, sizeof marg);
+        for (int r = b->lo[0]; r <= b->hi[0]; ++r)
+            for (int g = b->lo[1]; g <= b->hi[1]; ++g)
+                for (int bl = b->lo[2]; bl <= b->hi[2]; ++bl) {
+                    const int t = a == 0 ? r : a == 1 ? g : bl;
+                    for (int q = 0; q < 5; ++q)
+                        marg[t].m[q] += cells[(r * WU_LEVELS + g) * WU_LEVELS + bl].m[q];
+                }
+        wu_mom low;
+        memset(&low, 0, sizeof low);
+        for (int c = b->lo[a]; c < b->hi[a]; ++c) {
+            for (int q = 0; q < 5; ++q)
+                low.m[q] += marg[c].m[q];
+            wu_mom up;
+            for (int q = 0; q < 5; ++q)
+                up.m[q] = whole->m[q] - low.m[q];
+            if (low.m[0] == 0 || up.m[0] == 0)
+                continue;
+            const double v = wu_spread(&low) + wu_spread(&up);
+            if (v > best_v[a]) {
+                best_v[a] = v;
+                best_c[a] = c;
+                best_low[a] = low;
+            }
+        }
+    }
+    int a = 0;
+    if (best_v[1] > best_v[a])
+        a = 1;
+    if (best_v[2] > best_v[a])
+        a = 2;
+    if (best_c[a] < 0)
+        return 0;
+    *axis = a;
+    *plane = best_c[a];
+    *lower = best_low[a];
+    return 1;
+}
+
+/* Greedy bipartitioning into at most K boxes: starting from the whole grid,
+ * repeatedly split the box of largest wu_var (ties to the lowest box index)
+ * at its best cut; the lower part keeps the box's index and the upper part
+ * becomes the next box.  A box without an allowed cut gets variance 0 and is
+ * never chosen again; the process ends at K boxes or when every variance is
+ * 0.  Returns the number of boxes. */
+static int wu_partition(const wu_mom* cells, int32_t K, wu_box* boxes, wu_mom* mom)
+{
+    double var[256];
+    for (int a = 0; a < 3; ++a) {
+        boxes[0].lo[a] = 0;
+        boxes[0].hi[a] = WU_LEVELS - 1;
+    }
+    wu_box_moments(cells, &boxes[0], &mom[0]);
+    var[0] = wu_var(&boxes[0], &mom[0]);
+    int nb = 1;
+    while (nb < K) {
+        int next = 0;
+        for (int k = 1; k < nb; ++k)
+            if (var[k] > var[next])
+                next = k;
+        if (var[next] <= 0.0)
+            break;
+        int axis, plane;
+        wu_mom low;
+        if (!wu_best_cut(cells, &boxes[next], &mom[next], &axis, &plane, &low)) {
+            var[next] = 0.0;
+            continue;
+        }
+        boxes[nb] = boxes[next];
+        boxes[next].hi[axis] = plane;
+        boxes[nb].lo[axis] = plane + 1;
+        for (int q = 0; q < 5; ++q)
+            mom[nb].m[q] = mom[next].m[q] - low.m[q];
+        mom[next] = low;
+        var[next] = wu_var(&boxes[next], &mom[next]);
+        var[nb] = wu_var(&boxes[nb], &mom[nb]);
+        ++nb;
+    }
+    return nb;
+}
+
+static int wu_cells(const uint32_t* keys, const uint32_t* counts, int64_t n, wu_mom** out)
+{
+    wu_mom* cells = (wu_mom*)calloc(WU_CELLS, sizeof(wu_mom));
+    if (!cells)
+        return CQREF_ENOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        int r, g, b;
+        key_rgb(keys[i], &r, &g, &b);
+        wu_mom* c = &cells[((r >> 3) * WU_LEVELS + (g >> 3)) * WU_LEVELS + (b >> 3)];
+        const uint64_t w = counts[i];
+        c->m[0] += w;
+        c->m[1] += w * (uint64_t)r;
+        c->m[2] += w * (uint64_t)g;
+        c->m[3] += w * (uint64_t)b;
+        c->m[4] += w * (uint64_t)(r * r + g * g + b * b);
+    }
+    *out = cells;
+    return CQREF_OK;
+}
+
+/* WU initialization: the boxes' weighted means (FP64 quotients of the exact
+ * sums).  If the partition ends with fewer than K boxes, the remaining
+ * centres repeat the first box's mean (a repeated centre loses every tie to
+ * the lower index, so its cluster stays empty). */
+static int init_wu(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K, double* centers)
+{
+    wu_mom* cells;
+    int rc = wu_cells(keys, counts, n, &cells);
+    if (rc)
+        return rc;
+    wu_box boxes[256];
+    wu_mom mom[256];
+    const int nb = wu_partition(cells, K, boxes, mom);
+    for (int32_t k = 0; k < K; ++k) {
+        const wu_mom* m = &mom[k < nb ? k : 0];
+        for (int c = 0; c < 3; ++c)
+            centers[3 * k + c] = (double)m->m[1 + c] / (double)m->m[0];
+    }
+    free(cells);
+    return CQREF_OK;
+}
+
+int cqref_wu_boxes(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K, int32_t* boxes,
+                   int32_t* n_boxes)
+{
+    if (!keys || !counts || !boxes || !n_boxes || n < 1 || K < 1 || K > 256)
+        return CQREF_EINVAL;
+    wu_mom* cells;
+    int rc = wu_cells(keys, counts, n, &cells);
+    if (rc)
+        return rc;
+    wu_box bx[256];
+    wu_mom mom[256];
+    const int nb = wu_partition(cells, K, bx, mom);
+    for (int k = 0; k < nb; ++k)
+        for (int a = 0; a < 3; ++a) {
+            boxes[6 * k + a] = bx[k].lo[a];
+            boxes[6 * k + 3 + a] = bx[k].hi[a];
+        }
+    *n_boxes = nb;
+    free(cells);
+    return CQREF_OK;
+}
+
 int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K,
                int32_t scheme, uint64_t seed, double* centers, int32_t* k_used)
 {
     if (!keys || !counts || !centers || n < 1 || K < 1 || K > 256)
         return CQREF_EINVAL;
-    if (scheme < CQREF_INIT_FORGY || scheme > CQREF_INIT_SFF)
+    if (scheme < CQREF_INIT_FORGY || scheme > CQREF_INIT_WU)
         return CQREF_EINVAL;
     if (n <= K) {
         /* Fewer colours than palette entries: every colour is a centre. */
@@ -307,6 +518,8 @@ int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t 
         return init_var(keys, counts, n, K, centers);
     if (scheme == CQREF_INIT_SFF)
         return init_sff(keys, n, K, &rng, centers);
+    if (scheme == CQREF_INIT_WU)
+        return init_wu(keys, counts, n, K, centers);
     if (scheme == CQREF_INIT_FORGY) {
         int64_t* perm = (int64_t*)malloc((size_t)n * sizeof(int64_t));
         if (!perm)

@@ -20,7 +20,7 @@ extern "C" {
 
 enum { CQREF_OK = 0, CQREF_EINVAL = 1, CQREF_ECAPACITY = 2, CQREF_ENOMEM = 5 };
 enum { CQREF_INIT_FORGY = 0, CQREF_INIT_MAXMIN = 1, CQREF_INIT_KMEANSPP = 2, CQREF_INIT_USER = 3,
-       CQREF_INIT_VAR = 4, CQREF_INIT_SFF = 5 };
+       CQREF_INIT_VAR = 4, CQREF_INIT_SFF = 5, CQREF_INIT_WU = 6 };
 
 typedef struct {
     int32_t iters;      /* Lloyd iterations run                                  */
@@ -51,10 +51,17 @@ uint64_t cqref_uniform_below(uint64_t* s, uint64_t T);
 int cqref_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, int32_t subsample,
                     uint32_t* keys, uint32_t* counts, int64_t capacity, int64_t* n_unique);
 
-/* Initialization schemes of Section 2.3 (FGY, MMX, KPP, VAR, SFF) on the
- * unique colours. */
+/* Initialization schemes of Section 2.3 (FGY, MMX, KPP, VAR, SFF) and Wu's
+ * greedy orthogonal bipartitioning (WU, the initializer of WSM-WU in Section
+ * 3.3) on the unique colours. */
 int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K,
                int32_t scheme, uint64_t seed, double* centers, int32_t* k_used);
+
+/* The boxes of WU's partition for K (boxes[6 k .. 6 k + 5] = lo_r, lo_g,
+ * lo_b, hi_r, hi_g, hi_b over the 32 levels value >> 3, inclusive), in box
+ * index order; *n_boxes receives their number (at most K).  For tests. */
+int cqref_wu_boxes(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K, int32_t* boxes,
+                   int32_t* n_boxes);
 
 /* Weighted Lloyd iteration (Algo. 1 with the weights of Section 2.2) with
  * optional sort-means pruning (Algo. 2), relative-SSE stopping (Section 3.3). */

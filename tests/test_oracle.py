@@ -547,3 +547,160 @@ def test_subsampled_quantize_clusters_the_even_pixels_and_maps_all():
     D = ((X[:, None, :] - pal.astype(np.int64)[None, :, :]) ** 2).sum(-1)
     assert np.array_equal(idx.reshape(-1), np.argmin(D, axis=1))
     assert st["mse_img"] == pytest.approx(D.min(axis=1).mean(), rel=1e-12)
+
+
+# ---------------------------------------------------------------- WU (greedy orthogonal bipartitioning)
+def _cells_of(keys):
+    k = keys.astype(np.int64)
+    return np.stack([(k >> 19) & 31, (k >> 11) & 31, (k >> 3) & 31], 1)  # value >> 3 per channel
+
+
+def _in_box(cells, box):
+    lo, hi = np.asarray(box[:3]), np.asarray(box[3:])
+    return np.all((cells >= lo) & (cells <= hi), axis=1)
+
+
+def _sse_exact(keys, counts, mask):
+    """Sum over the pixels of the squared distance to their weighted mean,
+    as an exact fraction (the definition, from the colour list)."""
+    from fractions import Fraction
+
+    w = int(counts[mask].sum())
+    if w == 0:
+        return Fraction(0)
+    rgb = _rgb_of(keys[mask]).astype(np.int64)
+    n = counts[mask].astype(np.int64)
+    mean = [Fraction(int((n * rgb[:, c]).sum()), w) for c in range(3)]
+    return sum(int(ni) * sum((int(x[c]) - mean[c]) ** 2 for c in range(3)) for ni, x in zip(n, rgb))
+
+
+def _cuts(box):
+    for a in range(3):
+        for c in range(box[a], box[3 + a]):
+            lower, upper = list(box), list(box)
+            lower[3 + a] = c
+            upper[a] = c + 1
+            yield lower, upper
+
+
+def _wu_data(seed, n=160):
+    rng = np.random.default_rng(seed)
+    # clustered colours so that boxes differ clearly in spread
+    centres = rng.integers(20, 236, size=(5, 3))
+    pts = centres[rng.integers(0, 5, n)] + rng.normal(0, 18, (n, 3))
+    pts = np.clip(np.rint(pts), 0, 255).astype(np.uint32)
+    keys = np.unique((pts[:, 0] << 16) | (pts[:, 1] << 8) | pts[:, 2]).astype(np.uint32)
+    counts = rng.integers(1, 6, len(keys)).astype(np.uint32)
+    return keys, counts
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_wu_each_step_splits_the_worst_box_at_its_best_cut(seed):
+    """Wu's greedy step from K to K + 1 boxes, checked with exact squared
+    errors computed from the colours: the box that is split has the largest
+    error among the boxes with an allowed cut, the lower part keeps its index
+    and the upper part is appended, and the cut minimises the summed error of
+    the two parts over every plane along every channel."""
+    from fractions import Fraction
+
+    keys, counts = _wu_data(seed)
+    cells = _cells_of(keys)
+    tol = Fraction(1, 10 ** 12)
+    prev = oracle.wu_boxes(keys, counts, 1)
+    assert prev.tolist() == [[0, 0, 0, 31, 31, 31]]
+    for K in range(2, 14):
+        cur = oracle.wu_boxes(keys, counts, K)
+        assert len(cur) == len(prev) + 1
+        changed = [j for j in range(len(prev)) if not np.array_equal(cur[j], prev[j])]
+        assert len(changed) == 1
+        j = changed[0]
+        parent, lower, upper = prev[j].tolist(), cur[j].tolist(), cur[-1].tolist()
+        assert (lower, upper) in [(lo, up) for lo, up in _cuts(parent)]
+        # the split box: largest error among boxes that have an allowed cut
+        def cuttable(box):
+            return any(counts[_in_box(cells, lo)].sum() > 0 and counts[_in_box(cells, up)].sum() > 0
+                       for lo, up in _cuts(box))
+        errs = [_sse_exact(keys, counts, _in_box(cells, b)) if cuttable(b.tolist()) else Fraction(-1)
+                for b in prev]
+        assert errs[j] >= max(errs) * (1 - tol)
+        # the cut: least summed error over all allowed cuts of the parent
+        options = []
+        for lo, up in _cuts(parent):
+            ml, mu = _in_box(cells, lo), _in_box(cells, up)
+            if counts[ml].sum() > 0 and counts[mu].sum() > 0:
+                options.append(_sse_exact(keys, counts, ml) + _sse_exact(keys, counts, mu))
+        got = _sse_exact(keys, counts, _in_box(cells, lower)) + _sse_exact(keys, counts, _in_box(cells, upper))
+        assert got <= min(options) * (1 + tol)
+        prev = cur
+
+
+def test_wu_boxes_partition_the_grid_and_centres_are_box_means():
+    from fractions import Fraction
+
+    keys, counts = _wu_data(7, n=400)
+    K = 24
+    boxes = oracle.wu_boxes(keys, counts, K)
+    assert len(boxes) == K
+    grid = np.zeros((32, 32, 32), np.int32)
+    for b in boxes:
+        grid[b[0]:b[3] + 1, b[1]:b[4] + 1, b[2]:b[5] + 1] += 1
+    assert (grid == 1).all()  # disjoint and covering
+    cen, k_used = oracle.init(keys, counts, K, oracle.INIT_WU, 0)
+    assert k_used == K
+    cells = _cells_of(keys)
+    rgb = _rgb_of(keys).astype(np.int64)
+    for k, b in enumerate(boxes):
+        m = _in_box(cells, b)
+        w = int(counts[m].sum())
+        assert w > 0
+        for c in range(3):
+            assert cen[k, c] == float(Fraction(int((counts[m].astype(np.int64) * rgb[m, c]).sum()), w))
+
+
+def test_wu_one_box_is_the_weighted_mean_and_two_clusters_are_found():
+    from fractions import Fraction
+
+    keys, counts = _wu_data(3)
+    cen, _ = oracle.init(keys, counts, 1, oracle.INIT_WU, 0)
+    rgb = _rgb_of(keys).astype(np.int64)
+    w = int(counts.sum())
+    assert cen[0].tolist() == [float(Fraction(int((counts * rgb[:, c]).sum()), w)) for c in range(3)]
+    # two tight, far-apart groups (more colours than K): K = 2 gives their means
+    a = [(10 + i, 20, 30 + j) for i in range(3) for j in range(3)]
+    b = [(200, 180 + i, 90 + j) for i in range(3) for j in range(3)]
+    ks = np.array(sorted((r << 16) | (g << 8) | bl for r, g, bl in a + b), np.uint32)
+    cs = np.ones(len(ks), np.uint32)
+    cen, _ = oracle.init(ks, cs, 2, oracle.INIT_WU, 0)
+    got = sorted(map(tuple, cen.tolist()))
+    assert got == [(11.0, 20.0, 31.0), (200.0, 181.0, 91.0)]
+
+
+def test_wu_with_fewer_occupied_cells_than_k_repeats_the_first_mean():
+    # 12 colours in three cells (each cell's colours differ only below bit 3)
+    ks = np.array(sorted(((8 * c) << 16) | (i << 8) | j for c in (1, 9, 20) for i in range(2) for j in range(2)),
+                  np.uint32)
+    cs = np.arange(1, len(ks) + 1, dtype=np.uint32)
+    boxes = oracle.wu_boxes(ks, cs, 8)
+    assert len(boxes) == 3
+    cen, k_used = oracle.init(ks, cs, 8, oracle.INIT_WU, 0)
+    assert k_used == 8
+    assert all(cen[k].tolist() == cen[0].tolist() for k in range(3, 8))
+    assert len({tuple(c) for c in cen[:3].tolist()}) == 3
+
+
+def test_wu_ties_go_to_the_lower_channel_and_the_first_plane():
+    # two colours mirrored in R and B: every plane between them along R or B
+    # splits them with the same value (an exact tie in FP64: the same integer
+    # sums), and G offers no cut
+    ks = np.array(sorted([(40 << 16) | (100 << 8) | 200, (200 << 16) | (100 << 8) | 40]), np.uint32)
+    cs = np.array([3, 3], np.uint32)
+    boxes = oracle.wu_boxes(ks, cs, 2)
+    assert boxes.tolist() == [[0, 0, 0, 5, 31, 31], [6, 0, 0, 31, 31, 31]]
+    # G and B mirrored: G wins
+    ks = np.array(sorted([(100 << 16) | (40 << 8) | 200, (100 << 16) | (200 << 8) | 40]), np.uint32)
+    boxes = oracle.wu_boxes(ks, cs, 2)
+    assert boxes.tolist() == [[0, 0, 0, 31, 5, 31], [0, 6, 0, 31, 31, 31]]
+    # R and G mirrored: R wins
+    ks = np.array(sorted([(40 << 16) | (200 << 8) | 100, (200 << 16) | (40 << 8) | 100]), np.uint32)
+    boxes = oracle.wu_boxes(ks, cs, 2)
+    assert boxes.tolist() == [[0, 0, 0, 5, 31, 31], [6, 0, 0, 31, 31, 31]]
