@@ -45,14 +45,16 @@ typedef enum {
     CQ_EDEVICE = 4      /* HIP runtime error; see cq_last_error()              */
 } cq_status;
 
-/* Initialization schemes of Section 2.3. */
+/* Initialization schemes of Section 2.3, and WU, the initializer of WSM-WU
+ * in Section 3.3. */
 typedef enum {
     CQ_INIT_FORGY = 0,     /* K distinct colours drawn uniformly (FGY)              */
     CQ_INIT_MAXMIN = 1,    /* farthest-first after a uniform first colour (MMX)     */
     CQ_INIT_KMEANSPP = 2,  /* D^2 sampling, weighted by pixel counts (KPP)          */
     CQ_INIT_USER = 3,      /* centres supplied by the caller (WSM-X warm start)     */
     CQ_INIT_VAR = 4,       /* maximum variance: medians along the widest channel    */
-    CQ_INIT_SFF = 5        /* farthest first on a random subset (SFF)              */
+    CQ_INIT_SFF = 5,       /* farthest first on a random subset (SFF)              */
+    CQ_INIT_WU = 6         /* Wu's greedy orthogonal bipartitioning (WU)           */
 } cq_init_t;
 
 /* Run statistics (host structure). */
@@ -118,7 +120,16 @@ cq_status cq_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t row_st
  * the N pixels, and each group's lower-median pixel; no draws.  SFF draws a
  * subset of L = max(K, ceil(2 K ln K)) colours (at most N') as FGY draws, then
  * runs MMX on the subset in draw order (first centre subset[U(L)], ties to
- * the lowest subset position).  With CQ_INIT_USER the centres are left as
+ * the lowest subset position). WU (Wu's greedy orthogonal bipartitioning, no draws)
+ * cuts each channel into 32 levels (value >> 3) and, from the whole grid,
+ * repeatedly splits the box of largest weighted variance s2 - |m|^2 / w
+ * (pixel statistics; ties to the lowest box index; a box of one cell or with
+ * no allowed cut counts 0) at the plane maximizing |m_l|^2 / w_l +
+ * |m_u|^2 / w_u over two non-empty parts (first plane, then R, G, B on ties;
+ * the lower part keeps the index, the upper part is appended), until K boxes
+ * or no variance is left; the centres are the box means, and if fewer than K
+ * boxes result the rest repeat box 0's mean.  The criteria are FP64 in that
+ * operation order, the statistics exact integers.  With CQ_INIT_USER the centres are left as
  * given.  Synchronizes only if k_used is
  * non-null; a device-side failure of the initialization is reported by that
  * synchronization or by the next synchronizing call on the workspace. */

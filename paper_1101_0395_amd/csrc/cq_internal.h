@@ -215,6 +215,10 @@ struct JobResult {
     int32_t done, iters, converged, bad_input, sync_error, pad_;
 };
 
+// WU initialization: five uint64 statistics over a 33^3 grid (32 levels per
+// channel plus a zero border).
+constexpr size_t kWuTableBytes = sizeof(uint64_t) * 5 * 33 * 33 * 33;
+
 enum MapId {
     kMapHist = 0,
     kMapHistCount,   // histogram counting blocks
@@ -228,6 +232,7 @@ enum MapId {
     kMapInit,
     kMapVarTiles,    // VAR: colour tiles
     kMapVarGroups,   // VAR: one block per centre
+    kMapWu,          // WU: blocks of colours
     kNumMaps
 };
 
@@ -306,8 +311,11 @@ inline Layout make_layout(int64_t npix, int64_t n_cap, bool with_colour_arrays)
     // per colour
     const size_t d2_init = n > 0 ? sizeof(uint32_t) * (n + size_t(kInitThreads + 1) * kInitMaxBlocks) : 0;
     const size_t d2_km = sizeof(uint64_t) * 2 * n;
+    // init WU: the moment table
+    const size_t wu = n > 0 ? kWuTableBytes : 0;
     size_t work = hist > d2_init ? hist : d2_init;
     work = work > d2_km ? work : d2_km;
+    work = work > wu ? work : wu;
     o = align256(o + work);
     if (with_colour_arrays) {
         L.keys = o;   o = align256(o + sizeof(uint32_t) * n);
