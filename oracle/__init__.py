@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcqref.so")
 SRC_PATH = os.path.join(_HERE, "cqref.c")
 
-INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF, INIT_WU = 0, 1, 2, 3, 4, 5, 6
+INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF, INIT_WU, INIT_LBG = 0, 1, 2, 3, 4, 5, 6, 7
 OK, EINVAL, ECAPACITY, ENOMEM = 0, 1, 2, 5
 
 BUILD_CMD = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra",

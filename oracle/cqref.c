@@ -467,6 +467,51 @@ static int init_wu(const uint32_t* keys, const uint32_t* counts, int64_t n, int3
     return CQREF_OK;
 }
 
+/* LBG (Section 2.3, splitting; Linde, Buzo and Gray 1980).  The first centre
+ * is the weighted mean of the colours (FP64 quotients of the exact sums).  A
+ * stage doubles the m centres: centre j becomes c_j - eps, kept at index j,
+ * and c_j + eps, appended at index m + j, with eps = (1, 1, 1); when K is not
+ * a power of two the last stage splits only the first K - m centres.  After
+ * every stage the centres are refined by weighted Lloyd iterations (Algo. 1
+ * with the weights of Section 2.2) stopped by the rule of Section 3.3 with the
+ * paper's threshold 0.001, at most 100 iterations. */
+#define LBG_EPS 1.0
+#define LBG_TOL 0.001
+#define LBG_MAX_ITERS 100
+
+static int init_lbg(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K, double* centers)
+{
+    uint64_t N = 0, S[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        int r, g, b;
+        key_rgb(keys[i], &r, &g, &b);
+        N += counts[i];
+        S[0] += (uint64_t)counts[i] * (uint64_t)r;
+        S[1] += (uint64_t)counts[i] * (uint64_t)g;
+        S[2] += (uint64_t)counts[i] * (uint64_t)b;
+    }
+    for (int c = 0; c < 3; ++c)
+        centers[c] = (double)S[c] / (double)N;
+    uint8_t* assign = (uint8_t*)malloc((size_t)n);
+    if (!assign)
+        return CQREF_ENOMEM;
+    int32_t m = 1;
+    int rc = CQREF_OK;
+    while (m < K && rc == CQREF_OK) {
+        const int32_t split = 2 * m <= K ? m : K - m;
+        for (int32_t j = 0; j < split; ++j)
+            for (int c = 0; c < 3; ++c) {
+                const double v = centers[3 * j + c];
+                centers[3 * (m + j) + c] = v + LBG_EPS;
+                centers[3 * j + c] = v - LBG_EPS;
+            }
+        m += split;
+        rc = cqref_kmeans(keys, counts, n, m, centers, LBG_MAX_ITERS, LBG_TOL, 0, assign, NULL, NULL, NULL);
+    }
+    free(assign);
+    return rc;
+}
+
 int cqref_wu_boxes(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K, int32_t* boxes,
                    int32_t* n_boxes)
 {
@@ -494,7 +539,7 @@ int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t 
 {
     if (!keys || !counts || !centers || n < 1 || K < 1 || K > 256)
         return CQREF_EINVAL;
-    if (scheme < CQREF_INIT_FORGY || scheme > CQREF_INIT_WU)
+    if (scheme < CQREF_INIT_FORGY || scheme > CQREF_INIT_LBG)
         return CQREF_EINVAL;
     if (n <= K) {
         /* Fewer colours than palette entries: every colour is a centre. */
@@ -520,6 +565,8 @@ int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t 
         return init_sff(keys, n, K, &rng, centers);
     if (scheme == CQREF_INIT_WU)
         return init_wu(keys, counts, n, K, centers);
+    if (scheme == CQREF_INIT_LBG)
+        return init_lbg(keys, counts, n, K, centers);
     if (scheme == CQREF_INIT_FORGY) {
         int64_t* perm = (int64_t*)malloc((size_t)n * sizeof(int64_t));
         if (!perm)

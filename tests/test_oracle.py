@@ -704,3 +704,89 @@ def test_wu_ties_go_to_the_lower_channel_and_the_first_plane():
     ks = np.array(sorted([(40 << 16) | (200 << 8) | 100, (200 << 16) | (40 << 8) | 100]), np.uint32)
     boxes = oracle.wu_boxes(ks, cs, 2)
     assert boxes.tolist() == [[0, 0, 0, 5, 31, 31], [6, 0, 0, 31, 31, 31]]
+
+
+# ---------------------------------------------------------------- LBG (splitting)
+def _lbg_brute(keys, counts, K, eps=1.0, tol=0.001, max_iters=100):
+    """LBG of Section 2.3 in plain Python: the centroid, then stages that
+    split centre j into c_j - eps (kept) and c_j + eps (appended), each
+    followed by weighted Lloyd iterations (FP64 centres S / n, nearest centre by
+    FP64 distance with the lowest index on ties, empty clusters kept) until the
+    relative SSE decrease, computed exactly, is at most tol."""
+    from fractions import Fraction
+
+    rgb = [tuple(int(v) for v in x) for x in _rgb_of(keys)]
+    n = [int(c) for c in counts]
+    N = sum(n)
+    C = [[float(sum(w * x[c] for w, x in zip(n, rgb))) / float(N) for c in range(3)]]
+    m = 1
+    while m < K:
+        split = m if 2 * m <= K else K - m
+        for j in range(split):
+            C.append([v + eps for v in C[j]])
+            C[j] = [v - eps for v in C[j]]
+        m += split
+        prev = None
+        for it in range(1, max_iters + 1):
+            S = [[0, 0, 0] for _ in range(m)]
+            Q = [0] * m
+            W = [0] * m
+            for w, x in zip(n, rgb):
+                best, bd = 0, None
+                for k in range(m):
+                    dx, dy, dz = x[0] - C[k][0], x[1] - C[k][1], x[2] - C[k][2]
+                    d = (dx * dx + dy * dy) + dz * dz
+                    if bd is None or d < bd:
+                        best, bd = k, d
+                W[best] += w
+                Q[best] += w * (x[0] ** 2 + x[1] ** 2 + x[2] ** 2)
+                for c in range(3):
+                    S[best][c] += w * x[c]
+            for k in range(m):
+                if W[k]:
+                    C[k] = [float(S[k][c]) / float(W[k]) for c in range(3)]
+            sse = sum(Fraction(W[k] * Q[k] - sum(v * v for v in S[k]), W[k]) for k in range(m) if W[k])
+            if sse == 0 or (prev is not None and prev - sse <= Fraction(tol) * sse):
+                break
+            prev = sse
+    return np.array(C, np.float64)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_lbg_matches_brute_force(seed):
+    rng = np.random.default_rng(100 + seed)
+    keys, counts = _rand_colours(rng, 40, max_count=7)
+    for K in (1, 2, 3, 5, 6, 7, 8):
+        got, k_used = oracle.init(keys, counts, K, oracle.INIT_LBG, 0)
+        assert k_used == K
+        assert np.array_equal(got, _lbg_brute(keys, counts, K)), K
+
+
+def test_lbg_one_centre_is_the_centroid_and_four_groups_are_found():
+    from fractions import Fraction
+
+    rng = np.random.default_rng(9)
+    keys, counts = _rand_colours(rng, 30)
+    got, _ = oracle.init(keys, counts, 1, oracle.INIT_LBG, 0)
+    rgb = _rgb_of(keys).astype(np.int64)
+    w = int(counts.sum())
+    assert got[0].tolist() == [float(Fraction(int((counts * rgb[:, c]).sum()), w)) for c in range(3)]
+    # four tight groups along the grey axis: the splits along (1, 1, 1) find them
+    pts = [(v + i, v + j, v) for v in (20, 90, 160, 230) for i in range(2) for j in range(2)]
+    ks = np.array(sorted((r << 16) | (g << 8) | b for r, g, b in pts), np.uint32)
+    got, _ = oracle.init(ks, np.ones(len(ks), np.uint32), 4, oracle.INIT_LBG, 0)
+    assert sorted(map(tuple, got.tolist())) == [(v + 0.5, v + 0.5, float(v)) for v in (20, 90, 160, 230)]
+
+
+def test_lbg_split_of_a_single_colour_keeps_the_perturbed_centre():
+    # an isolated colour forms its own cluster after the first stage; at the
+    # second stage its two halves are equidistant from it, the kept half
+    # (lower index) takes it and the appended half c + eps stays empty
+    group = [(40 + i, 60 + j, 50) for i in range(4) for j in range(4)]
+    lone = (230, 230, 230)
+    ks = np.array(sorted((r << 16) | (g << 8) | b for r, g, b in group + [lone]), np.uint32)
+    cs = np.ones(len(ks), np.uint32)
+    got, _ = oracle.init(ks, cs, 4, oracle.INIT_LBG, 0)
+    assert [231.0, 231.0, 231.0] in got.tolist()
+    assert [230.0, 230.0, 230.0] in got.tolist()
+    assert np.array_equal(got, _lbg_brute(ks, cs, 4))
