@@ -54,7 +54,8 @@ typedef enum {
     CQ_INIT_USER = 3,      /* centres supplied by the caller (WSM-X warm start)     */
     CQ_INIT_VAR = 4,       /* maximum variance: medians along the widest channel    */
     CQ_INIT_SFF = 5,       /* farthest first on a random subset (SFF)              */
-    CQ_INIT_WU = 6         /* Wu's greedy orthogonal bipartitioning (WU)           */
+    CQ_INIT_WU = 6,        /* Wu's greedy orthogonal bipartitioning (WU)           */
+    CQ_INIT_LBG = 7        /* splitting from the centroid, refined by k-means (LBG) */
 } cq_init_t;
 
 /* Run statistics (host structure). */
@@ -129,7 +130,12 @@ cq_status cq_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t row_st
  * the lower part keeps the index, the upper part is appended), until K boxes
  * or no variance is left; the centres are the box means, and if fewer than K
  * boxes result the rest repeat box 0's mean.  The criteria are FP64 in that
- * operation order, the statistics exact integers.  With CQ_INIT_USER the centres are left as
+ * operation order, the statistics exact integers.  LBG starts from the weighted centroid and doubles the
+ * centres in stages: centre j becomes c_j - (1,1,1) in place and c_j + (1,1,1)
+ * at index m + j (a last partial stage splits the first K - m), each stage
+ * refined by weighted Lloyd iterations with the stopping rule of Section 3.3
+ * at the paper's threshold 0.001 (at most 100 iterations); it synchronizes
+ * `stream` once per stage.  With CQ_INIT_USER the centres are left as
  * given.  Synchronizes only if k_used is
  * non-null; a device-side failure of the initialization is reported by that
  * synchronization or by the next synchronizing call on the workspace. */

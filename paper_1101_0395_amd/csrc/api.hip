@@ -296,6 +296,45 @@ void set_counts(Batch& b, const std::vector<int64_t>& n)
     }
 }
 
+// LBG: the centroid (one iteration of a single centre from zero), then the
+// doubling stages, each refined by k-means with the threshold kLbgTol.  The
+// jobs still doubling form a batch of their own in the same descriptor
+// region; the batch's own descriptors are uploaded again at the end.
+static cq_status run_lbg(Batch& b)
+{
+    std::vector<int> jobs;
+    for (int j = 0; j < b.B; ++j)
+        if (b.h[j].scheme == CQ_INIT_LBG && b.h[j].n > b.h[j].K) jobs.push_back(j);
+    if (jobs.empty()) return CQ_OK;
+    std::vector<int32_t> have(jobs.size(), 0);  // centres so far (0: not even the centroid)
+    while (true) {
+        std::vector<int> act;
+        for (size_t i = 0; i < jobs.size(); ++i)
+            if (have[i] < b.h[jobs[i]].K) act.push_back(int(i));
+        if (act.empty()) break;
+        Batch st(int(act.size()), b.desc, b.s);
+        for (int q = 0; q < st.B; ++q) {
+            const int i = act[q];
+            JobDev J = b.h[jobs[i]];
+            const int32_t m = have[i];
+            const int32_t next = m == 0 ? 1 : (2 * m <= J.K ? 2 * m : J.K);
+            J.init_C = m;
+            J.K = next;
+            J.prune = m == 0 ? 0 : 1;
+            J.max_iters = m == 0 ? 1 : kLbgMaxIters;
+            J.tol = kLbgTol;
+            st.h[q] = J;
+            have[i] = next;
+        }
+        CQ_TRY(upload(st));
+        CQ_TRY(launch_lbg_stage(st.d_jobs(), st.B, st.s));
+        CQ_TRY(run_kmeans(st));
+        CQ_TRY(check_kmeans(st));
+        for (auto& v : st.staged) b.staged.push_back(std::move(v));
+    }
+    return upload(b);
+}
+
 cq_status run_init(Batch& b)
 {
     bool any_forgy = false, any_sff = false;
@@ -367,7 +406,7 @@ cq_status run_init(Batch& b)
         CQ_TRY(launch_init_coop(b.d_jobs(), b.d_maps() + kMapInit * (b.B + 1), b.B, total, lds, b.s));
         next = last;
     }
-    return CQ_OK;
+    return run_lbg(b);
 }
 
 // Iterations of every job until all have stopped.  Iterations are enqueued
@@ -537,8 +576,8 @@ cq_status check_job(const cq_job& j, int idx)
     if (s == CQ_OK) s = check_subsample(j.subsample);
     if (s == CQ_OK) s = check_k(j.K);
     if (s == CQ_OK && !j.palette) s = einval("palette is null");
-    if (s == CQ_OK && (int(j.scheme) < CQ_INIT_FORGY || int(j.scheme) > CQ_INIT_WU || j.scheme == CQ_INIT_USER))
-        s = einval("scheme must be FORGY, MAXMIN, KMEANSPP, VAR, SFF or WU");
+    if (s == CQ_OK && (int(j.scheme) < CQ_INIT_FORGY || int(j.scheme) > CQ_INIT_LBG || j.scheme == CQ_INIT_USER))
+        s = einval("scheme must be FORGY, MAXMIN, KMEANSPP, VAR, SFF, WU or LBG");
     if (s == CQ_OK) s = check_iters_tol(j.max_iters, j.tol);
     if (s != CQ_OK) {
         char msg[512];
@@ -618,7 +657,7 @@ cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique
     CQ_TRY(check_k(K));
     if (!keys || !counts || !centers) return einval("keys/counts/centers is null");
     if (n_unique < 1 || n_unique > kMaxPixels) return einval("n_unique = %lld out of range", (long long)n_unique);
-    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_WU) return einval("unknown init scheme %d", int(scheme));
+    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_LBG) return einval("unknown init scheme %d", int(scheme));
     const Layout L = make_layout(0, n_unique, false);
     CQ_TRY(check_ws(ws, ws_bytes, L.total));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
@@ -627,6 +666,7 @@ cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique
     J.keys = to_dev(const_cast<uint32_t*>(keys));
     J.counts = to_dev(const_cast<uint32_t*>(counts));
     J.centers = to_dev(centers);
+    J.assign = to_dev(reinterpret_cast<uint8_t*>(static_cast<char*>(ws) + L.assign));
     J.K = K;
     J.scheme = int(scheme);
     J.seed = seed;
@@ -723,8 +763,8 @@ cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stri
     CQ_TRY(check_subsample(subsample));
     CQ_TRY(check_k(K));
     if (!palette) return einval("palette is null");
-    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_WU || scheme == CQ_INIT_USER)
-        return einval("cq_quantize needs scheme FORGY, MAXMIN, KMEANSPP, VAR, SFF or WU");
+    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_LBG || scheme == CQ_INIT_USER)
+        return einval("cq_quantize needs scheme FORGY, MAXMIN, KMEANSPP, VAR, SFF, WU or LBG");
     CQ_TRY(check_iters_tol(max_iters, tol));
     const int64_t npix = int64_t(H) * W;
     const Layout L = make_layout(npix, npix, true);

@@ -215,6 +215,13 @@ struct JobResult {
     int32_t done, iters, converged, bad_input, sync_error, pad_;
 };
 
+// LBG initialization: the splitting vector (eps, eps, eps), and the stopping
+// threshold and iteration limit of the k-means refinement after each stage
+// (the threshold is the paper's, Section 3.3).
+constexpr double kLbgEps = 1.0;
+constexpr double kLbgTol = 0.001;
+constexpr int32_t kLbgMaxIters = 100;
+
 // WU initialization: five uint64 statistics over a 33^3 grid (32 levels per
 // channel plus a zero border).
 constexpr size_t kWuTableBytes = sizeof(uint64_t) * 5 * 33 * 33 * 33;
@@ -322,7 +329,13 @@ inline Layout make_layout(int64_t npix, int64_t n_cap, bool with_colour_arrays)
         L.counts = o; o = align256(o + sizeof(uint32_t) * n);
         L.assign = o; o = align256(o + n);
     } else {
-        L.keys = L.counts = L.assign = 0;
+        // memberships of the k-means refinement of an LBG initialization
+        L.keys = L.counts = 0;
+        L.assign = 0;
+        if (n > 0) {
+            L.assign = o;
+            o = align256(o + n);
+        }
     }
     L.total = o;
     return L;

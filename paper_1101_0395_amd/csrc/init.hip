@@ -852,6 +852,34 @@ cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s)
     return CQ_OK;
 }
 
+// LBG stage of each job of a batch (one block per job): with init_C = 0 the
+// single centre is set to zero (the start of the iteration that yields the
+// centroid); otherwise the first K - init_C of the init_C centres are split,
+// centre j becoming c_j - eps in place and c_j + eps at index init_C + j, with
+// eps = (1, 1, 1).
+__global__ void __launch_bounds__(kMaxK) k_lbg_stage(const JobDev* __restrict__ jobs)
+{
+    const JobDev& J = jobs[blockIdx.x];
+    double* __restrict__ c = gp(J.centers);
+    const int m = int(J.init_C);
+    if (m == 0) {
+        if (threadIdx.x < 3) c[threadIdx.x] = 0.0;
+        return;
+    }
+    const int split = J.K - m;
+    for (int t = threadIdx.x; t < 3 * split; t += blockDim.x) {
+        const double v = c[t];
+        c[3 * m + t] = v + kLbgEps;
+        c[t] = v - kLbgEps;
+    }
+}
+
+cq_status launch_lbg_stage(const JobDev* jobs, int B, hipStream_t s)
+{
+    CQ_TIMED_LAUNCH("k_lbg_stage", s, k_lbg_stage<<<B, kMaxK, 0, s>>>(jobs));
+    return CQ_OK;
+}
+
 cq_status launch_var(const JobDev* jobs, const int* maps, int B, int tiles, int groups, hipStream_t s)
 {
     CQ_TIMED_LAUNCH("k_var_tiles", s, k_var_tiles<<<tiles, kVarThreads, 0, s>>>(jobs, maps + kMapVarTiles * (B + 1), B));
