@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcqref.so")
 SRC_PATH = os.path.join(_HERE, "cqref.c")
 
-INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF, INIT_WU, INIT_LBG = 0, 1, 2, 3, 4, 5, 6, 7
+(INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF, INIT_WU, INIT_LBG,
+ INIT_DEN) = 0, 1, 2, 3, 4, 5, 6, 7, 8
 OK, EINVAL, ECAPACITY, ENOMEM = 0, 1, 2, 5
 
 BUILD_CMD = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra",
@@ -67,13 +68,15 @@ def lib():
         L.cqref_histogram.argtypes = [P, i32, i32, i64, i32, P, P, i64, ctypes.POINTER(i64)]
         L.cqref_init.argtypes = [P, P, i64, i32, i32, u64, P, ctypes.POINTER(i32)]
         L.cqref_wu_boxes.argtypes = [P, P, i64, i32, P, ctypes.POINTER(i32)]
+        L.cqref_den_quotas.argtypes = [P, i64, i32, P]
         L.cqref_sff_subset.argtypes = [i32, i64]
         L.cqref_sff_subset.restype = i64
         L.cqref_kmeans.argtypes = [P, P, i64, i32, P, i32, f64, i32, P, P, P, ctypes.POINTER(Stats)]
         L.cqref_map.argtypes = [P, i32, i32, i64, P, i32, P, P, ctypes.POINTER(u64)]
         L.cqref_quantize.argtypes = [P, i32, i32, i64, i32, i32, i32, u64, i32, f64, i32, P, P, P,
                                      ctypes.POINTER(Stats)]
-        for f in ("cqref_histogram", "cqref_init", "cqref_kmeans", "cqref_map", "cqref_quantize", "cqref_wu_boxes"):
+        for f in ("cqref_histogram", "cqref_init", "cqref_kmeans", "cqref_map", "cqref_quantize", "cqref_wu_boxes",
+                  "cqref_den_quotas"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -204,3 +207,11 @@ def wu_boxes(keys: np.ndarray, counts: np.ndarray, K: int) -> np.ndarray:
     _check("cqref_wu_boxes", lib().cqref_wu_boxes(_ptr(keys), _ptr(counts), len(keys), K, _ptr(boxes),
                                                   ctypes.byref(nb)))
     return boxes[: nb.value].copy()
+
+
+def den_quotas(keys: np.ndarray, K: int) -> np.ndarray:
+    """DEN's centres per cell (512 cells, (r >> 5) * 64 + (g >> 5) * 8 + (b >> 5))."""
+    keys = np.ascontiguousarray(keys, np.uint32)
+    quota = np.zeros(512, np.int32)
+    _check("cqref_den_quotas", lib().cqref_den_quotas(_ptr(keys), len(keys), K, _ptr(quota)))
+    return quota

@@ -512,6 +512,84 @@ static int init_lbg(const uint32_t* keys, const uint32_t* counts, int64_t n, int
     return rc;
 }
 
+/* DEN (Section 2.3, density-based; Al-Daoud and Roberts 1996).  The colour
+ * cube is cut uniformly into M = 8^3 cells (value >> 5 per channel, cell
+ * index (r >> 5) * 64 + (g >> 5) * 8 + (b >> 5)).  Cell c holding u_c of the
+ * n unique colours gets floor(K u_c / n) centres, and the K - (sum of those)
+ * centres left go one each to the cells of largest remainder (K u_c mod n),
+ * ties to the lower cell index; a quota never exceeds u_c.  Then, cell by cell
+ * in index order, the quota is drawn uniformly without replacement from the
+ * cell's colours in key order, as FGY draws (a partial Fisher-Yates shuffle,
+ * draw j uniform in [j, u_c)), all from the one splitmix64 stream; the centres
+ * follow in that order. */
+#define DEN_CELLS 512
+
+static int den_cell(uint32_t key)
+{
+    return (int)(((key >> 21) & 7u) * 64u + ((key >> 13) & 7u) * 8u + ((key >> 5) & 7u));
+}
+
+int cqref_den_quotas(const uint32_t* keys, int64_t n, int32_t K, int32_t* quota)
+{
+    if (!keys || !quota || n < 1 || K < 1 || K > 256 || K > n)
+        return CQREF_EINVAL;
+    int64_t u[DEN_CELLS] = {0};
+    for (int64_t i = 0; i < n; ++i)
+        ++u[den_cell(keys[i])];
+    int64_t rem[DEN_CELLS];
+    int32_t given = 0;
+    for (int c = 0; c < DEN_CELLS; ++c) {
+        quota[c] = (int32_t)(((int64_t)K * u[c]) / n);
+        rem[c] = ((int64_t)K * u[c]) % n;
+        given += quota[c];
+    }
+    for (int32_t left = K - given; left > 0; --left) {
+        int best = -1;
+        for (int c = 0; c < DEN_CELLS; ++c)
+            if (rem[c] > 0 && (best < 0 || rem[c] > rem[best]))
+                best = c;
+        ++quota[best];
+        rem[best] = 0;
+    }
+    return CQREF_OK;
+}
+
+static int init_den(const uint32_t* keys, int64_t n, int32_t K, uint64_t* rng, double* centers)
+{
+    int32_t quota[DEN_CELLS];
+    int rc = cqref_den_quotas(keys, n, K, quota);
+    if (rc)
+        return rc;
+    /* the colours of each cell in key order */
+    int64_t start[DEN_CELLS + 1] = {0};
+    for (int64_t i = 0; i < n; ++i)
+        ++start[den_cell(keys[i]) + 1];
+    for (int c = 0; c < DEN_CELLS; ++c)
+        start[c + 1] += start[c];
+    int64_t* order = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    if (!order)
+        return CQREF_ENOMEM;
+    int64_t fill[DEN_CELLS];
+    memcpy(fill, start, sizeof fill);
+    for (int64_t i = 0; i < n; ++i)
+        order[fill[den_cell(keys[i])]++] = i;
+    int32_t k = 0;
+    for (int c = 0; c < DEN_CELLS; ++c) {
+        int64_t* cell = order + start[c];
+        const int64_t uc = start[c + 1] - start[c];
+        for (int32_t j = 0; j < quota[c]; ++j) {
+            const int64_t r = j + (int64_t)cqref_uniform_below(rng, (uint64_t)(uc - j));
+            const int64_t t = cell[j];
+            cell[j] = cell[r];
+            cell[r] = t;
+            set_center_from_key(centers + 3 * k, keys[cell[j]]);
+            ++k;
+        }
+    }
+    free(order);
+    return CQREF_OK;
+}
+
 int cqref_wu_boxes(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K, int32_t* boxes,
                    int32_t* n_boxes)
 {
@@ -539,7 +617,7 @@ int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t 
 {
     if (!keys || !counts || !centers || n < 1 || K < 1 || K > 256)
         return CQREF_EINVAL;
-    if (scheme < CQREF_INIT_FORGY || scheme > CQREF_INIT_LBG)
+    if (scheme < CQREF_INIT_FORGY || scheme > CQREF_INIT_DEN)
         return CQREF_EINVAL;
     if (n <= K) {
         /* Fewer colours than palette entries: every colour is a centre. */
@@ -567,6 +645,8 @@ int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t 
         return init_wu(keys, counts, n, K, centers);
     if (scheme == CQREF_INIT_LBG)
         return init_lbg(keys, counts, n, K, centers);
+    if (scheme == CQREF_INIT_DEN)
+        return init_den(keys, n, K, &rng, centers);
     if (scheme == CQREF_INIT_FORGY) {
         int64_t* perm = (int64_t*)malloc((size_t)n * sizeof(int64_t));
         if (!perm)

@@ -21,7 +21,7 @@ extern "C" {
 enum { CQREF_OK = 0, CQREF_EINVAL = 1, CQREF_ECAPACITY = 2, CQREF_ENOMEM = 5 };
 enum { CQREF_INIT_FORGY = 0, CQREF_INIT_MAXMIN = 1, CQREF_INIT_KMEANSPP = 2, CQREF_INIT_USER = 3,
        CQREF_INIT_VAR = 4, CQREF_INIT_SFF = 5, CQREF_INIT_WU = 6,
-       CQREF_INIT_LBG = 7 };
+       CQREF_INIT_LBG = 7, CQREF_INIT_DEN = 8 };
 
 typedef struct {
     int32_t iters;      /* Lloyd iterations run                                  */
@@ -52,11 +52,15 @@ uint64_t cqref_uniform_below(uint64_t* s, uint64_t T);
 int cqref_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, int32_t subsample,
                     uint32_t* keys, uint32_t* counts, int64_t capacity, int64_t* n_unique);
 
-/* Initialization schemes of Section 2.3 (FGY, MMX, KPP, VAR, SFF, LBG) and Wu's
+/* Initialization schemes of Section 2.3 (FGY, MMX, KPP, VAR, SFF, LBG, DEN) and Wu's
  * greedy orthogonal bipartitioning (WU, the initializer of WSM-WU in Section
  * 3.3) on the unique colours. */
 int cqref_init(const uint32_t* keys, const uint32_t* counts, int64_t n, int32_t K,
                int32_t scheme, uint64_t seed, double* centers, int32_t* k_used);
+
+/* DEN's centres per cell (quota[512], cell (r >> 5) * 64 + (g >> 5) * 8 +
+ * (b >> 5)) for K <= n unique colours.  For tests. */
+int cqref_den_quotas(const uint32_t* keys, int64_t n, int32_t K, int32_t* quota);
 
 /* The boxes of WU's partition for K (boxes[6 k .. 6 k + 5] = lo_r, lo_g,
  * lo_b, hi_r, hi_g, hi_b over the 32 levels value >> 3, inclusive), in box

@@ -790,3 +790,71 @@ def test_lbg_split_of_a_single_colour_keeps_the_perturbed_centre():
     assert [231.0, 231.0, 231.0] in got.tolist()
     assert [230.0, 230.0, 230.0] in got.tolist()
     assert np.array_equal(got, _lbg_brute(ks, cs, 4))
+
+
+# ---------------------------------------------------------------- DEN (density-based)
+def _den_cell(k):
+    k = int(k)
+    return ((k >> 21) & 7) * 64 + ((k >> 13) & 7) * 8 + ((k >> 5) & 7)
+
+
+def _den_brute(keys, K, seed):
+    """DEN in plain Python: exact largest-remainder quotas over the 512 cells
+    (unique colours as the points), then per cell in index order a partial
+    Fisher-Yates over the cell's colours in key order."""
+    from fractions import Fraction
+
+    n = len(keys)
+    cells = [[] for _ in range(512)]
+    for k in keys:
+        cells[_den_cell(k)].append(int(k))
+    share = [Fraction(K * len(c), n) for c in cells]
+    quota = [int(s) for s in share]  # floor
+    left = K - sum(quota)
+    order = sorted(range(512), key=lambda c: (-(share[c] - quota[c]), c))
+    for c in order[:left]:
+        quota[c] += 1
+    st = _Stream(seed)
+    out = []
+    for c in range(512):
+        lst = list(cells[c])
+        for j in range(quota[c]):
+            r = j + st.below(len(lst) - j)
+            lst[j], lst[r] = lst[r], lst[j]
+            out.append([(lst[j] >> 16) & 255, (lst[j] >> 8) & 255, lst[j] & 255])
+    return np.array(out, np.float64), np.array(quota)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_den_matches_brute_force(seed):
+    rng = np.random.default_rng(200 + seed)
+    keys, counts = _rand_colours(rng, 700)
+    for K in (1, 7, 64, 256):
+        got, k_used = oracle.init(keys, counts, K, oracle.INIT_DEN, seed)
+        want, quota = _den_brute(keys, K, seed)
+        assert k_used == K
+        assert np.array_equal(oracle.den_quotas(keys, K), quota)
+        assert np.array_equal(got, want), K
+
+
+def test_den_quotas_follow_the_cell_populations():
+    # colours in three cells holding 60 %, 30 % and 10 % of them
+    rng = np.random.default_rng(5)
+    ks = []
+    for base, m in (((10, 10, 10), 60), ((200, 40, 40), 30), ((90, 220, 150), 10)):
+        while sum(1 for k in ks if _den_cell(k) == _den_cell((base[0] << 16) | (base[1] << 8) | base[2])) < m:
+            r, g, b = (int(v) for v in np.array(base) + rng.integers(0, 20, 3))
+            k = (r << 16) | (g << 8) | b
+            if k not in ks and _den_cell(k) == _den_cell((base[0] << 16) | (base[1] << 8) | base[2]):
+                ks.append(k)
+    keys = np.array(sorted(ks), np.uint32)
+    q = oracle.den_quotas(keys, 10)
+    assert sorted(q[q > 0].tolist()) == [1, 3, 6] and q.sum() == 10
+    # 7 centres: shares 4.2, 2.1, 0.7 -> floors 4, 2, 0 and the one left to the
+    # largest remainder (0.7)
+    q = oracle.den_quotas(keys, 7)
+    assert sorted(q[q > 0].tolist()) == [1, 2, 4]
+    cen, _ = oracle.init(keys, np.ones(len(keys), np.uint32), 7, oracle.INIT_DEN, 3)
+    assert len({tuple(c) for c in cen.tolist()}) == 7  # distinct colours
+    ckeys = [(int(r) << 16) | (int(g) << 8) | int(b) for r, g, b in cen]
+    assert all(k in set(keys.tolist()) for k in ckeys)
