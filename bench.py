@@ -184,9 +184,10 @@ def measure_init_schemes(cq, torch, imgs, dev, reps=3):
 
     kernels = {cq.INIT_FORGY: ["k_forgy"], cq.INIT_MAXMIN: ["k_init_coop"], cq.INIT_KMEANSPP: ["k_init_coop"],
                cq.INIT_VAR: ["k_var_tiles", "k_var_pick", "k_var_find"], cq.INIT_SFF: ["k_sff"],
-               cq.INIT_WU: ["k_wu_clear", "k_wu_accum", "k_wu_prefix", "k_wu_split"], cq.INIT_LBG: None}
+               cq.INIT_WU: ["k_wu_clear", "k_wu_accum", "k_wu_prefix", "k_wu_split"], cq.INIT_LBG: None,
+               cq.INIT_DEN: ["k_den_tiles", "k_den_pick", "k_den_find"]}
     names = {cq.INIT_FORGY: "FGY", cq.INIT_MAXMIN: "MMX", cq.INIT_KMEANSPP: "KPP", cq.INIT_VAR: "VAR",
-             cq.INIT_SFF: "SFF", cq.INIT_WU: "WU", cq.INIT_LBG: "LBG"}
+             cq.INIT_SFF: "SFF", cq.INIT_WU: "WU", cq.INIT_LBG: "LBG", cq.INIT_DEN: "DEN"}
     out = {}
     for scheme, kern in kernels.items():
         jobs = [cq.BatchJob(img, K, scheme, SEEDS[i], MAX_ITERS, TOL, True) for i, img in enumerate(imgs)]

@@ -55,7 +55,8 @@ typedef enum {
     CQ_INIT_VAR = 4,       /* maximum variance: medians along the widest channel    */
     CQ_INIT_SFF = 5,       /* farthest first on a random subset (SFF)              */
     CQ_INIT_WU = 6,        /* Wu's greedy orthogonal bipartitioning (WU)           */
-    CQ_INIT_LBG = 7        /* splitting from the centroid, refined by k-means (LBG) */
+    CQ_INIT_LBG = 7,       /* splitting from the centroid, refined by k-means (LBG) */
+    CQ_INIT_DEN = 8        /* centres per uniform cell by its share of colours (DEN) */
 } cq_init_t;
 
 /* Run statistics (host structure). */
@@ -135,7 +136,12 @@ cq_status cq_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t row_st
  * at index m + j (a last partial stage splits the first K - m), each stage
  * refined by weighted Lloyd iterations with the stopping rule of Section 3.3
  * at the paper's threshold 0.001 (at most 100 iterations); it synchronizes
- * `stream` once per stage.  With CQ_INIT_USER the centres are left as
+ * `stream` once per stage.  DEN cuts the cube into 512 cells (value >> 5 per
+ * channel, cell (r >> 5) * 64 + (g >> 5) * 8 + (b >> 5)); cell c with u_c of
+ * the N' colours gets floor(K u_c / N') centres and the rest go one each to
+ * the cells of largest remainder K u_c mod N' (ties to the lower cell); cell
+ * by cell the quota is drawn as FGY draws from the cell's colours in key
+ * order, on the one stream.  With CQ_INIT_USER the centres are left as
  * given.  Synchronizes only if k_used is
  * non-null; a device-side failure of the initialization is reported by that
  * synchronization or by the next synchronizing call on the workspace. */

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcq.so")
 
 CQ_OK, CQ_EINVAL, CQ_ECAPACITY, CQ_EWORKSPACE, CQ_EDEVICE = 0, 1, 2, 3, 4
-INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF, INIT_WU, INIT_LBG = 0, 1, 2, 3, 4, 5, 6, 7
+(INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF, INIT_WU, INIT_LBG,
+ INIT_DEN) = 0, 1, 2, 3, 4, 5, 6, 7, 8
 EXPORTS = ("cq_workspace_bytes", "cq_workspace_prepare", "cq_histogram", "cq_pixel_keys", "cq_init", "cq_kmeans",
            "cq_map", "cq_quantize", "cq_batch_workspace_bytes", "cq_batch_workspace_prepare",
            "cq_quantize_batch", "cq_engine_job_bytes", "cq_engine_workspace_bytes", "cq_engine_create",

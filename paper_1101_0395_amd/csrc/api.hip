@@ -357,6 +357,9 @@ cq_status run_init(Batch& b)
     auto var_job = [&](int j) { return b.h[j].scheme == CQ_INIT_VAR && b.h[j].n > b.h[j].K; };
     const int var_tiles = b.set_map(kMapVarTiles, [&](int j) { return var_job(j) ? var_tile_count(b.h[j].n) : 0; });
     const int var_groups = b.set_map(kMapVarGroups, [&](int j) { return var_job(j) ? b.h[j].K : 0; });
+    auto den_job = [&](int j) { return b.h[j].scheme == CQ_INIT_DEN && b.h[j].n > b.h[j].K; };
+    const int den_tiles = b.set_map(kMapDenTiles, [&](int j) { return den_job(j) ? den_tile_count(b.h[j].n) : 0; });
+    const int den_centres = b.set_map(kMapDenCentres, [&](int j) { return den_job(j) ? b.h[j].K : 0; });
     const int wu_blocks = b.set_map(kMapWu, [&](int j) {
         const JobDev& J = b.h[j];
         return J.scheme == CQ_INIT_WU && J.n > J.K ? wu_accum_blocks(J.n) : 0;
@@ -370,6 +373,7 @@ cq_status run_init(Batch& b)
     if (var_tiles > 0) CQ_TRY(launch_var(b.d_jobs(), b.d_maps(), b.B, var_tiles, var_groups, b.s));
     if (any_sff) CQ_TRY(launch_sff(b.d_jobs(), b.B, b.s));
     if (wu_blocks > 0) CQ_TRY(launch_wu(b.d_jobs(), b.d_maps(), b.B, wu_blocks, b.s));
+    if (den_tiles > 0) CQ_TRY(launch_den(b.d_jobs(), b.d_maps(), b.B, den_tiles, den_centres, b.s));
     int next = 0;
     while (true) {
         while (next < b.B && want[next] == 0) ++next;
@@ -576,8 +580,8 @@ cq_status check_job(const cq_job& j, int idx)
     if (s == CQ_OK) s = check_subsample(j.subsample);
     if (s == CQ_OK) s = check_k(j.K);
     if (s == CQ_OK && !j.palette) s = einval("palette is null");
-    if (s == CQ_OK && (int(j.scheme) < CQ_INIT_FORGY || int(j.scheme) > CQ_INIT_LBG || j.scheme == CQ_INIT_USER))
-        s = einval("scheme must be FORGY, MAXMIN, KMEANSPP, VAR, SFF, WU or LBG");
+    if (s == CQ_OK && (int(j.scheme) < CQ_INIT_FORGY || int(j.scheme) > CQ_INIT_DEN || j.scheme == CQ_INIT_USER))
+        s = einval("scheme must be FORGY, MAXMIN, KMEANSPP, VAR, SFF, WU, LBG or DEN");
     if (s == CQ_OK) s = check_iters_tol(j.max_iters, j.tol);
     if (s != CQ_OK) {
         char msg[512];
@@ -657,7 +661,7 @@ cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique
     CQ_TRY(check_k(K));
     if (!keys || !counts || !centers) return einval("keys/counts/centers is null");
     if (n_unique < 1 || n_unique > kMaxPixels) return einval("n_unique = %lld out of range", (long long)n_unique);
-    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_LBG) return einval("unknown init scheme %d", int(scheme));
+    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_DEN) return einval("unknown init scheme %d", int(scheme));
     const Layout L = make_layout(0, n_unique, false);
     CQ_TRY(check_ws(ws, ws_bytes, L.total));
     Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
@@ -763,8 +767,8 @@ cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stri
     CQ_TRY(check_subsample(subsample));
     CQ_TRY(check_k(K));
     if (!palette) return einval("palette is null");
-    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_LBG || scheme == CQ_INIT_USER)
-        return einval("cq_quantize needs scheme FORGY, MAXMIN, KMEANSPP, VAR, SFF, WU or LBG");
+    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_DEN || scheme == CQ_INIT_USER)
+        return einval("cq_quantize needs scheme FORGY, MAXMIN, KMEANSPP, VAR, SFF, WU, LBG or DEN");
     CQ_TRY(check_iters_tol(max_iters, tol));
     const int64_t npix = int64_t(H) * W;
     const Layout L = make_layout(npix, npix, true);

@@ -65,6 +65,8 @@ int var_tile_count(int64_t n);
 int wu_accum_blocks(int64_t n);
 cq_status launch_wu(const JobDev* jobs, const int* maps, int B, int accum_blocks, hipStream_t s);
 cq_status launch_lbg_stage(const JobDev* jobs, int B, hipStream_t s);
+int den_tile_count(int64_t n);
+cq_status launch_den(const JobDev* jobs, const int* maps, int B, int tiles, int centres, hipStream_t s);
 cq_status launch_sff(const JobDev* jobs, int B, hipStream_t s);
 int64_t sff_subset(int32_t K, int64_t n);
 cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, bool lds, hipStream_t s);

@@ -240,6 +240,8 @@ enum MapId {
     kMapVarTiles,    // VAR: colour tiles
     kMapVarGroups,   // VAR: one block per centre
     kMapWu,          // WU: blocks of colours
+    kMapDenTiles,    // DEN: colour tiles
+    kMapDenCentres,  // DEN: one block per centre
     kNumMaps
 };
 

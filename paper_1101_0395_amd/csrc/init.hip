@@ -852,6 +852,178 @@ cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s)
     return CQ_OK;
 }
 
+// ------------------------------------------------------------------ DEN
+// DEN (Section 2.3, density-based): the colour cube in 512 uniform cells
+// (value >> 5 per channel); cell c with u_c of the N' colours gets
+// floor(K u_c / N') centres and the K - (their sum) left over go one each to
+// the cells of largest remainder K u_c mod N' (ties to the lower cell); per
+// cell in index order the quota is drawn without replacement from the cell's
+// colours in key order, as FGY draws, all from the one splitmix64 stream.
+//   k_den_tiles  per tile of kDenTile key-ordered colours: its colours per
+//                cell, into a tile x cell matrix;
+//   k_den_pick   per job, one thread per cell: the matrix column turned into
+//                the exclusive prefix over the tiles, the quotas; then one
+//                thread takes the K draws in order, the Fisher-Yates swaps of
+//                a cell kept in LDS as (position, value) pairs, and records
+//                (cell, position in the cell) per centre;
+//   k_den_find   per centre: the tile holding that position (binary search on
+//                the prefixes) and the colour in it (a block scan).
+constexpr int kDenCells = 512;
+constexpr int kDenTile = 1024;
+
+__host__ __device__ __forceinline__ int64_t den_tiles(int64_t n) { return (n + kDenTile - 1) / kDenTile; }
+
+__device__ __forceinline__ uint32_t* den_matrix(const JobDev& J) { return gp(J.d2); }
+
+__device__ __forceinline__ int den_cell(uint32_t key)
+{
+    return int(((key >> 21) & 7u) * 64u + ((key >> 13) & 7u) * 8u + ((key >> 5) & 7u));
+}
+
+__global__ void __launch_bounds__(kDenCells) k_den_tiles(const JobDev* __restrict__ jobs,
+                                                         const int* __restrict__ map, int B)
+{
+    __shared__ uint32_t cnt[kDenCells];
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int64_t t = blockIdx.x - map[jb];
+    cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int k = threadIdx.x; k < kDenTile; k += kDenCells) {
+        const int64_t i = t * kDenTile + k;
+        if (i < J.n) atomicAdd(&cnt[den_cell(gp(J.keys)[i])], 1u);
+    }
+    __syncthreads();
+    den_matrix(J)[t * kDenCells + threadIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kDenCells) k_den_pick(const JobDev* __restrict__ jobs)
+{
+    __shared__ uint64_t s_rem[kDenCells];
+    __shared__ uint32_t s_u[kDenCells], s_q[kDenCells];
+    __shared__ uint32_t s_pos[2 * kMaxK], s_val[2 * kMaxK];
+    __shared__ uint32_t tmp[64];
+    const JobDev& J = jobs[blockIdx.x];
+    if (J.scheme != CQ_INIT_DEN || J.n <= J.K) return;
+    const int c = threadIdx.x;
+    const int64_t T = den_tiles(J.n);
+    uint32_t* __restrict__ h = den_matrix(J);
+    uint32_t u = 0;
+    constexpr int kBatch = 16;  // loads issued before the stores of a batch
+    for (int64_t t0 = 0; t0 < T; t0 += kBatch) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int e = 0; e < kBatch; ++e) v[e] = t0 + e < T ? h[(t0 + e) * kDenCells + c] : 0u;
+#pragma unroll
+        for (int e = 0; e < kBatch; ++e) {
+            if (t0 + e < T) h[(t0 + e) * kDenCells + c] = u;
+            u += v[e];
+        }
+    }
+    const uint64_t n = uint64_t(J.n);
+    const uint64_t share = uint64_t(J.K) * u;
+    uint32_t q = uint32_t(share / n);
+    const uint64_t rem = share - uint64_t(q) * n;
+    s_rem[c] = rem;
+    uint32_t given = 0;
+    block_exclusive_scan<uint32_t>(q, tmp, &given);  // also orders the s_rem stores before the reads
+    const uint32_t left = uint32_t(J.K) - given;
+    if (rem > 0) {
+        uint32_t rank = 0;
+        for (int d = 0; d < kDenCells; ++d) {
+            const uint64_t o = s_rem[d];
+            rank += (o > rem || (o == rem && d < c)) ? 1u : 0u;
+        }
+        if (rank < left) ++q;
+    }
+    s_q[c] = q;
+    s_u[c] = u;
+    __syncthreads();
+    if (c != 0) return;
+    uint64_t st = J.seed;
+    uint64_t* __restrict__ sel = gp(J.vals);
+    int slot = 0;
+    for (int cell = 0; cell < kDenCells; ++cell) {
+        const uint32_t qc = s_q[cell], uc = s_u[cell];
+        int len = 0;  // displaced positions of this cell so far
+        for (uint32_t j = 0; j < qc; ++j) {
+            const uint32_t r = j + uint32_t(uniform_below(st, uint64_t(uc - j)));
+            uint32_t a = j, b = r;
+            int ia = -1, ib = -1;
+            for (int e = 0; e < len; ++e) {
+                if (s_pos[e] == j) {
+                    a = s_val[e];
+                    ia = e;
+                }
+                if (s_pos[e] == r) {
+                    b = s_val[e];
+                    ib = e;
+                }
+            }
+            // position j takes the value at r, and r the value at j
+            if (ia < 0) {
+                ia = len++;
+                s_pos[ia] = j;
+            }
+            s_val[ia] = b;
+            if (r != j) {
+                if (ib < 0) {
+                    ib = len++;
+                    s_pos[ib] = r;
+                }
+                s_val[ib] = a;
+            }
+            sel[slot++] = (uint64_t(cell) << 32) | b;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kDenTile) k_den_find(const JobDev* __restrict__ jobs, const int* __restrict__ map,
+                                                       int B)
+{
+    __shared__ uint32_t tmp[64];
+    __shared__ int64_t s_tile;
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int g = blockIdx.x - map[jb];
+    const uint64_t target = gp(J.vals)[g];
+    const int cell = int(target >> 32);
+    const uint32_t pos = uint32_t(target);
+    const uint32_t* __restrict__ h = den_matrix(J);
+    if (threadIdx.x == 0) {
+        // the last tile whose prefix for the cell is at most pos holds it
+        int64_t lo = 0, hi = den_tiles(J.n);
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (h[mid * kDenCells + cell] <= pos) lo = mid; else hi = mid;
+        }
+        s_tile = lo;
+    }
+    __syncthreads();
+    const int64_t t = s_tile;
+    const uint32_t off = pos - h[t * kDenCells + cell];
+    const int64_t i = t * kDenTile + threadIdx.x;
+    uint32_t key = 0, f = 0;
+    if (i < J.n) {
+        key = gp(J.keys)[i];
+        f = den_cell(key) == cell ? 1u : 0u;
+    }
+    const uint32_t ex = block_exclusive_scan<uint32_t>(f, tmp, nullptr);
+    if (f && ex == off) write_center(gp(J.centers), g, key);
+}
+
+int den_tile_count(int64_t n) { return int(den_tiles(n)); }
+
+cq_status launch_den(const JobDev* jobs, const int* maps, int B, int tiles, int centres, hipStream_t s)
+{
+    CQ_TIMED_LAUNCH("k_den_tiles", s,
+                    k_den_tiles<<<tiles, kDenCells, 0, s>>>(jobs, maps + kMapDenTiles * (B + 1), B));
+    CQ_TIMED_LAUNCH("k_den_pick", s, k_den_pick<<<B, kDenCells, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_den_find", s,
+                    k_den_find<<<centres, kDenTile, 0, s>>>(jobs, maps + kMapDenCentres * (B + 1), B));
+    return CQ_OK;
+}
+
 // LBG stage of each job of a batch (one block per job): with init_C = 0 the
 // single centre is set to zero (the start of the iteration that yields the
 // centroid); otherwise the first K - init_C of the init_C centres are split,

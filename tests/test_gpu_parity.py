@@ -98,7 +98,7 @@ def _hist_pair(img, cqm, dev, ws):
 
 
 @pytest.mark.parametrize("scheme", [oracle.INIT_FORGY, oracle.INIT_MAXMIN, oracle.INIT_KMEANSPP, oracle.INIT_VAR,
-                                    oracle.INIT_SFF, oracle.INIT_WU, oracle.INIT_LBG])
+                                    oracle.INIT_SFF, oracle.INIT_WU, oracle.INIT_LBG, oracle.INIT_DEN])
 @pytest.mark.parametrize("K,seed", [(16, 0), (64, 3), (256, 1)])
 def test_init_parity(cqm, dev, ws_small, scheme, K, seed):
     _say(f"init scheme={scheme} K={K} seed={seed}")
