@@ -299,6 +299,30 @@ def measure_km_vs_wsm(cq, torch, imgs, dev, Ks=(32, 64, 128, 256), iters=20):
     return out
 
 
+def measure_k_sweep(cq, torch, imgs, dev, iters=20):
+    """WSM time against K = 2..256 (the figure of Section 3.2) in the setting
+    of the comparison table: FGY centres, at most 20 iterations (tol 0),
+    sort-means; the whole quantization (histogram to pixel map) per image, mean
+    over the eight stand-ins."""
+    ws = cq.Workspace(H, W, 256, dev)
+    pal = torch.zeros((256, 3), dtype=torch.uint8, device=dev)
+    oidx = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    orgb = torch.empty((H, W, 3), dtype=torch.uint8, device=dev)
+    ms = []
+    for k in range(2, 257):
+        cq.cq_quantize(imgs[0], k, cq.INIT_FORGY, 1, iters, 0.0, True, ws, palette=pal[:k], out_idx=oidx,
+                       out_rgb=orgb)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, img in enumerate(imgs):
+            cq.cq_quantize(img, k, cq.INIT_FORGY, SEEDS[i], iters, 0.0, True, ws, palette=pal[:k], out_idx=oidx,
+                           out_rgb=orgb)
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0) / len(imgs))
+    at = {k: ms[k - 2] for k in (2, 16, 32, 64, 128, 256)}
+    return {"ms_per_image_at": at, "ratio_256_over_16": at[256] / at[16], "ms_per_image_k2_to_256": ms}
+
+
 def recorded_traffic():
     """HBM bytes per launch of the sort-means pass from the committed counter
     summary, if it was measured on the kernel source as it is now; else None."""
@@ -327,6 +351,7 @@ def parse():
     ap.add_argument("--no-init-schemes", action="store_true", help="skip the per-initialization figures")
     ap.add_argument("--no-subsample", action="store_true", help="skip the 2:1 subsampling figures")
     ap.add_argument("--no-km-vs-wsm", action="store_true", help="skip the KM against WSM comparison")
+    ap.add_argument("--no-k-sweep", action="store_true", help="skip the WSM time against K = 2..256")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="finish with plain device-to-device copies of this many MiB (a known-size kernel "
                          "for scaling memory counters)")
@@ -460,6 +485,8 @@ def main():
         line["subsample_8x512"] = measure_subsample(cq, torch, imgs, dev)
     if not args.no_km_vs_wsm:
         line["km_vs_wsm_8x512"] = measure_km_vs_wsm(cq, torch, imgs, dev)
+    if not args.no_k_sweep:
+        line["wsm_time_vs_k_8x512"] = measure_k_sweep(cq, torch, imgs, dev)
 
     if not args.no_cpu_baseline:
         import oracle
