@@ -195,6 +195,39 @@ __device__ __forceinline__ bool near_tie(const Best& v)
 
 // Full search over the centres for one colour per lane.  All lanes walk the
 // same centre index, so every centre load has one address per wave.
+// The same search when every centre is an integer colour (after an
+// initialization that picks colours, before the first update): then each
+// FP64 distance above is an exact integer, and so is
+// |x - c|^2 = |x|^2 - (2 x.c - |c|^2).  Centre k is stored with
+// (255 - k) - (|c|^2 << 8), so a colour's value for it, (x.c << 9) plus that,
+// is ((2 x.c - |c|^2) << 8) | (255 - k) (x.c one four-byte dot product of the
+// colours packed in key order): the largest value is the nearest centre,
+// lowest index on ties, and the second largest gives the second smallest
+// distance, as the FP64 search counts it (an equal distance included).  `ent`
+// holds (packed centre, stored value) for the K centres, padded to an even
+// count with values too small to matter for K >= 2.
+__device__ __forceinline__ Best full_search_int(uint32_t x, const uint2* __restrict__ ent, int K)
+{
+    int b1 = -0x7fffffff - 1, b2 = -0x7fffffff - 1;
+    const int K2 = (K + 1) & ~1;
+#pragma unroll 4
+    for (int k = 0; k < K2; k += 2) {
+        const uint4 e = *reinterpret_cast<const uint4*>(ent + k);
+        const int v0 = int((__builtin_amdgcn_udot4(x, e.x, 0u, false) << 9) + e.y);
+        const int v1 = int((__builtin_amdgcn_udot4(x, e.z, 0u, false) << 9) + e.w);
+        b2 = max(b2, min(b1, v0));
+        b1 = max(b1, v0);
+        b2 = max(b2, min(b1, v1));
+        b1 = max(b1, v1);
+    }
+    const int xx = int(__builtin_amdgcn_udot4(x, x, 0u, false));
+    Best v;
+    v.bd = double(xx - (b1 >> 8));
+    v.second = K >= 2 ? double(xx - (b2 >> 8)) : __builtin_inf();
+    v.best = 255 - (b1 & 255);
+    return v;
+}
+
 __device__ __forceinline__ Best full_search(double x0, double x1, double x2,
                                             const double* __restrict__ centers, int K)
 {
@@ -248,6 +281,8 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
     __shared__ uint32_t ccount[kMaxK * kBuckets / 2];
     __shared__ unsigned long long red[2 * (kAssignThreads / 64)];
     __shared__ int s_slice;  // sort-means passes: the block's next slice of 64 colours
+    // full searches with integer centres: (packed centre, stored value)
+    __shared__ __align__(16) uint2 s_ent[kSortMeans ? 2 : kMaxK];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
@@ -276,6 +311,26 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
         const uint32_t* __restrict__ keys = gp(J.keys);
         const uint32_t* __restrict__ counts = gp(J.counts);
         uint8_t* __restrict__ assign = gp(J.assign);
+        // integer centres: the integer search (same results, fewer instructions)
+        bool whole = true;
+        for (int t = threadIdx.x; t < 3 * K; t += blockDim.x) {
+            const double c = centers[t];
+            whole = whole && c >= 0.0 && c <= 255.0 && c == __builtin_trunc(c);
+        }
+        const bool integral = __syncthreads_and(whole ? 1 : 0) != 0;
+        if (integral) {
+            for (int t = threadIdx.x; t < kMaxK; t += blockDim.x) {
+                uint32_t packed = 0;
+                int pp = 0x3fffff;
+                if (t < K) {
+                    const int r = int(centers[3 * t]), g = int(centers[3 * t + 1]), b = int(centers[3 * t + 2]);
+                    packed = (uint32_t(r) << 16) | (uint32_t(g) << 8) | uint32_t(b);
+                    pp = r * r + g * g + b * b;
+                }
+                s_ent[t] = make_uint2(packed, uint32_t((255 - t) - (pp << 8)));
+            }
+            __syncthreads();
+        }
         for (int64_t base = lo; base < hi; base += blockDim.x) {
             const int64_t i = base + threadIdx.x;
             const bool valid = i < hi;
@@ -283,7 +338,8 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
             const uint32_t w = valid ? counts[i] : 0u;
             int r, g, b;
             key_rgb(key, r, g, b);
-            const Best v = full_search(double(r), double(g), double(b), centers, K);
+            const Best v = integral ? full_search_int(key, s_ent, K)
+                                    : full_search(double(r), double(g), double(b), centers, K);
             if (valid) {
                 ndc += unsigned(K);
                 ties += near_tie(v) ? 1 : 0;
