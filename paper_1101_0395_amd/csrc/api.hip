@@ -328,7 +328,7 @@ static cq_status run_lbg(Batch& b)
         }
         CQ_TRY(upload(st));
         CQ_TRY(launch_lbg_stage(st.d_jobs(), st.B, st.s));
-        CQ_TRY(run_kmeans(st));
+        CQ_TRY(run_kmeans(st, false));
         CQ_TRY(check_kmeans(st));
         for (auto& v : st.staged) b.staged.push_back(std::move(v));
     }
@@ -416,7 +416,7 @@ cq_status run_init(Batch& b)
 // Iterations of every job until all have stopped.  Iterations are enqueued
 // in groups; a stopped job's blocks return at once, so one readback per group
 // suffices.
-cq_status run_kmeans(Batch& b)
+cq_status run_kmeans(Batch& b, bool memberships)
 {
     // every job iterates in step with the launches, so the host knows which
     // iterations regroup (the same rule as on the device)
@@ -463,9 +463,11 @@ cq_status run_kmeans(Batch& b)
         if (all_done) break;
     }
     if (!all_done) CQ_TRY(collect(b));  // the state after the last group
+    // the memberships in key order, for callers that return them (a pruned
+    // run holds them in its regrouped records until now)
     bool grouped = false;
     for (const JobDev& J : b.h) grouped = grouped || (J.prune && J.n > J.K);
-    if (grouped) CQ_TRY(launch_unpermute(b.d_jobs(), b.d_maps(), b.B, assign_total, b.s));
+    if (memberships && grouped) CQ_TRY(launch_unpermute(b.d_jobs(), b.d_maps(), b.B, assign_total, b.s));
     return CQ_OK;
 }
 
@@ -535,7 +537,7 @@ static cq_status run_quantize(Batch& b, cq_stats* stats)
     for (int j = 0; j < b.B; ++j) n[j] = b.res[j].n_unique;
     set_counts(b, n);
     CQ_TRY(run_init(b));
-    CQ_TRY(run_kmeans(b));
+    CQ_TRY(run_kmeans(b, false));
     CQ_TRY(check_init(b));
     CQ_TRY(check_kmeans(b));
     CQ_TRY(launch_palette(b.d_jobs(), b.B, b.s));
@@ -710,7 +712,7 @@ cq_status cq_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n_uniq
     J.tol = tol;
     J.prune = prune ? 1 : 0;
     set_counts(b, {n_unique});
-    CQ_TRY(run_kmeans(b));
+    CQ_TRY(run_kmeans(b, true));
     CQ_TRY(check_kmeans(b));
     if (palette) CQ_TRY(launch_palette(b.d_jobs(), 1, b.s));
     const JobResult r = b.res[0];

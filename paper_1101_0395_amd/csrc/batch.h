@@ -100,7 +100,7 @@ cq_status read_results(Batch& b, int slot, hipEvent_t done);
 cq_status run_histogram(Batch& b);
 void set_counts(Batch& b, const std::vector<int64_t>& n);
 cq_status run_init(Batch& b);
-cq_status run_kmeans(Batch& b);
+cq_status run_kmeans(Batch& b, bool memberships);
 cq_status run_map(Batch& b, bool with_err);
 cq_status check_init(const Batch& b);
 cq_status check_kmeans(const Batch& b);

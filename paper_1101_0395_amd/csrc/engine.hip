@@ -143,17 +143,8 @@ static cq_status engine_finish(cq_engine* e, const Batch& d, cq_engine_done* don
     *n_done = 0;
     if (fin.empty()) return CQ_OK;
     Batch f(int(fin.size()), e->desc, e->s);
-    bool grouped = false;
-    for (int i = 0; i < f.B; ++i) {
-        f.h[i] = e->active[fin[i]].dev;
-        grouped = grouped || (f.h[i].prune && f.h[i].n > f.h[i].K);
-    }
-    const int assign_total = f.set_map(kMapAssign, [&](int i) {
-        const JobDev& J = f.h[i];
-        return J.n <= J.K ? 0 : int((J.n + J.chunk - 1) / J.chunk);
-    });
+    for (int i = 0; i < f.B; ++i) f.h[i] = e->active[fin[i]].dev;
     CQ_TRY(upload(f));
-    if (grouped) CQ_TRY(launch_unpermute(f.d_jobs(), f.d_maps(), f.B, assign_total, f.s));
     CQ_TRY(launch_palette(f.d_jobs(), f.B, f.s));
     CQ_TRY(run_map(f, true));
     CQ_TRY(collect(f));

@@ -16,7 +16,8 @@
 //                    its 8192 keys in LDS, then the non-zero ones compacted in
 //                    ascending order in place;
 //   k_hist_ustarts   per job: the first output entry of every bucket and N';
-//   k_hist_emit      per bucket: the bucket's (key, count) pairs from there.
+//   k_hist_emit      per bucket (one wave each): the bucket's (key, count)
+//                    pairs from there.
 // Every launch covers all jobs of a batch.
 #include "cq_internal.h"
 
@@ -207,22 +208,29 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __res
     __shared__ uint32_t c[kHistLow];
     __shared__ uint32_t touched[kGroups / 32];
     __shared__ uint32_t tmp[64];
+    __shared__ uint32_t s_total[kHistBuckets / 256], s_start[kHistBuckets / 256];  // this block's buckets
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int cb0 = blockIdx.x - map[jb];
-    const int kCountBlocks = map[jb + 1] - map[jb];
+    const int kCountBlocks = map[jb + 1] - map[jb];  // at least 256
     for (int t = threadIdx.x; t < kHistLow; t += kHistThreads) c[t] = 0u;
     if (threadIdx.x < kGroups / 32) touched[threadIdx.x] = 0u;
+    // every bucket's pixel count and first slot at once, not one bucket after another
+    if (threadIdx.x < kHistBuckets / 256) {
+        const int b = cb0 + threadIdx.x * kCountBlocks;
+        s_total[threadIdx.x] = b < kHistBuckets ? gp(J.hbt)[b] : 0u;
+        s_start[threadIdx.x] = b < kHistBuckets ? gp(J.hbs)[b] : 0u;
+    }
     __syncthreads();
     constexpr int R = kHistLow / kHistThreads;  // 16 counters per thread in the compaction
     constexpr int kUnroll = 8;
-    for (int b = cb0; b < kHistBuckets; b += kCountBlocks) {
-        const uint32_t total = gp(J.hbt)[b];
+    for (int b = cb0, q = 0; b < kHistBuckets; b += kCountBlocks, ++q) {
+        const uint32_t total = s_total[q];
         if (total == 0) {
             if (threadIdx.x == 0) gp(J.hnu)[b] = 0u;
             continue;
         }
-        const uint32_t start = gp(J.hbs)[b];
+        const uint32_t start = s_start[q];
         uint16_t* __restrict__ hk = gp(J.hkeys) + start;
         uint32_t* __restrict__ hc = gp(J.hcnt) + start;
         // eight keys in flight per thread before their LDS atomics
@@ -272,10 +280,15 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __res
 
 // One block per (job, bucket): the bucket's pairs into keys / counts at the
 // prefix of the unique counts; entries past `capacity` are not written.
+// One wave per bucket, kHistThreads / 64 buckets per block.
+constexpr int kEmitPerBlock = kHistThreads / 64;
+
 __global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __restrict__ jobs)
 {
-    const JobDev& J = jobs[blockIdx.x / kHistBuckets];
-    const int b = blockIdx.x % kHistBuckets;
+    constexpr int kBlocksPerJob = kHistBuckets / kEmitPerBlock;
+    const JobDev& J = jobs[blockIdx.x / kBlocksPerJob];
+    const int b = (blockIdx.x % kBlocksPerJob) * kEmitPerBlock + int(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const uint32_t nb = gp(J.hnu)[b];
     if (nb == 0) return;
     const uint32_t start = gp(J.hbs)[b];
@@ -286,17 +299,17 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __rest
     uint32_t* __restrict__ counts = gp(J.counts);
     const int64_t capacity = J.capacity;
     constexpr int kUnroll = 4;
-    for (uint32_t j0 = 0; j0 < nb; j0 += kUnroll * kHistThreads) {
+    for (uint32_t j0 = 0; j0 < nb; j0 += kUnroll * 64) {
         uint32_t kq[kUnroll], cq[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const uint32_t j = j0 + u * kHistThreads + threadIdx.x;
+            const uint32_t j = j0 + u * 64 + lane;
             kq[u] = j < nb ? uint32_t(hk[j]) : 0u;
             cq[u] = j < nb ? hc[j] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const uint32_t j = j0 + u * kHistThreads + threadIdx.x;
+            const uint32_t j = j0 + u * 64 + lane;
             const int64_t o = out + j;
             if (j < nb && o < capacity) {
                 keys[o] = (uint32_t(b) << kHistLowBits) | kq[u];
@@ -354,7 +367,7 @@ cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total
     CQ_TIMED_LAUNCH("k_hist_scatter", s, k_hist_scatter<<<total_tiles, kHistThreads, 0, s>>>(jobs, tmap, B));
     CQ_TIMED_LAUNCH("k_hist_count", s, k_hist_count<<<total_count, kHistThreads, 0, s>>>(jobs, cmap, B));
     CQ_TIMED_LAUNCH("k_hist_ustarts", s, k_hist_ustarts<<<B, kHistThreads, 0, s>>>(jobs));
-    CQ_TIMED_LAUNCH("k_hist_emit", s, k_hist_emit<<<kHistBuckets * B, kHistThreads, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_hist_emit", s, k_hist_emit<<<kHistBuckets / kEmitPerBlock * B, kHistThreads, 0, s>>>(jobs));
     return CQ_OK;
 }
 
