@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __rest
     uint32_t* __restrict__ keys = gp(J.keys);
     uint32_t* __restrict__ counts = gp(J.counts);
     const int64_t capacity = J.capacity;
-    constexpr int kUnroll = 4;
+    constexpr int kUnroll = 16;  // loads in flight per lane (a bucket of a large image holds thousands)
     for (uint32_t j0 = 0; j0 < nb; j0 += kUnroll * 64) {
         uint32_t kq[kUnroll], cq[kUnroll];
 #pragma unroll
