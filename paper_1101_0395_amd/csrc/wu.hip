@@ -21,8 +21,8 @@
 //   k_wu_clear    the job's table of 5 x 33^3 uint64 (a zero border at index
 //                 0 of each axis, cell c at index c + 1) cleared;
 //   k_wu_accum    per block of colours: each colour's count, sums and s2 added
-//                 to its cell;
-//   k_wu_prefix   per job, one block: cumulative sums along b, then g, then r,
+//                 to its cell (summed over runs of one cell in a wave first);
+//   k_wu_prefix   three launches: cumulative sums along b, then g, then r,
 //                 so that entry (r, g, b) holds the statistics of the cells
 //                 below it on every axis and a box's statistics are an
 //                 8-corner inclusion-exclusion;
@@ -40,7 +40,6 @@ constexpr int kWuClearThreads = 256;
 constexpr int kWuClearBlocks = (kWuStats * kWuPlane + kWuClearThreads * 16 - 1) / (kWuClearThreads * 16);
 constexpr int kWuAccumThreads = 256;
 constexpr int kWuColoursPerBlock = 4096;
-constexpr int kWuPrefixThreads = 1024;
 
 static_assert(sizeof(uint64_t) * kWuStats * kWuPlane <= kWuTableBytes, "WU table region");
 
@@ -72,46 +71,65 @@ __global__ void __launch_bounds__(kWuAccumThreads) k_wu_accum(const JobDev* __re
     const uint32_t* __restrict__ keys = gp(J.keys);
     const uint32_t* __restrict__ counts = gp(J.counts);
     unsigned long long* __restrict__ t = reinterpret_cast<unsigned long long*>(wu_table(J));
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kWuAccumThreads) {
-        int r, g, b;
-        key_rgb(keys[i], r, g, b);
-        const uint64_t w = counts[i];
-        const int c = wu_at((r >> 3) + 1, (g >> 3) + 1, (b >> 3) + 1);
-        atomicAdd(t + c, (unsigned long long)w);
-        atomicAdd(t + kWuPlane + c, (unsigned long long)(w * uint64_t(r)));
-        atomicAdd(t + 2 * kWuPlane + c, (unsigned long long)(w * uint64_t(g)));
-        atomicAdd(t + 3 * kWuPlane + c, (unsigned long long)(w * uint64_t(b)));
-        atomicAdd(t + 4 * kWuPlane + c, (unsigned long long)(w * uint64_t(r * r + g * g + b * b)));
-    }
-}
-
-// Cumulative sums along one axis: a line is (statistic, two fixed indices);
-// `step` is the stride of the summed axis and `line_at` the first entry of a
-// line.
-template <typename F>
-__device__ __forceinline__ void wu_prefix_axis(uint64_t* __restrict__ t, int step, F line_at)
-{
-    for (int l = threadIdx.x; l < kWuStats * kWuSide * kWuSide; l += kWuPrefixThreads) {
-        const int q = l / (kWuSide * kWuSide), rest = l - q * kWuSide * kWuSide;
-        uint64_t* p = t + q * kWuPlane + line_at(rest / kWuSide, rest % kWuSide);
-        uint64_t acc = 0;
-        for (int i = 1; i < kWuSide; ++i) {
-            acc += p[i * step];
-            p[i * step] = acc;
+    const int lane = threadIdx.x & 63;
+    // the colours of a wave are consecutive in key order, so lanes of the same
+    // cell mostly sit next to each other: each run of equal cells is summed in
+    // the wave and added once, by its last lane
+    for (int64_t i0 = lo; i0 < hi; i0 += kWuAccumThreads) {
+        const int64_t i = i0 + threadIdx.x;
+        const bool valid = i < hi;
+        int r = 0, g = 0, b = 0;
+        uint64_t w = 0;
+        int c = -1;
+        if (valid) {
+            key_rgb(keys[i], r, g, b);
+            w = counts[i];
+            c = wu_at((r >> 3) + 1, (g >> 3) + 1, (b >> 3) + 1);
+        }
+        const uint64_t v[kWuStats] = {w, w * uint64_t(r), w * uint64_t(g), w * uint64_t(b),
+                                      w * uint64_t(r * r + g * g + b * b)};
+        const int c_prev = __shfl(c, lane > 0 ? lane - 1 : 0, 64);
+        const int c_next = __shfl(c, lane < 63 ? lane + 1 : 63, 64);
+        const bool head = lane == 0 || c_prev != c;
+        const bool tail = lane == 63 || c_next != c;
+        const int head_lane = wave_incl_max(head ? lane : 0);  // the first lane of this lane's run
+#pragma unroll
+        for (int q = 0; q < kWuStats; ++q) {
+            const uint64_t incl = wave_incl_scan(v[q]);
+            const uint64_t before = __shfl(incl - v[q], head_lane, 64);  // the scan just before the run
+            if (valid && tail) atomicAdd(t + q * kWuPlane + c, (unsigned long long)(incl - before));
         }
     }
 }
 
+// Cumulative sums along one axis (0: b, 1: g, 2: r), one line (a statistic
+// and the two other indices) per thread; the whole line is loaded before
+// anything is stored.  Three launches, one per axis, each over every job.
+constexpr int kWuLines = kWuStats * kWuSide * kWuSide;
+constexpr int kWuPrefixThreads = 256;
+constexpr int kWuPrefixBlocks = (kWuLines + kWuPrefixThreads - 1) / kWuPrefixThreads;
+
+template <int kAxis>
 __global__ void __launch_bounds__(kWuPrefixThreads) k_wu_prefix(const JobDev* __restrict__ jobs)
 {
-    const JobDev& J = jobs[blockIdx.x];
+    const JobDev& J = jobs[blockIdx.x / kWuPrefixBlocks];
     if (!wu_job(J)) return;
-    uint64_t* __restrict__ t = wu_table(J);
-    wu_prefix_axis(t, 1, [](int r, int g) { return wu_at(r, g, 0); });
-    __syncthreads();
-    wu_prefix_axis(t, kWuSide, [](int r, int b) { return wu_at(r, 0, b); });
-    __syncthreads();
-    wu_prefix_axis(t, kWuSide * kWuSide, [](int g, int b) { return wu_at(0, g, b); });
+    const int l = (blockIdx.x % kWuPrefixBlocks) * kWuPrefixThreads + threadIdx.x;
+    if (l >= kWuLines) return;
+    const int q = l / (kWuSide * kWuSide), rest = l - q * kWuSide * kWuSide;
+    const int u = rest / kWuSide, v = rest % kWuSide;
+    constexpr int step = kAxis == 0 ? 1 : (kAxis == 1 ? kWuSide : kWuSide * kWuSide);
+    const int first = kAxis == 0 ? wu_at(u, v, 0) : (kAxis == 1 ? wu_at(u, 0, v) : wu_at(0, u, v));
+    uint64_t* __restrict__ p = wu_table(J) + q * kWuPlane + first;
+    uint64_t x[kWuSide - 1];
+#pragma unroll
+    for (int i = 1; i < kWuSide; ++i) x[i - 1] = p[i * step];
+    uint64_t acc = 0;
+#pragma unroll
+    for (int i = 1; i < kWuSide; ++i) {
+        acc += x[i - 1];
+        p[i * step] = acc;
+    }
 }
 
 struct WuMom {
@@ -270,7 +288,9 @@ cq_status launch_wu(const JobDev* jobs, const int* maps, int B, int accum_blocks
     CQ_TIMED_LAUNCH("k_wu_clear", s, k_wu_clear<<<B * kWuClearBlocks, kWuClearThreads, 0, s>>>(jobs));
     CQ_TIMED_LAUNCH("k_wu_accum", s,
                     k_wu_accum<<<accum_blocks, kWuAccumThreads, 0, s>>>(jobs, maps + kMapWu * (B + 1), B));
-    CQ_TIMED_LAUNCH("k_wu_prefix", s, k_wu_prefix<<<B, kWuPrefixThreads, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_wu_prefix", s, k_wu_prefix<0><<<B * kWuPrefixBlocks, kWuPrefixThreads, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_wu_prefix", s, k_wu_prefix<1><<<B * kWuPrefixBlocks, kWuPrefixThreads, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_wu_prefix", s, k_wu_prefix<2><<<B * kWuPrefixBlocks, kWuPrefixThreads, 0, s>>>(jobs));
     CQ_TIMED_LAUNCH("k_wu_split", s, k_wu_split<<<B, 64, 0, s>>>(jobs));
     return CQ_OK;
 }
