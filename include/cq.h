@@ -109,41 +109,46 @@ cq_status cq_histogram(const uint8_t* img, int32_t H, int32_t W, int64_t row_str
 cq_status cq_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
                         uint32_t* keys, uint32_t* counts, void* stream);
 
-/* Section 2.3: initial centres from the N' unique colours.  centers is a
- * device double[K][3].  For N' <= K the centres are the colours in key order
- * followed by zeros and *k_used (host, nullable) is N'.  Random draws come
- * from one splitmix64 stream seeded with `seed`: FGY does a partial
- * Fisher-Yates shuffle (draw j uniform in [j, N')); MMX draws the first colour
- * uniformly; KPP draws the first colour with probability proportional to its
- * count and colour j with probability proportional to count * D^2.  VAR takes
- * the pixel data set (colour i repeated count_i times): the channel with the
- * largest pixel variance (ties: R, then G, then B), the pixels ordered by
- * (that channel's value, key), K groups [floor(g N / K), floor((g+1) N / K)) of
- * the N pixels, and each group's lower-median pixel; no draws.  SFF draws a
- * subset of L = max(K, ceil(2 K ln K)) colours (at most N') as FGY draws, then
- * runs MMX on the subset in draw order (first centre subset[U(L)], ties to
- * the lowest subset position). WU (Wu's greedy orthogonal bipartitioning, no draws)
- * cuts each channel into 32 levels (value >> 3) and, from the whole grid,
- * repeatedly splits the box of largest weighted variance s2 - |m|^2 / w
- * (pixel statistics; ties to the lowest box index; a box of one cell or with
- * no allowed cut counts 0) at the plane maximizing |m_l|^2 / w_l +
- * |m_u|^2 / w_u over two non-empty parts (first plane, then R, G, B on ties;
- * the lower part keeps the index, the upper part is appended), until K boxes
- * or no variance is left; the centres are the box means, and if fewer than K
- * boxes result the rest repeat box 0's mean.  The criteria are FP64 in that
- * operation order, the statistics exact integers.  LBG starts from the weighted centroid and doubles the
- * centres in stages: centre j becomes c_j - (1,1,1) in place and c_j + (1,1,1)
- * at index m + j (a last partial stage splits the first K - m), each stage
- * refined by weighted Lloyd iterations with the stopping rule of Section 3.3
- * at the paper's threshold 0.001 (at most 100 iterations); it synchronizes
- * `stream` once per stage.  DEN cuts the cube into 512 cells (value >> 5 per
- * channel, cell (r >> 5) * 64 + (g >> 5) * 8 + (b >> 5)); cell c with u_c of
- * the N' colours gets floor(K u_c / N') centres and the rest go one each to
- * the cells of largest remainder K u_c mod N' (ties to the lower cell); cell
- * by cell the quota is drawn as FGY draws from the cell's colours in key
- * order, on the one stream.  With CQ_INIT_USER the centres are left as
- * given.  Synchronizes only if k_used is
- * non-null; a device-side failure of the initialization is reported by that
+/* Section 2.3 (and WU of Section 3.3): initial centres from the N' unique
+ * colours.  centers is a device double[K][3].  For N' <= K the centres are the
+ * colours in key order followed by zeros and *k_used (host, nullable) is N'.
+ * Random draws come from one splitmix64 stream seeded with `seed`.
+ *  - FGY: a partial Fisher-Yates shuffle of the colours, draw j uniform in
+ *    [j, N').
+ *  - MMX: the first colour uniform, then farthest first by integer D^2 (ties
+ *    to the lowest index).
+ *  - KPP: the first colour with probability proportional to its count, colour
+ *    j then proportional to count * D^2.
+ *  - VAR (no draws): on the pixel data set (colour i repeated count_i times),
+ *    the channel of largest pixel variance (ties R, G, B), the pixels ordered
+ *    by (that channel's value, key), K groups [floor(g N / K),
+ *    floor((g+1) N / K)) of the N pixels, each group's lower-median pixel.
+ *  - SFF: a subset of L = max(K, ceil(2 K ln K)) colours (at most N') drawn as
+ *    FGY draws, then MMX on the subset in draw order (first centre
+ *    subset[U(L)], ties to the lowest subset position).
+ *  - WU (no draws): Wu's greedy orthogonal bipartitioning over 32 levels per
+ *    channel (value >> 3).  From the whole grid, the box of largest weighted
+ *    variance s2 - |m|^2 / w (ties to the lowest box index; a box of one cell,
+ *    or with no allowed cut, counts 0) is split at the plane maximizing
+ *    |m_l|^2 / w_l + |m_u|^2 / w_u over two non-empty parts (first plane,
+ *    then R, G, B on ties); the lower part keeps the index and the upper part
+ *    is appended, until K boxes or no variance is left.  The centres are the
+ *    box means; with fewer than K boxes the rest repeat box 0's mean.  The
+ *    statistics are exact integers, the criteria FP64 in that order.
+ *  - LBG (no draws): the weighted centroid, then stages that turn centre j of
+ *    m into c_j - (1,1,1) in place and c_j + (1,1,1) at index m + j (a last
+ *    partial stage splits the first K - m), each refined by weighted Lloyd
+ *    iterations stopped by the rule of Section 3.3 at the paper's threshold
+ *    0.001 (at most 100 iterations).  Synchronizes `stream` once per stage.
+ *  - DEN: 512 cells (value >> 5 per channel, cell (r >> 5) * 64 +
+ *    (g >> 5) * 8 + (b >> 5)); cell c with u_c of the N' colours gets
+ *    floor(K u_c / N') centres, and the rest go one each to the cells of
+ *    largest remainder K u_c mod N' (ties to the lower cell); cell by cell the
+ *    quota is drawn as FGY draws from the cell's colours in key order.
+ *  - USER: the centres are left as given.
+ * The workspace must hold cq_workspace_bytes(H, W, K) of an image with
+ * H W >= N'.  Synchronizes only if k_used is non-null or the scheme is LBG; a
+ * device-side failure of the initialization is reported by that
  * synchronization or by the next synchronizing call on the workspace. */
 cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique, int32_t K,
                   cq_init_t scheme, uint64_t seed, double* centers, int32_t* k_used /* host */,
