@@ -104,6 +104,16 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ 
 // with all 256 entries (zero past K), so any table byte indexes in bounds.
 constexpr int kMapGroupsPerThread = kMapGroupsPerBlock / kMapThreads;
 
+// The blocks of a launch go to the 8 XCDs in turn (block i to XCD i mod 8);
+// this gives XCD x the consecutive logical blocks [start_x, start_x + count_x),
+// so that each XCD's L2 serves one contiguous part of the data.
+__device__ __forceinline__ int xcd_block(int i, int n)
+{
+    const int x = i & 7, q = n >> 3, r = n & 7;
+    const int start = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return start + (i >> 3);
+}
+
 // Per-pixel search of a job with map_direct: block b takes the pixels
 // [4 b G, 4 (b + 1) G) (G = kMapGroupsPerBlock), one per thread per step.
 // Adds the pixels' squared errors to the job's sum if with_err.
@@ -149,9 +159,10 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
 {
     __shared__ uint32_t pal[kMaxK];
     __shared__ __align__(16) uint2 ent[kMaxK];  // read two entries at a time
-    const int jb = find_job(map, B, blockIdx.x);
+    const int blk = xcd_block(int(blockIdx.x), int(gridDim.x));
+    const int jb = find_job(map, B, blk);
     const JobDev& J = jobs[jb];
-    const int lb = blockIdx.x - map[jb];
+    const int lb = blk - map[jb];
     const int K = J.map_k;
     for (int t = threadIdx.x; t < kMaxK; t += blockDim.x) {
         const uint8_t* q = gp(J.palette) + 3 * t;
