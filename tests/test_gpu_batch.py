@@ -100,3 +100,24 @@ def test_batch_rejects_bad_job(cqm, dev):
     with pytest.raises(cqm.CqError) as e:
         cqm.cq_quantize_batch([good, bad], ws)
     assert e.value.code == cqm.CQ_EINVAL and "job 1" in str(e.value)
+
+
+def test_benchmark_batch_matches_oracle(cqm, dev):
+    """The batch the benchmark times (eight 512 x 512 stand-ins, seeds 1-8,
+    K = 256, k-means++, sort-means, tol 1e-4, at most 100 iterations, full map),
+    in one batched call as the benchmark makes it: every image bit for bit
+    against the oracle."""
+    import bench
+
+    _say("benchmark batch: 8 x 512x512, K=256")
+    host = [synth.smooth_field_blobs(bench.H, bench.W, s) for s in bench.SEEDS]
+    jobs = [cqm.BatchJob(torch.from_numpy(im).to(dev), bench.K, cqm.INIT_KMEANSPP, s, bench.MAX_ITERS, bench.TOL,
+                         True) for im, s in zip(host, bench.SEEDS)]
+    stats = cqm.cq_quantize_batch(jobs, cqm.BatchWorkspace(jobs, dev))
+    for im, s, job, st in zip(host, bench.SEEDS, jobs, stats):
+        rp, ri, rr, rs = oracle.quantize(im, bench.K, oracle.INIT_KMEANSPP, s, bench.MAX_ITERS, bench.TOL, prune=True)
+        assert np.array_equal(job.palette.cpu().numpy(), rp), s
+        assert np.array_equal(job.idx.cpu().numpy(), ri) and np.array_equal(job.rgb.cpu().numpy(), rr), s
+        for key in ("iters", "converged", "k_used", "n_unique", "ndc_total", "near_ties", "sse_final", "mse_float",
+                    "mse_img"):
+            assert st[key] == rs[key], (s, key)
