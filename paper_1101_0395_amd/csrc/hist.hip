@@ -193,8 +193,9 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_scatter(const JobDev* __r
 }
 
 // Per job, hist_count_blocks(npix) blocks (a power of two up to one per
-// bucket), block c of C taking the buckets c, c + C, ...: each bucket's keys
-// are counted in LDS, then the non-zero
+// bucket), block c of C taking the buckets c, c + C, ...: a bucket of at most
+// one key per thread is ranked through a bitmap of the keys present; a larger
+// bucket's keys are counted in LDS, then the non-zero
 // counters are compacted in ascending key order over the front of the
 // bucket's own range (its keys are all read before anything is written).  The
 // 8192 counters are cleared once; a bucket marks the groups of 64 counters it
@@ -209,12 +210,14 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __res
     __shared__ uint32_t touched[kGroups / 32];
     __shared__ uint32_t tmp[64];
     __shared__ uint32_t s_total[kHistBuckets / 256], s_start[kHistBuckets / 256];  // this block's buckets
+    __shared__ uint32_t s_bits[kHistLow / 32], s_wpre[kHistLow / 32];  // small buckets: keys present, ranks
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int cb0 = blockIdx.x - map[jb];
     const int kCountBlocks = map[jb + 1] - map[jb];  // at least 256
     for (int t = threadIdx.x; t < kHistLow; t += kHistThreads) c[t] = 0u;
     if (threadIdx.x < kGroups / 32) touched[threadIdx.x] = 0u;
+    if (threadIdx.x < kHistLow / 32) s_bits[threadIdx.x] = 0u;
     // every bucket's pixel count and first slot at once, not one bucket after another
     if (threadIdx.x < kHistBuckets / 256) {
         const int b = cb0 + threadIdx.x * kCountBlocks;
@@ -233,6 +236,33 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __res
         const uint32_t start = s_start[q];
         uint16_t* __restrict__ hk = gp(J.hkeys) + start;
         uint32_t* __restrict__ hc = gp(J.hcnt) + start;
+        if (total <= kHistThreads) {
+            // at most one key per thread: the first thread of each key marks
+            // it in a bitmap, and a key's rank among the distinct keys is the
+            // count of marks below it (an exclusive scan of the 256 words'
+            // population counts, then the word's own lower bits)
+            const uint32_t key = threadIdx.x < total ? uint32_t(hk[threadIdx.x]) : 0xffffffffu;
+            const bool first = key != 0xffffffffu && atomicAdd(&c[key], 1u) == 0u;
+            if (first) atomicOr(&s_bits[key >> 5], 1u << (key & 31u));
+            __syncthreads();
+            const uint32_t word = threadIdx.x < kHistLow / 32 ? s_bits[threadIdx.x] : 0u;
+            uint32_t nuniq = 0;
+            const uint32_t wpre = block_exclusive_scan<uint32_t>(__popc(word), tmp, &nuniq);
+            if (threadIdx.x < kHistLow / 32) s_wpre[threadIdx.x] = wpre;
+            __syncthreads();
+            if (first) {
+                const uint32_t w = key >> 5;
+                const uint32_t rank = s_wpre[w] + __popc(s_bits[w] & ((1u << (key & 31u)) - 1u));
+                hk[rank] = uint16_t(key);  // every key was read before the first barrier
+                hc[rank] = c[key];
+            }
+            if (threadIdx.x == 0) gp(J.hnu)[b] = nuniq;
+            __syncthreads();  // the counters and the bitmap are read
+            if (first) c[key] = 0u;
+            if (threadIdx.x < kHistLow / 32) s_bits[threadIdx.x] = 0u;
+            __syncthreads();
+            continue;
+        }
         // eight keys in flight per thread before their LDS atomics
         for (uint32_t i0 = 0; i0 < total; i0 += kUnroll * kHistThreads) {
             uint32_t kq[kUnroll];
