@@ -3,6 +3,7 @@
 // loop.  The single-image calls run as batches of one job.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <deque>
@@ -173,17 +174,74 @@ static void set_image(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64
     J.map_direct = subsample ? 1 : 0;
 }
 
-// Copies the job descriptors and block maps to the device.  Each upload reads
-// its own host snapshot, which outlives the asynchronous copy.
+// ------------------------------------------------------------ host buffers
+namespace {
+constexpr int kHostClasses = 24;  // size classes 1 KiB << c
+std::mutex g_host_mu;
+std::vector<void*> g_host_free[kHostClasses];
+
+int host_class(size_t n)
+{
+    int c = 0;
+    while (c < kHostClasses && (size_t(1024) << c) < n) ++c;
+    return c;
+}
+}  // namespace
+
+HostBuf::HostBuf(size_t n)
+{
+    const int c = host_class(n);
+    if (c < kHostClasses) {
+        cap_ = size_t(1024) << c;
+        {
+            std::lock_guard<std::mutex> lock(g_host_mu);
+            if (!g_host_free[c].empty()) {
+                p_ = g_host_free[c].back();
+                g_host_free[c].pop_back();
+                pinned_ = true;
+                return;
+            }
+        }
+        if (hipHostMalloc(&p_, cap_, hipHostMallocDefault) == hipSuccess) {
+            pinned_ = true;
+            return;
+        }
+        (void)hipGetLastError();  // fall back to pageable memory
+        p_ = nullptr;
+    }
+    cap_ = n;
+    p_ = malloc(n);
+    pinned_ = false;
+}
+
+void HostBuf::release()
+{
+    if (!p_) return;
+    if (pinned_) {
+        std::lock_guard<std::mutex> lock(g_host_mu);
+        g_host_free[host_class(cap_)].push_back(p_);
+    } else {
+        free(p_);
+    }
+    p_ = nullptr;
+}
+
+// Copies the job descriptors and block maps to the device in one copy, laid
+// out as in the descriptor region.  Each upload reads its own host snapshot,
+// which outlives the asynchronous copy.
 cq_status upload(Batch& b)
 {
-    const size_t jb = sizeof(JobDev) * size_t(b.B), mb = sizeof(int) * b.maps.size();
-    b.staged.emplace_back(jb + mb);
+    const size_t jb = sizeof(JobDev) * size_t(b.B), mo = desc_maps_off(b.B), mb = sizeof(int) * b.maps.size();
+    b.staged.emplace_back(mo + mb);
     char* snap = b.staged.back().data();
+    if (!snap) {
+        set_error("out of host memory");
+        return CQ_EDEVICE;
+    }
     memcpy(snap, b.h.data(), jb);
-    memcpy(snap + jb, b.maps.data(), mb);
-    CQ_HIP_TRY(hipMemcpyAsync(b.desc, snap, jb, hipMemcpyHostToDevice, b.s));
-    CQ_HIP_TRY(hipMemcpyAsync(b.d_maps(), snap + jb, mb, hipMemcpyHostToDevice, b.s));
+    memset(snap + jb, 0, mo - jb);
+    memcpy(snap + mo, b.maps.data(), mb);
+    CQ_HIP_TRY(hipMemcpyAsync(b.desc, snap, mo + mb, hipMemcpyHostToDevice, b.s));
     return CQ_OK;
 }
 
@@ -218,8 +276,15 @@ __global__ void k_zero_sq_err(const JobDev* __restrict__ jobs, int B)
 cq_status collect(Batch& b)
 {
     CQ_TIMED_LAUNCH("k_collect", b.s, k_collect<<<(b.B + 63) / 64, 64, 0, b.s>>>(b.d_jobs(), b.B, b.d_results()));
-    CQ_HIP_TRY(hipMemcpyAsync(b.res.data(), b.d_results(), sizeof(JobResult) * size_t(b.B), hipMemcpyDeviceToHost, b.s));
+    const size_t rb = sizeof(JobResult) * size_t(b.B);
+    HostBuf out(rb);
+    if (!out.data()) {
+        set_error("out of host memory");
+        return CQ_EDEVICE;
+    }
+    CQ_HIP_TRY(hipMemcpyAsync(out.data(), b.d_results(), rb, hipMemcpyDeviceToHost, b.s));
     CQ_HIP_TRY(hipStreamSynchronize(b.s));
+    memcpy(b.res.data(), out.data(), rb);
     b.staged.clear();  // every upload before this point has completed
     return CQ_OK;
 }
@@ -255,9 +320,15 @@ cq_status read_results(Batch& b, int slot, hipEvent_t done)
     hipStream_t side = nullptr;
     CQ_TRY(side_stream(&side));
     CQ_HIP_TRY(hipStreamWaitEvent(side, done, 0));
-    CQ_HIP_TRY(hipMemcpyAsync(b.res.data(), b.d_results(slot), sizeof(JobResult) * size_t(b.B), hipMemcpyDeviceToHost,
-                              side));
+    const size_t rb = sizeof(JobResult) * size_t(b.B);
+    HostBuf out(rb);
+    if (!out.data()) {
+        set_error("out of host memory");
+        return CQ_EDEVICE;
+    }
+    CQ_HIP_TRY(hipMemcpyAsync(out.data(), b.d_results(slot), rb, hipMemcpyDeviceToHost, side));
     CQ_HIP_TRY(hipStreamSynchronize(side));
+    memcpy(b.res.data(), out.data(), rb);
     return CQ_OK;
 }
 

@@ -13,6 +13,38 @@
 
 namespace cq {
 
+// A host buffer for asynchronous copies: pinned memory (hipHostMalloc) from
+// per-size free lists kept for the life of the process (a pageable source or
+// destination makes the runtime stage every copy), or pageable memory if no
+// pinned memory can be had.  The memory returns to its list on destruction.
+class HostBuf {
+public:
+    HostBuf() = default;
+    explicit HostBuf(size_t n);
+    HostBuf(HostBuf&& o) noexcept : p_(o.p_), cap_(o.cap_), pinned_(o.pinned_) { o.p_ = nullptr; }
+    HostBuf& operator=(HostBuf&& o) noexcept
+    {
+        if (this != &o) {
+            release();
+            p_ = o.p_;
+            cap_ = o.cap_;
+            pinned_ = o.pinned_;
+            o.p_ = nullptr;
+        }
+        return *this;
+    }
+    HostBuf(const HostBuf&) = delete;
+    HostBuf& operator=(const HostBuf&) = delete;
+    ~HostBuf() { release(); }
+    char* data() const { return static_cast<char*>(p_); }
+
+private:
+    void release();
+    void* p_ = nullptr;
+    size_t cap_ = 0;
+    bool pinned_ = false;
+};
+
 // Host view of one launch sequence: job descriptors, block maps, and the
 // device descriptor region they are copied to.
 struct Batch {
@@ -22,7 +54,7 @@ struct Batch {
     std::vector<JobDev> h;
     std::vector<int> maps;
     std::vector<JobResult> res;
-    std::deque<std::vector<char>> staged;  // host copies behind the uploads, kept until the stream is synchronized
+    std::deque<HostBuf> staged;  // host copies behind the uploads, kept until the stream is synchronized
 
     Batch(int nb, char* d, hipStream_t st)
         : B(nb), desc(d), s(st), h(size_t(nb)), maps(size_t(kNumMaps) * (nb + 1), 0), res(size_t(nb))

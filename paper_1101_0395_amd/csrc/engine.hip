@@ -39,7 +39,7 @@ struct cq_engine {
     int64_t next_ticket = 1;
     std::deque<cq::EngineJob> queue;   // submitted, waiting for a slot
     std::vector<cq::EngineJob> active;  // in flight, in admission order
-    std::deque<std::vector<char>> staged;  // upload snapshots of a finished phase, kept until the stream drains
+    std::deque<cq::HostBuf> staged;  // upload snapshots of a finished phase, kept until the stream drains
 };
 
 namespace cq {
