@@ -177,8 +177,18 @@ static void set_image(JobDev& J, const uint8_t* img, int32_t H, int32_t W, int64
 // ------------------------------------------------------------ host buffers
 namespace {
 constexpr int kHostClasses = 24;  // size classes 1 KiB << c
-std::mutex g_host_mu;
-std::vector<void*> g_host_free[kHostClasses];
+
+// Never destroyed, so a buffer released during process exit (an engine freed
+// late) still finds its list.
+struct HostPool {
+    std::mutex mu;
+    std::vector<void*> free_list[kHostClasses];
+};
+HostPool& host_pool()
+{
+    static HostPool* pool = new HostPool;
+    return *pool;
+}
 
 int host_class(size_t n)
 {
@@ -194,10 +204,11 @@ HostBuf::HostBuf(size_t n)
     if (c < kHostClasses) {
         cap_ = size_t(1024) << c;
         {
-            std::lock_guard<std::mutex> lock(g_host_mu);
-            if (!g_host_free[c].empty()) {
-                p_ = g_host_free[c].back();
-                g_host_free[c].pop_back();
+            HostPool& pool = host_pool();
+            std::lock_guard<std::mutex> lock(pool.mu);
+            if (!pool.free_list[c].empty()) {
+                p_ = pool.free_list[c].back();
+                pool.free_list[c].pop_back();
                 pinned_ = true;
                 return;
             }
@@ -218,8 +229,9 @@ void HostBuf::release()
 {
     if (!p_) return;
     if (pinned_) {
-        std::lock_guard<std::mutex> lock(g_host_mu);
-        g_host_free[host_class(cap_)].push_back(p_);
+        HostPool& pool = host_pool();
+        std::lock_guard<std::mutex> lock(pool.mu);
+        pool.free_list[host_class(cap_)].push_back(p_);
     } else {
         free(p_);
     }
