@@ -312,3 +312,44 @@ def test_full_size_4096(cqm, dev):
     mse = ((img.astype(np.float64) - gr.cpu().numpy().astype(np.float64)) ** 2).sum(-1).mean()
     assert st["mse_img"] == pytest.approx(mse, rel=1e-12)
     assert st["converged"] == 1
+
+
+@pytest.mark.gpu
+def test_every_colour_once(cqm, dev):
+    """The largest histogram there is: a 4096 x 4096 image holding each of the
+    2^24 colours once (a seeded permutation).  Histogram bit-exact (every key,
+    count 1), cooperative inits with runs read from memory, three pruned
+    k-means iterations bit-exact, and the map checked pixel by pixel on a
+    sample against the palette."""
+    _say("every 24-bit colour once (4096x4096)")
+    H = W = 4096
+    perm = np.random.default_rng(7).permutation(1 << 24).astype(np.uint32)
+    img = np.stack([(perm >> 16) & 255, (perm >> 8) & 255, perm & 255], -1).astype(np.uint8).reshape(H, W, 3)
+    ws = cqm.Workspace(H, W, 256, dev)
+    dimg = _to_dev(img, dev)
+    keys, counts = cqm.cq_histogram(dimg, ws)
+    gk, gc = _u32(keys), _u32(counts)
+    assert np.array_equal(gk, np.arange(1 << 24, dtype=np.uint32)) and np.all(gc == 1)
+    rk, rc = oracle.histogram(img)
+    assert np.array_equal(gk, rk) and np.array_equal(gc, rc)
+    for scheme, seed in ((oracle.INIT_KMEANSPP, 3), (oracle.INIT_MAXMIN, 4)):
+        c, _ = oracle.init(rk, rc, 16, scheme, seed)
+        g, _ = cqm.cq_init(keys, counts, 16, scheme, seed, ws)
+        assert np.array_equal(g.cpu().numpy(), c), scheme
+    c0, _ = oracle.init(rk, rc, 256, oracle.INIT_FORGY, 3)
+    g0, _ = cqm.cq_init(keys, counts, 256, oracle.INIT_FORGY, 3, ws)
+    assert np.array_equal(g0.cpu().numpy(), c0)
+    r = oracle.kmeans(rk, rc, c0, 3, 1e-4, True)
+    g = cqm.cq_kmeans(keys, counts, _to_dev(c0, dev), 3, 1e-4, True, ws)
+    _compare_kmeans(g, r)
+    idx, rgb, err = cqm.cq_map(dimg, keys, counts, g.palette, ws)
+    P = r.palette.astype(np.int64)
+    rng = np.random.default_rng(1)
+    ys, xs = rng.integers(0, H, 20000), rng.integers(0, W, 20000)
+    X = img[ys, xs].astype(np.int64)
+    D = ((X[:, None, :] - P[None, :, :]) ** 2).sum(-1)
+    want = np.argmin(D, axis=1)
+    assert np.array_equal(idx.cpu().numpy()[ys, xs], want)
+    assert np.array_equal(rgb.cpu().numpy()[ys, xs], r.palette[want])
+    sq = ((img.astype(np.int64) - rgb.cpu().numpy().astype(np.int64)) ** 2).sum()
+    assert err == sq
