@@ -101,6 +101,35 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert rc == cq.CQ_EINVAL
 
 
+def test_empty_inputs_are_rejected_without_a_device():
+    """An image with no pixels, a histogram with no colours and a batch with
+    no jobs are argument errors, reported before any device work."""
+    L = cq.lib()
+    fake = ctypes.c_void_p(0x10000)
+    n = ctypes.c_int64(0)
+    st = cq.CqStats()
+    k_used = ctypes.c_int32(0)
+    err = ctypes.c_uint64(0)
+    for H, W in ((0, 4), (4, 0), (-1, 4)):
+        rc, msg = _status(L.cq_histogram, fake, H, W, 12, 0, fake, fake, 16, ctypes.byref(n), fake, 1 << 30, None)
+        assert rc == cq.CQ_EINVAL and "positive" in msg, (H, W, msg)
+        rc, _ = _status(L.cq_pixel_keys, fake, H, W, 12, fake, fake, None)
+        assert rc == cq.CQ_EINVAL, (H, W)
+        rc, _ = _status(L.cq_map, fake, H, W, 12, fake, fake, 3, fake, 4, fake, None, ctypes.byref(err),
+                        fake, 1 << 30, None)
+        assert rc == cq.CQ_EINVAL, (H, W)
+        rc, _ = _status(L.cq_quantize, fake, H, W, 12, 0, 4, 2, 0, 10, 1e-4, 1, fake, None, None,
+                        ctypes.byref(st), fake, 1 << 30, None)
+        assert rc == cq.CQ_EINVAL, (H, W)
+    rc, msg = _status(L.cq_init, fake, fake, 0, 4, 2, 0, fake, ctypes.byref(k_used), fake, 1 << 30, None)
+    assert rc == cq.CQ_EINVAL and "n_unique" in msg
+    rc, msg = _status(L.cq_kmeans, fake, fake, 0, 4, fake, 10, 1e-4, 1, fake, None, None, ctypes.byref(st),
+                      fake, 1 << 30, None)
+    assert rc == cq.CQ_EINVAL and "n_unique" in msg
+    rc, msg = _status(L.cq_quantize_batch, None, 0, None, fake, 1 << 30, None)
+    assert rc == cq.CQ_EINVAL and "n_jobs" in msg
+
+
 def test_product_package_does_not_import_the_oracle():
     pkg = os.path.join(ROOT, "paper_1101_0395_amd")
     for dirpath, _, files in os.walk(pkg):
