@@ -353,3 +353,46 @@ def test_every_colour_once(cqm, dev):
     assert np.array_equal(rgb.cpu().numpy()[ys, xs], r.palette[want])
     sq = ((img.astype(np.int64) - rgb.cpu().numpy().astype(np.int64)) ** 2).sum()
     assert err == sq
+
+
+@pytest.mark.gpu
+def test_largest_image(cqm, dev):
+    """The largest image accepted, 2^28 pixels (16384 x 16384): a 4096 x 4096
+    stand-in tiled 4 x 4, so every colour's count is 16 times its count in the
+    tile.  Histogram bit-exact; FGY init and three pruned iterations bit-exact
+    against the oracle on that histogram; the map equal to the tile's map
+    repeated, and its squared-error sum 16 times the tile's."""
+    _say("largest image 16384x16384 (2^28 pixels)")
+    base = synth.smooth_field_blobs(4096, 4096, 42)
+    img = np.tile(base, (4, 4, 1))
+    H, W = img.shape[:2]
+    assert H * W == 1 << 28
+    ws = cqm.Workspace(H, W, 256, dev)
+    dimg = _to_dev(img, dev)
+    keys, counts = cqm.cq_histogram(dimg, ws)
+    bk, bc = oracle.histogram(base)
+    rk, rc = oracle.histogram(img)
+    assert np.array_equal(rk, bk) and np.array_equal(rc, bc * np.uint32(16))
+    assert np.array_equal(_u32(keys), rk) and np.array_equal(_u32(counts), rc)
+    _say(f"  N' = {len(bk)}")
+    c0, _ = oracle.init(bk, rc, 256, oracle.INIT_FORGY, 5)
+    g0, _ = cqm.cq_init(keys, counts, 256, oracle.INIT_FORGY, 5, ws)
+    assert np.array_equal(g0.cpu().numpy(), c0)
+    r = oracle.kmeans(bk, rc, c0, 3, 1e-4, True)
+    g = cqm.cq_kmeans(keys, counts, _to_dev(c0, dev), 3, 1e-4, True, ws)
+    _compare_kmeans(g, r)
+    # FGY ignores the counts and every weighted sum scales by 16: the run on
+    # the tile alone reaches the same centres with 16 times smaller SSE terms
+    rb = oracle.kmeans(bk, bc, c0, 3, 1e-4, True)
+    assert np.array_equal(rb.centers, r.centers)
+    assert np.array_equal(np.array(rb.sse_trace) * 16.0, np.array(r.sse_trace))
+    idx, rgb, err = cqm.cq_map(dimg, keys, counts, g.palette, ws)
+    ridx, rrgb, rerr = oracle.map_image(base, r.palette)
+    gi = idx.cpu().numpy()
+    del idx
+    assert np.array_equal(gi, np.tile(ridx, (4, 4)))
+    del gi
+    gr = rgb.cpu().numpy()
+    del rgb
+    assert np.array_equal(gr, np.tile(rrgb, (4, 4, 1)))
+    assert err == 16 * rerr

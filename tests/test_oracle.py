@@ -858,3 +858,23 @@ def test_den_quotas_follow_the_cell_populations():
     assert len({tuple(c) for c in cen.tolist()}) == 7  # distinct colours
     ckeys = [(int(r) << 16) | (int(g) << 8) | int(b) for r, g, b in cen]
     assert all(k in set(keys.tolist()) for k in ckeys)
+
+
+def test_scaling_every_count_by_a_power_of_two_scales_only_the_sse():
+    """Section 2.2's weighted means do not change when every pixel count is
+    multiplied by the same factor, and each SSE term is multiplied by it.  With
+    a factor of 16 the scaling is exact in floating point, so an image tiled
+    4 x 4 gives the same centres, memberships, NDC and near ties as the tile,
+    an SSE trace exactly 16 times larger, and the same stopping iteration."""
+    base = synth.smooth_field_blobs(48, 40, 3)
+    bk, bc = oracle.histogram(base)
+    tk, tc = oracle.histogram(np.tile(base, (4, 4, 1)))
+    assert np.array_equal(tk, bk) and np.array_equal(tc, bc * np.uint32(16))
+    c0, _ = oracle.init(bk, bc, 24, oracle.INIT_FORGY, 1)
+    for prune in (False, True):
+        a = oracle.kmeans(bk, bc, c0, 100, 1e-4, prune)
+        b = oracle.kmeans(tk, tc, c0, 100, 1e-4, prune)
+        assert np.array_equal(a.centers, b.centers) and np.array_equal(a.assign, b.assign)
+        assert np.array_equal(np.array(a.sse_trace) * 16.0, np.array(b.sse_trace))
+        for key in ("iters", "converged", "ndc_total", "near_ties", "mse_float"):
+            assert a.stats[key] == b.stats[key], key
