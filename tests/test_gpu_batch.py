@@ -1,7 +1,9 @@
 """GPU parity of the batch entry point: every job of a mixed batch (sizes,
 palette sizes, schemes, pruning, stopping settings) equals the CPU oracle and
 the same image quantized alone, bit for bit."""
+import os
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -75,6 +77,50 @@ def test_mixed_batch_matches_oracle_and_solo(cqm, dev):
             assert st[key] == rs[key], key
         sp, si, sr, ss = cqm.cq_quantize(job.img, K, scheme, seed, mi, tol, prune, solo_ws)
         assert torch.equal(sp, job.palette) and torch.equal(sr, job.rgb) and ss == st
+
+
+def test_largest_batch_matches_oracle(cqm, dev):
+    """The largest batch accepted, 4096 jobs, in one call: small images of
+    ragged sizes (1 x 1 to 24 x 24, few distinct channel values, so N' is
+    often at most K), K from 1 to 64, every initialization scheme, pruned and
+    unpruned, some subsampled, different stopping settings; every job bit for
+    bit against the oracle."""
+    n_jobs = 4096
+    _say(f"largest batch: {n_jobs} jobs")
+    schemes = (oracle.INIT_FORGY, oracle.INIT_MAXMIN, oracle.INIT_KMEANSPP, oracle.INIT_VAR, oracle.INIT_SFF,
+               oracle.INIT_WU, oracle.INIT_LBG, oracle.INIT_DEN)
+    rng = np.random.default_rng(2024)
+    specs, imgs = [], []
+    for i in range(n_jobs):
+        H, W = int(rng.integers(1, 25)), int(rng.integers(1, 25))
+        K = int(rng.integers(1, 65))
+        specs.append((K, schemes[i % len(schemes)], 100 + i, bool(i % 2), (1, 5, 20)[i % 3],
+                      (1e-4, 0.0)[i % 4 == 3], i % 5 == 4))
+        imgs.append(np.array(rng.integers(0, 6, (H, W, 3)) * 51, np.uint8))
+    jobs = [cqm.BatchJob(torch.from_numpy(im).to(dev), K, sc, seed, mi, tol, prune, subsample=sub)
+            for im, (K, sc, seed, prune, mi, tol, sub) in zip(imgs, specs)]
+    ws = cqm.BatchWorkspace(jobs, dev)
+    stats = cqm.cq_quantize_batch(jobs, ws)
+
+    # the oracle's C calls release the interpreter lock and share no state,
+    # so a thread pool runs them side by side (each call clears its own
+    # 2^24-entry tables, about 35 ms)
+    def reference(a):
+        im, (K, sc, seed, prune, mi, tol, sub) = a
+        return oracle.quantize(im, K, sc, seed, mi, tol, prune=prune, subsample=sub)
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as pool:
+        refs = list(pool.map(reference, zip(imgs, specs)))
+    for i, (job, im, st, (K, sc, seed, prune, mi, tol, sub), ref) in enumerate(
+            zip(jobs, imgs, stats, specs, refs)):
+        rp, ri, rr, rs = ref
+        what = f"job {i}: {im.shape[0]}x{im.shape[1]} K={K} scheme={sc} prune={prune} subsample={sub}"
+        assert np.array_equal(job.palette.cpu().numpy(), rp), what
+        assert np.array_equal(job.idx.cpu().numpy(), ri), what
+        assert np.array_equal(job.rgb.cpu().numpy(), rr), what
+        for key in ("iters", "converged", "k_used", "n_unique", "ndc_total", "near_ties", "sse_final",
+                    "mse_float", "mse_img"):
+            assert st[key] == rs[key], (what, key)
 
 
 def test_batch_rerun_is_deterministic(cqm, dev):
