@@ -191,6 +191,26 @@ def test_kmeans_coincident_user_centres(cqm, dev, ws_small):
         _compare_kmeans(g, r)
 
 
+def test_kmeans_empty_clusters_keep_their_centres(cqm, dev, ws_small):
+    """Two centres far outside the colour cube are nearest to no colour in any
+    iteration: their clusters stay empty and they keep their position (their
+    palette entries clamped to the cube); everything else equals the oracle,
+    pruned and unpruned."""
+    _say("kmeans empty clusters")
+    img = synth.smooth_field_blobs(96, 128, 5)
+    rk, rc, dk, dc = _hist_pair(img, cqm, dev, ws_small)
+    c0, _ = oracle.init(rk, rc, 20, oracle.INIT_KMEANSPP, 5)
+    c0[4] = (-300.0, 400.0, -300.0)
+    c0[17] = (1000.5, 1000.25, -1000.0)
+    for prune in (False, True):
+        r = oracle.kmeans(rk, rc, c0, 60, 0.0, prune)
+        g = cqm.cq_kmeans(dk, dc, _to_dev(c0, dev), 60, 0.0, prune, ws_small)
+        _compare_kmeans(g, r)
+        centres = g.centers.cpu().numpy()
+        assert np.array_equal(centres[4], c0[4]) and np.array_equal(centres[17], c0[17])
+        assert not np.any(g.assign.cpu().numpy() == 4) and not np.any(g.assign.cpu().numpy() == 17)
+
+
 def test_kmeans_max_iters_one_and_nonfinite_start(cqm, dev, ws_small):
     _say("kmeans max_iters=1 / non-finite start")
     img = synth.blobs_on_gradient(64, 64, 7)
