@@ -447,7 +447,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 distances, u32/u64 integer histogram and sums",
+        "dtype": "f64",
+        "dtype_detail": "f64 distances and centres; u32/u64 integer histogram counts and cluster sums",
         "data": "synthetic (seeded natural-image stand-ins)",
         "config": {"workload": "8 images 512x512x3 uint8 (seeds 1-8) per step, one batched call, "
                                "K=256, k-means++ init, sort-means pruned, tol 1e-4, max 100 iters, "
