@@ -878,3 +878,56 @@ def test_scaling_every_count_by_a_power_of_two_scales_only_the_sse():
         assert np.array_equal(np.array(a.sse_trace) * 16.0, np.array(b.sse_trace))
         for key in ("iters", "converged", "ndc_total", "near_ties", "mse_float"):
             assert a.stats[key] == b.stats[key], key
+
+
+def _sq_dist(a, b):
+    """Squared FP64 distances between the rows of a and b, (dx dx + dy dy) + dz dz."""
+    d = a[:, None, :] - b[None, :, :]
+    return (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+
+
+@pytest.mark.parametrize("seed,K", [(0, 8), (1, 16), (2, 32), (3, 12)])
+def test_sort_means_ndc_is_the_count_of_centres_within_twice_the_distance(seed, K):
+    """Section 2.2 counts, per colour and sort-means iteration, the centres
+    that are no more than twice as far from the colour's previous centre as
+    the colour itself (that centre included); the first iteration compares
+    every colour with all K centres.  A separate dense Lloyd in numpy (argmin
+    with the lowest index on ties, weighted means from integer sums, empty
+    clusters kept) gives the same memberships and centres as the oracle's
+    pruned run, and those counts, with the bound's 1e-12 relative slack, sum
+    to its NDC."""
+    img = synth.blobs_on_gradient(40, 48, seed)
+    keys, counts = oracle.histogram(img)
+    c0, _ = oracle.init(keys, counts, K, oracle.INIT_KMEANSPP, seed)
+    c0 = np.array(c0, np.float64).reshape(-1, 3)
+    if seed == 3:
+        c0[K - 1] = c0[0]  # coincident centres: distance 0 in the table
+    r = oracle.kmeans(keys, counts, c0, 12, 0.0, True)
+    X = np.stack([(keys >> 16) & 255, (keys >> 8) & 255, keys & 255], -1).astype(np.float64)
+    w = counts.astype(np.int64)
+    C = c0.copy()
+    prev_assign = None
+    ndc = 0
+    for it in range(1, r.stats["iters"] + 1):
+        D = _sq_dist(X, C)
+        A = np.argmin(D, axis=1)
+        if it == 1:
+            ndc += len(keys) * K
+        else:
+            prev = D[np.arange(len(keys)), prev_assign]
+            limit = 4.0 * prev * (1.0 + 1e-12)
+            DC = _sq_dist(C, C)
+            within = DC[prev_assign] <= limit[:, None]
+            within[np.arange(len(keys)), prev_assign] = False
+            ndc += int((1 + within.sum(axis=1)).sum())
+        Xi = X.astype(np.int64)
+        for k in range(K):
+            m = A == k
+            n = int(w[m].sum())
+            if n:
+                C[k] = (w[m][:, None] * Xi[m]).sum(axis=0).astype(np.float64) / float(n)
+        prev_assign = A
+    assert np.array_equal(A, r.assign)
+    assert np.array_equal(C, r.centers)
+    assert ndc == r.stats["ndc_total"]
+    assert ndc < r.stats["iters"] * len(keys) * K
