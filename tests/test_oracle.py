@@ -931,3 +931,158 @@ def test_sort_means_ndc_is_the_count_of_centres_within_twice_the_distance(seed, 
     assert np.array_equal(C, r.centers)
     assert ndc == r.stats["ndc_total"]
     assert ndc < r.stats["iters"] * len(keys) * K
+
+
+# ---------------------------------------------------------------- near ties
+
+def _near_tie_count(evaluated):
+    """Rows of evaluated distances (inf where not evaluated): a row is a near
+    tie when it has two finite entries or more and its two smallest (of the
+    multiset, so an exact repeat counts) differ by at most 1e-5 of the
+    second."""
+    s = np.sort(evaluated, axis=1)
+    d1, d2 = s[:, 0], s[:, 1]
+    return int(((d2 != np.inf) & ((d2 - d1) <= 1e-5 * d2)).sum())
+
+
+def _lattice_image(seed, H=40, W=48, step=64):
+    """60 colours on a lattice of spacing `step` per channel, each moved by
+    at most 1 per channel: many colours sit exactly half-way between two
+    lattice colours, so the first full search meets exact distance ties."""
+    rng = np.random.default_rng(seed)
+    base = rng.choice(np.arange(0, 256, step), size=(60, 3))
+    img = base[rng.integers(0, 60, H * W)] + rng.integers(-1, 2, (H * W, 3))
+    return np.clip(img, 0, 255).reshape(H, W, 3).astype(np.uint8)
+
+
+@pytest.mark.parametrize("seed,K,prune,lattice", [(0, 8, True, True), (1, 16, True, True), (2, 16, False, True),
+                                                  (3, 8, False, True), (4, 24, True, False),
+                                                  (5, 12, True, False)])
+def test_near_tie_count_matches_brute_force(seed, K, prune, lattice):
+    """The near-tie count is, per colour and iteration, whether the two
+    smallest distances the search evaluated differ by at most 1e-5 relative:
+    all K in a full search, and in a sort-means pass the previous centre and
+    every centre within twice its distance (the evaluated set of Section 2.2,
+    counted as in the NDC pin below).  A separate dense numpy Lloyd supplies
+    the centres of every iteration; the count is recomputed from the sorted
+    rows of evaluated distances."""
+    img = _lattice_image(seed) if lattice else synth.blobs_on_gradient(40, 48, seed)
+    keys, counts = oracle.histogram(img)
+    c0, _ = oracle.init(keys, counts, K, oracle.INIT_KMEANSPP, seed)
+    c0 = np.array(c0, np.float64).reshape(-1, 3)
+    if not lattice:
+        c0[K - 1] = c0[0]  # coincident centres: an exact tie in every first-iteration row
+    r = oracle.kmeans(keys, counts, c0, 12, 0.0, prune)
+    X = np.stack([(keys >> 16) & 255, (keys >> 8) & 255, keys & 255], -1).astype(np.float64)
+    Xi = X.astype(np.int64)
+    w = counts.astype(np.int64)
+    C = c0.copy()
+    prev_assign = None
+    ties = 0
+    rows = np.arange(len(keys))
+    for it in range(1, r.stats["iters"] + 1):
+        D = _sq_dist(X, C)
+        A = np.argmin(D, axis=1)
+        if it == 1 or not prune:
+            ties += _near_tie_count(D)
+        else:
+            prev = D[rows, prev_assign]
+            within = _sq_dist(C, C)[prev_assign] <= (4.0 * prev * (1.0 + 1e-12))[:, None]
+            within[rows, prev_assign] = True
+            ties += _near_tie_count(np.where(within, D, np.inf))
+        for k in range(K):
+            m = A == k
+            n = int(w[m].sum())
+            if n:
+                C[k] = (w[m][:, None] * Xi[m]).sum(axis=0).astype(np.float64) / float(n)
+        prev_assign = A
+    assert np.array_equal(A, r.assign) and np.array_equal(C, r.centers)
+    assert ties > 0  # the pin must see near ties to mean anything
+    assert ties == r.stats["near_ties"]
+
+
+def test_near_tie_in_a_sort_means_pass_at_a_fixed_point():
+    """Centres at red 40 and 120 are the means of their clusters (colours 0
+    and 80 once each and 40 ten times; 120 ten times), so they never move.
+    Colour 80 is at distance 1600 from both: an exact tie in the full first
+    iteration, and again in the sort-means pass of iteration 2, whose bound
+    4 x 1600 admits centre 1 (at 6400 from centre 0).  The run stops at
+    iteration 2 (no SSE drop, tol 0), with one near tie per iteration."""
+    keys = np.array([0, 40 << 16, 80 << 16, 120 << 16], np.uint32)
+    counts = np.array([1, 10, 1, 10], np.uint32)
+    for prune in (False, True):
+        r = oracle.kmeans(keys, counts, [[40, 0, 0], [120, 0, 0]], 10, 0.0, prune)
+        assert list(r.assign) == [0, 0, 0, 1] and r.stats["iters"] == 2
+        assert np.array_equal(r.centers, [[40, 0, 0], [120, 0, 0]])
+        assert r.stats["near_ties"] == 2
+        # iteration 2: colours 0 and 80 also evaluate centre 1 (6400 <= 4 x 1600)
+        assert r.stats["ndc_total"] == (8 + 2 + 1 + 2 + 1 if prune else 16)
+
+
+def test_near_ties_of_exact_ties_and_a_lone_centre():
+    """Closed cases: a colour equidistant from two centres is a near tie in
+    every full search; with K = 1 no second distance exists, so none is."""
+    keys = np.array([0x000000, 0x0A0000, 0x140000], np.uint32)  # r = 0, 10, 20
+    counts = np.array([1, 5, 1], np.uint32)
+    # centres 0 and 20: colour 10 is at 100 from both, the others at 0 and 400
+    r = oracle.kmeans(keys, counts, [[0, 0, 0], [20, 0, 0]], 1, 0.0, prune=False)
+    assert r.stats["near_ties"] == 1 and list(r.assign) == [0, 0, 1]
+    r1 = oracle.kmeans(keys, counts, [[10, 0, 0]], 5, 0.0, prune=True)
+    assert r1.stats["near_ties"] == 0
+
+
+# ------------------------------------------------------------ palette rounding
+
+def test_palette_rounds_exact_halves_up():
+    """The palette is floor(c + 0.5): a centre exactly half-way between two
+    integers goes up (round half to even would send 0.5, 2.5, ... down).  Two
+    colours (v, v, v) and (v + 1, v + 1, v + 1) with equal counts have the
+    exact mean v + 0.5 under K = 1."""
+    for v in range(0, 255):
+        keys = np.array([v * 0x010101, (v + 1) * 0x010101], np.uint32)
+        counts = np.array([3, 3], np.uint32)
+        r = oracle.kmeans(keys, counts, [[0, 0, 0]], 2, 0.0, prune=False)
+        assert r.centers[0, 0] == v + 0.5
+        assert list(r.palette[0]) == [v + 1] * 3, v
+    # just below a half stays down: (v, v + 1) with counts 2 : 1 is v + 1/3
+    keys = np.array([0x020202, 0x030303], np.uint32)
+    r = oracle.kmeans(keys, np.array([2, 1], np.uint32), [[0, 0, 0]], 2, 0.0, prune=False)
+    assert list(r.palette[0]) == [2, 2, 2]
+    # through the whole quantizer: a 1 x 2 image of those two colours, K = 1
+    img = np.array([[[4, 4, 4], [5, 5, 5]]], np.uint8)
+    pal, idx, _, st = oracle.quantize(img, 1, oracle.INIT_FORGY, 0, 5, 0.0, prune=False)
+    assert list(pal[0]) == [5, 5, 5] and st["mse_img"] == 0.5 * 3
+
+
+# --------------------------------------------------------- rejection sampling
+
+def _uniform_below_reference(raw, T):
+    """Rejection sampling from its definition with Python integers: the 2^64
+    raw outputs split into floor(2^64 / T) whole copies of [0, T) from the
+    top, and the 2^64 mod T lowest outputs are redrawn.  Yields (value, raw
+    outputs consumed) per draw."""
+    reject_below = (1 << 64) % T
+    used = 0
+    for r in raw:
+        used += 1
+        if r >= reject_below:
+            yield r % T, used
+            used = 0
+
+
+@pytest.mark.parametrize("T", [(1 << 63) + 1, (1 << 63) + 12345, 3 << 62, (1 << 64) - 1, 7, 1000003])
+def test_uniform_below_rejects_exactly_the_low_band(T):
+    """Values of uniform_below on the pinned splitmix64 stream equal
+    rejection sampling computed from the published raw outputs.  Above 2^63
+    almost half of the outputs are redrawn, so a plain r mod T (or a wrong
+    threshold) gives a different sequence after the first rejection."""
+    seed, n = 99, 400
+    raw = oracle.splitmix64(seed, 4 * n)
+    ref = list(_uniform_below_reference(raw, T))[:n]
+    assert len(ref) == n
+    got = oracle.uniform_below(seed, T, n)
+    assert got == [v for v, _ in ref]
+    rejected = sum(u - 1 for _, u in ref)
+    if T > (1 << 63) and T < (1 << 64) - 1:
+        assert rejected > n // 4  # the band is large: many redraws happened
+        assert got != [r % T for r in raw[:n]]
