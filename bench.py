@@ -1,16 +1,19 @@
 """Benchmark: exact weighted sort-means colour quantization on one MI355X.
 
-Workload: the eight 512 x 512 natural-image stand-ins (seeds 1..8), K = 256,
-k-means++ initialization, sort-means pruning, tol 1e-4, at most 100
-iterations, full pixel map (index and RGB images).  One step quantizes all
-eight images end to end (histogram, init, iterations, palette, map) from
+Headline workload: the mixed batch of 512 natural-image stand-ins (long side
+log-uniform in 64-2048, aspect 1-2, seeds 1,000,000 + i) with K = 256 for every
+image, k-means++ initialization, sort-means pruning, tol 1e-4, at most 100
+iterations, full pixel map (index and RGB images).  One step quantizes all 512
+images end to end (histogram, init, iterations, palette, map) from
 device-resident inputs with one batched call; the same images quantized one
-call per image (the plain path) are timed beside it.
+call per image (the plain path) are timed beside it.  The same batch with each
+image's own K (drawn from {16, ..., 256}) and the eight 512 x 512 stand-ins
+are reported as extra keys.
 
-Prints one JSON line: images/s, the distance-evaluation rate of the
-assignment kernel, the MSE relative error against the CPU oracle, a roofline
-entry for the dominant kernel (timed live with HIP events on the launch
-stream) and the oracle's own throughput on the host CPU.
+Prints one JSON line: images/s, the distance-evaluation rates, the MSE
+relative error against the CPU oracle on a sample, a roofline entry for the
+dominant kernel (timed live with HIP events on the launch stream) and the
+oracle's own throughput on the host CPU.
 """
 from __future__ import annotations
 
@@ -29,6 +32,7 @@ K = 256
 SEEDS = list(range(1, 9))
 MAX_ITERS = 100
 TOL = 1e-4
+C4_IMAGES = 512                # the mixed batch: seeds 1,000,000 + i
 
 PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
@@ -340,12 +344,141 @@ def recorded_traffic():
     return rec.get("traffic_bytes_per_launch")
 
 
+def cpu_info():
+    """CPU model and logical CPU count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def worker_count():
+    """Host processes or threads for input generation and the oracle sample:
+    the CPUs this process may run on, at most 16 (one GPU's share of a host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def make_jobs(cq, imgs, shapes, k_of, dev):
+    return [cq.BatchJob(img, k_of(i), cq.INIT_KMEANSPP, shapes[i][3], MAX_ITERS, TOL, True)
+            for i, img in enumerate(imgs)]
+
+
+def time_batched(cq, torch, jobs, bws, steps, warmup, timer=None):
+    """Warm-up steps, then `steps` timed batched calls bracketed by device
+    synchronizations; returns (seconds, stats of the last step, all stats)."""
+    for _ in range(warmup):
+        cq.cq_quantize_batch(jobs, bws)
+    torch.cuda.synchronize()
+    if timer is not None:
+        timer.enable()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(steps):
+        stats.append(cq.cq_quantize_batch(jobs, bws))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, stats[-1], stats
+
+
+def time_plain(cq, torch, jobs, dev, warm=8):
+    """The plain path: one cq_quantize call per image (each synchronizes), over
+    one workspace sized for the largest image; returns images/s."""
+    big = max(jobs, key=lambda j: j.img.shape[0] * j.img.shape[1])
+    ws = cq.Workspace(big.img.shape[0], big.img.shape[1], 256, dev)
+
+    def one(j):
+        cq.cq_quantize(j.img, j.palette.shape[0], cq.INIT_KMEANSPP, j.c.seed, MAX_ITERS, TOL, True, ws,
+                       palette=j.palette, out_idx=j.idx, out_rgb=j.rgb)
+
+    for j in jobs[:warm]:
+        one(j)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in jobs:
+        one(j)
+    torch.cuda.synchronize()
+    return len(jobs) / (time.perf_counter() - t0)
+
+
+def oracle_sample(host_imgs, shapes, k_of, budget_s, workers):
+    """The oracle on images of the batch in order, `workers` at a time (the
+    C library releases the GIL, so threads run it side by side), until about
+    `budget_s` seconds have passed; returns (results by image, seconds)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor, FIRST_COMPLETED, wait
+
+    res = {}
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        pending = {}
+        nxt = 0
+
+        def submit(i):
+            h, w, _, seed = shapes[i]
+            return pool.submit(oracle.quantize, host_imgs[i], k_of(i), oracle.INIT_KMEANSPP, seed, MAX_ITERS,
+                               TOL, True, False)
+
+        while nxt < len(host_imgs) and len(pending) < workers:
+            pending[submit(nxt)] = nxt
+            nxt += 1
+        while pending:
+            done, _ = wait(pending, return_when=FIRST_COMPLETED)
+            for f in done:
+                res[pending.pop(f)] = f.result()[3]
+            if nxt < len(host_imgs) and time.perf_counter() - t0 < budget_s:
+                pending[submit(nxt)] = nxt
+                nxt += 1
+    return res, time.perf_counter() - t0
+
+
+def oracle_stages(host_imgs, shapes, k_of, n=4):
+    """Single-threaded oracle time per stage (histogram, init, iterations,
+    map) on the first n images of the batch, in ms summed over them."""
+    import numpy as np
+
+    import oracle
+    out = {"histogram_ms": 0.0, "init_ms": 0.0, "kmeans_ms": 0.0, "map_ms": 0.0, "images": n, "pixels": 0}
+    for i in range(n):
+        img = host_imgs[i]
+        _, _, _, seed = shapes[i]
+        t = time.perf_counter()
+        keys, counts = oracle.histogram(img)
+        t1 = time.perf_counter()
+        c0, _ = oracle.init(keys, counts, k_of(i), oracle.INIT_KMEANSPP, seed)
+        t2 = time.perf_counter()
+        km = oracle.kmeans(keys, counts, c0, MAX_ITERS, TOL, True)
+        t3 = time.perf_counter()
+        oracle.map_image(img, km.palette)
+        t4 = time.perf_counter()
+        out["histogram_ms"] += 1e3 * (t1 - t)
+        out["init_ms"] += 1e3 * (t2 - t1)
+        out["kmeans_ms"] += 1e3 * (t3 - t2)
+        out["map_ms"] += 1e3 * (t4 - t3)
+        out["pixels"] += int(np.prod(img.shape[:2]))
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--images", type=int, default=C4_IMAGES,
+                    help="images of the mixed batch (the workload is defined at 512)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-call-per-image timings")
+    ap.add_argument("--no-drawn-k", action="store_true", help="skip the mixed batch with each image's own K")
+    ap.add_argument("--no-8x512", action="store_true", help="skip the eight 512x512 stand-ins")
     ap.add_argument("--no-large", action="store_true", help="skip the 4096x4096 histogram/map bandwidth figures")
     ap.add_argument("--no-serving", action="store_true", help="skip the continuous-batching latency figures")
     ap.add_argument("--no-init-schemes", action="store_true", help="skip the per-initialization figures")
@@ -355,8 +488,11 @@ def parse():
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="finish with plain device-to-device copies of this many MiB (a known-size kernel "
                          "for scaling memory counters)")
-    ap.add_argument("--cpu-budget-s", type=float, default=15.0,
-                    help="approximate CPU seconds for the oracle baseline sample")
+    ap.add_argument("--gen-threads", action="store_true",
+                    help="generate the inputs on threads instead of child processes (for runs under a profiler, "
+                         "which would follow every child process)")
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0,
+                    help="approximate wall seconds for the oracle baseline sample")
     return ap.parse_args()
 
 
@@ -369,75 +505,59 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    from paper_1101_0395_amd import synth
+
+    workers = worker_count()
+    shapes = synth.batch_shapes(args.images)
+    t_gen = time.perf_counter()
+    host_c4 = synth.batch_images(shapes, workers, threads=args.gen_threads)  # before the GPU is touched
+    gen_s = time.perf_counter() - t_gen
+    print(f"[bench] {len(host_c4)} images generated in {gen_s:.1f} s by {workers} processes", file=sys.stderr,
+          flush=True)
+
     import torch
 
-    from paper_1101_0395_amd import cq, synth
+    from paper_1101_0395_amd import cq
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     cq.lib()
-    host_imgs = [synth.smooth_field_blobs(H, W, s) for s in SEEDS]
-    imgs = [torch.from_numpy(im).to(dev) for im in host_imgs]
-    jobs = [cq.BatchJob(img, K, cq.INIT_KMEANSPP, SEEDS[i], MAX_ITERS, TOL, True)
-            for i, img in enumerate(imgs)]
+    imgs_c4 = [torch.from_numpy(im).to(dev) for im in host_c4]
+    n_pix = sum(int(im.shape[0]) * int(im.shape[1]) for im in host_c4)
+    k256 = lambda i: K  # noqa: E731
+    kdrawn = lambda i: shapes[i][2]  # noqa: E731
+
+    # ---- headline: the mixed batch with K = 256 for every image
+    jobs = make_jobs(cq, imgs_c4, shapes, k256, dev)
     bws = cq.BatchWorkspace(jobs, dev)
-
-    def step():
-        return cq.cq_quantize_batch(jobs, bws)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
     # every TIMER_EVERY-th launch of the roofline kernel is bracketed with HIP
     # events on its stream (bracketing all of them would slow the step itself)
     timer = cq.KernelTimer(ROOFLINE_KERNEL, max_launches=args.steps * (MAX_ITERS + 16), every=TIMER_EVERY)
-    timer.enable()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for _ in range(args.steps):
-        stats.extend(step())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    elapsed, last, all_stats = time_batched(cq, torch, jobs, bws, args.steps, args.warmup, timer)
     timed, timed_ms = timer.read()
     launches = timer.seen
     timer.disable()
     if timed == 0:
         raise RuntimeError(f"no launch of {ROOFLINE_KERNEL} was timed")
+    print(f"[bench] headline: {1e3 * elapsed / args.steps:.1f} ms per step", file=sys.stderr, flush=True)
     avg_launch_ms = timed_ms / timed
     kern_ms = avg_launch_ms * launches  # all launches of the kernel in the timed region
-    elapsed = t1 - t0
-
-    # the plain path: one image per call, same images and settings
-    ws1 = cq.Workspace(H, W, K, dev)
-    pal = torch.zeros((K, 3), dtype=torch.uint8, device=dev)
-    oidx = torch.empty((H, W), dtype=torch.uint8, device=dev)
-    orgb = torch.empty((H, W, 3), dtype=torch.uint8, device=dev)
-    plain_steps = max(1, min(args.steps, 2))
-    for img_i, img in enumerate(imgs):  # warm-up
-        cq.cq_quantize(img, K, cq.INIT_KMEANSPP, SEEDS[img_i], MAX_ITERS, TOL, True, ws1,
-                       palette=pal, out_idx=oidx, out_rgb=orgb)
-    torch.cuda.synchronize()
-    tp0 = time.perf_counter()
-    for _ in range(plain_steps):
-        for img_i, img in enumerate(imgs):
-            cq.cq_quantize(img, K, cq.INIT_KMEANSPP, SEEDS[img_i], MAX_ITERS, TOL, True, ws1,
-                           palette=pal, out_idx=oidx, out_rgb=orgb)
-    torch.cuda.synchronize()
-    plain_ips = plain_steps * len(SEEDS) / (time.perf_counter() - tp0)
-
-    n_img = args.steps * len(SEEDS)
+    stats = [s for st in all_stats for s in st]
+    n_img = len(stats)
     ndc = sum(s["ndc_total"] for s in stats)
     dense = sum(s["n_unique"] * K * s["iters"] for s in stats)
     # distance evaluations of the sort-means passes: all but the first
-    # iteration, which is a full search over the K centres
+    # iteration, which is a full search over the K centres (jobs with N' <= K
+    # run no iteration)
     walk_ndc = sum(s["ndc_total"] - s["n_unique"] * K for s in stats if s["iters"] >= 1)
     achieved_tflops = FLOP_PER_EVAL * walk_ndc / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
     batched_ips = n_img / elapsed
 
+    plain_ips = None if args.no_plain else time_plain(cq, torch, jobs, dev)
     line = {
-        "metric": "images/sec (512x512 RGB, K=256, k-means++, sort-means, full map)",
+        "metric": "images/sec (mixed batch of 512 RGB images, long side 64-2048, K=256, k-means++, "
+                  "sort-means, full map)",
         "value": batched_ips,
         "unit": "images/s",
         "n_gpus": 1,
@@ -450,14 +570,17 @@ def main():
         "dtype": "f64",
         "dtype_detail": "f64 distances and centres; u32/u64 integer histogram counts and cluster sums",
         "data": "synthetic (seeded natural-image stand-ins)",
-        "config": {"workload": "8 images 512x512x3 uint8 (seeds 1-8) per step, one batched call, "
-                               "K=256, k-means++ init, sort-means pruned, tol 1e-4, max 100 iters, "
-                               "full pixel map (index and RGB)",
-                   "images_per_step": len(SEEDS), "K": K, "H": H, "W": W,
-                   "mean_unique_colours": float(np.mean([s["n_unique"] for s in stats])),
-                   "mean_iters": float(np.mean([s["iters"] for s in stats]))},
+        "config": {"workload": f"{args.images} images uint8 HxWx3, long side log-uniform in [64, 2048], aspect "
+                               "U[1, 2], seeds 1,000,000 + i, per step one batched call, K=256 for every "
+                               "image, k-means++ init, sort-means pruned, tol 1e-4, max 100 iters, full "
+                               "pixel map (index and RGB)",
+                   "images_per_step": len(jobs), "K": K, "pixels_per_step": n_pix,
+                   "total_unique_colours": int(sum(s["n_unique"] for s in last)),
+                   "mean_iters": float(np.mean([s["iters"] for s in last])),
+                   "max_iters_run": int(max(s["iters"] for s in last))},
         "plain_images_per_s": plain_ips,
-        "batched_vs_plain": batched_ips / plain_ips,
+        "batched_vs_plain": batched_ips / plain_ips if plain_ips else None,
+        "pixels_per_s": n_pix * args.steps / elapsed,
         "evals_per_s_assign": walk_ndc / (kern_ms * 1e-3) if kern_ms > 0 else None,
         "evals_per_s_wall": ndc / elapsed,
         "dense_equiv_evals_per_s_wall": dense / elapsed,
@@ -474,7 +597,46 @@ def main():
             "timed_launches": timed,
             "avg_launch_us": 1e3 * avg_launch_ms,
         },
+        "input_generation_s": gen_s,
     }
+    headline_stats = last
+    del bws, jobs
+    torch.cuda.empty_cache()
+
+    if not args.no_drawn_k:
+        jobs = make_jobs(cq, imgs_c4, shapes, kdrawn, dev)
+        bws = cq.BatchWorkspace(jobs, dev)
+        sec, st, _ = time_batched(cq, torch, jobs, bws, max(1, min(args.steps, 3)), 1)
+        reps = max(1, min(args.steps, 3))
+        d = {"workload": "the same mixed batch, each image with its own K drawn from {16, 32, 64, 128, 256}",
+             "images_per_s": len(jobs) * reps / sec, "ms_per_step": 1e3 * sec / reps,
+             "evals_per_s_wall": sum(s["ndc_total"] for s in st) * reps / sec,
+             "total_unique_colours": int(sum(s["n_unique"] for s in st)),
+             "mean_iters": float(np.mean([s["iters"] for s in st]))}
+        if not args.no_plain:
+            p = time_plain(cq, torch, jobs, dev)
+            d["plain_images_per_s"] = p
+            d["batched_vs_plain"] = d["images_per_s"] / p
+        line["mixed_batch_drawn_k"] = d
+        del bws, jobs
+        torch.cuda.empty_cache()
+
+    host_imgs = [synth.smooth_field_blobs(H, W, s) for s in SEEDS]
+    imgs = [torch.from_numpy(im).to(dev) for im in host_imgs]
+    if not args.no_8x512:
+        jobs = [cq.BatchJob(img, K, cq.INIT_KMEANSPP, SEEDS[i], MAX_ITERS, TOL, True) for i, img in enumerate(imgs)]
+        bws = cq.BatchWorkspace(jobs, dev)
+        sec, st, _ = time_batched(cq, torch, jobs, bws, 20, 3)
+        d = {"workload": "8 images 512x512x3 (seeds 1-8), one batched call per step, K=256, k-means++, "
+                         "sort-means, tol 1e-4, max 100 iters, full map",
+             "images_per_s": len(jobs) * 20 / sec, "ms_per_step": 1e3 * sec / 20,
+             "mean_unique_colours": float(np.mean([s["n_unique"] for s in st])),
+             "mean_iters": float(np.mean([s["iters"] for s in st]))}
+        if not args.no_plain:
+            p = time_plain(cq, torch, jobs, dev)
+            d["plain_images_per_s"] = p
+            d["batched_vs_plain"] = d["images_per_s"] / p
+        line["batch_8x512"] = d
 
     if not args.no_large:
         line["hbm_bound_steps_4096"] = measure_large(cq, synth, torch, dev)
@@ -490,29 +652,29 @@ def main():
         line["wsm_time_vs_k_8x512"] = measure_k_sweep(cq, torch, imgs, dev)
 
     if not args.no_cpu_baseline:
-        import oracle
-
-        t = time.perf_counter()
-        done = 0
+        res, cpu_s = oracle_sample(host_c4, shapes, k256, args.cpu_budget_s, workers)
         mse_err = []
-        for i, im in enumerate(host_imgs):
-            _, _, _, rs = oracle.quantize(im, K, oracle.INIT_KMEANSPP, SEEDS[i], MAX_ITERS, TOL,
-                                          prune=True, want_images=True)
-            done += 1
-            g = stats[i]
-            mse_err.append(abs(g["mse_img"] - rs["mse_img"]) / rs["mse_img"])
-            if time.perf_counter() - t > args.cpu_budget_s:
-                break
-        cpu_s = time.perf_counter() - t
+        for i, rs in res.items():
+            g = headline_stats[i]
+            mse_err.append(abs(g["mse_img"] - rs["mse_img"]) / rs["mse_img"] if rs["mse_img"] else
+                           abs(g["mse_img"]))
+        model, ncpu = cpu_info()
+        sample_px = sum(int(host_c4[i].shape[0]) * int(host_c4[i].shape[1]) for i in res)
         line["cpu_baseline"] = {
-            "value": done / cpu_s,
+            "value": len(res) / cpu_s,
             "unit": "images/s",
-            "cores": 1,
+            "cores": workers,
             "kind": "oracle",
-            "sample": f"{done} of the 8 images, single-threaded C oracle, same settings",
+            "sample": f"the first {len(res)} images of the mixed batch (K=256, same settings, {sample_px} pixels), "
+                      f"the single-threaded C oracle run on {workers} threads at once, one image each",
+            "cpu_model": model,
+            "host_cpus": ncpu,
+            "pixels_per_s": sample_px / cpu_s,
+            "stages_1_core": oracle_stages(host_c4, shapes, k256),
         }
         line["mse_rel_err_max"] = max(mse_err)
         line["mse_rel_err_mean"] = float(np.mean(mse_err))
+        line["mse_rel_err_images"] = len(mse_err)
     print(json.dumps(line), flush=True)
 
     if args.calibration_copy_mib > 0:

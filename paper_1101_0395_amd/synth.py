@@ -19,6 +19,7 @@ __all__ = [
     "smooth_field_blobs",
     "batch_shapes",
     "batch_image",
+    "batch_images",
     "C1_SEEDS",
     "C2_SEEDS",
 ]
@@ -137,3 +138,30 @@ def batch_shapes(n: int, base_seed: int = 1_000_000, k_choices=(16, 32, 64, 128,
 def batch_image(H: int, W: int, seed: int) -> np.ndarray:
     """Image of a mixed batch: the natural-image stand-in with its own seed."""
     return smooth_field_blobs(H, W, seed + 7_919)
+
+
+def _batch_image_args(args):
+    H, W, seed = args
+    return batch_image(H, W, seed)
+
+
+def batch_images(shapes, workers: int = 1, threads: bool = False):
+    """The images of ``batch_shapes`` output (H, W, K, seed), in order,
+    generated by ``workers`` processes (started fresh, so that a caller that
+    already uses the GPU passes nothing of it to them), or by ``workers``
+    threads of this process if ``threads`` (slower: numpy holds the
+    interpreter lock for part of the work)."""
+    args = [(H, W, seed) for H, W, _, seed in shapes]
+    if workers <= 1 or len(args) <= 1:
+        return [_batch_image_args(a) for a in args]
+    if threads:
+        from concurrent.futures import ThreadPoolExecutor
+
+        with ThreadPoolExecutor(max_workers=workers) as pool:
+            return list(pool.map(_batch_image_args, args))
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+
+    ctx = multiprocessing.get_context("spawn")
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as pool:
+        return list(pool.map(_batch_image_args, args, chunksize=4))
