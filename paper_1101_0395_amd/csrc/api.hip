@@ -143,6 +143,7 @@ static void bind_slot(JobDev& J, char* slot, const Layout& L)
     J.rec = to_dev(reinterpret_cast<Rec*>(slot + L.rec));
     J.tix = to_dev(reinterpret_cast<int32_t*>(slot + L.tix));
     J.sums = to_dev(reinterpret_cast<unsigned long long*>(slot + L.sums));
+    J.cprev = to_dev(reinterpret_cast<double*>(slot + L.cprev));
     J.hkeys = to_dev(reinterpret_cast<uint16_t*>(slot + L.hkeys));
     J.hcnt = to_dev(reinterpret_cast<uint32_t*>(slot + L.hcnt));
     J.hmat = to_dev(reinterpret_cast<uint32_t*>(slot + L.hmat));
@@ -447,9 +448,6 @@ cq_status run_init(Batch& b)
         const JobDev& J = b.h[j];
         return J.scheme == CQ_INIT_WU && J.n > J.K ? wu_accum_blocks(J.n) : 0;
     });
-    const int cap = coop_capacity();
-    std::vector<int> want(size_t(b.B), 0);
-    coop_team_sizes(coop_n.data(), want.data(), b.B, cap);
     CQ_TRY(upload(b));
     CQ_TRY(launch_init_begin(b.d_jobs(), b.B, b.s));
     if (any_forgy) CQ_TRY(launch_forgy(b.d_jobs(), b.B, b.s));
@@ -457,41 +455,18 @@ cq_status run_init(Batch& b)
     if (any_sff) CQ_TRY(launch_sff(b.d_jobs(), b.B, b.s));
     if (wu_blocks > 0) CQ_TRY(launch_wu(b.d_jobs(), b.d_maps(), b.B, wu_blocks, b.s));
     if (den_tiles > 0) CQ_TRY(launch_den(b.d_jobs(), b.d_maps(), b.B, den_tiles, den_centres, b.s));
-    int next = 0;
-    while (true) {
-        while (next < b.B && want[next] == 0) ++next;
-        if (next >= b.B) break;
-        if (cap <= 0) {
-            set_error("cooperative launch is not available on this device");
-            return CQ_EDEVICE;
-        }
-        // the next wave: consecutive jobs whose teams fit the co-resident capacity
-        const int first = next;
-        int last = first, used = 0;
-        for (int j = first; j < b.B; ++j) {
-            if (want[j] == 0) {
-                last = j + 1;
-                continue;
-            }
-            const int g = want[j] < cap ? want[j] : cap;
-            if (used > 0 && used + g > cap) break;
-            used += g;
-            last = j + 1;
-        }
-        bool lds = true;
-        for (int j = 0; j < b.B; ++j) {
-            JobDev& J = b.h[j];
-            J.init_blocks = 0;
-            if (j < first || j >= last || want[j] == 0) continue;
-            const int g = want[j] < cap ? want[j] : cap;
-            J.init_blocks = g;
-            J.init_C = (J.n + g - 1) / g;
-            if (!coop_fits_lds(J.init_C)) lds = false;
+    std::vector<CoopLaunch> plan;
+    CQ_TRY(plan_coop(coop_n, plan));
+    for (const CoopLaunch& w : plan) {
+        for (int j = 0; j < b.B; ++j) b.h[j].init_blocks = 0;
+        for (size_t q = 0; q < w.jobs.size(); ++q) {
+            JobDev& J = b.h[w.jobs[q]];
+            J.init_blocks = w.blocks[q];
+            J.init_C = (J.n + w.blocks[q] - 1) / w.blocks[q];
         }
         const int total = b.set_map(kMapInit, [&](int j) { return b.h[j].init_blocks; });
         CQ_TRY(upload(b));
-        CQ_TRY(launch_init_coop(b.d_jobs(), b.d_maps() + kMapInit * (b.B + 1), b.B, total, lds, b.s));
-        next = last;
+        CQ_TRY(launch_init_coop(b.d_jobs(), b.d_maps() + kMapInit * (b.B + 1), b.B, total, w.variant, b.s));
     }
     return run_lbg(b);
 }

@@ -86,10 +86,17 @@ cq_status launch_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t ro
                             uint32_t* counts, hipStream_t s);
 cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_hist_blocks, int total_count,
                            hipStream_t s);
-int coop_capacity();
-int coop_team_blocks(int64_t n);
-void coop_team_sizes(const int64_t* n, int* want, int B, int cap);
-bool coop_fits_lds(int64_t C);
+// One cooperative initialization launch: the kernel variant (8 or 32
+// colours per thread in registers; 0: D^2 in global memory), its jobs and
+// their team sizes.
+struct CoopLaunch {
+    int variant = 32;
+    std::vector<int> jobs;
+    std::vector<int> blocks;
+};
+int coop_capacity(int variant);
+int64_t coop_reg_colours(int R);
+cq_status plan_coop(const std::vector<int64_t>& n, std::vector<CoopLaunch>& plan);
 cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s);
 cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s);
 cq_status launch_var(const JobDev* jobs, const int* maps, int B, int tiles, int groups, hipStream_t s);
@@ -101,7 +108,7 @@ int den_tile_count(int64_t n);
 cq_status launch_den(const JobDev* jobs, const int* maps, int B, int tiles, int centres, hipStream_t s);
 cq_status launch_sff(const JobDev* jobs, int B, hipStream_t s);
 int64_t sff_subset(int32_t K, int64_t n);
-cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, bool lds, hipStream_t s);
+cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, int variant, hipStream_t s);
 cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s);
 cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool first, int all_blocks,
                              int full_blocks, int walk_blocks, int update_blocks, bool regroup,

@@ -63,7 +63,11 @@ constexpr int kSumQ = 4 * kMaxK;
 // (cluster, bucket) pair are uint32 (a count is below 2^28), two per slot
 constexpr int kSumColours = 5 * kMaxK;
 constexpr int kSumCursor = kSumColours + kMaxK * kBuckets / 2;
-constexpr int kSumStride = kSumCursor + kMaxK * kBuckets / 2;
+// (pruned runs) the largest squared distance of a cluster's colours to the
+// centre they were assigned to, as the bit pattern of a non-negative double
+// (such patterns order as the values do)
+constexpr int kSumMaxD = kSumCursor + kMaxK * kBuckets / 2;
+constexpr int kSumStride = kSumMaxD + kMaxK;
 
 // Device-side control block, one per workspace.
 struct Meta {
@@ -136,6 +140,7 @@ struct JobDev {
     uint32_t CQ_GLOBAL* counts;
     uint8_t CQ_GLOBAL* assign;
     double CQ_GLOBAL* centers;
+    double CQ_GLOBAL* cprev;  // pruned runs: the centres the current iteration assigns to
     int64_t capacity;    // entries of keys / counts
     int64_t n;           // unique colours, set once the histogram is known
     int64_t chunk;       // colours per assignment / LUT block
@@ -272,7 +277,7 @@ inline size_t desc_results_off(int B)
 // ---------------------------------------------------------------- layout
 
 struct Layout {
-    size_t lut, meta, trace, rec, tix, sums, centers, palette, part, desc;
+    size_t lut, meta, trace, rec, tix, sums, centers, cprev, palette, part, desc;
     size_t chunks, work, hkeys, hcnt, hmat, hbt, hnu, hbs, hus, keys, counts, assign;
     size_t fixed_end;  // end of the regions every call may use
     size_t total;      // end including the per-pixel and per-colour regions
@@ -295,6 +300,7 @@ inline Layout make_layout(int64_t npix, int64_t n_cap, bool with_colour_arrays)
     L.tix = o;      o = align256(o + sizeof(int32_t) * (kMaxK * kRow + kTablePad));
     L.sums = o;     o = align256(o + sizeof(uint64_t) * 2 * kSumStride);  // two iterations
     L.centers = o;  o = align256(o + sizeof(double) * 3 * kMaxK);
+    L.cprev = o;    o = align256(o + sizeof(double) * 3 * kMaxK);
     L.palette = o;  o = align256(o + 3 * kMaxK);
     L.part = o;     o = align256(o + sizeof(uint64_t) * 2 * kMaxAssignBlocks);
     L.desc = o;     o = align256(o + desc_bytes(1));

@@ -10,7 +10,10 @@
 
 #include <math.h>
 
-#include "cq_internal.h"
+#include <algorithm>
+#include <vector>
+
+#include "batch.h"
 
 namespace cq {
 
@@ -477,18 +480,20 @@ __global__ void __launch_bounds__(kMaxK) k_init_begin(const JobDev* __restrict__
 //      KPP: r = U(total) from the block's own copy of the splitmix64 stream
 //      (every block draws the same values), and the block whose inclusive
 //      prefix of block sums first exceeds r.  That block alone finds the run
-//      and the colour holding r from its own LDS and publishes the colour's
+//      and the colour holding r from its own data and publishes the colour's
 //      key, tagged, in the team's pick slot; the others wait for it.
 // Published values are written and read with agent-scope relaxed atomics and
 // each reader checks the tag of the value it uses, so no fence (and no
 // write-back or invalidation of the L2) is needed: a value that is not there
 // yet is read again.  They are double-buffered by round parity: a block
 // writes a parity again only after every block has published the next round,
-// that is after all of them have finished reading it.  Runs are stored
-// transposed (entry u of thread t at u T + t), so the threads of a wave
-// touch consecutive words.
-constexpr int kCoopLdsCap = 8192;                    // colours per block kept in LDS (96 KiB)
-constexpr int kMaxRun = kCoopLdsCap / kInitThreads;  // run length when the colours fit in LDS
+// that is after all of them have finished reading it.  Per-thread data of a
+// run is stored transposed (entry u of thread t at u T + t), so the threads
+// of a wave touch consecutive words.
+//
+// Two kernels run these rounds: k_init_reg keeps a block's colours on chip
+// (the usual case), k_init_coop reads them from global memory every round
+// (teams whose colours exceed what kInitMaxBlocks blocks hold on chip).
 constexpr int kTagShift = 46;      // KPP sums stay below 2^46 (2^28 pixels x 3 x 255^2)
 constexpr uint64_t kValMask = (1ull << kTagShift) - 1ull;
 constexpr uint32_t kIndexBits = 28;  // MMX: colour index below 2^28, D^2 below 2^18
@@ -526,10 +531,9 @@ __device__ __forceinline__ void store_tagged(uint64_t* p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// kLds: the block's colours (key, count, D^2) stay in LDS for all rounds
-// (R <= kMaxRun); otherwise they are read from global memory every round and
-// each thread keeps the D^2 of its run in global memory.
-template <bool kLds>
+// Colours of every block read from global memory in every round, each
+// thread keeping the D^2 of its run in global memory (teams too large for the
+// register kernel below).
 __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __restrict__ jobs,
                                                             const int* __restrict__ map, int B)
 {
@@ -539,9 +543,6 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
     __shared__ int64_t s_pick;
     __shared__ uint32_t s_key;
     __shared__ int s_ok;
-    __shared__ uint32_t lkey[kLds ? kCoopLdsCap : 1];
-    __shared__ uint32_t lcnt[kLds ? kCoopLdsCap : 1];
-    __shared__ uint32_t ld2[kLds ? kCoopLdsCap : 1];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int G = J.init_blocks;  // team size, <= kInitMaxBlocks
@@ -566,27 +567,6 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
     const int wave = t >> 6, lane = t & 63;
     const int qlo = t * R;  // this thread's run, block-local colour indices
     const int qn = mine_n - qlo >= R ? R : (mine_n > qlo ? mine_n - qlo : 0);
-    if constexpr (kLds) {
-        // coalesced loads, transposed stores (R <= kMaxRun)
-        uint32_t kk[kMaxRun], cc[kMaxRun];
-#pragma unroll
-        for (int p = 0; p < kMaxRun; ++p) {
-            const int q = p * kInitThreads + t;
-            const bool in = p < R && q < mine_n;
-            kk[p] = in ? keys[lo + q] : 0u;
-            cc[p] = in ? counts[lo + q] : 0u;
-        }
-#pragma unroll
-        for (int p = 0; p < kMaxRun; ++p) {
-            const int q = p * kInitThreads + t;
-            if (p < R && q < mine_n) {
-                const int x = (q % R) * kInitThreads + q / R;
-                lkey[x] = kk[p];
-                lcnt[x] = cc[p];
-                ld2[x] = 0xFFFFFFFFu;
-            }
-        }
-    }
     uint64_t rng = J.seed;  // wave 0 draws; every block draws the same values
     int cr = 0, cg = 0, cb = 0;
     for (int j = 0; j < K; ++j) {
@@ -615,29 +595,11 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
                 }
                 return m;
             };
-            if constexpr (kLds) {
-                uint32_t kq[kMaxRun], cq[kMaxRun], oq[kMaxRun];
-#pragma unroll
-                for (int u = 0; u < kMaxRun; ++u) {
-                    const int x = u * kInitThreads + t;
-                    kq[u] = u < qn ? lkey[x] : 0u;
-                    cq[u] = u < qn ? lcnt[x] : 0u;
-                    oq[u] = (u < qn && j > 1) ? ld2[x] : 0xFFFFFFFFu;
-                }
-#pragma unroll
-                for (int u = 0; u < kMaxRun; ++u) {
-                    if (u < qn) {
-                        const uint32_t m = step(u, kq[u], cq[u], oq[u]);
-                        if (j > 0) ld2[u * kInitThreads + t] = m;
-                    }
-                }
-            } else {
-                for (int u = 0; u < qn; ++u) {
-                    const int x = u * kInitThreads + t;
-                    const int64_t i = lo + qlo + u;
-                    const uint32_t m = step(u, keys[i], counts[i], j > 1 ? d2own[x] : 0xFFFFFFFFu);
-                    if (j > 0) d2own[x] = m;
-                }
+            for (int u = 0; u < qn; ++u) {
+                const int x = u * kInitThreads + t;
+                const int64_t i = lo + qlo + u;
+                const uint32_t m = step(u, keys[i], counts[i], j > 1 ? d2own[x] : 0xFFFFFFFFu);
+                if (j > 0) d2own[x] = m;
             }
             if (kpp) s_run[t] = acc;
             acc = kpp ? wave_sum(acc) : wave_max(acc);
@@ -715,14 +677,9 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
                                     uint32_t kx = 0;
                                     if (in) {
                                         const int x = u * kInitThreads + tr;
-                                        if constexpr (kLds) {
-                                            kx = lkey[x];
-                                            w = uint64_t(lcnt[x]) * (j == 0 ? 1u : ld2[x]);
-                                        } else {
-                                            const int64_t i = lo + int64_t(tr) * R + u;
-                                            kx = keys[i];
-                                            w = uint64_t(counts[i]) * (j == 0 ? 1u : d2own[x]);
-                                        }
+                                        const int64_t i = lo + int64_t(tr) * R + u;
+                                        kx = keys[i];
+                                        w = uint64_t(counts[i]) * (j == 0 ? 1u : d2own[x]);
                                     }
                                     const uint64_t incl = carry + wave_incl_scan(w);
                                     const unsigned long long hit = __ballot(in && incl > r);
@@ -784,67 +741,352 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
     }
 }
 
-// ------------------------------------------------------------------ host
-// Co-resident blocks of k_init_coop<true> on this device (0: no cooperative launch).
-int coop_capacity()
+// ------------------------------------------------------------------------
+// The same rounds with every thread's run of up to R colours on chip: the
+// keys and D^2 in VGPRs, the counts (KPP) in dynamic LDS, transposed (entry
+// u of thread t at u T + t).  A block holds up to R T colours (32768 at
+// R = 32).  A team of one block (G = 1) exchanges nothing through memory:
+// the block's total is the job's total and its own threads find the pick.  In a team of several blocks the protocol above carries the block
+// totals and the pick.  In the block that holds r, the thread that holds it
+// finds the colour among its own registers.
+template <int R>
+__global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restrict__ jobs,
+                                                           const int* __restrict__ map, int B)
 {
-    static int max_coop = -1;
-    if (max_coop < 0) {
+    extern __shared__ uint32_t lcnt[];                 // [R T] counts, transposed
+    __shared__ uint64_t s_wave[kInitThreads / 64];     // per-wave sums (KPP) or maxima (MMX)
+    __shared__ uint64_t s_run[kInitThreads];           // KPP: the threads' run sums of n D^2
+    __shared__ uint64_t s_val[kInitMaxBlocks];
+    __shared__ uint64_t s_rloc;  // r minus the weights before the owner thread's run
+    __shared__ uint32_t s_key;   // the colour picked in this round
+    __shared__ int s_owner;      // the thread of this block holding r
+    __shared__ int s_state;      // 0: a wait gave up, 1: pick in s_key, 2: this block holds r
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int G = J.init_blocks;  // team size, <= kInitMaxBlocks
+    const int tb = blockIdx.x - map[jb];
+    const uint32_t* __restrict__ keys = gp(J.keys);
+    const uint32_t* __restrict__ counts = gp(J.counts);
+    const int64_t n = J.n;
+    const int K = J.K;
+    const bool kpp = J.scheme == CQ_INIT_KMEANSPP;
+    const int64_t C = J.init_C;                                // colours per block, <= R T
+    const int Rr = int((C + kInitThreads - 1) / kInitThreads);  // run length, <= R
+    uint64_t* __restrict__ tags = gp(J.vals);                       // [2][kInitMaxBlocks]
+    uint64_t* __restrict__ pick = gp(J.vals) + 2 * kInitMaxBlocks;  // [2]: KPP picked key
+    Meta* __restrict__ meta = gp(J.meta);
+    double* __restrict__ centers = gp(J.centers);
+    const int64_t lo = int64_t(tb) * C;
+    const int64_t hi = lo + C < n ? lo + C : n;
+    const int mine_n = hi > lo ? int(hi - lo) : 0;
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    const int qlo = t * Rr;
+    const int qn = mine_n - qlo >= Rr ? Rr : (mine_n > qlo ? mine_n - qlo : 0);
+    // coalesced loads through the LDS array: the keys first (into registers),
+    // then the counts (which stay).  A thread pads its run to R entries with
+    // D^2 0 and count 0, which weigh nothing and never hold the largest D^2
+    // (some real colour of the job is farther than 0 from every centre
+    // while fewer than N' are chosen).
+    uint32_t ky[R], d2[R];
+    for (int p = 0; p < Rr; ++p) {
+        const int q = p * kInitThreads + t;
+        if (q < mine_n) lcnt[(q % Rr) * kInitThreads + q / Rr] = keys[lo + q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        ky[u] = u < qn ? lcnt[u * kInitThreads + t] : 0u;
+        d2[u] = u < qn ? 0xFFFFFFFFu : 0u;
+    }
+    __syncthreads();
+    if (kpp) {
+        for (int p = 0; p < Rr; ++p) {
+            const int q = p * kInitThreads + t;
+            if (q < mine_n) lcnt[(q % Rr) * kInitThreads + q / Rr] = counts[lo + q];
+        }
+        for (int u = qn; u < R; ++u) lcnt[u * kInitThreads + t] = 0u;
+    }
+    uint64_t rng = J.seed;  // wave 0 draws; every block draws the same values
+    uint32_t pick_key = 0;
+    for (int j = 0; j < K; ++j) {
+        const int par = j & 1;
+        const uint64_t tag = uint64_t(j + 1) << kTagShift;
+        __syncthreads();  // the previous round's readers of the shared values are done
+        // 1. own run: D^2 against the previous pick (from four-byte dot
+        // products of the packed colours: |x - c|^2 = x.x + c.c - 2 x.c; in
+        // round 0 there is no pick and nothing changes), then the run's sum
+        // of n D^2 (KPP; the counts alone in round 0) or its largest D^2,
+        // first position on ties (MMX).  All R entries, padding included,
+        // in straight-line code: the registers of the run are never under a
+        // branch.
+        const uint32_t none = j == 0 ? 0xFFFFFFFFu : 0u;
+        const uint32_t cc = __builtin_amdgcn_udot4(pick_key, pick_key, 0u, false);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            asm volatile("" : "+v"(ky[u]));  // keeps x.x from being held across rounds
+            const uint32_t xx = __builtin_amdgcn_udot4(ky[u], ky[u], 0u, false);
+            const uint32_t xc = __builtin_amdgcn_udot4(ky[u], pick_key, 0u, false);
+            const uint32_t d = (xx + cc - 2u * xc) | none;
+            d2[u] = d2[u] < d ? d2[u] : d;
+        }
+        uint64_t acc = 0;
+        if (kpp) {
+#pragma unroll
+            for (int u = 0; u < R; ++u)
+                acc += uint64_t(lcnt[u * kInitThreads + t]) * ((d2[u] & ~none) | (none & 1u));
+        } else {
+            uint32_t best_m = d2[0], best_u = 0;
+#pragma unroll
+            for (int u = 1; u < R; ++u) {
+                best_u = d2[u] > best_m ? uint32_t(u) : best_u;
+                best_m = d2[u] > best_m ? d2[u] : best_m;
+            }
+            if (qn > 0)
+                acc = (uint64_t(best_m) << kIndexBits) |
+                      uint64_t(((1u << kIndexBits) - 1u) - uint32_t(lo + qlo + int(best_u)));
+        }
+        if (!kpp && j == 0) {
+            // MMX: the first colour uniform over the colours
+            if (t == 0) {
+                s_key = keys[uniform_below(rng, uint64_t(n))];
+                s_state = 1;
+            }
+        } else {
+            if (kpp) s_run[t] = acc;
+            acc = kpp ? wave_sum(acc) : wave_max(acc);
+            if (lane == 0) s_wave[wave] = acc;
+            __syncthreads();
+            if (wave == 0) {
+                // 2. the block's value, then the team's
+                uint64_t v = lane < kInitThreads / 64 ? s_wave[lane] : 0ull;
+                v = kpp ? wave_sum(v) : wave_max(v);
+                uint64_t total = v;
+                int ok = 1;
+                uint32_t spins = 0;
+                auto keep_waiting = [&]() {
+                    if (__hip_atomic_load(&meta->sync_error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                        ++spins > kSpinLimit)
+                        return false;
+                    __builtin_amdgcn_s_sleep(1);
+                    return true;
+                };
+                if (G > 1) {
+                    if (lane == 0) store_tagged(&tags[par * kInitMaxBlocks + tb], tag | v);
+                    uint64_t part = 0;
+                    for (int c0 = 0; c0 < G; c0 += 64) {
+                        const int c = c0 + lane;
+                        uint64_t x = 0;
+                        if (c < G) {
+                            for (;;) {
+                                x = load_tagged(&tags[par * kInitMaxBlocks + c]);
+                                if ((x & ~kValMask) == tag) break;
+                                if (!keep_waiting()) {
+                                    ok = 0;
+                                    break;
+                                }
+                            }
+                            x &= kValMask;
+                            s_val[c] = x;
+                        }
+                        part = kpp ? part + x : (x > part ? x : part);
+                    }
+                    total = kpp ? wave_sum(part) : wave_max(part);
+                }
+                int state = 1;
+                if (__ballot(ok == 0) != 0ull) {
+                    state = 0;
+                } else if (kpp) {
+                    // 3. the block holding r, then (there) the thread holding it
+                    const uint64_t r = total ? uniform_below(rng, total) : 0ull;
+                    uint64_t base = 0;
+                    const int64_t c = G > 1 ? wave_find(G, r, &base, [&](int64_t x) { return s_val[x]; }) : 0;
+                    if (c == tb) {
+                        state = 2;
+                        const int64_t tr = wave_find(kInitThreads, r, &base, [&](int64_t x) { return s_run[x]; });
+                        if (lane == 0) {
+                            s_owner = tr < 0 ? 0 : int(tr);  // tr >= 0 since r < total
+                            s_rloc = r - base;
+                        }
+                    } else {
+                        uint64_t x = 0;
+                        for (;;) {
+                            x = load_tagged(&pick[par]);
+                            if ((x & ~kValMask) == tag) break;
+                            if (!keep_waiting()) {
+                                ok = 0;
+                                break;
+                            }
+                        }
+                        if (__ballot(ok == 0) != 0ull) state = 0;
+                        if (lane == 0) s_key = uint32_t(x) & 0xffffffu;
+                    }
+                } else {
+                    // MMX: the largest (D^2, -index) names the colour
+                    const int64_t pk =
+                        int64_t(((1u << kIndexBits) - 1u) - uint32_t(total & ((1u << kIndexBits) - 1u)));
+                    if (lane == 0) s_key = keys[pk < n ? pk : 0];  // every colour packs a non-zero value
+                }
+                if (state == 0 && lane == 0)
+                    __hip_atomic_store(&meta->sync_error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0) s_state = state;
+            }
+        }
+        __syncthreads();
+        const int state = s_state;
+        if (state == 0) return;
+        if (state == 2) {
+            // the owner thread walks its own run
+            if (t == s_owner) {
+                const uint64_t rl = s_rloc;
+                uint64_t acc = 0;
+                uint32_t key = ky[0];
+                bool found = false;
+#pragma unroll
+                for (int u = 0; u < R; ++u) {
+                    const uint64_t w = uint64_t(lcnt[u * kInitThreads + t]) * (j == 0 ? 1u : d2[u]);
+                    const bool hit = !found && acc + w > rl;
+                    key = hit ? ky[u] : key;
+                    acc += found || hit ? 0ull : w;
+                    found = found || hit;
+                }
+                s_key = key;
+                if (G > 1) store_tagged(&pick[par], tag | key);
+            }
+            __syncthreads();
+        }
+        pick_key = s_key;
+        if (t == 0 && tb == 0) {
+            write_center(centers, j, pick_key);
+            if (j == K - 1) meta->rng = rng;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host
+// Colours per thread of the register kernels, smallest first.
+constexpr int kCoopVariants = 4;
+constexpr int kCoopR[kCoopVariants] = {4, 8, 16, 24};
+
+// Colours per block of the register kernels (R colours per thread).
+int64_t coop_reg_colours(int R) { return int64_t(R) * kInitThreads; }
+
+static size_t coop_dyn_lds(int variant) { return variant > 0 ? sizeof(uint32_t) * size_t(variant) * kInitThreads : 0; }
+
+static const void* coop_kernel(int variant)
+{
+    switch (variant) {
+    case 4: return reinterpret_cast<const void*>(k_init_reg<4>);
+    case 8: return reinterpret_cast<const void*>(k_init_reg<8>);
+    case 16: return reinterpret_cast<const void*>(k_init_reg<16>);
+    case 24: return reinterpret_cast<const void*>(k_init_reg<24>);
+    default: return reinterpret_cast<const void*>(k_init_coop);
+    }
+}
+
+// Co-resident blocks of a cooperative initialization kernel on this device
+// (0: no cooperative launch).  variant: 4, 8, 16 or 24, the register kernels
+// with that many colours per thread; 0, the kernel that keeps D^2 in global
+// memory.
+int coop_capacity(int variant)
+{
+    static int cached[kCoopVariants + 1] = {-1, -1, -1, -1, -1};
+    int slot = kCoopVariants;
+    for (int v = 0; v < kCoopVariants; ++v)
+        if (kCoopR[v] == variant) slot = v;
+    if (cached[slot] < 0) {
         int dev = 0, cus = 0, per_cu = 0, coop_ok = 0;
-        max_coop = 0;
+        cached[slot] = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&coop_ok, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess &&
             coop_ok &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(k_init_coop<true>), kInitThreads, 0) == hipSuccess)
-            max_coop = cus * per_cu;
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, coop_kernel(variant), kInitThreads,
+                                                         coop_dyn_lds(variant)) == hipSuccess)
+            cached[slot] = cus * per_cu;
     }
-    return max_coop;
+    return cached[slot];
 }
 
-// Preferred team size for a job of n colours (before the whole-launch cap).
-int coop_team_blocks(int64_t n)
+// Launch plan of the cooperative initializations (MMX, KPP) of a batch:
+// n[j] colours of job j (0: none).  Jobs are taken largest first, in three
+// classes, each class in launches that fit the co-resident capacity of the
+// kernel that runs them:
+//  - at most 24576 colours: one register block each (a team of one block
+//    exchanges nothing through memory), with the smallest R that holds the
+//    launch's largest job;
+//  - up to kInitMaxBlocks x 24576 colours: teams of ceil(n / (R T))
+//    register blocks, with the smallest R for which the launch's teams fit
+//    the capacity (fewer colours per thread, less of each round's work per
+//    block), R = 24 when only that fits;
+//  - more: kInitMaxBlocks blocks of the kernel that keeps D^2 in global
+//    memory.
+cq_status plan_coop(const std::vector<int64_t>& n, std::vector<CoopLaunch>& plan)
 {
-    static int override_blocks = -1;
-    if (override_blocks < 0) {
-        const char* env = getenv("CQ_INIT_BLOCKS");
-        override_blocks = env ? atoi(env) : 0;
+    plan.clear();
+    std::vector<int> order;
+    for (int j = 0; j < int(n.size()); ++j)
+        if (n[j] > 0) order.push_back(j);
+    if (order.empty()) return CQ_OK;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+    int cap[kCoopVariants];
+    for (int v = 0; v < kCoopVariants; ++v) cap[v] = coop_capacity(kCoopR[v]);
+    const int cap0 = coop_capacity(0);
+    for (int v = 0; v < kCoopVariants; ++v)
+        if (cap[v] <= 0 || cap0 <= 0) {
+            set_error("cooperative launch is not available on this device");
+            return CQ_EDEVICE;
+        }
+    constexpr int kBig = kCoopVariants - 1;
+    const int64_t cmax = coop_reg_colours(kCoopR[kBig]);
+    auto blocks_at = [](int64_t cnt, int64_t per) { return int((cnt + per - 1) / per); };
+    auto cls = [&](int j) { return n[j] > cmax * kInitMaxBlocks ? 0 : (n[j] > cmax ? 1 : 2); };
+    auto fit = [&](int64_t cnt) {  // smallest variant holding cnt colours in one block
+        int v = 0;
+        while (v < kBig && coop_reg_colours(kCoopR[v]) < cnt) ++v;
+        return v;
+    };
+    size_t q = 0;
+    while (q < order.size()) {
+        const int c = cls(order[q]);
+        CoopLaunch w;
+        const int v0 = c == 2 ? fit(n[order[q]]) : kBig;  // the launch's largest job comes first
+        const int capw = c == 0 ? cap0 : cap[v0];
+        int used = 0;
+        while (q < order.size() && cls(order[q]) == c) {
+            const int j = order[q];
+            int g = 1;
+            if (c == 0) g = kInitMaxBlocks < capw ? kInitMaxBlocks : capw;
+            if (c == 1) g = blocks_at(n[j], cmax);
+            if (used > 0 && used + g > capw) break;
+            w.jobs.push_back(j);
+            w.blocks.push_back(g);
+            used += g;
+            ++q;
+        }
+        w.variant = c == 0 ? 0 : kCoopR[v0];
+        if (c == 1) {
+            // the smallest R whose teams fit
+            for (int v = 0; v < kBig; ++v) {
+                const int64_t per = coop_reg_colours(kCoopR[v]);
+                int need = 0;
+                bool ok = true;
+                for (int j : w.jobs) {
+                    const int g = blocks_at(n[j], per);
+                    ok = ok && g <= kInitMaxBlocks;
+                    need += g;
+                }
+                if (ok && need <= cap[v]) {
+                    w.variant = kCoopR[v];
+                    for (size_t i = 0; i < w.jobs.size(); ++i) w.blocks[i] = blocks_at(n[w.jobs[i]], per);
+                    break;
+                }
+            }
+        }
+        plan.push_back(std::move(w));
     }
-    int64_t g = override_blocks > 0 ? override_blocks : (n + kCoopLdsCap - 1) / kCoopLdsCap;
-    if (g < 1) g = 1;
-    if (g > kInitMaxBlocks) g = kInitMaxBlocks;
-    return int(g);
+    return CQ_OK;
 }
-
-// Team sizes of the cooperative jobs of a batch (n[j] colours; 0: no team).
-// Each job needs at least the blocks whose LDS holds its colours; when all
-// of those fit the co-resident capacity together, the spare blocks are shared
-// out in proportion to the colours (a smaller share of every round's update
-// per block), keeping at least one colour per thread.  CQ_INIT_BLOCKS forces
-// a fixed size.
-void coop_team_sizes(const int64_t* n, int* want, int B, int cap)
-{
-    int need = 0;
-    int64_t ncol = 0;
-    for (int j = 0; j < B; ++j) {
-        want[j] = n[j] > 0 ? coop_team_blocks(n[j]) : 0;
-        need += want[j];
-        ncol += n[j] > 0 ? n[j] : 0;
-    }
-    const char* env = getenv("CQ_INIT_BLOCKS");
-    if ((env && atoi(env) > 0) || cap <= 0 || need > cap || ncol == 0) return;
-    const int64_t spare = cap - need;
-    for (int j = 0; j < B; ++j) {
-        if (want[j] == 0) continue;
-        int64_t g = want[j] + spare * n[j] / ncol;
-        const int64_t most = n[j] / kInitThreads > want[j] ? n[j] / kInitThreads : want[j];
-        g = g < most ? g : most;
-        want[j] = int(g < kInitMaxBlocks ? g : kInitMaxBlocks);
-    }
-}
-
-bool coop_fits_lds(int64_t C) { return (C + kInitThreads - 1) / kInitThreads <= kMaxRun; }
 
 cq_status launch_init_begin(const JobDev* jobs, int B, hipStream_t s)
 {
@@ -1082,14 +1324,14 @@ cq_status launch_forgy(const JobDev* jobs, int B, hipStream_t s)
     return CQ_OK;
 }
 
-// One cooperative launch running the teams of `B` jobs (`total` blocks).
-cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, bool lds, hipStream_t s)
+// One cooperative launch running the teams of `B` jobs (`total` blocks) with
+// the kernel `variant` (see coop_capacity).
+cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, int variant, hipStream_t s)
 {
     void* args[] = {(void*)&jobs, (void*)&map, (void*)&B};
-    const void* fn = lds ? reinterpret_cast<const void*>(k_init_coop<true>)
-                         : reinterpret_cast<const void*>(k_init_coop<false>);
     timer_begin("k_init_coop", s);
-    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(total), dim3(kInitThreads), args, 0, s);
+    const hipError_t e = hipLaunchCooperativeKernel(coop_kernel(variant), dim3(total), dim3(kInitThreads), args,
+                                                    coop_dyn_lds(variant), s);
     timer_end("k_init_coop", s);
     if (e != hipSuccess) {
         set_error("cooperative init launch failed: %s", hipGetErrorString(e));

@@ -76,30 +76,37 @@ __device__ __forceinline__ void bin_add(unsigned long long* bins, bool valid, in
                  w * unsigned(r * r + g * g + b * b));
 }
 
-// Running statistics of the colours a lane has put into one cluster.
+// Running statistics of the colours a lane has put into one cluster, and
+// the largest squared distance among them (bit pattern of the double).
 struct Acc {
     int k;  // -1: empty
-    unsigned long long n, s0, s1, s2, q;
+    unsigned long long n, s0, s1, s2, q, dmax;
 };
 
-__device__ __forceinline__ void acc_add(Acc& a, unsigned long long* bins, int k,
-                                        unsigned long long w, int r, int g, int b)
+__device__ __forceinline__ void acc_flush(const Acc& a, unsigned long long* bins, unsigned long long* maxd)
+{
+    atomicAdd(&bins[kSumN + a.k], a.n);
+    atomicAdd(&bins[kSumS + 3 * a.k + 0], a.s0);
+    atomicAdd(&bins[kSumS + 3 * a.k + 1], a.s1);
+    atomicAdd(&bins[kSumS + 3 * a.k + 2], a.s2);
+    atomicAdd(&bins[kSumQ + a.k], a.q);
+    atomicMax(&maxd[a.k], a.dmax);
+}
+
+__device__ __forceinline__ void acc_add(Acc& a, unsigned long long* bins, unsigned long long* maxd, int k,
+                                        unsigned long long w, int r, int g, int b, double d)
 {
     if (k != a.k) {
-        if (a.k >= 0) {
-            atomicAdd(&bins[kSumN + a.k], a.n);
-            atomicAdd(&bins[kSumS + 3 * a.k + 0], a.s0);
-            atomicAdd(&bins[kSumS + 3 * a.k + 1], a.s1);
-            atomicAdd(&bins[kSumS + 3 * a.k + 2], a.s2);
-            atomicAdd(&bins[kSumQ + a.k], a.q);
-        }
-        a = Acc{k, 0ull, 0ull, 0ull, 0ull, 0ull};
+        if (a.k >= 0) acc_flush(a, bins, maxd);
+        a = Acc{k, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
     }
     a.n += w;
     a.s0 += w * unsigned(r);
     a.s1 += w * unsigned(g);
     a.s2 += w * unsigned(b);
     a.q += w * unsigned(r * r + g * g + b * b);
+    const unsigned long long db = (unsigned long long)__double_as_longlong(d);
+    a.dmax = db > a.dmax ? db : a.dmax;
 }
 
 // Distance bucket of a colour: two per octave of d + 1, from 4 up (bucket 0
@@ -160,8 +167,10 @@ __device__ __forceinline__ void flush_counters(unsigned long long ndc, unsigned 
 }
 
 // Adds the block's non-empty cluster bins and (cluster, bucket) colour
-// counts to the job's statistics.
-__device__ __forceinline__ void flush_bins(const unsigned long long* bins, const uint32_t* ccount, int K,
+// counts to the job's statistics; in pruned runs (ccount and maxd non-null)
+// also the largest squared distance of each cluster's colours.
+__device__ __forceinline__ void flush_bins(const unsigned long long* bins, const uint32_t* ccount,
+                                           const unsigned long long* maxd, int K,
                                            unsigned long long* __restrict__ sums)
 {
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
@@ -172,6 +181,7 @@ __device__ __forceinline__ void flush_bins(const unsigned long long* bins, const
         atomicAdd(&sums[kSumS + 3 * k + 1], bins[kSumS + 3 * k + 1]);
         atomicAdd(&sums[kSumS + 3 * k + 2], bins[kSumS + 3 * k + 2]);
         atomicAdd(&sums[kSumQ + k], bins[kSumQ + k]);
+        if (maxd) atomicMax(&sums[kSumMaxD + k], maxd[k]);
     }
     if (!ccount) return;
     for (int w = threadIdx.x; w < K * kBuckets / 2; w += blockDim.x) {
@@ -280,6 +290,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
     // word (a block holds at most 32768 colours)
     __shared__ uint32_t ccount[kMaxK * kBuckets / 2];
     __shared__ unsigned long long red[2 * (kAssignThreads / 64)];
+    __shared__ unsigned long long s_maxd[kMaxK];  // pruned runs: per cluster, the largest squared distance
     __shared__ int s_slice;  // sort-means passes: the block's next slice of 64 colours
     // full searches with integer centres: (packed centre, stored value)
     __shared__ __align__(16) uint2 s_ent[kSortMeans ? 2 : kMaxK];
@@ -300,8 +311,15 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
     unsigned long long* __restrict__ sums = gp(J.sums) + (it & 1) * kSumStride;
     uint64_t* __restrict__ grp = gp(J.grp) + record_buffer(it, J.regroup_period) * n;
     for (int t = threadIdx.x; t < 5 * kMaxK; t += blockDim.x) bins[t] = 0ull;
-    if (J.prune)
+    if (J.prune) {
         for (int t = threadIdx.x; t < K * kBuckets / 2; t += blockDim.x) ccount[t] = 0u;
+        for (int t = threadIdx.x; t < K; t += blockDim.x) s_maxd[t] = 0ull;
+        // the centres of this assignment, kept for the update (which
+        // replaces them): the distance a centre moves bounds how far the
+        // next scans of its cluster's colours can reach
+        if (lb == 0)
+            for (int t = threadIdx.x; t < 3 * K; t += blockDim.x) gp(J.cprev)[t] = gp(J.centers)[t];
+    }
     if (threadIdx.x == 0) s_slice = 0;
     __syncthreads();
 
@@ -348,6 +366,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                     const int bk = dist_bucket(v.bd);
                     grp[i] = pack_colour(key, v.best, w, bk);
                     count_pair(ccount, v.best * kBuckets + bk);
+                    atomicMax(&s_maxd[v.best], (unsigned long long)__double_as_longlong(v.bd));
                 }
             }
             bin_add(bins, valid, v.best, w, r, g, b);
@@ -355,7 +374,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
     } else {
         const Rec CQ_CONST* rec = cp(J.rec);
         const int32_t CQ_CONST* tix = cp(J.tix);
-        Acc acc{-1, 0ull, 0ull, 0ull, 0ull, 0ull};
+        Acc acc{-1, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
         // the waves take the block's slices of 64 colours in order from an LDS
         // counter, so a wave that finishes early takes more of them; each wave
         // takes its next slice, and starts loading it, before working on the
@@ -453,25 +472,20 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 ndc += evals;
                 ties += near_tie(v) ? 1 : 0;
                 const int bk = dist_bucket(v.bd);
-                grp[i] = pack_colour(key, v.best, w, bk);
+                const uint64_t rec_new = pack_colour(key, v.best, w, bk);
+                if (rec_new != g0) grp[i] = rec_new;  // most records stay as they are
                 count_pair(ccount, v.best * kBuckets + bk);
-                acc_add(acc, bins, v.best, w, r, g, b);
+                acc_add(acc, bins, s_maxd, v.best, w, r, g, b, v.bd);
             }
         }
         // each lane's last cluster straight into LDS: lanes that share a
         // cluster are serialized by the LDS unit, cheaper than reducing
         // five 64-bit values across the wave
-        if (acc.k >= 0) {
-            atomicAdd(&bins[kSumN + acc.k], acc.n);
-            atomicAdd(&bins[kSumS + 3 * acc.k + 0], acc.s0);
-            atomicAdd(&bins[kSumS + 3 * acc.k + 1], acc.s1);
-            atomicAdd(&bins[kSumS + 3 * acc.k + 2], acc.s2);
-            atomicAdd(&bins[kSumQ + acc.k], acc.q);
-        }
+        if (acc.k >= 0) acc_flush(acc, bins, s_maxd);
     }
     __syncthreads();
     flush_counters(ndc, ties, red, gp(J.part) + 2 * lb);
-    flush_bins(bins, J.prune ? ccount : nullptr, K, sums);
+    flush_bins(bins, J.prune ? ccount : nullptr, J.prune ? s_maxd : nullptr, K, sums);
 }
 
 // Exact unsigned 128-bit value converted to double by the fixed rule
@@ -619,7 +633,8 @@ __device__ __forceinline__ void load_row_order(const JobDev& J, int a, int K, in
     }
 }
 
-__device__ __forceinline__ void build_row(const JobDev& J, int a, int K, const double* c, const int* prev)
+__device__ __forceinline__ void build_row(const JobDev& J, int a, int K, const double* c, const int* prev,
+                                          double reach)
 {
     const int lane = threadIdx.x & 63;
     Rec* __restrict__ row = gp(J.rec) + a * kRow;
@@ -701,16 +716,31 @@ __device__ __forceinline__ void build_row(const JobDev& J, int a, int K, const d
             }
         }
     }
+    // The scans of this row (colours whose previous centre is a) evaluate
+    // entries up to their own bound, which is at most `reach`; P entries lie
+    // within it (the own entry first).  A scan reads whole rounds of kWalk
+    // entries after the own one, and the round after one whose last entry
+    // is within its bound, so the entries it can read end with the round
+    // that holds entry P (at least the first round).  Only those records are
+    // written; the centre order is written whole, since the next update
+    // starts its sort from it.
+    int within = 0;
+#pragma unroll
+    for (int i = 0; i < kPerLane; ++i) within += (kPerLane * lane + i < K && k[i] <= reach) ? 1 : 0;
+    const int P = wave_sum(within);
+    const int last = (P + kWalk - 1) / kWalk * kWalk;
 #pragma unroll
     for (int i = 0; i < kPerLane; ++i) {
         const int e = kPerLane * lane + i;
         if (e >= K) continue;
-        Rec r;
-        r.c0 = c[3 * x[i]];
-        r.c1 = c[3 * x[i] + 1];
-        r.c2 = c[3 * x[i] + 2];
-        r.d = x[i] == a ? 0.0 : k[i];
-        row[e] = r;
+        if (e <= last) {
+            Rec r;
+            r.c0 = c[3 * x[i]];
+            r.c1 = c[3 * x[i] + 1];
+            r.c2 = c[3 * x[i] + 2];
+            r.d = x[i] == a ? 0.0 : k[i];
+            row[e] = r;
+        }
         trow[e] = x[i];
     }
 }
@@ -851,7 +881,21 @@ __global__ void __launch_bounds__(kMaxK) k_update(const JobDev* __restrict__ job
         }
     }
     if (!J.prune) return;
-    if (r < K) build_row(J, r, K, c, prev);
+    if (r < K) {
+        // Bound of every scan of row r in the next iteration.  A colour x in
+        // cluster r was at squared distance at most M from the centre c it
+        // was assigned to (the cluster's largest), and the centre moved to
+        // c' by s = |c' - c|, so |x - c'| <= sqrt(M) + s, and its scan bound
+        // 4 |x - c'|^2 (1 + 1e-12) is at most 4 (sqrt(M) + s)^2 (1 + 1e-12).
+        // The relative 1e-9 and absolute 1e-9 on top cover the rounding of
+        // every step here and in the scan's own distance.
+        const double m = __longlong_as_double((long long)cur[kSumMaxD + r]);
+        const double* __restrict__ cp = gp(J.cprev);
+        const double s2 = dist_f64(c[3 * r], c[3 * r + 1], c[3 * r + 2], cp[3 * r], cp[3 * r + 1], cp[3 * r + 2]);
+        const double rad = __builtin_sqrt(m) + __builtin_sqrt(s2);
+        const double reach = 4.0 * rad * rad * (1.0 + 1e-12) * (1.0 + 1e-9) + 1e-9;
+        build_row(J, r, K, c, prev, reach);
+    }
 }
 
 // Pruned runs that grouped their colours: the final cluster of every colour
