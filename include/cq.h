@@ -146,7 +146,11 @@ cq_status cq_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t row_st
  *    largest remainder K u_c mod N' (ties to the lower cell); cell by cell the
  *    quota is drawn as FGY draws from the cell's colours in key order.
  *  - USER: the centres are left as given.
- * The workspace must hold cq_workspace_bytes(H, W, K) of an image with
+ * The colours must be as cq_histogram gives them: keys below 2^24 in
+ * ascending order, counts summing to at most 2^28 (the k-means++ weights
+ * n D^2 are summed in 46 bits); other inputs give unspecified centres or
+ * CQ_EDEVICE from a cooperative wait that gives up, never an access out of
+ * bounds.  The workspace must hold cq_workspace_bytes(H, W, K) of an image with
  * H W >= N'.  Synchronizes only if k_used is non-null or the scheme is LBG; a
  * device-side failure of the initialization is reported by that
  * synchronization or by the next synchronizing call on the workspace. */
@@ -171,7 +175,10 @@ cq_status cq_init(const uint32_t* keys, const uint32_t* counts, int64_t n_unique
  * uint8[K][3], nullable) receives floor(c + 0.5) clamped to [0, 255];
  * sse_trace (host double[max_iters], nullable) receives SSE_1..SSE_iters.
  * For N' <= K the centres become the colours and no iteration runs.
- * 1 <= max_iters <= 100000, tol >= 0.  A pruned run keeps two 8-byte
+ * 1 <= max_iters <= 100000, tol >= 0.  Every key must be below 2^24 and
+ * the counts must sum to at most 2^28 (a pruned run packs a count in 28
+ * bits): a run with more than K colours checks this on the device first and
+ * returns CQ_EINVAL without iterating.  A pruned run keeps two 8-byte
  * records per colour in the workspace: cq_workspace_bytes(H, W, K) of any
  * image with H W >= N' is enough.  Synchronizes `stream`. */
 cq_status cq_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n_unique, int32_t K,
@@ -309,6 +316,40 @@ cq_status cq_engine_pending(const cq_engine* engine, int32_t* queued, int32_t* r
  * queued or in flight are dropped; after a failed step it first waits for
  * `stream`.  NULL is accepted. */
 void cq_engine_destroy(cq_engine* engine);
+
+/* ------------------------------------------------------------------------
+ * Launch schedule of the Lloyd iterations.  How the iteration kernels are
+ * tiled does not change any result, only the speed: the colours each
+ * assignment block takes (few, so that a small batch still fills the GPU;
+ * many, so that a large one pays less per block) and how often a pruned run
+ * regroups its colours by (cluster, distance) for the sort-means scans
+ * (every iteration keeps the scans of a wave short; less often saves the
+ * regrouping's traffic).  A call that iterates over C unique colours in all
+ * (the sum of N' over its jobs with N' > K) uses the last entry whose
+ * min_colours <= C.  The built-in table holds the schedules that
+ * paper_1101_0395_amd/autotune.py measured fastest on this GPU for batches
+ * of those sizes.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t min_colours;     /* the entry applies from this many colours on          */
+    int32_t assign_chunk;    /* colours per assignment block: a multiple of 256 in
+                                [256, 32768] (raised where a job would need more than
+                                8192 blocks)                                           */
+    int32_t regroup_period;  /* pruned runs regroup at iterations 1-4 and at every
+                                multiple of this (>= 1)                                */
+} cq_schedule;
+
+/* Replaces the process-wide schedule table with n (1..32) entries whose
+ * min_colours start at 0 and increase; n = 0 restores the built-in table.
+ * CQ_EINVAL for anything else (the table is left as it was).  Takes effect
+ * for calls and engine admissions that start afterwards; calls already
+ * running keep the schedule they started with.  No device work. */
+cq_status cq_set_schedule(const cq_schedule* table /* host */, int32_t n);
+
+/* The current table: *n (host) receives its length and the first
+ * min(n, capacity) entries are copied to table (host, nullable when
+ * capacity is 0). */
+cq_status cq_get_schedule(cq_schedule* table /* host */, int32_t capacity, int32_t* n /* host */);
 
 /* Kernel timing for measurement harnesses (not needed for quantization).
  * While enabled, launches of the kernel named `kernel` (for example

@@ -23,7 +23,8 @@ EXPORTS = ("cq_workspace_bytes", "cq_workspace_prepare", "cq_histogram", "cq_pix
            "cq_map", "cq_quantize", "cq_batch_workspace_bytes", "cq_batch_workspace_prepare",
            "cq_quantize_batch", "cq_engine_job_bytes", "cq_engine_workspace_bytes", "cq_engine_create",
            "cq_engine_submit", "cq_engine_step", "cq_engine_pending", "cq_engine_destroy",
-           "cq_timer_enable", "cq_timer_read", "cq_timer_disable", "cq_last_error")
+           "cq_set_schedule", "cq_get_schedule", "cq_timer_enable", "cq_timer_read", "cq_timer_disable",
+           "cq_last_error")
 
 
 class CqStats(ctypes.Structure):
@@ -60,6 +61,14 @@ class CqJob(ctypes.Structure):
         ("out_idx", ctypes.c_void_p),
         ("out_rgb", ctypes.c_void_p),
         ("subsample", ctypes.c_int32),
+    ]
+
+
+class CqSchedule(ctypes.Structure):
+    _fields_ = [
+        ("min_colours", ctypes.c_int64),
+        ("assign_chunk", ctypes.c_int32),
+        ("regroup_period", ctypes.c_int32),
     ]
 
 
@@ -124,6 +133,10 @@ def lib() -> ctypes.CDLL:
             getattr(L, f).restype = ctypes.c_int
         L.cq_engine_destroy.argtypes = [P]
         L.cq_engine_destroy.restype = None
+        L.cq_set_schedule.argtypes = [ctypes.POINTER(CqSchedule), i32]
+        L.cq_get_schedule.argtypes = [ctypes.POINTER(CqSchedule), i32, ctypes.POINTER(i32)]
+        for f in ("cq_set_schedule", "cq_get_schedule"):
+            getattr(L, f).restype = ctypes.c_int
         L.cq_timer_enable.argtypes = [ctypes.c_char_p, i32, i32]
         L.cq_timer_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(f64), ctypes.POINTER(i64)]
         L.cq_timer_disable.argtypes = []
@@ -133,6 +146,22 @@ def lib() -> ctypes.CDLL:
         L.cq_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
+
+
+def set_schedule(table):
+    """Replace the library's launch schedule with [(min_colours, assign_chunk,
+    regroup_period), ...]; an empty list restores the built-in table."""
+    arr = (CqSchedule * max(1, len(table)))(*[CqSchedule(int(m), int(c), int(p)) for m, c, p in table])
+    _check("cq_set_schedule", lib().cq_set_schedule(arr if table else None, len(table)))
+
+
+def get_schedule():
+    """The library's launch schedule as [(min_colours, assign_chunk, regroup_period), ...]."""
+    n = ctypes.c_int32(0)
+    _check("cq_get_schedule", lib().cq_get_schedule(None, 0, ctypes.byref(n)))
+    arr = (CqSchedule * max(1, n.value))()
+    _check("cq_get_schedule", lib().cq_get_schedule(arr, n.value, ctypes.byref(n)))
+    return [(e.min_colours, e.assign_chunk, e.regroup_period) for e in arr[: n.value]]
 
 
 class KernelTimer:
@@ -312,13 +341,24 @@ class BatchJob:
     """One image of a batch with its outputs (device tensors)."""
 
     def __init__(self, img: torch.Tensor, K: int, scheme: int, seed: int, max_iters: int, tol: float,
-                 prune: bool = True, want_idx: bool = True, want_rgb: bool = True, subsample: bool = False):
+                 prune: bool = True, want_idx: bool = True, want_rgb: bool = True, subsample: bool = False,
+                 palette: torch.Tensor | None = None, idx: torch.Tensor | None = None,
+                 rgb: torch.Tensor | None = None):
+        """Output tensors may be given (palette uint8 [K, 3], idx uint8 [H, W],
+        rgb uint8 [H, W, 3], contiguous, on the image's device); the others
+        are allocated."""
         H, W, stride = _image_args(img)
         dev = img.device
         self.img = img
-        self.palette = torch.zeros((K, 3), dtype=torch.uint8, device=dev)
-        self.idx = torch.empty((H, W), dtype=torch.uint8, device=dev) if want_idx else None
-        self.rgb = torch.empty((H, W, 3), dtype=torch.uint8, device=dev) if want_rgb else None
+        for t, shape in ((palette, (K, 3)), (idx, (H, W)), (rgb, (H, W, 3))):
+            if t is not None and (t.dtype != torch.uint8 or tuple(t.shape) != shape or not t.is_contiguous()
+                                  or t.device != dev):
+                raise ValueError(f"output tensor must be contiguous uint8 {shape} on {dev}")
+        self.palette = palette if palette is not None else torch.zeros((K, 3), dtype=torch.uint8, device=dev)
+        self.idx = (idx if idx is not None else torch.empty((H, W), dtype=torch.uint8, device=dev)) if want_idx \
+            else None
+        self.rgb = (rgb if rgb is not None else torch.empty((H, W, 3), dtype=torch.uint8, device=dev)) if want_rgb \
+            else None
         self.c = CqJob(ctypes.c_void_p(img.data_ptr()), H, W, stride, K, scheme, seed, max_iters, tol,
                        int(bool(prune)), ctypes.c_void_p(self.palette.data_ptr()),
                        ctypes.c_void_p(self.idx.data_ptr()) if want_idx else None,

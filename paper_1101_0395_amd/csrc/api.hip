@@ -245,8 +245,17 @@ void HostBuf::release()
 cq_status upload(Batch& b)
 {
     const size_t jb = sizeof(JobDev) * size_t(b.B), mo = desc_maps_off(b.B), mb = sizeof(int) * b.maps.size();
-    b.staged.emplace_back(mo + mb);
-    char* snap = b.staged.back().data();
+    char* snap = nullptr;
+    if (b.host_stage) {
+        if (mo + mb > b.host_stage_bytes) {
+            set_error("descriptor upload of %zu bytes exceeds the host staging area", mo + mb);
+            return CQ_EDEVICE;
+        }
+        snap = b.host_stage;
+    } else {
+        b.staged.emplace_back(mo + mb);
+        snap = b.staged.back().data();
+    }
     if (!snap) {
         set_error("out of host memory");
         return CQ_EDEVICE;
@@ -290,6 +299,16 @@ cq_status collect(Batch& b)
 {
     CQ_TIMED_LAUNCH("k_collect", b.s, k_collect<<<(b.B + 63) / 64, 64, 0, b.s>>>(b.d_jobs(), b.B, b.d_results()));
     const size_t rb = sizeof(JobResult) * size_t(b.B);
+    if (b.host_stage) {
+        if (rb > b.host_stage_bytes) {
+            set_error("status readback of %zu bytes exceeds the host staging area", rb);
+            return CQ_EDEVICE;
+        }
+        CQ_HIP_TRY(hipMemcpyAsync(b.host_stage, b.d_results(), rb, hipMemcpyDeviceToHost, b.s));
+        CQ_HIP_TRY(hipStreamSynchronize(b.s));
+        memcpy(b.res.data(), b.host_stage, rb);
+        return CQ_OK;
+    }
     HostBuf out(rb);
     if (!out.data()) {
         set_error("out of host memory");
@@ -304,7 +323,7 @@ cq_status collect(Batch& b)
 
 // Stream (one per device, default priority, never destroyed) for readbacks
 // that must not queue behind later work on the caller's stream.
-static cq_status side_stream(hipStream_t* out)
+cq_status side_stream(hipStream_t* out)
 {
     static std::mutex mu;
     static std::map<int, hipStream_t> streams;
@@ -334,6 +353,18 @@ cq_status read_results(Batch& b, int slot, hipEvent_t done)
     CQ_TRY(side_stream(&side));
     CQ_HIP_TRY(hipStreamWaitEvent(side, done, 0));
     const size_t rb = sizeof(JobResult) * size_t(b.B);
+    if (b.host_stage) {
+        // a copy to pageable memory returns once complete; the area is free
+        // again before the next upload
+        if (rb > b.host_stage_bytes) {
+            set_error("status readback of %zu bytes exceeds the host staging area", rb);
+            return CQ_EDEVICE;
+        }
+        CQ_HIP_TRY(hipMemcpyAsync(b.host_stage, b.d_results(slot), rb, hipMemcpyDeviceToHost, side));
+        CQ_HIP_TRY(hipStreamSynchronize(side));
+        memcpy(b.res.data(), b.host_stage, rb);
+        return CQ_OK;
+    }
     HostBuf out(rb);
     if (!out.data()) {
         set_error("out of host memory");
@@ -370,12 +401,18 @@ cq_status run_histogram(Batch& b)
 }
 
 // Once N' is known (from the histogram or from the caller).
+// The launch schedule follows the colours of the jobs that iterate.
 void set_counts(Batch& b, const std::vector<int64_t>& n)
 {
+    int64_t colours = 0;
+    for (int j = 0; j < b.B; ++j)
+        if (n[j] > b.h[j].K) colours += n[j];
+    const cq_schedule sched = schedule_for(colours);
     for (int j = 0; j < b.B; ++j) {
         JobDev& J = b.h[j];
         J.n = n[j];
-        J.chunk = assign_chunk(J.n);
+        J.chunk = assign_chunk(J.n, sched.assign_chunk);
+        J.regroup_period = sched.regroup_period;
         J.map_k = int32_t(J.n < J.K ? J.n : J.K);
     }
 }
@@ -397,6 +434,9 @@ static cq_status run_lbg(Batch& b)
             if (have[i] < b.h[jobs[i]].K) act.push_back(int(i));
         if (act.empty()) break;
         Batch st(int(act.size()), b.desc, b.s);
+        st.host_stage = b.host_stage;
+        st.host_stage_bytes = b.host_stage_bytes;
+        st.fixed_events = b.fixed_events;
         for (int q = 0; q < st.B; ++q) {
             const int i = act[q];
             JobDev J = b.h[jobs[i]];
@@ -474,12 +514,12 @@ cq_status run_init(Batch& b)
 // Iterations of every job until all have stopped.  Iterations are enqueued
 // in groups; a stopped job's blocks return at once, so one readback per group
 // suffices.
-cq_status run_kmeans(Batch& b, bool memberships)
+cq_status run_kmeans(Batch& b, bool memberships, bool check)
 {
-    // every job iterates in step with the launches, so the host knows which
-    // iterations regroup (the same rule as on the device)
-    const int period = regroup_period();
-    for (JobDev& J : b.h) J.regroup_period = period;
+    // every job iterates in step with the launches and all share the
+    // schedule's regrouping period, so the host knows which iterations
+    // regroup (the same rule as on the device)
+    const int period = b.B > 0 ? b.h[0].regroup_period : 1;
     int max_iters = 0;
     for (const JobDev& J : b.h) max_iters = J.max_iters > max_iters ? J.max_iters : max_iters;
     auto assign_blocks = [&](int j) {
@@ -499,12 +539,17 @@ cq_status run_kmeans(Batch& b, bool memberships)
     });
     CQ_TRY(upload(b));
     CQ_TRY(launch_kmeans_begin(b.d_jobs(), b.B, b.s));
+    if (check) CQ_TRY(launch_check_colours(b.d_jobs(), b.d_maps(), b.B, assign_total, b.s));
     if (assign_total == 0) return collect(b);
     // The status of group g is read while group g + 1 runs: the device never
     // waits for the host, and the group enqueued after the last job stopped
     // costs only early returns.
-    EventPair ev;
-    CQ_TRY(ev.create());
+    EventPair own;
+    hipEvent_t* ev_pair = b.fixed_events;
+    if (!ev_pair) {
+        CQ_TRY(own.create());
+        ev_pair = own.ev;
+    }
     const int group = 8;
     bool all_done = false;
     for (int it = 1, g = 0; it <= max_iters; it += group, ++g) {
@@ -513,9 +558,9 @@ cq_status run_kmeans(Batch& b, bool memberships)
             CQ_TRY(launch_kmeans_iter(b.d_jobs(), b.d_maps(), b.B, it + q == 1, assign_total, full_total,
                                       walk_total, update_total, regroup_at(it + q, period), table_total,
                                       b.s));
-        CQ_TRY(collect_async(b, g & 1, ev.ev[g & 1]));
+        CQ_TRY(collect_async(b, g & 1, ev_pair[g & 1]));
         if (g == 0) continue;
-        CQ_TRY(read_results(b, (g - 1) & 1, ev.ev[(g - 1) & 1]));
+        CQ_TRY(read_results(b, (g - 1) & 1, ev_pair[(g - 1) & 1]));
         all_done = true;
         for (const JobResult& r : b.res) all_done = all_done && r.done;
         if (all_done) break;
@@ -580,14 +625,18 @@ cq_status check_init(const Batch& b)
 // After the iterations (fields written by the k-means begin kernel).
 cq_status check_kmeans(const Batch& b)
 {
-    for (int j = 0; j < b.B; ++j)
-        if (b.res[j].bad_input) return einval("job %d: initial centres contain a non-finite value", j);
+    for (int j = 0; j < b.B; ++j) {
+        const int bad = b.res[j].bad_input;
+        if (bad & 1) return einval("job %d: initial centres contain a non-finite value", j);
+        if (bad & 2) return einval("job %d: a colour key is not below 2^24", j);
+        if (bad & 4) return einval("job %d: the counts sum to more than 2^28", j);
+    }
     return CQ_OK;
 }
 
 // Whole quantizer for a filled batch (histogram -> init -> k-means ->
 // palette -> map); fills stats (nullable, one per job).
-static cq_status run_quantize(Batch& b, cq_stats* stats)
+cq_status run_quantize(Batch& b, cq_stats* stats)
 {
     CQ_TRY(run_histogram(b));
     CQ_TRY(collect(b));
@@ -649,6 +698,34 @@ cq_status check_job(const cq_job& j, int idx)
         snprintf(g_error, sizeof g_error, "%s", msg);
     }
     return s;
+}
+
+// cq_quantize on a given workspace; host_stage / events (nullable) make the
+// call use a fixed host staging area and fixed readback events instead of
+// pooled pinned buffers and new events.
+cq_status quantize_into(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes, int32_t subsample,
+                        int32_t K, cq_init_t scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
+                        uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, cq_stats* stats, void* ws,
+                        size_t ws_bytes, void* stream, char* host_stage, size_t host_stage_bytes,
+                        hipEvent_t* events)
+{
+    CQ_TRY(check_image(img, H, W, row_stride_bytes));
+    CQ_TRY(check_subsample(subsample));
+    CQ_TRY(check_k(K));
+    if (!palette) return einval("palette is null");
+    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_DEN || scheme == CQ_INIT_USER)
+        return einval("cq_quantize needs scheme FORGY, MAXMIN, KMEANSPP, VAR, SFF, WU, LBG or DEN");
+    CQ_TRY(check_iters_tol(max_iters, tol));
+    const int64_t npix = int64_t(H) * W;
+    const Layout L = make_layout(npix, npix, true);
+    CQ_TRY(check_ws(ws, ws_bytes, L.total));
+    Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
+    b.host_stage = host_stage;
+    b.host_stage_bytes = host_stage_bytes;
+    b.fixed_events = events;
+    fill_quantize_job(b.h[0], img, H, W, row_stride_bytes, subsample, K, int(scheme), seed, max_iters, tol, prune,
+                      palette, out_idx, out_rgb, static_cast<char*>(ws));
+    return run_quantize(b, stats);
 }
 
 }  // namespace cq
@@ -770,7 +847,7 @@ cq_status cq_kmeans(const uint32_t* keys, const uint32_t* counts, int64_t n_uniq
     J.tol = tol;
     J.prune = prune ? 1 : 0;
     set_counts(b, {n_unique});
-    CQ_TRY(run_kmeans(b, true));
+    CQ_TRY(run_kmeans(b, true, true));
     CQ_TRY(check_kmeans(b));
     if (palette) CQ_TRY(launch_palette(b.d_jobs(), 1, b.s));
     const JobResult r = b.res[0];
@@ -823,20 +900,8 @@ cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stri
                       size_t ws_bytes, void* stream)
 {
     clear_error();
-    CQ_TRY(check_image(img, H, W, row_stride_bytes));
-    CQ_TRY(check_subsample(subsample));
-    CQ_TRY(check_k(K));
-    if (!palette) return einval("palette is null");
-    if (int(scheme) < CQ_INIT_FORGY || int(scheme) > CQ_INIT_DEN || scheme == CQ_INIT_USER)
-        return einval("cq_quantize needs scheme FORGY, MAXMIN, KMEANSPP, VAR, SFF, WU, LBG or DEN");
-    CQ_TRY(check_iters_tol(max_iters, tol));
-    const int64_t npix = int64_t(H) * W;
-    const Layout L = make_layout(npix, npix, true);
-    CQ_TRY(check_ws(ws, ws_bytes, L.total));
-    Batch b(1, at<char>(ws, L.desc), static_cast<hipStream_t>(stream));
-    fill_quantize_job(b.h[0], img, H, W, row_stride_bytes, subsample, K, int(scheme), seed, max_iters, tol, prune,
-                      palette, out_idx, out_rgb, static_cast<char*>(ws));
-    return run_quantize(b, stats);
+    return quantize_into(img, H, W, row_stride_bytes, subsample, K, scheme, seed, max_iters, tol, prune, palette,
+                         out_idx, out_rgb, stats, ws, ws_bytes, stream, nullptr, 0, nullptr);
 }
 
 size_t cq_batch_workspace_bytes(const cq_job* jobs, int32_t n_jobs)
@@ -878,6 +943,18 @@ cq_status cq_quantize_batch(const cq_job* jobs, int32_t n_jobs, cq_stats* stats,
         slot += slot_bytes(j);
     }
     return run_quantize(b, stats);
+}
+
+cq_status cq_set_schedule(const cq_schedule* table, int32_t n)
+{
+    clear_error();
+    return set_schedule(table, n);
+}
+
+cq_status cq_get_schedule(cq_schedule* table, int32_t capacity, int32_t* n)
+{
+    clear_error();
+    return get_schedule(table, capacity, n);
 }
 
 cq_status cq_timer_enable(const char* kernel, int32_t max_launches, int32_t every)

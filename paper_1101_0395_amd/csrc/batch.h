@@ -55,6 +55,14 @@ struct Batch {
     std::vector<int> maps;
     std::vector<JobResult> res;
     std::deque<HostBuf> staged;  // host copies behind the uploads, kept until the stream is synchronized
+    // When set, uploads and readbacks go through this pageable host area
+    // instead of pooled pinned buffers (the path that allocates nothing): a
+    // copy from pageable memory has consumed its source when the call
+    // returns, and a copy to it has completed, so the area is reused at once.
+    char* host_stage = nullptr;
+    size_t host_stage_bytes = 0;
+    // events of the pipelined status readback, owned elsewhere when set
+    hipEvent_t* fixed_events = nullptr;
 
     Batch(int nb, char* d, hipStream_t st)
         : B(nb), desc(d), s(st), h(size_t(nb)), maps(size_t(kNumMaps) * (nb + 1), 0), res(size_t(nb))
@@ -110,13 +118,16 @@ cq_status launch_sff(const JobDev* jobs, int B, hipStream_t s);
 int64_t sff_subset(int32_t K, int64_t n);
 cq_status launch_init_coop(const JobDev* jobs, const int* map, int B, int total, int variant, hipStream_t s);
 cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s);
+cq_status launch_check_colours(const JobDev* jobs, const int* maps, int B, int blocks, hipStream_t s);
 cq_status launch_kmeans_iter(const JobDev* jobs, const int* maps, int B, bool first, int all_blocks,
                              int full_blocks, int walk_blocks, int update_blocks, bool regroup,
                              int table_blocks, hipStream_t s);
-int regroup_period();
 int update_table_blocks(int K, int prune);
 cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s);
-int64_t assign_chunk(int64_t n);
+int64_t assign_chunk(int64_t n, int32_t scheduled);
+cq_schedule schedule_for(int64_t colours);
+cq_status set_schedule(const cq_schedule* table, int32_t n);
+cq_status get_schedule(cq_schedule* table, int32_t capacity, int32_t* n);
 int64_t regroup_blocks(int64_t n);
 cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int blocks, hipStream_t s);
 int map_blocks(int64_t npix);
@@ -139,8 +150,20 @@ cq_status read_results(Batch& b, int slot, hipEvent_t done);
 cq_status run_histogram(Batch& b);
 void set_counts(Batch& b, const std::vector<int64_t>& n);
 cq_status run_init(Batch& b);
-cq_status run_kmeans(Batch& b, bool memberships);
+// memberships: write the final memberships in key order (cq_kmeans);
+// check: validate caller-supplied colours first (keys below 2^24, counts
+// summing to at most 2^28; a job that fails runs no iteration and
+// check_kmeans reports it).
+cq_status run_kmeans(Batch& b, bool memberships, bool check = false);
 cq_status run_map(Batch& b, bool with_err);
+cq_status run_quantize(Batch& b, cq_stats* stats);  // histogram -> init -> k-means -> palette -> map
+cq_status quantize_into(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes, int32_t subsample,
+                        int32_t K, cq_init_t scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,
+                        uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, cq_stats* stats, void* ws,
+                        size_t ws_bytes, void* stream, char* host_stage, size_t host_stage_bytes,
+                        hipEvent_t* events);
+// The device's readback stream (created on first use, never destroyed).
+cq_status side_stream(hipStream_t* out);
 cq_status check_init(const Batch& b);
 cq_status check_kmeans(const Batch& b);
 void fill_stats(const JobDev& J, const JobResult& r, cq_stats& st, bool with_img);

@@ -34,7 +34,6 @@ struct cq_engine {
     char* pool_base = nullptr;  // slots
     cq::ExtentPool pool;
     hipStream_t s = nullptr;
-    int period = 1;
     bool failed = false;
     int64_t next_ticket = 1;
     std::deque<cq::EngineJob> queue;   // submitted, waiting for a slot
@@ -59,7 +58,6 @@ static std::vector<int> engine_admit(cq_engine* e)
         const cq_job& j = q.spec;
         fill_quantize_job(q.dev, j.img, j.H, j.W, j.row_stride_bytes, j.subsample, j.K, int(j.scheme), j.seed, j.max_iters,
                           j.tol, j.prune, j.palette, j.out_idx, j.out_rgb, e->pool_base + off);
-        q.dev.regroup_period = e->period;
         q.it = 0;
         fresh.push_back(int(e->active.size()));
         e->active.push_back(q);
@@ -224,7 +222,6 @@ cq_status cq_engine_create(int32_t max_jobs, void* ws, size_t ws_bytes, void* st
     e->pool_base = static_cast<char*>(ws) + head;
     e->pool = ExtentPool(ws_bytes - head, 256);
     e->s = static_cast<hipStream_t>(stream);
-    e->period = regroup_period();
     *engine = e;
     return CQ_OK;
 }

@@ -864,9 +864,12 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
                 uint64_t total = v;
                 int ok = 1;
                 uint32_t spins = 0;
+                // the team's error flag is read every 64th spin only, so that a
+                // poll is one load
                 auto keep_waiting = [&]() {
-                    if (__hip_atomic_load(&meta->sync_error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                        ++spins > kSpinLimit)
+                    if (++spins > kSpinLimit ||
+                        ((spins & 63u) == 0 &&
+                         __hip_atomic_load(&meta->sync_error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0))
                         return false;
                     __builtin_amdgcn_s_sleep(1);
                     return true;
@@ -902,11 +905,35 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
                     uint64_t base = 0;
                     const int64_t c = G > 1 ? wave_find(G, r, &base, [&](int64_t x) { return s_val[x]; }) : 0;
                     if (c == tb) {
+                        // the thread holding r: lane l sums the runs of threads
+                        // [l S, (l + 1) S), one scan finds the lane, and the
+                        // lane's S run sums (broadcast) the thread
                         state = 2;
-                        const int64_t tr = wave_find(kInitThreads, r, &base, [&](int64_t x) { return s_run[x]; });
+                        constexpr int S = kInitThreads / 64;
+                        uint64_t rv[S];
+                        uint64_t lsum = 0;
+#pragma unroll
+                        for (int u = 0; u < S; ++u) {
+                            rv[u] = s_run[lane * S + u];
+                            lsum += rv[u];
+                        }
+                        const uint64_t lincl = base + wave_incl_scan(lsum);
+                        const unsigned long long hitl = __ballot(lincl > r);
+                        const int l = hitl ? __ffsll(hitl) - 1 : 63;  // hitl != 0 since r < total
+                        uint64_t before = __shfl(lincl - lsum, l, 64);
+                        int tr = l * S + S - 1;
+                        bool found = false;
+#pragma unroll
+                        for (int u = 0; u < S; ++u) {
+                            const uint64_t v = __shfl(rv[u], l, 64);
+                            const bool hit = !found && before + v > r;
+                            tr = hit ? l * S + u : tr;
+                            before += (found || hit) ? 0ull : v;
+                            found = found || hit;
+                        }
                         if (lane == 0) {
-                            s_owner = tr < 0 ? 0 : int(tr);  // tr >= 0 since r < total
-                            s_rloc = r - base;
+                            s_owner = tr;
+                            s_rloc = r - before;
                         }
                     } else {
                         uint64_t x = 0;

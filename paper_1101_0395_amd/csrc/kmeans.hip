@@ -17,7 +17,9 @@
 // launches serve every iteration and a stopped job's blocks return at once.
 #include <stdlib.h>
 
-#include "cq_internal.h"
+#include <mutex>
+
+#include "batch.h"
 
 // Every floating-point operation in this file is rounded on its own.
 #pragma clang fp contract(off)
@@ -25,6 +27,7 @@
 namespace cq {
 
 constexpr int kAssignThreads = 256;
+constexpr int kMaxAssignChunk = 32768;  // colours per block: the (cluster, bucket) counters are 16 bits
 constexpr int kScatterChunk = 2048;  // colours per regrouping block
 
 // Adds the five cluster statistics (n, S_r, S_g, S_b, Q) of the valid lanes
@@ -992,6 +995,62 @@ __global__ void __launch_bounds__(kMaxK) k_kmeans_begin(const JobDev* __restrict
     }
 }
 
+// Caller-supplied colours (cq_kmeans): every key must be a 24-bit colour and
+// the counts must sum to at most 2^28 (the pixels of the largest image), so
+// that a count fits the 28 bits a pruned run's packed record gives it and the
+// cluster sums stay exact.  Block b of job j checks the colours
+// [b chunk, (b + 1) chunk), flags a key outside the range (bad_input bit 2)
+// and adds its counts to total_w; k_check_finish flags a total above 2^28
+// (bit 4) and stops a job with any flag before its first iteration.
+constexpr uint64_t kMaxTotalWeight = uint64_t(1) << 28;
+
+__global__ void __launch_bounds__(kAssignThreads) k_check_colours(const JobDev* __restrict__ jobs,
+                                                                  const int* __restrict__ map, int B)
+{
+    __shared__ unsigned long long red[kAssignThreads / 64];
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int lb = blockIdx.x - map[jb];
+    const int64_t lo = int64_t(lb) * J.chunk;
+    const int64_t hi = lo + J.chunk < J.n ? lo + J.chunk : J.n;
+    const uint32_t* __restrict__ keys = gp(J.keys);
+    const uint32_t* __restrict__ counts = gp(J.counts);
+    unsigned long long sum = 0;
+    bool bad = false;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        bad = bad || keys[i] >= kNumKeys;
+        sum += counts[i];
+    }
+    sum = wave_sum(sum);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    Meta* __restrict__ meta = gp(J.meta);
+    if (__syncthreads_or(bad ? 1 : 0) && threadIdx.x == 0) atomicOr(&meta->bad_input, 2);
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kAssignThreads / 64; ++w) t += red[w];
+        atomicAdd(reinterpret_cast<unsigned long long*>(&meta->total_w), t);
+    }
+}
+
+__global__ void k_check_finish(const JobDev* __restrict__ jobs)
+{
+    Meta* __restrict__ meta = gp(jobs[blockIdx.x].meta);
+    if (threadIdx.x != 0) return;
+    int bad = meta->bad_input;
+    if (meta->total_w > kMaxTotalWeight) bad |= 4;
+    meta->bad_input = bad;
+    meta->total_w = 0;
+    if (bad) meta->done = 1;
+}
+
+cq_status launch_check_colours(const JobDev* jobs, const int* maps, int B, int blocks, hipStream_t s)
+{
+    if (blocks > 0)
+        CQ_TIMED_LAUNCH("k_check_colours", s, k_check_colours<<<blocks, kAssignThreads, 0, s>>>(jobs, maps + kMapAssign * (B + 1), B));
+    CQ_TIMED_LAUNCH("k_check_finish", s, k_check_finish<<<B, 64, 0, s>>>(jobs));
+    return CQ_OK;
+}
+
 // ------------------------------------------------------------------ host
 cq_status launch_kmeans_begin(const JobDev* jobs, int B, hipStream_t s)
 {
@@ -1032,17 +1091,6 @@ int64_t regroup_blocks(int64_t n) { return (n + kScatterChunk - 1) / kScatterChu
 // Update blocks of a job before its regrouping blocks.
 int update_table_blocks(int K, int prune) { return table_blocks_of(K, prune); }
 
-// Iterations between regroupings of the colour records (after the first
-// four); the environment variable CQ_REGROUP_PERIOD overrides the default.
-int regroup_period()
-{
-    static const int p = [] {
-        const char* e = getenv("CQ_REGROUP_PERIOD");
-        const int v = e ? atoi(e) : 0;
-        return v > 0 ? v : 1;
-    }();
-    return p;
-}
 
 cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s)
 {
@@ -1050,18 +1098,95 @@ cq_status launch_palette(const JobDev* jobs, int B, hipStream_t s)
     return CQ_OK;
 }
 
-// Colours per assignment block (a multiple of the block size); the
-// environment variable CQ_ASSIGN_CHUNK overrides the default.
-int64_t assign_chunk(int64_t n)
+// ------------------------------------------------------------ schedules
+// The launch schedule of the iterations: colours per assignment block and
+// the regrouping period, by the number of colours one call iterates over.
+// Results never depend on it; only the speed does.  The built-in table is
+// the one the autotuner measured (paper_1101_0395_amd/autotune.py).
+namespace {
+constexpr int kMaxSchedules = 32;
+const cq_schedule kDefaultSchedule[] = {
+    {0, 1024, 1},
+    {4149731, 2048, 1},
+    {34861447, 8192, 2},
+};
+struct ScheduleTable {
+    std::mutex mu;
+    cq_schedule e[kMaxSchedules];
+    int n = 0;
+};
+ScheduleTable& schedules()
 {
-    static const int64_t forced = [] {
-        const char* e = getenv("CQ_ASSIGN_CHUNK");
-        return e ? int64_t(atoll(e)) : int64_t(0);
+    static ScheduleTable* t = [] {
+        ScheduleTable* x = new ScheduleTable;
+        x->n = int(sizeof kDefaultSchedule / sizeof kDefaultSchedule[0]);
+        for (int i = 0; i < x->n; ++i) x->e[i] = kDefaultSchedule[i];
+        return x;
     }();
-    int64_t chunk = 4 * kAssignThreads;
-    if (forced > 0) chunk = forced;
-    if ((n + chunk - 1) / chunk > kMaxAssignBlocks) chunk = (n + kMaxAssignBlocks - 1) / kMaxAssignBlocks;
-    return (chunk + kAssignThreads - 1) / kAssignThreads * kAssignThreads;
+    return *t;
 }
+}  // namespace
+
+cq_schedule schedule_for(int64_t colours)
+{
+    ScheduleTable& t = schedules();
+    std::lock_guard<std::mutex> lock(t.mu);
+    cq_schedule s = t.e[0];
+    for (int i = 1; i < t.n; ++i)
+        if (colours >= t.e[i].min_colours) s = t.e[i];
+    return s;
+}
+
+cq_status set_schedule(const cq_schedule* table, int32_t n)
+{
+    if (n < 0 || n > kMaxSchedules) return einval("n = %d outside [0, %d]", n, kMaxSchedules);
+    if (n > 0 && !table) return einval("table is null");
+    for (int32_t i = 0; i < n; ++i) {
+        const cq_schedule& x = table[i];
+        if (i == 0 ? x.min_colours != 0 : x.min_colours <= table[i - 1].min_colours)
+            return einval("entry %d: min_colours must start at 0 and increase", i);
+        if (x.assign_chunk < kAssignThreads || x.assign_chunk > kMaxAssignChunk || x.assign_chunk % kAssignThreads)
+            return einval("entry %d: assign_chunk %d is not a multiple of %d in [%d, %d]", i, x.assign_chunk,
+                          kAssignThreads, kAssignThreads, kMaxAssignChunk);
+        if (x.regroup_period < 1 || x.regroup_period > kMaxIters)
+            return einval("entry %d: regroup_period %d outside [1, %d]", i, x.regroup_period, kMaxIters);
+    }
+    ScheduleTable& t = schedules();
+    std::lock_guard<std::mutex> lock(t.mu);
+    if (n == 0) {
+        t.n = int(sizeof kDefaultSchedule / sizeof kDefaultSchedule[0]);
+        for (int i = 0; i < t.n; ++i) t.e[i] = kDefaultSchedule[i];
+    } else {
+        t.n = n;
+        for (int i = 0; i < n; ++i) t.e[i] = table[i];
+    }
+    return CQ_OK;
+}
+
+cq_status get_schedule(cq_schedule* table, int32_t capacity, int32_t* n)
+{
+    if (!n) return einval("n is null");
+    ScheduleTable& t = schedules();
+    std::lock_guard<std::mutex> lock(t.mu);
+    *n = t.n;
+    if (capacity < 0) return einval("capacity is negative");
+    if (capacity > 0 && !table) return einval("table is null");
+    for (int i = 0; i < t.n && i < capacity; ++i) table[i] = t.e[i];
+    return CQ_OK;
+}
+
+// Colours per assignment / colour-table block of a job of n colours under
+// the schedule's chunk: at least enough that the job needs at most
+// kMaxAssignBlocks blocks, a multiple of the block size, at most
+// kMaxAssignChunk (the per-block counters of (cluster, bucket) pairs are
+// 16 bits wide).
+int64_t assign_chunk(int64_t n, int32_t scheduled)
+{
+    int64_t chunk = scheduled;
+    if ((n + chunk - 1) / chunk > kMaxAssignBlocks) chunk = (n + kMaxAssignBlocks - 1) / kMaxAssignBlocks;
+    chunk = (chunk + kAssignThreads - 1) / kAssignThreads * kAssignThreads;
+    return chunk < kMaxAssignChunk ? chunk : kMaxAssignChunk;
+}
+
 
 }  // namespace cq

@@ -2,7 +2,7 @@
 //
 // The nearest palette entry depends only on the colour, so it is found once
 // per unique colour (exact integer distances, lowest index on ties) and stored
-// in a 2^24-entry byte table indexed by the colour key.  Only the N' entries of
+// in a 2^24-entry byte table indexed by the colour (channel bits interleaved).  Only the N' entries of
 // the image's colours are written; the per-pixel map then reads each pixel,
 // looks its key up and writes the index and/or the palette colour.  The squared
 // error of every pixel is n_i |x_i - P_lut|^2 summed over the unique colours,
@@ -17,6 +17,31 @@ namespace cq {
 
 constexpr int kLutThreads = 256;
 constexpr int kMapThreads = 256;
+
+// Position of colour (r, g, b) in the byte table: the bits of the three
+// channels interleaved (Morton order, b in bits 0, 3, 6, ..., g one above, r
+// two above).  Colours close in all three channels then share cache lines of
+// the table, so the pixels of an image region, whose colours differ a little
+// in every channel, look up few distinct lines and mostly hit the L2.  (In
+// key order a line holds 128 values of b at one (r, g): neighbouring pixels
+// whose r or g differ land on different lines.)
+__device__ __forceinline__ uint32_t spread_bits(uint32_t x)
+{
+    x = (x | (x << 8)) & 0x0000F00Fu;
+    x = (x | (x << 4)) & 0x000C30C3u;
+    x = (x | (x << 2)) & 0x00249249u;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t lut_slot(uint32_t r, uint32_t g, uint32_t b)
+{
+    return (spread_bits(r) << 2) | (spread_bits(g) << 1) | spread_bits(b);
+}
+
+__device__ __forceinline__ uint32_t lut_slot_key(uint32_t key)
+{
+    return lut_slot(key >> 16, (key >> 8) & 0xffu, key & 0xffu);
+}
 constexpr int kMapGroupsPerBlock = 1024;  // 4-pixel groups per map block
 
 // Nearest-entry search.  Since |x - p|^2 = |x|^2 - (2 x.p - |p|^2), the
@@ -81,7 +106,7 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ 
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         const uint32_t key = keys[i];
         uint32_t d;
-        lut[key] = uint8_t(nearest_entry(key, ent, K2, &d));
+        lut[lut_slot_key(key)] = uint8_t(nearest_entry(key, ent, K2, &d));
         if (with_err) err += (unsigned long long)counts[i] * d;
     }
     if (!with_err) return;
@@ -197,14 +222,11 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
         uint32_t ix[kMapGroupsPerThread][4];
 #pragma unroll
         for (int s = 0; s < kMapGroupsPerThread; ++s) {
-            const uint32_t k0 = ((a[s] & 0xffu) << 16) | (a[s] & 0xff00u) | ((a[s] >> 16) & 0xffu);
-            const uint32_t k1 = ((a[s] >> 24) << 16) | ((b[s] & 0xffu) << 8) | ((b[s] >> 8) & 0xffu);
-            const uint32_t k2 = (((b[s] >> 16) & 0xffu) << 16) | ((b[s] >> 24) << 8) | (c[s] & 0xffu);
-            const uint32_t k3 = (((c[s] >> 8) & 0xffu) << 16) | (((c[s] >> 16) & 0xffu) << 8) | (c[s] >> 24);
-            ix[s][0] = lut[k0];
-            ix[s][1] = lut[k1];
-            ix[s][2] = lut[k2];
-            ix[s][3] = lut[k3];
+            // a = R0 G0 B0 R1, b = G1 B1 R2 G2, c = B2 R3 G3 B3 (bytes, low first)
+            ix[s][0] = lut[lut_slot(a[s] & 0xffu, (a[s] >> 8) & 0xffu, (a[s] >> 16) & 0xffu)];
+            ix[s][1] = lut[lut_slot(a[s] >> 24, b[s] & 0xffu, (b[s] >> 8) & 0xffu)];
+            ix[s][2] = lut[lut_slot((b[s] >> 16) & 0xffu, b[s] >> 24, c[s] & 0xffu)];
+            ix[s][3] = lut[lut_slot((c[s] >> 8) & 0xffu, (c[s] >> 16) & 0xffu, c[s] >> 24)];
         }
 #pragma unroll
         for (int s = 0; s < kMapGroupsPerThread; ++s) {
@@ -226,7 +248,7 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
         if (rem > 0 && ngroups >= g0 && ngroups < g1 && threadIdx.x < rem) {
             const int64_t px = (ngroups << 2) + threadIdx.x;
             const uint8_t* p = img + 3 * px;
-            const uint32_t idx = lut[(uint32_t(p[0]) << 16) | (uint32_t(p[1]) << 8) | uint32_t(p[2])];
+            const uint32_t idx = lut[lut_slot(p[0], p[1], p[2])];
             if (out_idx) out_idx[px] = uint8_t(idx);
             if (out_rgb) {
                 out_rgb[3 * px + 0] = uint8_t(pal[idx]);
@@ -240,7 +262,7 @@ __global__ void __launch_bounds__(kMapThreads) k_map(const JobDev* __restrict__ 
         for (int64_t p = p0 + threadIdx.x; p < p1; p += kMapThreads) {
             const uint32_t y = uint32_t(p) / uint32_t(W), x = uint32_t(p) - y * uint32_t(W);  // p < 2^28
             const uint8_t* q = img + int64_t(y) * J.stride + 3 * x;
-            const uint32_t idx = lut[(uint32_t(q[0]) << 16) | (uint32_t(q[1]) << 8) | uint32_t(q[2])];
+            const uint32_t idx = lut[lut_slot(q[0], q[1], q[2])];
             if (out_idx) out_idx[p] = uint8_t(idx);
             if (out_rgb) {
                 out_rgb[3 * p + 0] = uint8_t(pal[idx]);

@@ -16,5 +16,7 @@ int main(void)
     printf("cq_stats size %zu\n", sizeof(cq_stats));
     printf("cq_engine_done size %zu\n", sizeof(cq_engine_done));
     F(cq_engine_done, ticket); F(cq_engine_done, status); F(cq_engine_done, stats);
+    printf("cq_schedule size %zu\n", sizeof(cq_schedule));
+    F(cq_schedule, min_colours); F(cq_schedule, assign_chunk); F(cq_schedule, regroup_period);
     return 0;
 }

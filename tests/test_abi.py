@@ -190,3 +190,42 @@ def test_engine_sizes_and_argument_checks_without_a_device():
     finally:
         L.cq_engine_destroy(h)
     L.cq_engine_destroy(None)
+
+
+def test_schedule_table_round_trip_and_checks_without_a_device():
+    """cq_set_schedule / cq_get_schedule: a valid table is stored as given, an
+    invalid one is refused and leaves the table as it was, and n = 0
+    restores the built-in table."""
+    builtin = cq.get_schedule()
+    assert builtin[0][0] == 0 and all(a[0] < b[0] for a, b in zip(builtin, builtin[1:]))
+    try:
+        cq.set_schedule([(0, 512, 3), (1000, 8192, 1)])
+        assert cq.get_schedule() == [(0, 512, 3), (1000, 8192, 1)]
+        for bad in ([(5, 1024, 1)],                      # first entry not at 0
+                    [(0, 1024, 1), (0, 2048, 1)],        # not increasing
+                    [(0, 1000, 1)],                      # not a multiple of 256
+                    [(0, 65536, 1)],                     # above 32768
+                    [(0, 1024, 0)]):                     # period below 1
+            with pytest.raises(cq.CqError) as e:
+                cq.set_schedule(bad)
+            assert e.value.code == cq.CQ_EINVAL
+            assert cq.get_schedule() == [(0, 512, 3), (1000, 8192, 1)]
+    finally:
+        cq.set_schedule([])
+    assert cq.get_schedule() == builtin
+
+
+def test_builtin_schedule_is_the_tuned_table():
+    """The library's built-in schedule is the table the autotuner wrote
+    (paper_1101_0395_amd/schedule.json), and every tuned workload's
+    measured best is the entry that its colour count selects."""
+    import json
+    with open(os.path.join(ROOT, "paper_1101_0395_amd", "schedule.json")) as f:
+        tuned = json.load(f)
+    cq.set_schedule([])
+    table = [tuple(e) for e in tuned["table"]]
+    assert cq.get_schedule() == table
+    for r in tuned["results"]:
+        chosen = [e for e in table if e[0] <= r["colours"]][-1]
+        best = min(r["ms"], key=r["ms"].get)
+        assert (chosen[1], chosen[2]) == tuple(int(v) for v in best.split(",")), r["workload"]

@@ -226,6 +226,34 @@ def test_kmeans_max_iters_one_and_nonfinite_start(cqm, dev, ws_small):
     assert e.value.code == cqm.CQ_EINVAL
 
 
+def test_kmeans_rejects_keys_and_counts_out_of_range(cqm, dev, ws_small):
+    """Caller-supplied colours: a key of 2^24 or more, or counts summing to
+    more than 2^28, are refused with CQ_EINVAL before any iteration, pruned
+    or not; the same colours within range run (and match the oracle)."""
+    _say("kmeans argument range on the device")
+    img = synth.blobs_on_gradient(64, 64, 11)
+    rk, rc, dk, dc = _hist_pair(img, cqm, dev, ws_small)
+    c0, _ = oracle.init(rk, rc, 16, oracle.INIT_MAXMIN, 11)
+    for prune in (False, True):
+        bad_keys = dk.clone()
+        bad_keys[len(rk) // 2] = 1 << 24
+        with pytest.raises(cqm.CqError) as e:
+            cqm.cq_kmeans(bad_keys, dc, _to_dev(c0, dev), 5, 1e-4, prune, ws_small)
+        assert e.value.code == cqm.CQ_EINVAL and "2^24" in str(e.value)
+        heavy = dc.clone()
+        heavy[0] = (1 << 28) - int(rc[1:].sum()) + 1  # total 2^28 + 1
+        with pytest.raises(cqm.CqError) as e:
+            cqm.cq_kmeans(dk, heavy, _to_dev(c0, dev), 5, 1e-4, prune, ws_small)
+        assert e.value.code == cqm.CQ_EINVAL and "2^28" in str(e.value)
+        edge = dc.clone()
+        edge[0] = (1 << 28) - int(rc[1:].sum())  # total exactly 2^28: accepted
+        hk = rc.copy()
+        hk[0] = (1 << 28) - int(rc[1:].sum())
+        r = oracle.kmeans(rk, hk, c0, 5, 1e-4, prune)
+        g = cqm.cq_kmeans(dk, edge, _to_dev(c0, dev), 5, 1e-4, prune, ws_small)
+        _compare_kmeans(g, r)
+
+
 @pytest.mark.parametrize("K", [1, 5, 16, 255, 256])
 def test_map_parity(cqm, dev, ws_small, K):
     _say(f"map K={K}")

@@ -44,11 +44,12 @@ def test_public_structs_match_binding_layout(tmp_path):
     subprocess.run(["gcc", "-std=c11", "-O0", "-I", os.path.join(ROOT, "include"), src, "-o", str(exe)],
                    check=True, capture_output=True, text=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60, check=True).stdout
-    py = {"cq_job": cq.CqJob, "cq_stats": cq.CqStats, "cq_engine_done": cq.CqEngineDone}
+    py = {"cq_job": cq.CqJob, "cq_stats": cq.CqStats, "cq_engine_done": cq.CqEngineDone,
+          "cq_schedule": cq.CqSchedule}
     seen = 0
     for line in out.splitlines():
         name, field, value = line.split()
         want = ctypes.sizeof(py[name]) if field == "size" else getattr(py[name], field).offset
         assert int(value) == want, line
         seen += 1
-    assert seen == 20
+    assert seen == 24
