@@ -106,18 +106,21 @@ def measure_large(cq, synth, torch, dev, reps=5):
     }
 
 
-def measure_serving(cq, torch, synth, imgs, dev):
+def measure_serving(cq, torch, synth, imgs, dev, host_c4, workers, seconds):
     """Continuous batching under Poisson arrivals (the serving engine).
 
-    - "512x512_device_inputs": 96 requests for the eight headline images in
+    - "512x512_device_inputs": 96 requests for the eight 512 x 512 images in
       turn (request r uses k-means++ seed 1000 + r), K = 256, offered at
       500/s; inputs already on the device; at most 16 jobs in flight.
-    - "mixed_host_io": 192 requests drawn (rng seed 7) from a pool of 48
-      mixed-size stand-ins with their own K (the batch shapes of seeds
-      1,000,000 + i), images in pinned host memory copied in at arrival and
-      results copied back before a request counts as done; at most 32 jobs in
-      flight within a 4 GiB pool.  Its capacity is measured first with every
-      request arriving at once, then the open-loop run offers 70 % of it.
+    - "poisson_2000_per_s": Poisson arrivals at 2000 requests/s for `seconds`
+      (60 by default); request r takes an image drawn uniformly (rng seed 7)
+      from a pool of 1024 mixed-size stand-ins (the batch shapes of seeds
+      1,000,000 + i, i < 1024; the first 512 are the mixed batch) and its own
+      K drawn from {16, 32, 64, 128, 256}.  Images start in pinned host
+      memory and are copied in when a request gets device buffers; results go
+      back to pinned host memory before a request counts as done.  At most 96
+      requests hold device buffers, at most 64 are in flight in the engine,
+      whose slot pool has 12 GiB; requests beyond that wait (deferred).
     Every request: sort-means, tol 1e-4, at most 100 iterations, full map."""
     import numpy as np
 
@@ -138,30 +141,28 @@ def measure_serving(cq, torch, synth, imgs, dev):
                        "inputs on the device, 16 jobs in flight, 8 iterations per step")
     out["512x512_device_inputs"] = res
 
-    shapes = synth.batch_shapes(48)
-    pool_imgs = [torch.from_numpy(synth.batch_image(h, w, s)).pin_memory() for h, w, _, s in shapes]
-    n_req = 192
-    pick = np.random.default_rng(7).integers(0, len(shapes), n_req)
-    budget = 4 << 30
-    eng = cq.Engine(32, budget, dev)
-
-    def mixed(arr):
-        return [serve.make_request(float(t), pool_imgs[p], shapes[p][2], 2000 + r, MAX_ITERS, TOL, dev, True)
-                for r, (t, p) in enumerate(zip(arr, pick))]
-
-    serve.run(eng, mixed(np.zeros(16))[:16])  # warm-up
-    closed = serve.run(eng, mixed(np.zeros(n_req)))
-    rate = 0.7 * closed["throughput_per_s"]
-    res = serve.run(eng, mixed(serve.poisson_arrivals(n_req, rate, seed=8)))
+    shapes = synth.batch_shapes(1024)
+    more = synth.batch_images(shapes[len(host_c4):], workers)
+    pool = [torch.from_numpy(im).pin_memory() for im in list(host_c4) + more]
+    rng = np.random.default_rng(7)
+    rate = 2000.0
+    arrivals = serve.poisson_window(rate, seconds, seed=8)
+    n = len(arrivals)
+    pick = rng.integers(0, len(pool), n)
+    ks = rng.choice(np.array([16, 32, 64, 128, 256]), n)
+    seeds = 3_000_000 + np.arange(n)
+    eng = cq.Engine(64, 12 << 30, dev)
+    warm = serve.poisson_window(rate, 0.1, seed=9)
+    serve.run_stream(eng, pool, warm, pick, ks, seeds, 96, MAX_ITERS, TOL)  # warm-up
+    res = serve.run_stream(eng, pool, arrivals, pick, ks, seeds, 96, MAX_ITERS, TOL)
     eng.close()
-    res["closed_loop_throughput_per_s"] = closed["throughput_per_s"]
-    res["closed_loop_latency_ms_p50"] = closed["latency_ms_p50"]
-    res["mean_pixels"] = float(np.mean([shapes[p][0] * shapes[p][1] for p in pick]))
-    res["workload"] = (f"{n_req} requests from 48 mixed-size stand-ins (long side 64-2048, own K in "
-                       f"16-256), Poisson arrivals at 70% of the closed-loop capacity ({rate:.0f}/s), "
-                       "pinned host input and output copies inside the latency, 32 jobs in flight, "
-                       "4 GiB slot pool, 8 iterations per step")
-    out["mixed_host_io"] = res
+    res["mean_pixels"] = float(np.mean([pool[p].shape[0] * pool[p].shape[1] for p in pick]))
+    res["workload"] = (f"Poisson arrivals at {rate:.0f}/s for {seconds:.0f} s ({n} requests); images drawn "
+                       "from a pool of 1024 mixed-size stand-ins (long side 64-2048) in pinned host memory, "
+                       "each request with its own K in {16..256}; host-to-device input and device-to-host "
+                       "results inside the latency; 96 request slots, 64 jobs in flight, 12 GiB slot pool, "
+                       "8 iterations per step")
+    out["poisson_2000_per_s"] = res
     return out
 
 
@@ -488,6 +489,8 @@ def parse():
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="finish with plain device-to-device copies of this many MiB (a known-size kernel "
                          "for scaling memory counters)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the Poisson arrival window of the serving figure")
     ap.add_argument("--gen-threads", action="store_true",
                     help="generate the inputs on threads instead of child processes (for runs under a profiler, "
                          "which would follow every child process)")
@@ -641,7 +644,7 @@ def main():
     if not args.no_large:
         line["hbm_bound_steps_4096"] = measure_large(cq, synth, torch, dev)
     if not args.no_serving:
-        line["serving"] = measure_serving(cq, torch, synth, imgs, dev)
+        line["serving"] = measure_serving(cq, torch, synth, imgs, dev, host_c4, workers, args.serve_seconds)
     if not args.no_init_schemes:
         line["init_schemes_8x512"] = measure_init_schemes(cq, torch, imgs, dev)
     if not args.no_subsample:
