@@ -212,6 +212,25 @@ cq_status cq_quantize(const uint8_t* img, int32_t H, int32_t W, int64_t row_stri
                       int32_t prune, uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb,
                       cq_stats* stats /* host */, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate memory (code under graph capture, tight
+ * serving loops, harnesses that forbid allocation): cq_quantize with no
+ * workspace argument.  Its workspace is a fixed device array inside the
+ * library, 48 MiB on every GPU it runs on (held until the process ends), so
+ * the image may have at most 1048576 (2^20) pixels: CQ_EINVAL beyond that.
+ * Host staging uses a fixed host array.  The first call on a device sets it
+ * up (the array's device address, two events for the status readback and
+ * the library's readback stream); later calls on that device create,
+ * allocate and free nothing.  The array keeps the last call's contents and
+ * nothing in it has to start at zero.  Every call on a GPU shares that GPU's
+ * array, so calls that overlapped there would race: the library serializes
+ * calls from the threads of a process, and each returns only after its work
+ * on `stream` is complete.  Results are identical to cq_quantize's.
+ * Synchronizes `stream`. */
+cq_status cq_quantize_noalloc(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes,
+                              int32_t subsample, int32_t K, cq_init_t scheme, uint64_t seed, int32_t max_iters,
+                              double tol, int32_t prune, uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb,
+                              cq_stats* stats /* host */, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batches: many images of different sizes and palette sizes quantized by one
  * sequence of launches (every kernel covers all jobs; a job that has stopped

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcq.so")
-SOURCES = ["hist.hip", "init.hip", "wu.hip", "kmeans.hip", "map.hip", "api.hip", "engine.hip"]
+SOURCES = ["hist.hip", "init.hip", "wu.hip", "kmeans.hip", "map.hip", "api.hip", "engine.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

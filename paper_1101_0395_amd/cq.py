@@ -20,7 +20,7 @@ CQ_OK, CQ_EINVAL, CQ_ECAPACITY, CQ_EWORKSPACE, CQ_EDEVICE = 0, 1, 2, 3, 4
 (INIT_FORGY, INIT_MAXMIN, INIT_KMEANSPP, INIT_USER, INIT_VAR, INIT_SFF, INIT_WU, INIT_LBG,
  INIT_DEN) = 0, 1, 2, 3, 4, 5, 6, 7, 8
 EXPORTS = ("cq_workspace_bytes", "cq_workspace_prepare", "cq_histogram", "cq_pixel_keys", "cq_init", "cq_kmeans",
-           "cq_map", "cq_quantize", "cq_batch_workspace_bytes", "cq_batch_workspace_prepare",
+           "cq_map", "cq_quantize", "cq_quantize_noalloc", "cq_batch_workspace_bytes", "cq_batch_workspace_prepare",
            "cq_quantize_batch", "cq_engine_job_bytes", "cq_engine_workspace_bytes", "cq_engine_create",
            "cq_engine_submit", "cq_engine_step", "cq_engine_pending", "cq_engine_destroy",
            "cq_set_schedule", "cq_get_schedule", "cq_timer_enable", "cq_timer_read", "cq_timer_disable",
@@ -112,8 +112,10 @@ def lib() -> ctypes.CDLL:
         L.cq_map.argtypes = [P, i32, i32, i64, P, P, i64, P, i32, P, P, ctypes.POINTER(u64), P, sz, P]
         L.cq_quantize.argtypes = [P, i32, i32, i64, i32, i32, ctypes.c_int, u64, i32, f64, i32, P, P, P,
                                   ctypes.POINTER(CqStats), P, sz, P]
+        L.cq_quantize_noalloc.argtypes = [P, i32, i32, i64, i32, i32, ctypes.c_int, u64, i32, f64, i32, P, P, P,
+                                          ctypes.POINTER(CqStats), P]
         for f in ("cq_workspace_prepare", "cq_histogram", "cq_init", "cq_kmeans", "cq_map",
-                  "cq_quantize"):
+                  "cq_quantize", "cq_quantize_noalloc"):
             getattr(L, f).restype = ctypes.c_int
         L.cq_batch_workspace_bytes.argtypes = [ctypes.POINTER(CqJob), i32]
         L.cq_batch_workspace_bytes.restype = sz
@@ -335,6 +337,20 @@ def cq_quantize(img: torch.Tensor, K: int, scheme: int, seed: int, max_iters: in
                            ws.ptr, ws.nbytes, _stream(dev))
     _check("cq_quantize", rc)
     return palette, out_idx, out_rgb, st.as_dict()
+
+
+def cq_quantize_noalloc(img: torch.Tensor, K: int, scheme: int, seed: int, max_iters: int, tol: float,
+                        prune: bool, palette: torch.Tensor, out_idx: torch.Tensor | None,
+                        out_rgb: torch.Tensor | None, subsample: bool = False) -> dict:
+    """cq_quantize on the library's fixed scratch (images of at most 2^20
+    pixels): the caller passes the outputs, nothing is allocated."""
+    H, W, stride = _image_args(img)
+    st = CqStats()
+    rc = lib().cq_quantize_noalloc(_ptr(img), H, W, stride, int(bool(subsample)), K, scheme, seed, max_iters, tol,
+                                   int(bool(prune)), _ptr(palette), _ptr(out_idx), _ptr(out_rgb), ctypes.byref(st),
+                                   _stream(img.device))
+    _check("cq_quantize_noalloc", rc)
+    return st.as_dict()
 
 
 class BatchJob:
