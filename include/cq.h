@@ -384,6 +384,13 @@ cq_status cq_timer_enable(const char* kernel, int32_t max_launches, int32_t ever
 cq_status cq_timer_read(int64_t* launches /* host */, double* total_ms /* host */, int64_t* seen /* host */);
 cq_status cq_timer_disable(void);
 
+/* Releases the objects the library keeps for the whole process: pooled
+ * pinned host buffers, its readback streams, the kernel timer's events and
+ * the set-up of cq_quantize_noalloc.  Call it with no work of the library
+ * pending, for instance before the process exits (so that they are gone
+ * before the runtime's own teardown); later calls re-create what they need. */
+void cq_release_resources(void);
+
 /* Thread-local description of the last error on this thread ("" if none);
  * valid until the next cq_* call on the same thread. */
 const char* cq_last_error(void);

@@ -7,6 +7,7 @@ torch's current stream.  The library must have been built
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -24,7 +25,7 @@ EXPORTS = ("cq_workspace_bytes", "cq_workspace_prepare", "cq_histogram", "cq_pix
            "cq_quantize_batch", "cq_engine_job_bytes", "cq_engine_workspace_bytes", "cq_engine_create",
            "cq_engine_submit", "cq_engine_step", "cq_engine_pending", "cq_engine_destroy",
            "cq_set_schedule", "cq_get_schedule", "cq_timer_enable", "cq_timer_read", "cq_timer_disable",
-           "cq_last_error")
+           "cq_release_resources", "cq_last_error")
 
 
 class CqStats(ctypes.Structure):
@@ -144,10 +145,25 @@ def lib() -> ctypes.CDLL:
         L.cq_timer_disable.argtypes = []
         for f in ("cq_timer_enable", "cq_timer_read", "cq_timer_disable"):
             getattr(L, f).restype = ctypes.c_int
+        L.cq_release_resources.argtypes = []
+        L.cq_release_resources.restype = None
         L.cq_last_error.argtypes = []
         L.cq_last_error.restype = ctypes.c_char_p
         _lib = L
+        # the library's pinned buffers, streams and events go before the
+        # interpreter's own teardown (and the runtime's after it)
+        atexit.register(_release)
     return _lib
+
+
+def _release():
+    if _lib is None or not torch.cuda.is_initialized():
+        return
+    try:
+        torch.cuda.synchronize()
+    except Exception:
+        pass
+    _lib.cq_release_resources()
 
 
 def set_schedule(table):

@@ -142,6 +142,7 @@ static void bind_slot(JobDev& J, char* slot, const Layout& L)
     J.trace = to_dev(reinterpret_cast<double*>(slot + L.trace));
     J.rec = to_dev(reinterpret_cast<Rec*>(slot + L.rec));
     J.tix = to_dev(reinterpret_cast<int32_t*>(slot + L.tix));
+    J.ord = to_dev(reinterpret_cast<uint8_t*>(slot + L.ord));
     J.sums = to_dev(reinterpret_cast<unsigned long long*>(slot + L.sums));
     J.cprev = to_dev(reinterpret_cast<double*>(slot + L.cprev));
     J.hkeys = to_dev(reinterpret_cast<uint16_t*>(slot + L.hkeys));
@@ -321,15 +322,24 @@ cq_status collect(Batch& b)
     return CQ_OK;
 }
 
-// Stream (one per device, default priority, never destroyed) for readbacks
-// that must not queue behind later work on the caller's stream.
+// Stream (one per device, default priority) for readbacks that must not
+// queue behind later work on the caller's stream; destroyed only by
+// cq_release_resources.
+namespace {
+std::mutex g_side_mu;
+std::map<int, hipStream_t>& side_streams()
+{
+    static std::map<int, hipStream_t>* m = new std::map<int, hipStream_t>;
+    return *m;
+}
+}  // namespace
+
 cq_status side_stream(hipStream_t* out)
 {
-    static std::mutex mu;
-    static std::map<int, hipStream_t> streams;
     int dev = 0;
     CQ_HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lock(mu);
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    std::map<int, hipStream_t>& streams = side_streams();
     auto it = streams.find(dev);
     if (it == streams.end()) {
         hipStream_t st = nullptr;
@@ -531,7 +541,7 @@ cq_status run_kmeans(Batch& b, bool memberships, bool check)
     const int walk_total = b.set_map(kMapAssignWalk, [&](int j) { return b.h[j].prune ? assign_blocks(j) : 0; });
     const int update_total = b.set_map(kMapUpdate, [&](int j) {
         const JobDev& J = b.h[j];
-        return J.n <= J.K ? 0 : update_table_blocks(J.K, J.prune) + (J.prune ? int(regroup_blocks(J.n)) : 0);
+        return J.n <= J.K ? 0 : update_table_blocks(J.K, J.prune) + (J.prune ? int(regroup_blocks(J.n, J.chunk)) : 0);
     });
     const int table_total = b.set_map(kMapUpdateTable, [&](int j) {
         const JobDev& J = b.h[j];
@@ -726,6 +736,28 @@ cq_status quantize_into(const uint8_t* img, int32_t H, int32_t W, int64_t row_st
     fill_quantize_job(b.h[0], img, H, W, row_stride_bytes, subsample, K, int(scheme), seed, max_iters, tol, prune,
                       palette, out_idx, out_rgb, static_cast<char*>(ws));
     return run_quantize(b, stats);
+}
+
+// The library's process-wide objects: pooled pinned host buffers, readback
+// streams, the kernel timer's events and the allocation-free entry point's
+// per-device events.  Re-created on demand by later calls.
+void release_resources()
+{
+    {
+        HostPool& pool = host_pool();
+        std::lock_guard<std::mutex> lock(pool.mu);
+        for (auto& list : pool.free_list) {
+            for (void* p : list) (void)hipHostFree(p);
+            list.clear();
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_side_mu);
+        for (auto& kv : side_streams()) (void)hipStreamDestroy(kv.second);
+        side_streams().clear();
+    }
+    timer_release();
+    noalloc_release();
 }
 
 }  // namespace cq
@@ -1007,6 +1039,8 @@ cq_status cq_timer_disable(void)
     timer_release();
     return CQ_OK;
 }
+
+void cq_release_resources(void) { release_resources(); }
 
 const char* cq_last_error(void) { return g_error; }
 

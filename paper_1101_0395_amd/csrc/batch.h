@@ -128,7 +128,7 @@ int64_t assign_chunk(int64_t n, int32_t scheduled);
 cq_schedule schedule_for(int64_t colours);
 cq_status set_schedule(const cq_schedule* table, int32_t n);
 cq_status get_schedule(cq_schedule* table, int32_t capacity, int32_t* n);
-int64_t regroup_blocks(int64_t n);
+int64_t regroup_blocks(int64_t n, int64_t chunk);
 cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int blocks, hipStream_t s);
 int map_blocks(int64_t npix);
 cq_status launch_lut(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s);
@@ -162,7 +162,9 @@ cq_status quantize_into(const uint8_t* img, int32_t H, int32_t W, int64_t row_st
                         uint8_t* palette, uint8_t* out_idx, uint8_t* out_rgb, cq_stats* stats, void* ws,
                         size_t ws_bytes, void* stream, char* host_stage, size_t host_stage_bytes,
                         hipEvent_t* events);
-// The device's readback stream (created on first use, never destroyed).
+// Releases the per-device set-up of the allocation-free entry point.
+void noalloc_release();
+// The device's readback stream (created on first use).
 cq_status side_stream(hipStream_t* out);
 cq_status check_init(const Batch& b);
 cq_status check_kmeans(const Batch& b);

@@ -115,7 +115,7 @@ static cq_status engine_iterate(cq_engine* e, Batch& d, int32_t iters)
             if (!iterating(j)) return 0;
             const EngineJob& x = e->active[j];
             const bool regroup = x.dev.prune && regroup_at(x.it + 1, x.dev.regroup_period);
-            return update_table_blocks(x.dev.K, x.dev.prune) + (regroup ? int(regroup_blocks(x.dev.n)) : 0);
+            return update_table_blocks(x.dev.K, x.dev.prune) + (regroup ? int(regroup_blocks(x.dev.n, x.dev.chunk)) : 0);
         });
         if (full + walk == 0) break;
         if (!uploaded || d.maps != sent) {

@@ -505,8 +505,8 @@ __device__ __forceinline__ double u128_to_f64(unsigned __int128 v)
 // record buffer ordered by (cluster, bucket), a counting sort whose offsets
 // are the prefix sums of the (cluster, bucket) colour counts.  The order
 // inside a pair is whatever the atomics give; no result depends on it.  Block
-// s of the job's regrouping blocks takes the records
-// [s kScatterChunk, (s + 1) kScatterChunk).
+// s of the job's regrouping blocks takes the records [s chunk, (s + 1) chunk)
+// (chunk: the job's assignment block size), kScatterChunk at a time.
 constexpr int kPairs = kMaxK * kBuckets;
 constexpr int kPairsPer = kPairs / kMaxK;  // pairs per thread in the regrouping scan
 // LDS words of the regrouping offsets: pair cb lives at cb + cb / kPairsPer,
@@ -527,13 +527,16 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const ui
     uint64_t* __restrict__ dst = gp(J.grp) + (rb ^ 1) * n;
     const unsigned long long below = (1ull << lane) - 1ull;
     constexpr int kPasses = kScatterChunk / kMaxK;
-    // the block's records first, in flight while the offsets are computed
+    // the block takes J.chunk records (the assignment blocks' size) in
+    // sub-chunks of kScatterChunk: the offsets are computed once per block
+    const int64_t lo = int64_t(s) * J.chunk;
+    const int64_t hi = lo + J.chunk < n ? lo + J.chunk : n;
+    // the first sub-chunk's records first, in flight while the offsets are computed
     uint64_t g[kPasses];
-    const int64_t lo = int64_t(s) * kScatterChunk;
 #pragma unroll
     for (int u = 0; u < kPasses; ++u) {
         const int64_t i = lo + u * kMaxK + k;
-        g[u] = i < n ? src[i] : 0ull;
+        g[u] = i < hi ? src[i] : 0ull;
     }
     // pair counts: coalesced loads into LDS, then each thread scans its run
     // of kPer consecutive pairs
@@ -557,38 +560,47 @@ __device__ __forceinline__ void regroup(const JobDev& J, int s, int it, const ui
         run += c[u];
     }
     __syncthreads();
-    // every record of the block is ranked within its wave's group of equal
-    // (cluster, bucket) first; the group leaders then reserve their places
-    // with atomics that are all in flight together
-    int cbv[kPasses], lead[kPasses], rank[kPasses];
-    uint32_t pos[kPasses];
+    for (int64_t sub = lo; sub < hi; sub += kScatterChunk) {
+        if (sub > lo) {
 #pragma unroll
-    for (int u = 0; u < kPasses; ++u) {
-        const bool valid = lo + u * kMaxK + k < n;
-        cbv[u] = int((uint32_t(g[u]) >> 24) & 255u) * kBuckets + int(g[u] >> 60);
-        lead[u] = -1;
-        rank[u] = 0;
-        int gsize = 0;
-        unsigned long long pending = __ballot(valid);
-        while (pending) {
-            const int leader = __ffsll(pending) - 1;
-            const int cs = __builtin_amdgcn_readlane(cbv[u], leader);
-            const bool mine = valid && cbv[u] == cs;
-            const unsigned long long mask = __ballot(mine);
-            if (mine) {
-                lead[u] = leader;
-                rank[u] = __popcll(mask & below);
+            for (int u = 0; u < kPasses; ++u) {
+                const int64_t i = sub + u * kMaxK + k;
+                g[u] = i < hi ? src[i] : 0ull;
             }
-            if (lane == leader) gsize = __popcll(mask);
-            pending &= ~mask;
         }
-        pos[u] = 0;
-        if (gsize > 0) pos[u] = atomicAdd(&cursor[cbv[u]], uint32_t(gsize));
-    }
+        // every record of the sub-chunk is ranked within its wave's group of
+        // equal (cluster, bucket) first; the group leaders then reserve
+        // their places with atomics that are all in flight together
+        int cbv[kPasses], lead[kPasses], rank[kPasses];
+        uint32_t pos[kPasses];
 #pragma unroll
-    for (int u = 0; u < kPasses; ++u) {
-        const uint32_t base = __shfl(pos[u], lead[u] < 0 ? 0 : lead[u], 64);
-        if (lead[u] >= 0) dst[start[cbv[u] + cbv[u] / kPer] + base + rank[u]] = g[u];
+        for (int u = 0; u < kPasses; ++u) {
+            const bool valid = sub + u * kMaxK + k < hi;
+            cbv[u] = int((uint32_t(g[u]) >> 24) & 255u) * kBuckets + int(g[u] >> 60);
+            lead[u] = -1;
+            rank[u] = 0;
+            int gsize = 0;
+            unsigned long long pending = __ballot(valid);
+            while (pending) {
+                const int leader = __ffsll(pending) - 1;
+                const int cs = __builtin_amdgcn_readlane(cbv[u], leader);
+                const bool mine = valid && cbv[u] == cs;
+                const unsigned long long mask = __ballot(mine);
+                if (mine) {
+                    lead[u] = leader;
+                    rank[u] = __popcll(mask & below);
+                }
+                if (lane == leader) gsize = __popcll(mask);
+                pending &= ~mask;
+            }
+            pos[u] = 0;
+            if (gsize > 0) pos[u] = atomicAdd(&cursor[cbv[u]], uint32_t(gsize));
+        }
+#pragma unroll
+        for (int u = 0; u < kPasses; ++u) {
+            const uint32_t base = __shfl(pos[u], lead[u] < 0 ? 0 : lead[u], 64);
+            if (lead[u] >= 0) dst[start[cbv[u] + cbv[u] / kPer] + base + rank[u]] = g[u];
+        }
     }
 }
 
@@ -628,11 +640,13 @@ __device__ __forceinline__ void cmp_swap(double& k0, int& i0, double& k1, int& i
 __device__ __forceinline__ void load_row_order(const JobDev& J, int a, int K, int it, int* prev)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t* __restrict__ trow = gp(J.tix) + a * kRow;
+    const uint8_t* __restrict__ orow = gp(J.ord) + a * kRow;
+    // lane l's four order bytes in one load (rows are kRow bytes apart)
+    const uint32_t four = (it > 1 && a < K) ? reinterpret_cast<const uint32_t*>(orow)[lane] : 0u;
 #pragma unroll
     for (int i = 0; i < kPerLane; ++i) {
         const int e = kPerLane * lane + i;
-        prev[i] = (it > 1 && e < K && a < K) ? trow[e] : e;
+        prev[i] = (it > 1 && e < K && a < K) ? int((four >> (8 * i)) & 255u) : e;
     }
 }
 
@@ -732,20 +746,21 @@ __device__ __forceinline__ void build_row(const JobDev& J, int a, int K, const d
     for (int i = 0; i < kPerLane; ++i) within += (kPerLane * lane + i < K && k[i] <= reach) ? 1 : 0;
     const int P = wave_sum(within);
     const int last = (P + kWalk - 1) / kWalk * kWalk;
+    uint32_t four = 0;
 #pragma unroll
     for (int i = 0; i < kPerLane; ++i) {
         const int e = kPerLane * lane + i;
-        if (e >= K) continue;
-        if (e <= last) {
-            Rec r;
-            r.c0 = c[3 * x[i]];
-            r.c1 = c[3 * x[i] + 1];
-            r.c2 = c[3 * x[i] + 2];
-            r.d = x[i] == a ? 0.0 : k[i];
-            row[e] = r;
-        }
+        four |= uint32_t(x[i] & 255) << (8 * i);
+        if (e >= K || e > last) continue;
+        Rec r;
+        r.c0 = c[3 * x[i]];
+        r.c1 = c[3 * x[i] + 1];
+        r.c2 = c[3 * x[i] + 2];
+        r.d = x[i] == a ? 0.0 : k[i];
+        row[e] = r;
         trow[e] = x[i];
     }
+    reinterpret_cast<uint32_t*>(gp(J.ord) + a * kRow)[lane] = four;  // entries past K are never read
 }
 
 // Update step, SSE, stopping rule and, in pruned runs, the sorted table and
@@ -1086,7 +1101,8 @@ cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int block
     return CQ_OK;
 }
 
-int64_t regroup_blocks(int64_t n) { return (n + kScatterChunk - 1) / kScatterChunk; }
+// Regrouping blocks of a job: one per assignment block's worth of records.
+int64_t regroup_blocks(int64_t n, int64_t chunk) { return (n + chunk - 1) / chunk; }
 
 // Update blocks of a job before its regrouping blocks.
 int update_table_blocks(int K, int prune) { return table_blocks_of(K, prune); }

@@ -59,6 +59,15 @@ static cq_status device_setup(DeviceSetup** out)
     return CQ_OK;
 }
 
+void noalloc_release()
+{
+    std::lock_guard<std::mutex> lock(g_setup_mu);
+    for (auto& kv : g_setup)
+        for (auto e : kv.second.ev)
+            if (e) (void)hipEventDestroy(e);
+    g_setup.clear();
+}
+
 }  // namespace cq
 
 using namespace cq;
