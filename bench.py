@@ -70,7 +70,7 @@ def measure_large(cq, synth, torch, dev, reps=5):
             raise RuntimeError(f"no launches of {names} were timed")
         return total
 
-    hist_names = ["k_hist_buckets", "k_hist_colscan", "k_hist_scatter", "k_hist_count", "k_hist_emit"]
+    hist_names = ["k_hist_part", "k_hist_count", "k_hist_emit"]
     hist_ms = timed(hist_names, lambda: cq.cq_histogram(img, ws))
     full_kernels = dict(per_kernel)
     keys_s, _ = cq.cq_histogram(img, ws, subsample=True)
@@ -241,7 +241,7 @@ def measure_subsample(cq, torch, imgs, dev, reps=3):
         torch.cuda.synchronize()
         step_ms = 1e3 * (time.perf_counter() - t0) / reps
         kern_us = {}
-        for name in ("k_hist_buckets", "k_hist_scatter", "k_hist_count", "k_lut", "k_map"):
+        for name in ("k_hist_part", "k_hist_count", "k_hist_emit", "k_lut", "k_map"):
             t = cq.KernelTimer(name, reps)
             t.enable()
             for _ in range(reps):

@@ -146,12 +146,11 @@ static void bind_slot(JobDev& J, char* slot, const Layout& L)
     J.sums = to_dev(reinterpret_cast<unsigned long long*>(slot + L.sums));
     J.cprev = to_dev(reinterpret_cast<double*>(slot + L.cprev));
     J.hkeys = to_dev(reinterpret_cast<uint16_t*>(slot + L.hkeys));
+    J.hk2 = to_dev(reinterpret_cast<uint16_t*>(slot + L.hk2));
     J.hcnt = to_dev(reinterpret_cast<uint32_t*>(slot + L.hcnt));
     J.hmat = to_dev(reinterpret_cast<uint32_t*>(slot + L.hmat));
-    J.hbt = to_dev(reinterpret_cast<uint32_t*>(slot + L.hbt));
     J.hnu = to_dev(reinterpret_cast<uint32_t*>(slot + L.hnu));
     J.hbs = to_dev(reinterpret_cast<uint32_t*>(slot + L.hbs));
-    J.hus = to_dev(reinterpret_cast<uint32_t*>(slot + L.hus));
     J.part = to_dev(reinterpret_cast<unsigned long long*>(slot + L.part));
     J.vals = to_dev(reinterpret_cast<uint64_t*>(slot + L.chunks));
     J.d2 = to_dev(reinterpret_cast<uint32_t*>(slot + L.work));
@@ -406,8 +405,10 @@ cq_status run_histogram(Batch& b)
 {
     const int total = b.set_map(kMapHist, [&](int j) { return hist_blocks(hist_pixels(b.h[j])); });
     const int count = b.set_map(kMapHistCount, [&](int j) { return hist_count_blocks(hist_pixels(b.h[j])); });
+    int64_t max_tiles = 1;
+    for (const JobDev& J : b.h) max_tiles = hist_tiles(hist_pixels(J)) > max_tiles ? hist_tiles(hist_pixels(J)) : max_tiles;
     CQ_TRY(upload(b));
-    return launch_histogram(b.d_jobs(), b.d_maps(), b.B, total, count, b.s);
+    return launch_histogram(b.d_jobs(), b.d_maps(), b.B, total, count, int(max_tiles), b.s);
 }
 
 // Once N' is known (from the histogram or from the caller).

@@ -119,13 +119,12 @@ struct JobDev {
     uint8_t CQ_GLOBAL* palette;
     uint8_t CQ_GLOBAL* out_idx;
     uint8_t CQ_GLOBAL* out_rgb;
-    uint16_t CQ_GLOBAL* hkeys;  // histogram: low key bits of the pixels, partitioned by bucket
-    uint32_t CQ_GLOBAL* hcnt;   // histogram: compacted counts per bucket
-    uint32_t CQ_GLOBAL* hmat;   // histogram: bucket x tile counts, then their prefixes
-    uint32_t CQ_GLOBAL* hbt;    // histogram: pixels per bucket
+    uint16_t CQ_GLOBAL* hkeys;  // histogram: low key bits of the pixels, each tile's sorted by bucket
+    uint16_t CQ_GLOBAL* hk2;    // histogram: compacted low key bits, bucket after bucket
+    uint32_t CQ_GLOBAL* hcnt;   // histogram: compacted counts, bucket after bucket
+    uint32_t CQ_GLOBAL* hmat;   // histogram: tile x bucket, pixel count | start inside the tile << 16
     uint32_t CQ_GLOBAL* hnu;    // histogram: unique colours per bucket
-    uint32_t CQ_GLOBAL* hbs;    // histogram: first pixel slot of each bucket
-    uint32_t CQ_GLOBAL* hus;    // histogram: first output entry of each bucket
+    uint32_t CQ_GLOBAL* hbs;    // histogram: first compacted entry of each bucket
     uint8_t CQ_GLOBAL* lut;
     Meta CQ_GLOBAL* meta;
     double CQ_GLOBAL* trace;
@@ -279,7 +278,7 @@ inline size_t desc_results_off(int B)
 
 struct Layout {
     size_t lut, meta, trace, rec, tix, ord, sums, centers, cprev, palette, part, desc;
-    size_t chunks, work, hkeys, hcnt, hmat, hbt, hnu, hbs, hus, keys, counts, assign;
+    size_t chunks, work, hkeys, hk2, hcnt, hmat, hnu, hbs, keys, counts, assign;
     size_t fixed_end;  // end of the regions every call may use
     size_t total;      // end including the per-pixel and per-colour regions
 };
@@ -316,12 +315,11 @@ inline Layout make_layout(int64_t npix, int64_t n_cap, bool with_colour_arrays)
     size_t hist = 0;
     if (np > 0) {
         L.hkeys = o + hist; hist = align256(hist + sizeof(uint16_t) * np);
+        L.hk2 = o + hist;   hist = align256(hist + sizeof(uint16_t) * np);
         L.hcnt = o + hist;  hist = align256(hist + sizeof(uint32_t) * np);
         L.hmat = o + hist;  hist = align256(hist + sizeof(uint32_t) * size_t(kHistBuckets) * size_t(hist_tiles(npix)));
-        L.hbt = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
         L.hnu = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
         L.hbs = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
-        L.hus = o + hist;   hist = align256(hist + sizeof(uint32_t) * kHistBuckets);
     }
     // init (colours beyond what LDS holds): D^2, kInitThreads R entries per
     // block (below n + kInitThreads per block); k-means: two uint64 records

@@ -2,28 +2,28 @@
 // and their pixel counts, in ascending key order.
 //
 // The paper hashes colours into a chained table.  Here the 2^24 keys are split
-// into kHistBuckets buckets of consecutive keys (the top 11 bits), and the
-// pixels are partitioned by bucket before each bucket is counted in LDS, so no
-// global counter is ever incremented by more than one block:
-//   k_hist_buckets   per tile of pixels: pixels per bucket (LDS), one column
-//                    of the bucket x tile count matrix;
-//   k_hist_colscan   per bucket: exclusive prefix of its row over the tiles,
-//                    and the bucket's pixel total;
-//   k_hist_starts    per job: the first pixel slot of every bucket;
-//   k_hist_scatter   per tile: every pixel's low 13 key bits into its bucket's
-//                    range (bucket start + the tile's prefix + rank);
-//   k_hist_count     per bucket (a fixed number of blocks per job): counts of
-//                    its 8192 keys in LDS, then the non-zero ones compacted in
-//                    ascending order in place;
-//   k_hist_ustarts   per job: the first output entry of every bucket and N';
+// into kHistBuckets buckets of consecutive keys (the top 11 bits), and every
+// tile of pixels is sorted by bucket in LDS before each bucket is counted in
+// LDS, so no global counter is ever incremented by more than one block:
+//   k_hist_part      per tile: pixels per bucket (LDS), their exclusive prefix
+//                    over the buckets (the tile-local starts), the tile's low
+//                    key bits sorted by bucket into the tile's own range, and
+//                    the tile's row of counts and starts;
+//   k_hist_count     per bucket (a fixed number of blocks per job): the
+//                    bucket's segments of every tile counted in LDS, the
+//                    non-zero counters compacted in ascending order at the
+//                    bucket's place in the compacted arrays (the sum over the
+//                    tiles of the bucket's tile-local starts);
 //   k_hist_emit      per bucket (one wave each): the bucket's (key, count)
-//                    pairs from there.
-// Every launch covers all jobs of a batch.
+//                    pairs at its first output entry, and N'.
+// The image is read from HBM once, into registers; every launch covers all
+// jobs of a batch.
 #include "cq_internal.h"
 
 namespace cq {
 
 constexpr int kHistThreads = 512;
+static_assert(kHistTile <= 32768, "a tile's bucket counts and starts share one 32-bit word");
 
 // Key of the pixel p (row-major index) of a job's histogram view.
 __device__ __forceinline__ uint32_t load_key(const uint8_t* __restrict__ img, int64_t p, int32_t W,
@@ -49,20 +49,24 @@ __device__ __forceinline__ void unpack4(uint32_t a, uint32_t b, uint32_t c, uint
     k[3] = (((c >> 8) & 0xffu) << 16) | (((c >> 16) & 0xffu) << 8) | (c >> 24);
 }
 
-// Calls f(key, valid) for the pixels of tile `lb` of the histogram view, four
-// pixels per thread per step from three dword loads when the view is packed.
-template <typename F>
-__device__ __forceinline__ void for_tile_pixels(const JobDev& J, int64_t lb, F f)
-{
-    const uint8_t* __restrict__ img = gp(J.img);
-    const int64_t npix = hist_pixels(J);
-    const int64_t p0 = lb * kHistTile;
-    const int64_t p1 = p0 + kHistTile < npix ? p0 + kHistTile : npix;
-    if (J.hpacked) {
+// The pixels of tile `lb` of a packed histogram view, held in registers:
+// four pixels per thread per step in three dwords, plus one pixel of the
+// tail of an image whose pixel count is not a multiple of 4.  visit(f) calls
+// f(key, valid) for each of them.
+struct PackedTile {
+    static constexpr int kSteps = kHistTile / 4 / kHistThreads;
+    uint32_t a[kSteps], b[kSteps], c[kSteps], tail;
+    int64_t g0, g1, tp, p1;
+
+    __device__ __forceinline__ void load(const JobDev& J, int64_t lb)
+    {
+        const uint8_t* __restrict__ img = gp(J.img);
         const uint32_t* __restrict__ w = reinterpret_cast<const uint32_t*>(img);
-        const int64_t g0 = p0 >> 2, g1 = p1 >> 2;  // whole groups of four pixels
-        constexpr int kSteps = kHistTile / 4 / kHistThreads;
-        uint32_t a[kSteps], b[kSteps], c[kSteps];
+        const int64_t npix = hist_pixels(J);
+        const int64_t p0 = lb * kHistTile;
+        p1 = p0 + kHistTile < npix ? p0 + kHistTile : npix;
+        g0 = p0 >> 2;
+        g1 = p1 >> 2;  // whole groups of four pixels
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) {  // all loads first
             const int64_t g = g0 + s * kHistThreads + threadIdx.x;
@@ -71,6 +75,13 @@ __device__ __forceinline__ void for_tile_pixels(const JobDev& J, int64_t lb, F f
             b[s] = in ? w[3 * g + 1] : 0u;
             c[s] = in ? w[3 * g + 2] : 0u;
         }
+        tp = g1 * 4 + threadIdx.x;
+        tail = tp < p1 ? load_key(img, tp, J.hW, J.hstride, 3, true) : 0u;
+    }
+
+    template <typename F>
+    __device__ __forceinline__ void visit(F f) const
+    {
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) {
             const bool in = g0 + s * kHistThreads + threadIdx.x < g1;
@@ -79,18 +90,39 @@ __device__ __forceinline__ void for_tile_pixels(const JobDev& J, int64_t lb, F f
 #pragma unroll
             for (int q = 0; q < 4; ++q) f(k[q], in);
         }
-        // the last tile of an image whose pixel count is not a multiple of 4
-        const int64_t tail = g1 * 4 + threadIdx.x;
-        const bool tin = tail < p1;
-        f(tin ? load_key(img, tail, J.hW, J.hstride, 3, true) : 0u, tin);
-    } else {
+        f(tail, tp < p1);
+    }
+};
+
+// The pixels of tile `lb` of a strided view (every second pixel of every
+// second row, or rows with padding), one pixel per thread per step, read
+// again on every visit (the second time mostly from the L2).
+struct StridedTile {
+    const uint8_t* img;
+    int64_t p0, p1, stride;
+    int32_t W, pitch;
+
+    __device__ __forceinline__ void load(const JobDev& J, int64_t lb)
+    {
+        img = gp(J.img);
+        const int64_t npix = hist_pixels(J);
+        p0 = lb * kHistTile;
+        p1 = p0 + kHistTile < npix ? p0 + kHistTile : npix;
+        stride = J.hstride;
+        W = J.hW;
+        pitch = J.hpitch;
+    }
+
+    template <typename F>
+    __device__ __forceinline__ void visit(F f) const
+    {
         for (int64_t p = p0; p < p1; p += kHistThreads) {
             const int64_t q = p + threadIdx.x;
             const bool in = q < p1;
-            f(in ? load_key(img, q, J.hW, J.hstride, J.hpitch, false) : 0u, in);
+            f(in ? load_key(img, q, W, stride, pitch, false) : 0u, in);
         }
     }
-}
+};
 
 // Exclusive prefix of kHistBuckets values (one block of kHistThreads
 // threads, kHistBuckets / kHistThreads consecutive values per thread);
@@ -116,144 +148,215 @@ __device__ __forceinline__ uint32_t bucket_scan(const uint32_t* __restrict__ v, 
 }
 
 // ------------------------------------------------------------------ kernels
-__global__ void __launch_bounds__(kHistThreads) k_hist_buckets(const JobDev* __restrict__ jobs,
-                                                               const int* __restrict__ map, int B)
+// One block per tile of kHistTile pixels, read from HBM once into registers.
+// The tile's pixels are counted per bucket in LDS; the exclusive prefix of
+// the counts over the buckets gives each bucket's start inside the tile; the
+// pixels' low key bits are placed at those starts in LDS (the order inside a
+// bucket is whatever the LDS atomics give) and stored to the tile's own
+// range of hkeys in one coalesced pass.  The tile's counts and starts go to
+// its row of hmat (tile-major), both in one word: count | start << 16 (each
+// at most kHistTile = 2^15).
+template <typename Tile>
+__device__ __forceinline__ void part_tile(const JobDev& J, int lb, const Tile& tile, uint32_t* cnt,
+                                          uint32_t* tmp, uint16_t* skey)
+{
+    // one LDS atomic per pixel: lanes with different buckets proceed together,
+    // lanes that share one are serialized by the LDS unit
+    tile.visit([&](uint32_t key, bool in) {
+        if (in) atomicAdd(&cnt[key >> kHistLowBits], 1u);
+    });
+    __syncthreads();
+    uint32_t* __restrict__ mrow = gp(J.hmat) + int64_t(lb) * kHistBuckets;
+    {
+        uint32_t v[kPerBucketThread], sum = 0;
+#pragma unroll
+        for (int u = 0; u < kPerBucketThread; ++u) {
+            v[u] = cnt[threadIdx.x * kPerBucketThread + u];
+            sum += v[u];
+        }
+        uint32_t pre = block_exclusive_scan<uint32_t>(sum, tmp, nullptr);
+#pragma unroll
+        for (int u = 0; u < kPerBucketThread; ++u) {
+            const int b = threadIdx.x * kPerBucketThread + u;
+            mrow[b] = v[u] | (pre << 16);
+            cnt[b] = pre;  // becomes the bucket's cursor
+            pre += v[u];
+        }
+    }
+    __syncthreads();
+    // each pixel's low bits to its bucket's cursor
+    tile.visit([&](uint32_t key, bool in) {
+        if (in) skey[atomicAdd(&cnt[key >> kHistLowBits], 1u)] = uint16_t(key & (kHistLow - 1));
+    });
+    __syncthreads();
+    const int64_t npix = hist_pixels(J);
+    const int64_t p0 = int64_t(lb) * kHistTile;
+    const int n = int(p0 + kHistTile < npix ? kHistTile : npix - p0);
+    // pairs of keys as one dword where the tile's range allows (it starts at
+    // a multiple of kHistTile, so it is 4-byte aligned)
+    uint32_t* __restrict__ out2 = reinterpret_cast<uint32_t*>(gp(J.hkeys) + p0);
+    const uint32_t* s2 = reinterpret_cast<const uint32_t*>(skey);
+    for (int i = threadIdx.x; i < n / 2; i += kHistThreads) out2[i] = s2[i];
+    if ((n & 1) && threadIdx.x == 0) gp(J.hkeys)[p0 + n - 1] = skey[n - 1];
+}
+
+__global__ void __launch_bounds__(kHistThreads) k_hist_part(const JobDev* __restrict__ jobs,
+                                                            const int* __restrict__ map, int B)
 {
     __shared__ uint32_t cnt[kHistBuckets];
+    __shared__ uint32_t tmp[64];
+    __shared__ __align__(16) uint16_t skey[kHistTile];
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int lb = blockIdx.x - map[jb];
     for (int t = threadIdx.x; t < kHistBuckets; t += kHistThreads) cnt[t] = 0u;
-    __syncthreads();
-    // one LDS atomic per pixel: lanes with different buckets proceed together,
-    // lanes that share one are serialized by the LDS unit
-    for_tile_pixels(J, lb, [&](uint32_t key, bool in) {
-        if (in) atomicAdd(&cnt[key >> kHistLowBits], 1u);
-    });
-    __syncthreads();
-    const int64_t ntiles = hist_tiles(hist_pixels(J));
-    uint32_t* __restrict__ mat = gp(J.hmat);
-    for (int t = threadIdx.x; t < kHistBuckets; t += kHistThreads) mat[t * ntiles + lb] = cnt[t];
-}
-
-// One block per (job, bucket): exclusive prefix over the tiles, in place.
-__global__ void __launch_bounds__(256) k_hist_colscan(const JobDev* __restrict__ jobs)
-{
-    __shared__ uint32_t tmp[64];
-    const JobDev& J = jobs[blockIdx.x / kHistBuckets];
-    const int b = blockIdx.x % kHistBuckets;
-    const int64_t ntiles = hist_tiles(hist_pixels(J));
-    uint32_t* __restrict__ row = gp(J.hmat) + b * ntiles;
-    uint32_t carry = 0;
-    for (int64_t t0 = 0; t0 < ntiles; t0 += blockDim.x) {
-        const int64_t t = t0 + threadIdx.x;
-        const uint32_t v = t < ntiles ? row[t] : 0u;
-        uint32_t tot = 0;
-        const uint32_t ex = block_exclusive_scan<uint32_t>(v, tmp, &tot);
-        if (t < ntiles) row[t] = carry + ex;
-        carry += tot;
+    if (J.hpacked) {
+        PackedTile tile;
+        tile.load(J, lb);
+        __syncthreads();
+        part_tile(J, lb, tile, cnt, tmp, skey);
+    } else {
+        StridedTile tile;
+        tile.load(J, lb);
+        __syncthreads();
+        part_tile(J, lb, tile, cnt, tmp, skey);
     }
-    if (threadIdx.x == 0) gp(J.hbt)[b] = carry;
 }
 
-// One block per job: first pixel slot of every bucket.
-__global__ void __launch_bounds__(kHistThreads) k_hist_starts(const JobDev* __restrict__ jobs)
-{
-    __shared__ uint32_t tmp[64];
-    const JobDev& J = jobs[blockIdx.x];
-    bucket_scan(gp(J.hbt), gp(J.hbs), tmp);
-}
-
-// One block per job: first output entry of every bucket, and N'.
-__global__ void __launch_bounds__(kHistThreads) k_hist_ustarts(const JobDev* __restrict__ jobs)
-{
-    __shared__ uint32_t tmp[64];
-    const JobDev& J = jobs[blockIdx.x];
-    const uint32_t total = bucket_scan(gp(J.hnu), gp(J.hus), tmp);
-    if (threadIdx.x == 0) gp(J.meta)->n_unique = int64_t(total);
-}
-
-__global__ void __launch_bounds__(kHistThreads) k_hist_scatter(const JobDev* __restrict__ jobs,
-                                                               const int* __restrict__ map, int B)
-{
-    __shared__ uint32_t pos[kHistBuckets];
-    const int jb = find_job(map, B, blockIdx.x);
-    const JobDev& J = jobs[jb];
-    const int lb = blockIdx.x - map[jb];
-    const int64_t ntiles = hist_tiles(hist_pixels(J));
-    const uint32_t* __restrict__ mat = gp(J.hmat);
-    const uint32_t* __restrict__ bs = gp(J.hbs);
-    for (int b = threadIdx.x; b < kHistBuckets; b += kHistThreads)
-        pos[b] = bs[b] + mat[b * ntiles + lb];  // bucket start + this tile's prefix
-    __syncthreads();
-    uint16_t* __restrict__ hk = gp(J.hkeys);
-    for_tile_pixels(J, lb, [&](uint32_t key, bool in) {
-        if (in) hk[atomicAdd(&pos[key >> kHistLowBits], 1u)] = uint16_t(key & (kHistLow - 1));
-    });
-}
-
-// Per job, hist_count_blocks(npix) blocks (a power of two up to one per
-// bucket), block c of C taking the buckets c, c + C, ...: a bucket of at most
-// one key per thread is ranked through a bitmap of the keys present; a larger
-// bucket's keys are counted in LDS, then the non-zero
-// counters are compacted in ascending key order over the front of the
-// bucket's own range (its keys are all read before anything is written).  The
-// 8192 counters are cleared once; a bucket marks the groups of 64 counters it
-// touches, and only those are read back and cleared again, so a bucket costs
-// in proportion to its contents.
-constexpr int kGroups = kHistLow / 64;  // 128 groups of 64 counters
+// Per job, hist_count_blocks(npix) blocks (a power of two from 256 up to one
+// per bucket); block c of C takes the virtual buckets c, c + C, ....  Virtual
+// bucket v = 8 j + x is bucket 256 (j / 32) + 32 x + j mod 32.  Workgroups
+// are handed to the eight XCDs in turn, so x = v mod 8 is the block's XCD (C
+// and every job's first block index are multiples of 8), and an XCD takes
+// whole groups of 32 consecutive buckets, every eighth group: the 128-byte
+// lines of hmat, and the neighbouring segments of hkeys, that a group's
+// blocks share are fetched into one L2, while the work of any range of
+// colours is spread over all XCDs.
+//
+// A bucket's pixels are its segment of every tile (tile t's row of hmat gives
+// the segment's length and start inside the tile).  The non-empty segments
+// are listed in tile order with their first position in the bucket's
+// concatenation and the offset that turns a position into an hkeys index;
+// the bucket's place in the compacted arrays hk2 / hcnt is the sum over the
+// tiles of its tile-local starts (the number of pixels of all lower buckets).
+// A bucket of at most one key per thread is ranked through a bitmap of the
+// keys present.  A larger bucket is read in windows of kHistWindow positions:
+// a bitmap marks the positions where a segment starts, and each wave reads 64
+// consecutive positions per load, a lane's segment being the one before it
+// plus the marks up to the lane (a population count), so no lane searches.
+// Its keys are counted in LDS; the 8192 counters are cleared once, a bucket
+// marks the groups of 64 counters it touches, and only those are read back
+// and cleared again, so a bucket costs in proportion to its contents.  The
+// distinct keys go, in ascending order with their counts, to the bucket's
+// place.  Dynamic LDS: the segment starts (tiles + 1 entries) and offsets
+// (tiles entries).
+constexpr int kGroups = kHistLow / 64;   // 128 groups of 64 counters
+constexpr int kHistWindow = 16384;       // positions per bitmap window
+static_assert(kHistWindow % (64 * (kHistThreads / 64)) == 0, "whole 64-position words per wave");
 
 __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __restrict__ jobs,
                                                              const int* __restrict__ map, int B)
 {
     __shared__ uint32_t c[kHistLow];
     __shared__ uint32_t touched[kGroups / 32];
-    __shared__ uint32_t tmp[64];
-    __shared__ uint32_t s_total[kHistBuckets / 256], s_start[kHistBuckets / 256];  // this block's buckets
-    __shared__ uint32_t s_bits[kHistLow / 32], s_wpre[kHistLow / 32];  // small buckets: keys present, ranks
+    __shared__ uint64_t tmp[64];
+    // small buckets: keys present and their ranks; large ones: segment starts of a window
+    __shared__ __align__(8) uint32_t s_bits[kHistWindow / 32];
+    __shared__ uint32_t s_total, s_start, s_nseg;
+    extern __shared__ uint32_t seg[];  // [ntiles + 1] starts, then [ntiles] offsets
+    uint32_t* s_wpre = s_bits + kHistLow / 32;
+    static_assert(kHistWindow / 32 >= 2 * (kHistLow / 32), "the small-bucket arrays fit the window bitmap");
     const int jb = find_job(map, B, blockIdx.x);
     const JobDev& J = jobs[jb];
     const int cb0 = blockIdx.x - map[jb];
-    const int kCountBlocks = map[jb + 1] - map[jb];  // at least 256
+    const int kCountBlocks = map[jb + 1] - map[jb];
+    const int ntiles = int(hist_tiles(hist_pixels(J)));
+    uint32_t* cstart = seg;
+    int32_t* coff = reinterpret_cast<int32_t*>(seg + ntiles + 1);
     for (int t = threadIdx.x; t < kHistLow; t += kHistThreads) c[t] = 0u;
     if (threadIdx.x < kGroups / 32) touched[threadIdx.x] = 0u;
-    if (threadIdx.x < kHistLow / 32) s_bits[threadIdx.x] = 0u;
-    // every bucket's pixel count and first slot at once, not one bucket after another
-    if (threadIdx.x < kHistBuckets / 256) {
-        const int b = cb0 + threadIdx.x * kCountBlocks;
-        s_total[threadIdx.x] = b < kHistBuckets ? gp(J.hbt)[b] : 0u;
-        s_start[threadIdx.x] = b < kHistBuckets ? gp(J.hbs)[b] : 0u;
-    }
-    __syncthreads();
+    for (int t = threadIdx.x; t < kHistLow / 32; t += kHistThreads) s_bits[t] = 0u;
+    const uint32_t* __restrict__ mat = gp(J.hmat);
+    const uint16_t* __restrict__ hkeys = gp(J.hkeys);
     constexpr int R = kHistLow / kHistThreads;  // 16 counters per thread in the compaction
-    constexpr int kUnroll = 8;
-    for (int b = cb0, q = 0; b < kHistBuckets; b += kCountBlocks, ++q) {
-        const uint32_t total = s_total[q];
+    constexpr int kUnroll = 16;                 // loads in flight per lane
+    static_assert(kHistBuckets % 256 == 0, "groups of 32 buckets dealt to eight XCDs");
+    const int wave = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63);
+    for (int vb = cb0; vb < kHistBuckets; vb += kCountBlocks) {
+        const int j = vb >> 3;
+        const int b = (j >> 5) * 256 + (vb & 7) * 32 + (j & 31);
+        // the non-empty segments: one scan of (count of them, their lengths)
+        uint64_t carry = 0;
+        uint32_t place = 0;
+        for (int t0 = 0; t0 < ntiles; t0 += kHistThreads) {
+            const int t = t0 + threadIdx.x;
+            const uint32_t m = t < ntiles ? mat[int64_t(t) * kHistBuckets + b] : 0u;
+            const uint32_t len = m & 0xffffu, sst = m >> 16;
+            uint64_t tot = 0;
+            const uint64_t ex = carry + block_exclusive_scan<uint64_t>((uint64_t(len != 0u) << 32) | len, tmp, &tot);
+            if (len != 0u) {
+                const uint32_t js = uint32_t(ex >> 32), pos = uint32_t(ex);
+                cstart[js] = pos;
+                coff[js] = int32_t(t * kHistTile + int(sst) - int(pos));
+            }
+            carry += tot;
+            place += sst;
+        }
+        place = wave_sum(place);
+        if (lane == 0) reinterpret_cast<uint32_t*>(tmp)[wave] = place;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t p = 0;
+            for (int w = 0; w < kHistThreads / 64; ++w) p += reinterpret_cast<uint32_t*>(tmp)[w];
+            const uint32_t nseg = uint32_t(carry >> 32), total = uint32_t(carry);
+            s_start = p;
+            s_total = total;
+            s_nseg = nseg;
+            cstart[nseg] = total;
+            gp(J.hbs)[b] = p;
+        }
+        __syncthreads();
+        const uint32_t total = s_total, nseg = s_nseg;
         if (total == 0) {
             if (threadIdx.x == 0) gp(J.hnu)[b] = 0u;
             continue;
         }
-        const uint32_t start = s_start[q];
-        uint16_t* __restrict__ hk = gp(J.hkeys) + start;
+        const uint32_t start = s_start;
+        uint16_t* __restrict__ hk = gp(J.hk2) + start;
         uint32_t* __restrict__ hc = gp(J.hcnt) + start;
+        // number of segments starting before position i (cstart ascending)
+        auto starts_below = [&](uint32_t i) -> uint32_t {
+            uint32_t lo = 0, hi = nseg;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (cstart[mid] < i) lo = mid + 1; else hi = mid;
+            }
+            return lo;
+        };
         if (total <= kHistThreads) {
             // at most one key per thread: the first thread of each key marks
             // it in a bitmap, and a key's rank among the distinct keys is the
             // count of marks below it (an exclusive scan of the 256 words'
             // population counts, then the word's own lower bits)
-            const uint32_t key = threadIdx.x < total ? uint32_t(hk[threadIdx.x]) : 0xffffffffu;
+            const uint32_t i = threadIdx.x;
+            uint32_t key = 0xffffffffu;
+            if (i < total) {
+                const uint32_t js = starts_below(i + 1) - 1;  // the last segment starting at or before i
+                key = uint32_t(hkeys[int64_t(coff[js]) + i]);
+            }
             const bool first = key != 0xffffffffu && atomicAdd(&c[key], 1u) == 0u;
             if (first) atomicOr(&s_bits[key >> 5], 1u << (key & 31u));
             __syncthreads();
             const uint32_t word = threadIdx.x < kHistLow / 32 ? s_bits[threadIdx.x] : 0u;
             uint32_t nuniq = 0;
-            const uint32_t wpre = block_exclusive_scan<uint32_t>(__popc(word), tmp, &nuniq);
+            const uint32_t wpre =
+                block_exclusive_scan<uint32_t>(__popc(word), reinterpret_cast<uint32_t*>(tmp), &nuniq);
             if (threadIdx.x < kHistLow / 32) s_wpre[threadIdx.x] = wpre;
             __syncthreads();
             if (first) {
                 const uint32_t w = key >> 5;
                 const uint32_t rank = s_wpre[w] + __popc(s_bits[w] & ((1u << (key & 31u)) - 1u));
-                hk[rank] = uint16_t(key);  // every key was read before the first barrier
+                hk[rank] = uint16_t(key);
                 hc[rank] = c[key];
             }
             if (threadIdx.x == 0) gp(J.hnu)[b] = nuniq;
@@ -263,21 +366,45 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __res
             __syncthreads();
             continue;
         }
-        // eight keys in flight per thread before their LDS atomics
-        for (uint32_t i0 = 0; i0 < total; i0 += kUnroll * kHistThreads) {
-            uint32_t kq[kUnroll];
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t i = i0 + u * kHistThreads + threadIdx.x;
-                kq[u] = i < total ? uint32_t(hk[i]) : 0xffffffffu;
+        const uint64_t* bits64 = reinterpret_cast<const uint64_t*>(s_bits);
+        const uint64_t below = lane == 63 ? ~uint64_t(0) : (uint64_t(2) << lane) - 1u;  // marks at or before the lane
+        for (uint32_t w0 = 0; w0 < total; w0 += kHistWindow) {
+            const uint32_t w1 = w0 + kHistWindow < total ? w0 + kHistWindow : total;
+            // the window's segment starts, as marks
+            for (int t = threadIdx.x; t < kHistWindow / 32; t += kHistThreads) s_bits[t] = 0u;
+            const uint32_t jlo = starts_below(w0), jhi = starts_below(w1);
+            __syncthreads();
+            for (uint32_t js = jlo + threadIdx.x; js < jhi; js += kHistThreads) {
+                const uint32_t r = cstart[js] - w0;
+                atomicOr(&s_bits[r >> 5], 1u << (r & 31u));
             }
+            __syncthreads();
+            // wave w takes positions [a, e) of the window, whole words of 64
+            const uint32_t pw = (w1 - w0 + kHistThreads - 1) / kHistThreads * 64;
+            const uint32_t a = w0 + uint32_t(wave) * pw;
+            const uint32_t e = a + pw < w1 ? a + pw : w1;
+            uint32_t jbase = a < e ? starts_below(a) : 0u;  // segments starting before a
+            for (uint32_t base = a; base < e; base += 64 * kUnroll) {
+                uint32_t kq[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                if (kq[u] == 0xffffffffu) continue;
-                if (atomicAdd(&c[kq[u]], 1u) == 0u) atomicOr(&touched[kq[u] >> 11], 1u << ((kq[u] >> 6) & 31u));
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint32_t wb = base + 64 * u;
+                    const uint64_t marks = wb < e ? bits64[(wb - w0) >> 6] : 0u;
+                    // the lane's segment: the last one starting at or before it
+                    const uint32_t js = jbase + uint32_t(__popcll(marks & below)) - 1u;
+                    jbase += uint32_t(__popcll(marks));
+                    const uint32_t i = wb + uint32_t(lane);
+                    kq[u] = i < e ? uint32_t(hkeys[int64_t(coff[js]) + i]) : 0xffffffffu;
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (kq[u] == 0xffffffffu) continue;
+                    if (atomicAdd(&c[kq[u]], 1u) == 0u)
+                        atomicOr(&touched[kq[u] >> 11], 1u << ((kq[u] >> 6) & 31u));
+                }
             }
+            __syncthreads();  // the window's marks are read
         }
-        __syncthreads();
         // thread t owns counters [t R, (t + 1) R), inside group t R / 64
         const int g = threadIdx.x * R / 64;
         const bool hit = (touched[g >> 5] >> (g & 31)) & 1u;
@@ -289,7 +416,7 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __res
             nz += v[u] != 0u;
         }
         uint32_t nuniq = 0;
-        uint32_t o = block_exclusive_scan<uint32_t>(nz, tmp, &nuniq);
+        uint32_t o = block_exclusive_scan<uint32_t>(nz, reinterpret_cast<uint32_t*>(tmp), &nuniq);
         if (hit) {
 #pragma unroll
             for (int u = 0; u < R; ++u) {
@@ -304,27 +431,37 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __res
         if (threadIdx.x == 0) gp(J.hnu)[b] = nuniq;
         __syncthreads();  // every touched counter is cleared and the mask was read
         if (threadIdx.x < kGroups / 32) touched[threadIdx.x] = 0u;
+        // the small-bucket bitmap must start empty
+        for (int t = threadIdx.x; t < kHistLow / 32; t += kHistThreads) s_bits[t] = 0u;
         __syncthreads();
     }
 }
 
-// One block per (job, bucket): the bucket's pairs into keys / counts at the
-// prefix of the unique counts; entries past `capacity` are not written.
-// One wave per bucket, kHistThreads / 64 buckets per block.
+// The (key, count) pairs of every bucket, at the bucket's first output entry
+// (the exclusive prefix of the unique counts of the buckets, which each block
+// computes for itself from the 2048 counts); entries past `capacity` are not
+// written.  One wave per bucket, kHistThreads / 64 buckets per block; the
+// first block of a job also stores N'.
 constexpr int kEmitPerBlock = kHistThreads / 64;
 
 __global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __restrict__ jobs)
 {
+    __shared__ uint32_t us[kHistBuckets];
+    __shared__ uint32_t tmp[64];
     constexpr int kBlocksPerJob = kHistBuckets / kEmitPerBlock;
     const JobDev& J = jobs[blockIdx.x / kBlocksPerJob];
-    const int b = (blockIdx.x % kBlocksPerJob) * kEmitPerBlock + int(threadIdx.x >> 6);
+    const int blk = blockIdx.x % kBlocksPerJob;
+    const uint32_t n_unique = bucket_scan(gp(J.hnu), us, tmp);
+    if (blk == 0 && threadIdx.x == 0) gp(J.meta)->n_unique = int64_t(n_unique);
+    __syncthreads();
+    const int b = blk * kEmitPerBlock + int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const uint32_t nb = gp(J.hnu)[b];
     if (nb == 0) return;
     const uint32_t start = gp(J.hbs)[b];
-    const uint16_t* __restrict__ hk = gp(J.hkeys) + start;
+    const uint16_t* __restrict__ hk = gp(J.hk2) + start;
     const uint32_t* __restrict__ hc = gp(J.hcnt) + start;
-    const int64_t out = gp(J.hus)[b];
+    const int64_t out = us[b];
     uint32_t* __restrict__ keys = gp(J.keys);
     uint32_t* __restrict__ counts = gp(J.counts);
     const int64_t capacity = J.capacity;
@@ -387,16 +524,13 @@ cq_status launch_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t ro
 }
 
 cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_tiles, int total_count,
-                           hipStream_t s)
+                           int max_tiles, hipStream_t s)
 {
     const int* tmap = maps + kMapHist * (B + 1);
     const int* cmap = maps + kMapHistCount * (B + 1);
-    CQ_TIMED_LAUNCH("k_hist_buckets", s, k_hist_buckets<<<total_tiles, kHistThreads, 0, s>>>(jobs, tmap, B));
-    CQ_TIMED_LAUNCH("k_hist_colscan", s, k_hist_colscan<<<kHistBuckets * B, 256, 0, s>>>(jobs));
-    CQ_TIMED_LAUNCH("k_hist_starts", s, k_hist_starts<<<B, kHistThreads, 0, s>>>(jobs));
-    CQ_TIMED_LAUNCH("k_hist_scatter", s, k_hist_scatter<<<total_tiles, kHistThreads, 0, s>>>(jobs, tmap, B));
-    CQ_TIMED_LAUNCH("k_hist_count", s, k_hist_count<<<total_count, kHistThreads, 0, s>>>(jobs, cmap, B));
-    CQ_TIMED_LAUNCH("k_hist_ustarts", s, k_hist_ustarts<<<B, kHistThreads, 0, s>>>(jobs));
+    const size_t seg_lds = sizeof(uint32_t) * (2 * size_t(max_tiles) + 1);
+    CQ_TIMED_LAUNCH("k_hist_part", s, k_hist_part<<<total_tiles, kHistThreads, 0, s>>>(jobs, tmap, B));
+    CQ_TIMED_LAUNCH("k_hist_count", s, k_hist_count<<<total_count, kHistThreads, seg_lds, s>>>(jobs, cmap, B));
     CQ_TIMED_LAUNCH("k_hist_emit", s, k_hist_emit<<<kHistBuckets / kEmitPerBlock * B, kHistThreads, 0, s>>>(jobs));
     return CQ_OK;
 }
