@@ -118,9 +118,9 @@ def measure_serving(cq, torch, synth, imgs, dev, host_c4, workers, seconds):
       1,000,000 + i, i < 1024; the first 512 are the mixed batch) and its own
       K drawn from {16, 32, 64, 128, 256}.  Images start in pinned host
       memory and are copied in when a request gets device buffers; results go
-      back to pinned host memory before a request counts as done.  At most 96
-      requests hold device buffers, at most 64 are in flight in the engine,
-      whose slot pool has 12 GiB; requests beyond that wait (deferred).
+      back to pinned host memory before a request counts as done.  At most 192
+      requests hold device buffers, at most 128 are in flight in the engine,
+      whose slot pool has 24 GiB; requests beyond that wait (deferred).
     Every request: sort-means, tol 1e-4, at most 100 iterations, full map."""
     import numpy as np
 
@@ -151,16 +151,16 @@ def measure_serving(cq, torch, synth, imgs, dev, host_c4, workers, seconds):
     pick = rng.integers(0, len(pool), n)
     ks = rng.choice(np.array([16, 32, 64, 128, 256]), n)
     seeds = 3_000_000 + np.arange(n)
-    eng = cq.Engine(64, 12 << 30, dev)
+    eng = cq.Engine(128, 24 << 30, dev)
     warm = serve.poisson_window(rate, 0.1, seed=9)
-    serve.run_stream(eng, pool, warm, pick, ks, seeds, 96, MAX_ITERS, TOL)  # warm-up
-    res = serve.run_stream(eng, pool, arrivals, pick, ks, seeds, 96, MAX_ITERS, TOL)
+    serve.run_stream(eng, pool, warm, pick, ks, seeds, 192, MAX_ITERS, TOL)  # warm-up
+    res = serve.run_stream(eng, pool, arrivals, pick, ks, seeds, 192, MAX_ITERS, TOL)
     eng.close()
     res["mean_pixels"] = float(np.mean([pool[p].shape[0] * pool[p].shape[1] for p in pick]))
     res["workload"] = (f"Poisson arrivals at {rate:.0f}/s for {seconds:.0f} s ({n} requests); images drawn "
                        "from a pool of 1024 mixed-size stand-ins (long side 64-2048) in pinned host memory, "
                        "each request with its own K in {16..256}; host-to-device input and device-to-host "
-                       "results inside the latency; 96 request slots, 64 jobs in flight, 12 GiB slot pool, "
+                       "results inside the latency; 192 request slots, 128 jobs in flight, 24 GiB slot pool, "
                        "8 iterations per step")
     out["poisson_2000_per_s"] = res
     return out

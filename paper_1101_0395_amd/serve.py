@@ -135,7 +135,8 @@ def run_stream(engine: cq.Engine, pool: list[torch.Tensor], arrivals: np.ndarray
     request r quantizes the pinned host image pool[pick[r]] with K = ks[r]
     (k-means++ seeded seeds[r], sort-means).  At most `slots` requests hold
     device buffers at once; a request that arrives while all are taken waits
-    in a host backlog (it is "deferred").  A request is copied to the device
+    in a host backlog (it is "deferred": counted when the requests already
+    waiting take every free slot).  A request is copied to the device
     when it gets a slot, submitted to the engine (which admits it when its
     pool range is free), and done once its palette, index image and RGB image
     are back in pinned host memory; its latency runs from its arrival to
@@ -159,7 +160,7 @@ def run_stream(engine: cq.Engine, pool: list[torch.Tensor], arrivals: np.ndarray
     while done_n < n:
         now = time.perf_counter() - t0
         while i < n and arrivals[i] <= now:
-            if backlog or not free:
+            if len(backlog) >= len(free):  # every free slot is already spoken for
                 deferred += 1
             backlog.append(i)
             i += 1
