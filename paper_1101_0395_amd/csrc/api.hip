@@ -585,11 +585,18 @@ cq_status run_kmeans(Batch& b, bool memberships, bool check)
     return CQ_OK;
 }
 
-cq_status run_map(Batch& b, bool with_err)
+cq_status run_map(Batch& b, bool with_err, bool from_records)
 {
     // a job whose table covers every colour of its image maps through it and
     // sums the squared error over the colours; one that searches the palette
-    // per pixel sums it over the pixels in the map kernel
+    // per pixel sums it over the pixels in the map kernel.  A pruned job just
+    // out of its k-means run searches from its colours' clusters, through
+    // its palette's sorted distance rows.
+    for (JobDev& J : b.h) J.lut_rec = (from_records && J.prune && !J.map_direct && J.n > J.K) ? 1 : 0;
+    const int rows_total = b.set_map(kMapPalRows, [&](int j) {
+        const JobDev& J = b.h[j];
+        return J.lut_rec ? pal_rows_blocks(J.map_k) : 0;
+    });
     const int lut_total = b.set_map(kMapLut, [&](int j) {
         const JobDev& J = b.h[j];
         return J.map_direct ? 0 : int((J.n + J.chunk - 1) / J.chunk);
@@ -601,6 +608,7 @@ cq_status run_map(Batch& b, bool with_err)
     });
     CQ_TRY(upload(b));
     if (with_err) CQ_TIMED_LAUNCH("k_zero_sq_err", b.s, k_zero_sq_err<<<(b.B + 63) / 64, 64, 0, b.s>>>(b.d_jobs(), b.B));
+    if (rows_total > 0) CQ_TRY(launch_pal_rows(b.d_jobs(), b.d_maps(), b.B, rows_total, b.s));
     if (lut_total > 0) CQ_TRY(launch_lut(b.d_jobs(), b.d_maps(), b.B, lut_total, with_err ? 1 : 0, b.s));
     if (pix_total > 0) CQ_TRY(launch_map(b.d_jobs(), b.d_maps(), b.B, pix_total, with_err ? 1 : 0, b.s));
     return CQ_OK;
@@ -659,7 +667,7 @@ cq_status run_quantize(Batch& b, cq_stats* stats)
     CQ_TRY(check_init(b));
     CQ_TRY(check_kmeans(b));
     CQ_TRY(launch_palette(b.d_jobs(), b.B, b.s));
-    CQ_TRY(run_map(b, true));
+    CQ_TRY(run_map(b, true, true));
     CQ_TRY(collect(b));
     if (stats)
         for (int j = 0; j < b.B; ++j) fill_stats(b.h[j], b.res[j], stats[j], true);
@@ -919,7 +927,7 @@ cq_status cq_map(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_by
     J.map_k = K;
     J.packed = J.packed && (reinterpret_cast<uintptr_t>(out_idx) & 3u) == 0 &&
                (reinterpret_cast<uintptr_t>(out_rgb) & 3u) == 0;
-    CQ_TRY(run_map(b, sq_err_sum != nullptr));
+    CQ_TRY(run_map(b, sq_err_sum != nullptr, false));
     if (sq_err_sum) {
         CQ_TRY(collect(b));
         *sq_err_sum = b.res[0].sq_err;

@@ -132,6 +132,8 @@ int64_t regroup_blocks(int64_t n, int64_t chunk);
 cq_status launch_unpermute(const JobDev* jobs, const int* maps, int B, int blocks, hipStream_t s);
 int map_blocks(int64_t npix);
 cq_status launch_lut(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s);
+int pal_rows_blocks(int K);
+cq_status launch_pal_rows(const JobDev* jobs, const int* maps, int B, int total, hipStream_t s);
 cq_status launch_map(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s);
 
 // argument checks (set the thread's error text)
@@ -155,7 +157,9 @@ cq_status run_init(Batch& b);
 // summing to at most 2^28; a job that fails runs no iteration and
 // check_kmeans reports it).
 cq_status run_kmeans(Batch& b, bool memberships, bool check = false);
-cq_status run_map(Batch& b, bool with_err);
+// from_records: the jobs come straight from their k-means runs, so a pruned
+// job's colour table may start each colour at its final cluster.
+cq_status run_map(Batch& b, bool with_err, bool from_records);
 cq_status run_quantize(Batch& b, cq_stats* stats);  // histogram -> init -> k-means -> palette -> map
 cq_status quantize_into(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride_bytes, int32_t subsample,
                         int32_t K, cq_init_t scheme, uint64_t seed, int32_t max_iters, double tol, int32_t prune,

@@ -150,7 +150,8 @@ struct JobDev {
     int32_t packed;      // image rows are contiguous and 4-byte aligned
     int32_t map_k;       // palette entries the pixel map searches
     int32_t regroup_period;  // pruned runs: regroup the colours at iterations 1-4 and every this many
-    int32_t pad_;
+    int32_t lut_rec;     // the colour table starts each colour's search at its cluster's entry
+                         // (a pruned run's final records) instead of searching every entry
     // the pixels the histogram counts: the whole image, or after 2:1
     // subsampling its pixels at even row and column
     int64_t hstride;     // bytes between rows of the view
@@ -240,6 +241,7 @@ enum MapId {
     kMapUpdate,      // table blocks and regrouping blocks
     kMapUpdateTable, // table blocks only (iterations without regrouping)
     kMapLut,
+    kMapPalRows,     // palette rows sorted by distance (colour tables searched from the clusters)
     kMapPix,
     kMapInit,
     kMapVarTiles,    // VAR: colour tiles

@@ -144,7 +144,7 @@ static cq_status engine_finish(cq_engine* e, const Batch& d, cq_engine_done* don
     for (int i = 0; i < f.B; ++i) f.h[i] = e->active[fin[i]].dev;
     CQ_TRY(upload(f));
     CQ_TRY(launch_palette(f.d_jobs(), f.B, f.s));
-    CQ_TRY(run_map(f, true));
+    CQ_TRY(run_map(f, true, true));
     CQ_TRY(collect(f));
     for (int i = 0; i < f.B; ++i) {
         const EngineJob& x = e->active[fin[i]];

@@ -82,10 +82,86 @@ __device__ __forceinline__ int nearest_entry(uint32_t x, const uint2* ent, int K
     return 255 - (best & 255);
 }
 
+// Squared distance between two colours packed in key order.
+__device__ __forceinline__ uint32_t packed_dist(uint32_t x, uint32_t p)
+{
+    return __builtin_amdgcn_udot4(x, x, 0u, false) + __builtin_amdgcn_udot4(p, p, 0u, false) -
+           2u * __builtin_amdgcn_udot4(x, p, 0u, false);
+}
+
+// Rows of the palette's distance table: row p lists every entry q by
+// (|P_p - P_q|^2, q) ascending, as one word (|P_p - P_q|^2 << 8) | q (a
+// squared distance is below 2^18).  One wave per row, four entries per lane,
+// sorted by a bitonic network (partners four or more entries apart are in
+// other lanes, in the same register).  Only jobs with lut_rec get blocks.
+constexpr int kPalRowsPerBlock = 4;
+constexpr int kPalPerLane = kMaxK / 64;
+
+__global__ void __launch_bounds__(64 * kPalRowsPerBlock) k_pal_rows(const JobDev* __restrict__ jobs,
+                                                                   const int* __restrict__ map, int B)
+{
+    const int jb = find_job(map, B, blockIdx.x);
+    const JobDev& J = jobs[jb];
+    const int K = J.map_k;
+    const int p = (blockIdx.x - map[jb]) * kPalRowsPerBlock + int(threadIdx.x >> 6);
+    if (p >= K) return;  // whole waves; no block barrier follows
+    const int lane = threadIdx.x & 63;
+    const uint8_t* __restrict__ pal = gp(J.palette);
+    const int pr = pal[3 * p], pg = pal[3 * p + 1], pb = pal[3 * p + 2];
+    uint32_t v[kPalPerLane];
+#pragma unroll
+    for (int i = 0; i < kPalPerLane; ++i) {
+        const int q = kPalPerLane * lane + i;
+        if (q < K) {
+            const int dr = int(pal[3 * q]) - pr, dg = int(pal[3 * q + 1]) - pg, db = int(pal[3 * q + 2]) - pb;
+            v[i] = (uint32_t(dr * dr + dg * dg + db * db) << 8) | uint32_t(q);
+        } else {
+            v[i] = 0xffffffffu;
+        }
+    }
+    for (int size = 2; size <= kMaxK; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= kPalPerLane) {
+#pragma unroll
+                for (int i = 0; i < kPalPerLane; ++i) {
+                    const uint32_t o = __shfl_xor(v[i], stride / kPalPerLane, 64);
+                    const int e = kPalPerLane * lane + i;
+                    const bool ascending = (e & size) == 0;
+                    const bool lower = (e & stride) == 0;
+                    v[i] = (lower == ascending) ? (o < v[i] ? o : v[i]) : (o > v[i] ? o : v[i]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < kPalPerLane; ++i) {
+                    if (i & stride) continue;
+                    const int j = i | stride;
+                    const bool ascending = ((kPalPerLane * lane + i) & size) == 0;
+                    const uint32_t lo = v[i] < v[j] ? v[i] : v[j], hi = v[i] < v[j] ? v[j] : v[i];
+                    v[i] = ascending ? lo : hi;
+                    v[j] = ascending ? hi : lo;
+                }
+            }
+        }
+    }
+    uint32_t* __restrict__ row = reinterpret_cast<uint32_t*>(gp(J.tix)) + int64_t(p) * kRow;
+#pragma unroll
+    for (int i = 0; i < kPalPerLane; ++i)
+        if (kPalPerLane * lane + i < K) row[kPalPerLane * lane + i] = v[i];
+}
+
 // Nearest rounded palette entry of every unique colour (exact integer
 // distances, lowest index on ties) into the job's byte table; adds
 // n_i |x_i - P|^2 to the job's squared-error sum.  Block b of job j takes the
 // colours [b chunk, (b + 1) chunk).
+//
+// A job with lut_rec reads its colours from the final records of its pruned
+// run, each with the cluster c it was last assigned to, and scans row c of
+// the palette's distance table: an entry q with |P_c - P_q| > 2 |x - P_c|
+// is farther from x than P_c (|x - P_q| >= |P_c - P_q| - |x - P_c|), so the
+// scan stops at the first entry with |P_c - P_q|^2 > 4 |x - P_c|^2, having
+// seen every entry at least as near as P_c: the same nearest entry, and the
+// same lowest index among equals, as a search of all entries.  Any other job
+// searches all entries.
 __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ jobs,
                                                      const int* __restrict__ map, int B, int with_err)
 {
@@ -103,11 +179,39 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ 
     const int64_t lo = int64_t(lb) * J.chunk;
     const int64_t hi = lo + J.chunk < J.n ? lo + J.chunk : J.n;
     unsigned long long err = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const uint32_t key = keys[i];
-        uint32_t d;
-        lut[lut_slot_key(key)] = uint8_t(nearest_entry(key, ent, K2, &d));
-        if (with_err) err += (unsigned long long)counts[i] * d;
+    const int iters = gp(J.meta)->iters;
+    if (J.lut_rec && iters >= 1) {
+        const uint64_t* __restrict__ g = gp(J.grp) + record_buffer(iters, J.regroup_period) * J.n;
+        const uint32_t* __restrict__ rows = reinterpret_cast<const uint32_t*>(gp(J.tix));
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const uint64_t rec = g[i];
+            const uint32_t key = uint32_t(rec) & 0xffffffu;
+            const int c = int(uint32_t(rec) >> 24);
+            const uint32_t w = uint32_t(rec >> 32) & 0x0fffffffu;
+            uint32_t bd = packed_dist(key, ent[c].x);
+            int bq = c;
+            const uint32_t lim = 4u * bd;
+            const uint32_t* __restrict__ row = rows + int64_t(c) * kRow;
+            for (int e = 0; e < J.map_k; ++e) {
+                const uint32_t v = row[e];
+                if ((v >> 8) > lim) break;
+                const int q = int(v & 255u);
+                const uint32_t d = packed_dist(key, ent[q].x);
+                if (d < bd || (d == bd && q < bq)) {
+                    bd = d;
+                    bq = q;
+                }
+            }
+            lut[lut_slot_key(key)] = uint8_t(bq);
+            if (with_err) err += (unsigned long long)w * bd;
+        }
+    } else {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const uint32_t key = keys[i];
+            uint32_t d;
+            lut[lut_slot_key(key)] = uint8_t(nearest_entry(key, ent, K2, &d));
+            if (with_err) err += (unsigned long long)counts[i] * d;
+        }
     }
     if (!with_err) return;
     err = wave_sum(err);
@@ -287,6 +391,14 @@ cq_status launch_lut(const JobDev* jobs, const int* maps, int B, int total, int 
     CQ_TIMED_LAUNCH("k_lut", s, k_lut<<<total, kLutThreads, 0, s>>>(jobs, maps + kMapLut * (B + 1), B, with_err));
     return CQ_OK;
 }
+
+cq_status launch_pal_rows(const JobDev* jobs, const int* maps, int B, int total, hipStream_t s)
+{
+    CQ_TIMED_LAUNCH("k_pal_rows", s, k_pal_rows<<<total, 64 * kPalRowsPerBlock, 0, s>>>(jobs, maps + kMapPalRows * (B + 1), B));
+    return CQ_OK;
+}
+
+int pal_rows_blocks(int K) { return (K + kPalRowsPerBlock - 1) / kPalRowsPerBlock; }
 
 cq_status launch_map(const JobDev* jobs, const int* maps, int B, int total, int with_err, hipStream_t s)
 {
