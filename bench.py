@@ -37,7 +37,14 @@ C4_IMAGES = 512                # the mixed batch: seeds 1,000,000 + i
 PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X vector FP64
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 FLOP_PER_EVAL = 8              # 3 sub, 3 mul, 2 add per FP64 squared distance
-ROOFLINE_KERNEL = "k_assign_walk"  # sort-means nearest-centre passes, FP64 VALU
+# Algorithmic bytes of one colour in one sort-means pass: its 8-byte record
+# (key, count, previous cluster, distance bucket) read, and written back with
+# the new cluster.  At 8 FLOP x ~3.4 evaluations per colour that is under 2
+# FLOP per byte, far below the FP64 ridge (78.6 TFLOP/s / 8 TB/s), so HBM is
+# the roof: the mixed batch's 99 M records (0.8 GB) do not stay in the
+# 256 MiB MALL from one pass to the next.
+WALK_BYTES_PER_COLOUR = 16
+ROOFLINE_KERNEL = "k_assign_walk"  # sort-means nearest-centre passes
 TIMER_EVERY = 8                    # HIP-event bracket on every 8th launch of it
 
 
@@ -333,7 +340,7 @@ def recorded_traffic():
     summary, if it was measured on the kernel source as it is now; else None."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_assign_walk_traffic_8x512.md")
+    path = os.path.join(ROOT, "profiles", "k_assign_walk_traffic_mixed_batch.md")
     try:
         text = open(path).read()
         rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
@@ -555,6 +562,11 @@ def main():
     # run no iteration)
     walk_ndc = sum(s["ndc_total"] - s["n_unique"] * K for s in stats if s["iters"] >= 1)
     achieved_tflops = FLOP_PER_EVAL * walk_ndc / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
+    # colours the sort-means passes read: every colour of a job in each of its
+    # iterations after the first
+    walk_colours = sum(s["n_unique"] * (s["iters"] - 1) for s in stats if s["iters"] >= 2)
+    walk_bytes_per_launch = WALK_BYTES_PER_COLOUR * walk_colours / max(1, launches)
+    achieved_gbs = walk_bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     batched_ips = n_img / elapsed
 
     plain_ips = None if args.no_plain else time_plain(cq, torch, jobs, dev)
@@ -590,15 +602,20 @@ def main():
         "ndc_per_colour_iter": ndc / max(1, sum(s["n_unique"] * s["iters"] for s in stats)),
         "roofline": {
             "kernel": ROOFLINE_KERNEL,
-            "bound": "alu",
-            "achieved": achieved_tflops,
-            "peak": PEAK_FP64_VALU_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / PEAK_FP64_VALU_TFLOPS,
+            "bound": "hbm",
+            "achieved": achieved_gbs,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved_gbs / PEAK_HBM_GBS,
             "traffic": recorded_traffic(),
+            "algorithmic_bytes_per_launch": walk_bytes_per_launch,
             "launches": launches,
             "timed_launches": timed,
             "avg_launch_us": 1e3 * avg_launch_ms,
+            # the same launches against the FP64 vector peak (8 FLOP per
+            # evaluated distance)
+            "fp64_view": {"achieved_tflops": achieved_tflops, "peak_tflops": PEAK_FP64_VALU_TFLOPS,
+                          "frac": achieved_tflops / PEAK_FP64_VALU_TFLOPS},
         },
         "input_generation_s": gen_s,
     }
