@@ -378,6 +378,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
         const Rec CQ_CONST* rec = cp(J.rec);
         const int32_t CQ_CONST* tix = cp(J.tix);
         Acc acc{-1, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+        unsigned long long wave_evals = 0;  // the same in every lane
         // the waves take the block's slices of 64 colours in order from an LDS
         // counter, so a wave that finishes early takes more of them; each wave
         // takes its next slice, and starts loading it, before working on the
@@ -400,7 +401,6 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
             key_rgb(key, r, g, b);
             const double x0 = double(r), x1 = double(g), x2 = double(b);
             Best v{0.0, __builtin_inf(), 0};
-            unsigned evals = 0;
             unsigned long long pending = __ballot(valid);
             while (pending) {
                 const int leader = __ffsll(pending) - 1;
@@ -432,8 +432,12 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                     v.bd = prev;
                     v.second = __builtin_inf();
                     v.best = ps;
-                    evals = 1;
                 }
+                // the distance count is a block total: the wave adds its
+                // evaluations in scalar registers (lane masks), and lane 0
+                // reports them
+                const unsigned long long mine_mask = __builtin_amdgcn_ballot_w64(mine);
+                wave_evals += (unsigned long long)__popcll(mine_mask);
                 // entries j .. j + kWalk - 1 per round; the table is padded so
                 // that the last round of a row, and the round loaded ahead of
                 // it, stay inside the allocation
@@ -450,15 +454,23 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                     }
 #pragma unroll
                     for (int u = 0; u < kWalk; ++u) {
-                        // bitwise logic keeps the round free of branches
-                        const bool within = mine & (j + u < K) & (q[u].d <= limit);
+                        // bitwise logic keeps the round free of branches; an
+                        // entry outside the lane's bound counts as infinitely
+                        // far, which changes neither the nearest nor the
+                        // second nearest distance (bd <= second always, and
+                        // the new second is min(second, max(bd, d)))
+                        // lanes of this row whose bound takes the entry, as a
+                        // lane mask (compare predicate 5: ordered less or equal)
+                        const unsigned long long wm =
+                            j + u < K ? (__builtin_amdgcn_fcmp(q[u].d, limit, 5) & mine_mask) : 0ull;
+                        const bool within = __builtin_amdgcn_inverse_ballot_w64(wm);
                         const double d = dist_f64(x0, x1, x2, q[u].c0, q[u].c1, q[u].c2);
-                        const bool better = within & ((d < v.bd) | ((d == v.bd) & (tq[u] < v.best)));
-                        const bool sec = within & !better & (d < v.second);
-                        v.second = better ? v.bd : (sec ? d : v.second);
-                        v.bd = better ? d : v.bd;
+                        const double de = within ? d : __builtin_inf();
+                        const bool better = (de < v.bd) | ((de == v.bd) & (tq[u] < v.best));
+                        v.second = __builtin_fmin(v.second, __builtin_fmax(v.bd, de));
+                        v.bd = __builtin_fmin(v.bd, de);
                         v.best = better ? tq[u] : v.best;
-                        evals += within ? 1u : 0u;
+                        wave_evals += (unsigned long long)__popcll(wm);
                         // one entry at a time: fewer registers, more waves per SIMD
                         __builtin_amdgcn_sched_barrier(0);
                     }
@@ -472,7 +484,6 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 pending &= ~__ballot(mine);
             }
             if (valid) {
-                ndc += evals;
                 ties += near_tie(v) ? 1 : 0;
                 const int bk = dist_bucket(v.bd);
                 const uint64_t rec_new = pack_colour(key, v.best, w, bk);
@@ -481,6 +492,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 acc_add(acc, bins, s_maxd, v.best, w, r, g, b, v.bd);
             }
         }
+        if (lane == 0) ndc += wave_evals;
         // each lane's last cluster straight into LDS: lanes that share a
         // cluster are serialized by the LDS unit, cheaper than reducing
         // five 64-bit values across the wave
