@@ -228,9 +228,10 @@ __device__ __forceinline__ Best full_search_int(uint32_t x, const uint2* __restr
         const uint4 e = *reinterpret_cast<const uint4*>(ent + k);
         const int v0 = int((__builtin_amdgcn_udot4(x, e.x, 0u, false) << 9) + e.y);
         const int v1 = int((__builtin_amdgcn_udot4(x, e.z, 0u, false) << 9) + e.w);
-        b2 = max(b2, min(b1, v0));
+        // the second largest of (b1, b2, v) is their median (one v_med3)
+        b2 = max(min(b1, b2), min(max(b1, b2), v0));
         b1 = max(b1, v0);
-        b2 = max(b2, min(b1, v1));
+        b2 = max(min(b1, b2), min(max(b1, b2), v1));
         b1 = max(b1, v1);
     }
     const int xx = int(__builtin_amdgcn_udot4(x, x, 0u, false));
