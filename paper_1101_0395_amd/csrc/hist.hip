@@ -254,7 +254,7 @@ constexpr int kGroups = kHistLow / 64;   // 128 groups of 64 counters
 constexpr int kHistWindow = 16384;       // positions per bitmap window
 static_assert(kHistWindow % (64 * (kHistThreads / 64)) == 0, "whole 64-position words per wave");
 
-__global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __restrict__ jobs,
+__global__ void __launch_bounds__(kHistThreads, 4) k_hist_count(const JobDev* __restrict__ jobs,
                                                              const int* __restrict__ map, int B)
 {
     __shared__ uint32_t c[kHistLow];
@@ -263,6 +263,7 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __res
     // small buckets: keys present and their ranks; large ones: segment starts of a window
     __shared__ __align__(8) uint32_t s_bits[kHistWindow / 32];
     __shared__ uint32_t s_total, s_start, s_nseg;
+    __shared__ int s_def[kHistThreads / 64], s_ndef;  // buckets the wave pass leaves to the block
     extern __shared__ uint32_t seg[];  // [ntiles + 1] starts, then [ntiles] offsets
     uint32_t* s_wpre = s_bits + kHistLow / 32;
     static_assert(kHistWindow / 32 >= 2 * (kHistLow / 32), "the small-bucket arrays fit the window bitmap");
@@ -282,9 +283,82 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_count(const JobDev* __res
     constexpr int kUnroll = 16;                 // loads in flight per lane
     static_assert(kHistBuckets % 256 == 0, "groups of 32 buckets dealt to eight XCDs");
     const int wave = int(threadIdx.x >> 6), lane = int(threadIdx.x & 63);
-    for (int vb = cb0; vb < kHistBuckets; vb += kCountBlocks) {
+    // the block's buckets: virtual buckets cb0 + i C
+    const int nmine = (kHistBuckets - cb0 + kCountBlocks - 1) / kCountBlocks;
+    auto bucket_of = [&](int i) {
+        const int vb = cb0 + i * kCountBlocks;
         const int j = vb >> 3;
-        const int b = (j >> 5) * 256 + (vb & 7) * 32 + (j & 31);
+        return (j >> 5) * 256 + (vb & 7) * 32 + (j & 31);
+    };
+    // Wave pass (small images, whose tiles fit one wave, and blocks of at
+    // most one bucket per wave): wave w takes the block's bucket w on its
+    // own, with no block barrier.  Lane t scans tile t's segment; an empty
+    // bucket, or one of at most 64 pixels, is finished here: each lane takes
+    // one pixel (its tile is the last non-empty one starting at or before
+    // it: a prefix maximum over positions marked in a 64-byte LDS row), the
+    // wave sorts the keys (bitonic, across lanes), and the first lane of each
+    // run of equal keys writes the key and the run's length at its rank.
+    // Larger buckets are left to the block-wide code below.
+    const bool wave_pass = ntiles <= 64 && nmine <= kHistThreads / 64;
+    if (wave_pass) {
+        if (threadIdx.x == 0) s_ndef = 0;
+        __syncthreads();
+        if (wave < nmine) {
+            const int b = bucket_of(wave);
+            const uint32_t m = lane < ntiles ? mat[int64_t(lane) * kHistBuckets + b] : 0u;
+            const uint32_t len = m & 0xffffu, sst = m >> 16;
+            const uint64_t v = (uint64_t(len != 0u) << 32) | len;
+            const uint64_t incl = wave_incl_scan(v);
+            const uint32_t pos = uint32_t(incl - v);
+            const uint32_t total = uint32_t(read_lane(incl, 63));
+            const uint32_t place = wave_sum(sst);
+            if (lane == 0) gp(J.hbs)[b] = place;
+            if (total == 0) {
+                if (lane == 0) gp(J.hnu)[b] = 0u;
+            } else if (total > 64) {
+                if (lane == 0) s_def[atomicAdd(&s_ndef, 1)] = b;
+            } else {
+                uint8_t* own = reinterpret_cast<uint8_t*>(s_bits) + 64 * wave;
+                own[lane] = 0;
+                __builtin_amdgcn_wave_barrier();
+                if (len != 0u) own[pos] = uint8_t(lane);
+                __builtin_amdgcn_wave_barrier();
+                const int t = wave_incl_max(int(own[lane]));
+                const int32_t off = int32_t(lane * kHistTile + int(sst) - int(pos));
+                const int32_t toff = __shfl(off, t, 64);
+                uint32_t key = uint32_t(lane) < total ? uint32_t(hkeys[int64_t(toff) + lane]) : 0xffffu;
+                // bitonic sort of the 64 lanes' keys, ascending
+                for (int k = 2; k <= 64; k <<= 1) {
+                    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                        const uint32_t o = uint32_t(__shfl_xor(int(key), jj, 64));
+                        const bool up = (lane & k) == 0, lower = (lane & jj) == 0;
+                        key = (lower == up) ? (o < key ? o : key) : (o > key ? o : key);
+                    }
+                }
+                const uint32_t prev = uint32_t(__shfl_up(int(key), 1, 64));
+                const bool valid = key != 0xffffu;
+                const bool head = valid && (lane == 0 || prev != key);
+                const unsigned long long heads = __ballot(head);
+                if (head) {
+                    const unsigned long long below = (1ull << lane) - 1ull;
+                    const unsigned long long after = heads & ~(below | (1ull << lane));
+                    const uint32_t next = after ? uint32_t(__ffsll(after) - 1) : total;
+                    const uint32_t rank = uint32_t(__popcll(heads & below));
+                    gp(J.hk2)[place + rank] = uint16_t(key);
+                    gp(J.hcnt)[place + rank] = next - uint32_t(lane);
+                }
+                if (lane == 0) gp(J.hnu)[b] = uint32_t(__popcll(heads));
+            }
+        }
+        __syncthreads();
+        // the LDS rows the waves used start the small-bucket bitmap, which
+        // must be empty
+        for (int t = threadIdx.x; t < kHistThreads / 4; t += kHistThreads) s_bits[t] = 0u;
+        __syncthreads();
+    }
+    const int nlist = wave_pass ? s_ndef : nmine;
+    for (int li = 0; li < nlist; ++li) {
+        const int b = wave_pass ? s_def[li] : bucket_of(li);
         // the non-empty segments: one scan of (count of them, their lengths)
         uint64_t carry = 0;
         uint32_t place = 0;

@@ -96,6 +96,7 @@ __device__ __forceinline__ uint32_t packed_dist(uint32_t x, uint32_t p)
 // other lanes, in the same register).  Only jobs with lut_rec get blocks.
 constexpr int kPalRowsPerBlock = 4;
 constexpr int kPalPerLane = kMaxK / 64;
+static_assert(kRow % 4 == 0, "palette rows are read four entries at a time");
 
 __global__ void __launch_bounds__(64 * kPalRowsPerBlock) k_pal_rows(const JobDev* __restrict__ jobs,
                                                                    const int* __restrict__ map, int B)
@@ -192,14 +193,26 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ 
             int bq = c;
             const uint32_t lim = 4u * bd;
             const uint32_t* __restrict__ row = rows + int64_t(c) * kRow;
-            for (int e = 0; e < J.map_k; ++e) {
-                const uint32_t v = row[e];
-                if ((v >> 8) > lim) break;
-                const int q = int(v & 255u);
-                const uint32_t d = packed_dist(key, ent[q].x);
-                if (d < bd || (d == bd && q < bq)) {
-                    bd = d;
-                    bq = q;
+            // four entries per load round trip (a row has kRow entries, a
+            // multiple of four; those past K are never compared)
+            const int K = J.map_k;
+            bool more = true;
+            for (int e0 = 0; more && e0 < K; e0 += 4) {
+                const uint4 v4 = *reinterpret_cast<const uint4*>(row + e0);
+                const uint32_t vs[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t v = vs[u];
+                    if (!more || e0 + u >= K || (v >> 8) > lim) {
+                        more = false;
+                        continue;
+                    }
+                    const int q = int(v & 255u);
+                    const uint32_t d = packed_dist(key, ent[q].x);
+                    if (d < bd || (d == bd && q < bq)) {
+                        bd = d;
+                        bq = q;
+                    }
                 }
             }
             lut[lut_slot_key(key)] = uint8_t(bq);
