@@ -741,6 +741,18 @@ __global__ void __launch_bounds__(kInitThreads) k_init_coop(const JobDev* __rest
     }
 }
 
+// Inclusive scan within each row of 16 lanes (lane 15 of a row holds the
+// row's sum).
+__device__ __forceinline__ uint64_t row16_incl_scan(uint64_t x)
+{
+    const uint64_t z = 0;
+    x += dpp_move<kDppRowShr1, 0xf>(z, x);
+    x += dpp_move<kDppRowShr2, 0xf>(z, x);
+    x += dpp_move<kDppRowShr4, 0xf>(z, x);
+    x += dpp_move<kDppRowShr8, 0xf>(z, x);
+    return x;
+}
+
 // ------------------------------------------------------------------------
 // The same rounds with every thread's run of up to R colours on chip: the
 // keys and D^2 in VGPRs, the counts (KPP) in dynamic LDS, transposed (entry
@@ -754,8 +766,9 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
                                                            const int* __restrict__ map, int B)
 {
     extern __shared__ uint32_t lcnt[];                 // [R T] counts, transposed
-    __shared__ uint64_t s_wave[kInitThreads / 64];     // per-wave sums (KPP) or maxima (MMX)
+    __shared__ uint64_t s_wave[kInitThreads / 64];     // MMX: per-wave maxima
     __shared__ uint64_t s_run[kInitThreads];           // KPP: the threads' run sums of n D^2
+    __shared__ uint64_t s_grp[kInitThreads / 16];      // KPP: sums of 16 consecutive threads' runs
     __shared__ uint64_t s_val[kInitMaxBlocks];
     __shared__ uint64_t s_rloc;  // r minus the weights before the owner thread's run
     __shared__ uint32_t s_key;   // the colour picked in this round
@@ -853,14 +866,22 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
                 s_state = 1;
             }
         } else {
-            if (kpp) s_run[t] = acc;
-            acc = kpp ? wave_sum(acc) : wave_max(acc);
-            if (lane == 0) s_wave[wave] = acc;
+            if (kpp) {
+                s_run[t] = acc;
+                // the sum of each row of 16 lanes (threads 16 g .. 16 g + 15)
+                const uint64_t rs = row16_incl_scan(acc);
+                if ((lane & 15) == 15) s_grp[t >> 4] = rs;
+            } else {
+                acc = wave_max(acc);
+                if (lane == 0) s_wave[wave] = acc;
+            }
             __syncthreads();
             if (wave == 0) {
-                // 2. the block's value, then the team's
-                uint64_t v = lane < kInitThreads / 64 ? s_wave[lane] : 0ull;
-                v = kpp ? wave_sum(v) : wave_max(v);
+                // 2. the block's value, then the team's; KPP: lane l holds
+                // the sum of the runs of threads [16 l, 16 l + 16)
+                static_assert(kInitThreads == 1024, "64 groups of 16 threads, one per lane of wave 0");
+                const uint64_t grp = kpp ? s_grp[lane] : 0ull;
+                uint64_t v = kpp ? wave_sum(grp) : wave_max(lane < kInitThreads / 64 ? s_wave[lane] : 0ull);
                 uint64_t total = v;
                 int ok = 1;
                 uint32_t spins = 0;
@@ -905,34 +926,21 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
                     uint64_t base = 0;
                     const int64_t c = G > 1 ? wave_find(G, r, &base, [&](int64_t x) { return s_val[x]; }) : 0;
                     if (c == tb) {
-                        // the thread holding r: lane l sums the runs of threads
-                        // [l S, (l + 1) S), one scan finds the lane, and the
-                        // lane's S run sums (broadcast) the thread
+                        // the thread holding r: one scan of the 64 group sums
+                        // finds the group, a second one of the group's 16 run
+                        // sums (one per lane) the thread
                         state = 2;
-                        constexpr int S = kInitThreads / 64;
-                        uint64_t rv[S];
-                        uint64_t lsum = 0;
-#pragma unroll
-                        for (int u = 0; u < S; ++u) {
-                            rv[u] = s_run[lane * S + u];
-                            lsum += rv[u];
-                        }
-                        const uint64_t lincl = base + wave_incl_scan(lsum);
+                        const uint64_t lincl = base + wave_incl_scan(grp);
                         const unsigned long long hitl = __ballot(lincl > r);
                         const int l = hitl ? __ffsll(hitl) - 1 : 63;  // hitl != 0 since r < total
-                        uint64_t before = __shfl(lincl - lsum, l, 64);
-                        int tr = l * S + S - 1;
-                        bool found = false;
-#pragma unroll
-                        for (int u = 0; u < S; ++u) {
-                            const uint64_t v = __shfl(rv[u], l, 64);
-                            const bool hit = !found && before + v > r;
-                            tr = hit ? l * S + u : tr;
-                            before += (found || hit) ? 0ull : v;
-                            found = found || hit;
-                        }
+                        const uint64_t gbefore = __shfl(lincl - grp, l, 64);
+                        const uint64_t rv = lane < 16 ? s_run[16 * l + lane] : 0ull;
+                        const uint64_t incl2 = gbefore + wave_incl_scan(rv);
+                        const unsigned long long hitu = __ballot(lane < 16 && incl2 > r);
+                        const int u = hitu ? __ffsll(hitu) - 1 : 15;
+                        const uint64_t before = __shfl(incl2 - rv, u, 64);
                         if (lane == 0) {
-                            s_owner = tr;
+                            s_owner = 16 * l + u;
                             s_rloc = r - before;
                         }
                     } else {
