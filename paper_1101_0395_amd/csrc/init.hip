@@ -820,12 +820,17 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
         }
         for (int u = qn; u < R; ++u) lcnt[u * kInitThreads + t] = 0u;
     }
+    __syncthreads();  // the counts are in place (a thread wrote other threads' entries)
     uint64_t rng = J.seed;  // wave 0 draws; every block draws the same values
     uint32_t pick_key = 0;
     for (int j = 0; j < K; ++j) {
         const int par = j & 1;
         const uint64_t tag = uint64_t(j + 1) << kTagShift;
-        __syncthreads();  // the previous round's readers of the shared values are done
+        // No barrier is needed here: this round's first shared writes (run
+        // and group sums, MMX wave maxima) were last read by wave 0 before
+        // the previous round's barrier after step 2, and the values every
+        // thread reads at the end of a round (state, owner, key) are written
+        // again only after this round's barrier after step 1.
         // 1. own run: D^2 against the previous pick (from four-byte dot
         // products of the packed colours: |x - c|^2 = x.x + c.c - 2 x.c; in
         // round 0 there is no pick and nothing changes), then the run's sum
