@@ -420,14 +420,36 @@ __host__ __device__ __forceinline__ uint64_t mod_u64(uint64_t r, uint64_t T)
     return uint64_t(m);
 }
 
+// r mod T as mod_u64, with the quotient estimates taken as products by
+// inv ~ 1 / T instead of quotients (the exact remainder is checked the same
+// way, so the result never depends on inv).
+__device__ __forceinline__ uint64_t mod_u64_inv(uint64_t r, uint64_t T, double inv)
+{
+    if (T == 1) return 0;
+    const uint64_t q1 = uint64_t(double(r) * inv);  // below 2^64 for T >= 2
+    int64_t m = int64_t(r - q1 * T);
+    const int64_t q2 = int64_t(__builtin_floor(double(m) * inv));
+    m -= q2 * int64_t(T);
+    if (m < 0) m += int64_t(T);
+    if (m >= int64_t(T)) m -= int64_t(T);
+    if (T >= (1ull << 52) || m < 0 || m >= int64_t(T)) return r % T;
+    return uint64_t(m);
+}
+
 // Uniform integer in [0, T), T >= 1: outputs below 2^64 mod T are redrawn.
+// The remainder of each draw is computed beside the threshold's (they do not
+// depend on each other), with one reciprocal for both.
 __device__ __forceinline__ uint64_t uniform_below(uint64_t& s, uint64_t T)
 {
-    const uint64_t reject_below = mod_u64(0ull - T, T);
-    for (;;) {
-        const uint64_t r = splitmix64(s);
-        if (r >= reject_below) return mod_u64(r, T);
+    const double inv = 1.0 / double(T);
+    const uint64_t reject_below = mod_u64_inv(0ull - T, T, inv);
+    uint64_t r = splitmix64(s);
+    uint64_t m = mod_u64_inv(r, T, inv);
+    while (r < reject_below) {
+        r = splitmix64(s);
+        m = mod_u64_inv(r, T, inv);
     }
+    return m;
 }
 
 // ---------------------------------------------------------------- wave-wide

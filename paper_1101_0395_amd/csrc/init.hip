@@ -850,9 +850,17 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
         }
         uint64_t acc = 0;
         if (kpp) {
+            // weight n D^2, or n in round 0 (where D^2 is still 2^32 - 1 for
+            // a colour and 0 for padding, whose count is 0); two sums, so the
+            // multiply-adds form two chains
+            const uint32_t wcap = j == 0 ? 1u : 0xFFFFFFFFu;
+            uint64_t acc1 = 0;
 #pragma unroll
-            for (int u = 0; u < R; ++u)
-                acc += uint64_t(lcnt[u * kInitThreads + t]) * ((d2[u] & ~none) | (none & 1u));
+            for (int u = 0; u < R; u += 2) {
+                acc += uint64_t(lcnt[u * kInitThreads + t]) * (d2[u] < wcap ? d2[u] : wcap);
+                if (u + 1 < R) acc1 += uint64_t(lcnt[(u + 1) * kInitThreads + t]) * (d2[u + 1] < wcap ? d2[u + 1] : wcap);
+            }
+            acc += acc1;
         } else {
             uint32_t best_m = d2[0], best_u = 0;
 #pragma unroll
