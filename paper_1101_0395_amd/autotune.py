@@ -27,8 +27,8 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_PATH = os.path.join(HERE, "schedule.json")
-CHUNKS = (1024, 2048, 4096, 8192)
-PERIODS = (1, 2, 4)
+CHUNKS = (1024, 2048, 4096, 8192, 16384)
+PERIODS = (1, 2, 3, 4)
 MAX_ITERS, TOL = 100, 1e-4
 
 

@@ -1136,7 +1136,7 @@ namespace {
 constexpr int kMaxSchedules = 32;
 const cq_schedule kDefaultSchedule[] = {
     {0, 1024, 1},
-    {4149731, 2048, 1},
+    {4149731, 2048, 2},
     {34861447, 8192, 2},
 };
 struct ScheduleTable {
