@@ -533,21 +533,29 @@ cq_status run_kmeans(Batch& b, bool memberships, bool check)
     const int period = b.B > 0 ? b.h[0].regroup_period : 1;
     int max_iters = 0;
     for (const JobDev& J : b.h) max_iters = J.max_iters > max_iters ? J.max_iters : max_iters;
-    auto assign_blocks = [&](int j) {
-        const JobDev& J = b.h[j];
-        return J.n <= J.K ? 0 : int((J.n + J.chunk - 1) / J.chunk);
+    // jobs the host knows to be still iterating; a job that stopped gets no
+    // more blocks once the host has read so
+    std::vector<char> active(size_t(b.B), 1);
+    int assign_total = 0, full_total = 0, walk_total = 0, update_total = 0, table_total = 0;
+    auto set_iteration_maps = [&]() {
+        auto assign_blocks = [&](int j) {
+            const JobDev& J = b.h[j];
+            return (J.n <= J.K || !active[size_t(j)]) ? 0 : int((J.n + J.chunk - 1) / J.chunk);
+        };
+        assign_total = b.set_map(kMapAssign, assign_blocks);
+        full_total = b.set_map(kMapAssignFull, [&](int j) { return b.h[j].prune ? 0 : assign_blocks(j); });
+        walk_total = b.set_map(kMapAssignWalk, [&](int j) { return b.h[j].prune ? assign_blocks(j) : 0; });
+        update_total = b.set_map(kMapUpdate, [&](int j) {
+            const JobDev& J = b.h[j];
+            if (J.n <= J.K || !active[size_t(j)]) return 0;
+            return update_table_blocks(J.K, J.prune) + (J.prune ? int(regroup_blocks(J.n, J.chunk)) : 0);
+        });
+        table_total = b.set_map(kMapUpdateTable, [&](int j) {
+            const JobDev& J = b.h[j];
+            return (J.n <= J.K || !active[size_t(j)]) ? 0 : update_table_blocks(J.K, J.prune);
+        });
     };
-    const int assign_total = b.set_map(kMapAssign, assign_blocks);
-    const int full_total = b.set_map(kMapAssignFull, [&](int j) { return b.h[j].prune ? 0 : assign_blocks(j); });
-    const int walk_total = b.set_map(kMapAssignWalk, [&](int j) { return b.h[j].prune ? assign_blocks(j) : 0; });
-    const int update_total = b.set_map(kMapUpdate, [&](int j) {
-        const JobDev& J = b.h[j];
-        return J.n <= J.K ? 0 : update_table_blocks(J.K, J.prune) + (J.prune ? int(regroup_blocks(J.n, J.chunk)) : 0);
-    });
-    const int table_total = b.set_map(kMapUpdateTable, [&](int j) {
-        const JobDev& J = b.h[j];
-        return J.n <= J.K ? 0 : update_table_blocks(J.K, J.prune);
-    });
+    set_iteration_maps();
     CQ_TRY(upload(b));
     CQ_TRY(launch_kmeans_begin(b.d_jobs(), b.B, b.s));
     if (check) CQ_TRY(launch_check_colours(b.d_jobs(), b.d_maps(), b.B, assign_total, b.s));
@@ -561,8 +569,24 @@ cq_status run_kmeans(Batch& b, bool memberships, bool check)
         CQ_TRY(own.create());
         ev_pair = own.ev;
     }
+    // As jobs stop, the colours still iterating shrink, and the schedule for
+    // that smaller count may take fewer colours per assignment block (which
+    // changes no result: the blocks only partition each job's colours; the
+    // regrouping period stays, since it fixes which record buffer each
+    // iteration reads).  New block counts and maps are uploaded behind the
+    // group already queued, so they apply from the group after it.
+    auto replan = [&]() -> cq_status {
+        int64_t colours = 0;
+        for (int j = 0; j < b.B; ++j)
+            if (active[size_t(j)] && b.h[j].n > b.h[j].K) colours += b.h[j].n;
+        const cq_schedule sched = schedule_for(colours);
+        for (int j = 0; j < b.B; ++j)
+            if (active[size_t(j)]) b.h[j].chunk = assign_chunk(b.h[j].n, sched.assign_chunk);
+        set_iteration_maps();
+        return upload(b);
+    };
     const int group = 8;
-    bool all_done = false;
+    bool all_done = false, replanned = false;
     for (int it = 1, g = 0; it <= max_iters; it += group, ++g) {
         const int n_it = it + group - 1 <= max_iters ? group : max_iters - it + 1;
         for (int q = 0; q < n_it; ++q)
@@ -573,8 +597,26 @@ cq_status run_kmeans(Batch& b, bool memberships, bool check)
         if (g == 0) continue;
         CQ_TRY(read_results(b, (g - 1) & 1, ev_pair[(g - 1) & 1]));
         all_done = true;
-        for (const JobResult& r : b.res) all_done = all_done && r.done;
+        bool stopped = false;
+        for (int j = 0; j < b.B; ++j) {
+            all_done = all_done && b.res[size_t(j)].done;
+            if (b.res[size_t(j)].done && active[size_t(j)]) {
+                active[size_t(j)] = 0;
+                stopped = true;
+            }
+        }
         if (all_done) break;
+        if (stopped && it + group <= max_iters) {
+            CQ_TRY(replan());
+            replanned = true;
+        }
+    }
+    if (replanned) {
+        // every job's blocks again, for the passes after the iterations
+        // (the key-order memberships, the colour table)
+        std::fill(active.begin(), active.end(), 1);
+        set_iteration_maps();
+        CQ_TRY(upload(b));
     }
     if (!all_done) CQ_TRY(collect(b));  // the state after the last group
     // the memberships in key order, for callers that return them (a pruned
