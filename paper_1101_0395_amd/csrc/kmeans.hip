@@ -201,6 +201,24 @@ __device__ __forceinline__ void count_pair(uint32_t* ccount, int cb)
     atomicAdd(&ccount[cb >> 1], 1u << ((cb & 1) << 4));
 }
 
+// FP64 minimum and maximum of two numbers (never NaN here), as single
+// instructions: the compiler's fmin and fmax first quiet their operands when
+// it cannot tell that they are results of arithmetic (values carried across
+// a loop), one more instruction each.
+__device__ __forceinline__ double min_f64(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ double max_f64(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 __device__ __forceinline__ bool near_tie(const Best& v)
 {
     return v.second != __builtin_inf() && (v.second - v.bd) <= 1e-5 * v.second;
@@ -401,7 +419,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
             int r, g, b;
             key_rgb(key, r, g, b);
             const double x0 = double(r), x1 = double(g), x2 = double(b);
-            Best v{0.0, __builtin_inf(), 0};
+            Best vf{0.0, __builtin_inf(), 0};  // the lane's result, kept when its own row is walked
             unsigned long long pending = __ballot(valid);
             while (pending) {
                 const int leader = __ffsll(pending) - 1;
@@ -428,24 +446,48 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                              "s"(q[3].d), "s"(tq[0]), "s"(tq[1]), "s"(tq[2]), "s"(tq[3]));
                 const double prev = dist_f64(x0, x1, x2, own.c0, own.c1, own.c2);
                 const double limit = 4.0 * prev * (1.0 + 1e-12);
-                const double reach = wave_max(mine ? limit : -1.0);  // same value in every lane
-                if (mine) {
-                    v.bd = prev;
-                    v.second = __builtin_inf();
-                    v.best = ps;
-                }
+                // Every lane of the wave follows the row; the lanes of other
+                // rows keep their own results in vf.  The nearest centre and
+                // its distance are taken over every entry walked, also those
+                // beyond a lane's bound: such an entry is farther than the
+                // own centre (the bound's relative margin of 1e-12 exceeds the
+                // rounding of the three distances involved by far), so it is
+                // never nearer than the best so far, nor equal to it.  The
+                // second smallest distance over the entries walked is at most
+                // the one over the entries the lane evaluates; it is made
+                // exact below where the near-tie test depends on it.
+                Best v{prev, __builtin_inf(), ps};
                 // the distance count is a block total: the wave adds its
                 // evaluations in scalar registers (lane masks), and lane 0
                 // reports them
                 const unsigned long long mine_mask = __builtin_amdgcn_ballot_w64(mine);
                 wave_evals += (unsigned long long)__popcll(mine_mask);
+                auto visit = [&](const Rec& e, int te) {
+                    // lanes of this row whose bound takes the entry (compare
+                    // predicate 5: ordered less or equal), for the count only
+                    wave_evals += (unsigned long long)__popcll(__builtin_amdgcn_fcmp(e.d, limit, 5) & mine_mask);
+                    const double d = dist_f64(x0, x1, x2, e.c0, e.c1, e.c2);
+                    // an exact tie (rare): the lower centre index wins; the
+                    // empty statement keeps the branch from becoming selects
+                    if (__builtin_amdgcn_fcmp(d, v.bd, 1) != 0ull) {
+                        asm volatile("");
+                        v.best = d == v.bd && te < v.best ? te : v.best;
+                    }
+                    const bool better = d < v.bd;
+                    v.second = min_f64(v.second, max_f64(v.bd, d));
+                    v.bd = min_f64(v.bd, d);
+                    v.best = better ? te : v.best;
+                };
                 // entries j .. j + kWalk - 1 per round; the table is padded so
                 // that the last round of a row, and the round loaded ahead of
                 // it, stay inside the allocation
                 for (int j = 1; j < K; j += kWalk) {
                     Rec qn[kWalk];
                     int tqn[kWalk];
-                    const bool ahead = j + kWalk < K && q[kWalk - 1].d <= reach;
+                    // the next round is needed if the bound of some lane of
+                    // the row takes this round's last entry
+                    const bool ahead =
+                        j + kWalk < K && (__builtin_amdgcn_fcmp(q[kWalk - 1].d, limit, 5) & mine_mask) != 0ull;
                     if (ahead) {
 #pragma unroll
                         for (int u = 0; u < kWalk; ++u) {
@@ -453,27 +495,18 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                             tqn[u] = trow[j + kWalk + u];
                         }
                     }
+                    if (j + kWalk <= K) {
 #pragma unroll
-                    for (int u = 0; u < kWalk; ++u) {
-                        // bitwise logic keeps the round free of branches; an
-                        // entry outside the lane's bound counts as infinitely
-                        // far, which changes neither the nearest nor the
-                        // second nearest distance (bd <= second always, and
-                        // the new second is min(second, max(bd, d)))
-                        // lanes of this row whose bound takes the entry, as a
-                        // lane mask (compare predicate 5: ordered less or equal)
-                        const unsigned long long wm =
-                            j + u < K ? (__builtin_amdgcn_fcmp(q[u].d, limit, 5) & mine_mask) : 0ull;
-                        const bool within = __builtin_amdgcn_inverse_ballot_w64(wm);
-                        const double d = dist_f64(x0, x1, x2, q[u].c0, q[u].c1, q[u].c2);
-                        const double de = within ? d : __builtin_inf();
-                        const bool better = (de < v.bd) | ((de == v.bd) & (tq[u] < v.best));
-                        v.second = __builtin_fmin(v.second, __builtin_fmax(v.bd, de));
-                        v.bd = __builtin_fmin(v.bd, de);
-                        v.best = better ? tq[u] : v.best;
-                        wave_evals += (unsigned long long)__popcll(wm);
-                        // one entry at a time: fewer registers, more waves per SIMD
-                        __builtin_amdgcn_sched_barrier(0);
+                        for (int u = 0; u < kWalk; ++u) {
+                            visit(q[u], tq[u]);
+                            // one entry at a time: fewer registers, more waves per SIMD
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    } else {
+                        // the row's last round: its entries from K on are no centres
+#pragma unroll
+                        for (int u = 0; u < kWalk; ++u)
+                            if (j + u < K) visit(q[u], tq[u]);
                     }
                     if (!ahead) break;
 #pragma unroll
@@ -482,15 +515,38 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                         tq[u] = tqn[u];
                     }
                 }
-                pending &= ~__ballot(mine);
+                // The near-tie test, (second - bd) <= 1e-5 second, depends on
+                // the exact second smallest distance s only where the lower
+                // bound s' above is within twice that tolerance: from
+                // s' - bd > 2e-5 s' and s >= s' follows s - bd > 1e-5 s with a
+                // margin of about 1e-5 s, far above the rounding of the test.
+                // Those lanes (a few in ten thousand) read the entries their
+                // bound takes again: the smallest distance of the entries
+                // other than the nearest one's.
+                const bool recheck =
+                    mine && v.second != __builtin_inf() && (v.second - v.bd) <= 2e-5 * v.second;
+                if (__ballot(recheck) != 0ull) {
+                    double s2 = ps != v.best ? prev : __builtin_inf();
+                    for (int j = 1; j < K; ++j) {
+                        const Rec e = row[j];
+                        // no lane of the row evaluates this entry, or any later one
+                        if ((__builtin_amdgcn_fcmp(e.d, limit, 5) & mine_mask) == 0ull) break;
+                        const int te = trow[j];
+                        const double d = dist_f64(x0, x1, x2, e.c0, e.c1, e.c2);
+                        if (e.d <= limit && te != v.best) s2 = __builtin_fmin(s2, d);
+                    }
+                    if (recheck) v.second = s2;
+                }
+                if (mine) vf = v;
+                pending &= ~mine_mask;
             }
             if (valid) {
-                ties += near_tie(v) ? 1 : 0;
-                const int bk = dist_bucket(v.bd);
-                const uint64_t rec_new = pack_colour(key, v.best, w, bk);
+                ties += near_tie(vf) ? 1 : 0;
+                const int bk = dist_bucket(vf.bd);
+                const uint64_t rec_new = pack_colour(key, vf.best, w, bk);
                 if (rec_new != g0) grp[i] = rec_new;  // most records stay as they are
-                count_pair(ccount, v.best * kBuckets + bk);
-                acc_add(acc, bins, s_maxd, v.best, w, r, g, b, v.bd);
+                count_pair(ccount, vf.best * kBuckets + bk);
+                acc_add(acc, bins, s_maxd, vf.best, w, r, g, b, vf.bd);
             }
         }
         if (lane == 0) ndc += wave_evals;
