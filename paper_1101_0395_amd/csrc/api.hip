@@ -141,7 +141,7 @@ static void bind_slot(JobDev& J, char* slot, const Layout& L)
     J.meta = to_dev(reinterpret_cast<Meta*>(slot + L.meta));
     J.trace = to_dev(reinterpret_cast<double*>(slot + L.trace));
     J.rec = to_dev(reinterpret_cast<Rec*>(slot + L.rec));
-    J.tix = to_dev(reinterpret_cast<int32_t*>(slot + L.tix));
+    J.prow = to_dev(reinterpret_cast<uint32_t*>(slot + L.prow));
     J.ord = to_dev(reinterpret_cast<uint8_t*>(slot + L.ord));
     J.sums = to_dev(reinterpret_cast<unsigned long long*>(slot + L.sums));
     J.cprev = to_dev(reinterpret_cast<double*>(slot + L.cprev));

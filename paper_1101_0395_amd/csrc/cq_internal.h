@@ -129,7 +129,7 @@ struct JobDev {
     Meta CQ_GLOBAL* meta;
     double CQ_GLOBAL* trace;
     Rec CQ_GLOBAL* rec;   // sorted table rows (kMaxK x kRow)
-    int32_t CQ_GLOBAL* tix; // centre index of the table entries a scan reads (kMaxK x kRow)
+    uint32_t CQ_GLOBAL* prow; // colour table: the palette's distance rows, sorted (kMaxK x kRow)
     uint8_t CQ_GLOBAL* ord; // every row's whole centre order (kMaxK x kRow bytes), the next sort's start
     unsigned long long CQ_GLOBAL* sums;
     unsigned long long CQ_GLOBAL* part;  // per assignment block: distance count, near-tie count
@@ -279,7 +279,7 @@ inline size_t desc_results_off(int B)
 // ---------------------------------------------------------------- layout
 
 struct Layout {
-    size_t lut, meta, trace, rec, tix, ord, sums, centers, cprev, palette, part, desc;
+    size_t lut, meta, trace, rec, prow, ord, sums, centers, cprev, palette, part, desc;
     size_t chunks, work, hkeys, hk2, hcnt, hmat, hnu, hbs, keys, counts, assign;
     size_t fixed_end;  // end of the regions every call may use
     size_t total;      // end including the per-pixel and per-colour regions
@@ -297,9 +297,9 @@ inline Layout make_layout(int64_t npix, int64_t n_cap, bool with_colour_arrays)
     L.lut = o;      o = align256(o + kNumKeys);
     L.meta = o;     o = align256(o + 512);
     L.trace = o;    o = align256(o + sizeof(double) * kMaxIters);
-    // both tables: kTablePad entries past the last row for the final round of a walk
+    // the sorted table: kTablePad entries past the last row for the final round of a walk
     L.rec = o;      o = align256(o + sizeof(Rec) * (kMaxK * kRow + kTablePad));
-    L.tix = o;      o = align256(o + sizeof(int32_t) * (kMaxK * kRow + kTablePad));
+    L.prow = o;     o = align256(o + sizeof(uint32_t) * kMaxK * kRow);
     L.ord = o;      o = align256(o + size_t(kMaxK) * kRow);  // the rows' centre order, one byte per entry
     L.sums = o;     o = align256(o + sizeof(uint64_t) * 2 * kSumStride);  // two iterations
     L.centers = o;  o = align256(o + sizeof(double) * 3 * kMaxK);

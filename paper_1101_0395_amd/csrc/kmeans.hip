@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
         }
     } else {
         const Rec CQ_CONST* rec = cp(J.rec);
-        const int32_t CQ_CONST* tix = cp(J.tix);
+        const uint8_t CQ_CONST* ord = cp(J.ord);
         Acc acc{-1, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
         unsigned long long wave_evals = 0;  // the same in every lane
         // the waves take the block's slices of 64 colours in order from an LDS
@@ -425,26 +425,24 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 const int leader = __ffsll(pending) - 1;
                 const int ps = __builtin_amdgcn_readlane(p, leader);
                 const bool mine = valid && p == ps;
+                // row ps of the table: entry 0 is centre ps itself, then the
+                // other centres by distance from it; their indices are the
+                // row's centre order, one byte each (four to a word)
                 const Rec CQ_CONST* row = rec + ps * kRow;
-                const int32_t CQ_CONST* trow = tix + ps * kRow;
-                // the own entry and the first round in one round trip; each
-                // round's evaluation overlaps the loads of the next
-                const Rec own = row[0];
+                const uint32_t CQ_CONST* orow = reinterpret_cast<const uint32_t CQ_CONST*>(ord + ps * kRow);
+                // the first round (the own entry and three more) in one round
+                // trip; each round's evaluation overlaps the loads of the next
                 Rec q[kWalk];
-                int tq[kWalk];
 #pragma unroll
-                for (int u = 0; u < kWalk; ++u) {
-                    q[u] = row[1 + u];
-                    tq[u] = trow[1 + u];
-                }
-                // an empty statement that needs both: the loads are issued
-                // here, and waited for together, not one after the other
-                static_assert(kWalk == 4, "the statement below names every entry of a round");
-                asm volatile("" ::"s"(own.c0), "s"(own.c1), "s"(own.c2), "s"(q[0].c0), "s"(q[0].c1), "s"(q[0].c2),
-                             "s"(q[0].d), "s"(q[1].c0), "s"(q[1].c1), "s"(q[1].c2), "s"(q[1].d), "s"(q[2].c0),
-                             "s"(q[2].c1), "s"(q[2].c2), "s"(q[2].d), "s"(q[3].c0), "s"(q[3].c1), "s"(q[3].c2),
-                             "s"(q[3].d), "s"(tq[0]), "s"(tq[1]), "s"(tq[2]), "s"(tq[3]));
-                const double prev = dist_f64(x0, x1, x2, own.c0, own.c1, own.c2);
+                for (int u = 0; u < kWalk; ++u) q[u] = row[u];
+                uint32_t t4 = orow[0];
+                // an empty statement that needs them all: the loads are
+                // issued here, and waited for together, not one after the other
+                static_assert(kWalk == 4, "a round's centre indices are one word; the statement below names every entry");
+                asm volatile("" ::"s"(q[0].c0), "s"(q[0].c1), "s"(q[0].c2), "s"(q[1].c0), "s"(q[1].c1), "s"(q[1].c2),
+                             "s"(q[1].d), "s"(q[2].c0), "s"(q[2].c1), "s"(q[2].c2), "s"(q[2].d), "s"(q[3].c0),
+                             "s"(q[3].c1), "s"(q[3].c2), "s"(q[3].d), "s"(t4));
+                const double prev = dist_f64(x0, x1, x2, q[0].c0, q[0].c1, q[0].c2);
                 const double limit = 4.0 * prev * (1.0 + 1e-12);
                 // Every lane of the wave follows the row; the lanes of other
                 // rows keep their own results in vf.  The nearest centre and
@@ -481,39 +479,37 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 // entries j .. j + kWalk - 1 per round; the table is padded so
                 // that the last round of a row, and the round loaded ahead of
                 // it, stay inside the allocation
-                for (int j = 1; j < K; j += kWalk) {
+                for (int j = 0; j < K; j += kWalk) {
                     Rec qn[kWalk];
-                    int tqn[kWalk];
+                    uint32_t t4n = 0;
                     // the next round is needed if the bound of some lane of
                     // the row takes this round's last entry
                     const bool ahead =
                         j + kWalk < K && (__builtin_amdgcn_fcmp(q[kWalk - 1].d, limit, 5) & mine_mask) != 0ull;
                     if (ahead) {
 #pragma unroll
-                        for (int u = 0; u < kWalk; ++u) {
-                            qn[u] = row[j + kWalk + u];
-                            tqn[u] = trow[j + kWalk + u];
-                        }
+                        for (int u = 0; u < kWalk; ++u) qn[u] = row[j + kWalk + u];
+                        t4n = orow[(j + kWalk) / kWalk];
                     }
-                    if (j + kWalk <= K) {
+                    if (j > 0 && j + kWalk <= K) {
 #pragma unroll
                         for (int u = 0; u < kWalk; ++u) {
-                            visit(q[u], tq[u]);
+                            visit(q[u], int((t4 >> (8 * u)) & 255u));
                             // one entry at a time: fewer registers, more waves per SIMD
                             __builtin_amdgcn_sched_barrier(0);
                         }
                     } else {
-                        // the row's last round: its entries from K on are no centres
+                        // the row's first round (its entry 0, the own centre,
+                        // is taken above) or its last (entries from K on are
+                        // no centres)
 #pragma unroll
                         for (int u = 0; u < kWalk; ++u)
-                            if (j + u < K) visit(q[u], tq[u]);
+                            if (j + u > 0 && j + u < K) visit(q[u], int((t4 >> (8 * u)) & 255u));
                     }
                     if (!ahead) break;
 #pragma unroll
-                    for (int u = 0; u < kWalk; ++u) {
-                        q[u] = qn[u];
-                        tq[u] = tqn[u];
-                    }
+                    for (int u = 0; u < kWalk; ++u) q[u] = qn[u];
+                    t4 = t4n;
                 }
                 // The near-tie test, (second - bd) <= 1e-5 second, depends on
                 // the exact second smallest distance s only where the lower
@@ -531,7 +527,7 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                         const Rec e = row[j];
                         // no lane of the row evaluates this entry, or any later one
                         if ((__builtin_amdgcn_fcmp(e.d, limit, 5) & mine_mask) == 0ull) break;
-                        const int te = trow[j];
+                        const int te = int((orow[j / kWalk] >> (8 * (j % kWalk))) & 255u);
                         const double d = dist_f64(x0, x1, x2, e.c0, e.c1, e.c2);
                         if (e.d <= limit && te != v.best) s2 = __builtin_fmin(s2, d);
                     }
@@ -724,7 +720,6 @@ __device__ __forceinline__ void build_row(const JobDev& J, int a, int K, const d
 {
     const int lane = threadIdx.x & 63;
     Rec* __restrict__ row = gp(J.rec) + a * kRow;
-    int32_t* __restrict__ trow = gp(J.tix) + a * kRow;
     const double a0 = c[3 * a], a1 = c[3 * a + 1], a2 = c[3 * a + 2];
     double k[kPerLane];
     int x[kPerLane];
@@ -805,16 +800,17 @@ __device__ __forceinline__ void build_row(const JobDev& J, int a, int K, const d
     // The scans of this row (colours whose previous centre is a) evaluate
     // entries up to their own bound, which is at most `reach`; P entries lie
     // within it (the own entry first).  A scan reads whole rounds of kWalk
-    // entries after the own one, and the round after one whose last entry
-    // is within its bound, so the entries it can read end with the round
-    // that holds entry P (at least the first round).  Only those records are
-    // written; the centre order is written whole, since the next update
+    // entries (entries 0 .. kWalk - 1 first), and the round after one whose
+    // last entry is within its bound, so the entries it can read end with
+    // the round that holds entry P (at least the first round).  Only those
+    // records are written; the centre order, which also gives the scans the
+    // centre index of each entry, is written whole, since the next update
     // starts its sort from it.
     int within = 0;
 #pragma unroll
     for (int i = 0; i < kPerLane; ++i) within += (kPerLane * lane + i < K && k[i] <= reach) ? 1 : 0;
     const int P = wave_sum(within);
-    const int last = (P + kWalk - 1) / kWalk * kWalk;
+    const int last = P / kWalk * kWalk + kWalk - 1;
     uint32_t four = 0;
 #pragma unroll
     for (int i = 0; i < kPerLane; ++i) {
@@ -827,7 +823,6 @@ __device__ __forceinline__ void build_row(const JobDev& J, int a, int K, const d
         r.c2 = c[3 * x[i] + 2];
         r.d = x[i] == a ? 0.0 : k[i];
         row[e] = r;
-        trow[e] = x[i];
     }
     reinterpret_cast<uint32_t*>(gp(J.ord) + a * kRow)[lane] = four;  // entries past K are never read
 }

@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(64 * kPalRowsPerBlock) k_pal_rows(const JobDev
             }
         }
     }
-    uint32_t* __restrict__ row = reinterpret_cast<uint32_t*>(gp(J.tix)) + int64_t(p) * kRow;
+    uint32_t* __restrict__ row = gp(J.prow) + int64_t(p) * kRow;
 #pragma unroll
     for (int i = 0; i < kPalPerLane; ++i)
         if (kPalPerLane * lane + i < K) row[kPalPerLane * lane + i] = v[i];
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(kLutThreads) k_lut(const JobDev* __restrict__ 
     const int iters = gp(J.meta)->iters;
     if (J.lut_rec && iters >= 1) {
         const uint64_t* __restrict__ g = gp(J.grp) + record_buffer(iters, J.regroup_period) * J.n;
-        const uint32_t* __restrict__ rows = reinterpret_cast<const uint32_t*>(gp(J.tix));
+        const uint32_t* __restrict__ rows = gp(J.prow);
         for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
             const uint64_t rec = g[i];
             const uint32_t key = uint32_t(rec) & 0xffffffu;
