@@ -445,15 +445,18 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 const double prev = dist_f64(x0, x1, x2, q[0].c0, q[0].c1, q[0].c2);
                 const double limit = 4.0 * prev * (1.0 + 1e-12);
                 // Every lane of the wave follows the row; the lanes of other
-                // rows keep their own results in vf.  The nearest centre and
-                // its distance are taken over every entry walked, also those
-                // beyond a lane's bound: such an entry is farther than the
-                // own centre (the bound's relative margin of 1e-12 exceeds the
-                // rounding of the three distances involved by far), so it is
-                // never nearer than the best so far, nor equal to it.  The
-                // second smallest distance over the entries walked is at most
-                // the one over the entries the lane evaluates; it is made
-                // exact below where the near-tie test depends on it.
+                // rows keep their own results in vf.  The nearest distance is
+                // taken over every entry walked, also those beyond a lane's
+                // bound: such an entry is farther than the own centre (the
+                // bound's relative margin of 1e-12 exceeds the rounding of
+                // the three distances involved by far), so it is never nearer
+                // than the best so far, nor equal to it.  The centre is the
+                // first one met at that distance, which is the right one
+                // unless another entry lies at exactly the same distance.
+                // The second smallest distance over the entries walked is at
+                // most the one over the entries the lane evaluates, and equal
+                // to the nearest distance if there is such a tie; both are
+                // made exact below where they matter.
                 Best v{prev, __builtin_inf(), ps};
                 // the distance count is a block total: the wave adds its
                 // evaluations in scalar registers (lane masks), and lane 0
@@ -465,12 +468,6 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                     // predicate 5: ordered less or equal), for the count only
                     wave_evals += (unsigned long long)__popcll(__builtin_amdgcn_fcmp(e.d, limit, 5) & mine_mask);
                     const double d = dist_f64(x0, x1, x2, e.c0, e.c1, e.c2);
-                    // an exact tie (rare): the lower centre index wins; the
-                    // empty statement keeps the branch from becoming selects
-                    if (__builtin_amdgcn_fcmp(d, v.bd, 1) != 0ull) {
-                        asm volatile("");
-                        v.best = d == v.bd && te < v.best ? te : v.best;
-                    }
                     const bool better = d < v.bd;
                     v.second = min_f64(v.second, max_f64(v.bd, d));
                     v.bd = min_f64(v.bd, d);
@@ -516,22 +513,37 @@ __global__ void __launch_bounds__(kAssignThreads) k_assign(const JobDev* __restr
                 // bound s' above is within twice that tolerance: from
                 // s' - bd > 2e-5 s' and s >= s' follows s - bd > 1e-5 s with a
                 // margin of about 1e-5 s, far above the rounding of the test.
-                // Those lanes (a few in ten thousand) read the entries their
-                // bound takes again: the smallest distance of the entries
-                // other than the nearest one's.
+                // The same lanes include every lane with an exact tie at the
+                // nearest distance (s' = bd).  They (a few in ten thousand)
+                // read the entries their bound takes again: the nearest
+                // centre is the lowest index at distance bd, and the second
+                // smallest distance is bd if two entries lie there, else the
+                // smallest distance above bd.
                 const bool recheck =
                     mine && v.second != __builtin_inf() && (v.second - v.bd) <= 2e-5 * v.second;
                 if (__ballot(recheck) != 0ull) {
-                    double s2 = ps != v.best ? prev : __builtin_inf();
+                    int at_bd = prev == v.bd ? 1 : 0;
+                    int low = prev == v.bd ? ps : kMaxK;
+                    double above = prev > v.bd ? prev : __builtin_inf();
                     for (int j = 1; j < K; ++j) {
                         const Rec e = row[j];
                         // no lane of the row evaluates this entry, or any later one
                         if ((__builtin_amdgcn_fcmp(e.d, limit, 5) & mine_mask) == 0ull) break;
                         const int te = int((orow[j / kWalk] >> (8 * (j % kWalk))) & 255u);
                         const double d = dist_f64(x0, x1, x2, e.c0, e.c1, e.c2);
-                        if (e.d <= limit && te != v.best) s2 = __builtin_fmin(s2, d);
+                        if (e.d <= limit) {
+                            if (d == v.bd) {
+                                ++at_bd;
+                                low = te < low ? te : low;
+                            } else {
+                                above = __builtin_fmin(above, d);
+                            }
+                        }
                     }
-                    if (recheck) v.second = s2;
+                    if (recheck) {
+                        v.best = low;
+                        v.second = at_bd >= 2 ? v.bd : above;
+                    }
                 }
                 if (mine) vf = v;
                 pending &= ~mine_mask;

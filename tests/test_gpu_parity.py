@@ -211,6 +211,46 @@ def test_kmeans_empty_clusters_keep_their_centres(cqm, dev, ws_small):
         assert not np.any(g.assign.cpu().numpy() == 4) and not np.any(g.assign.cpu().numpy() == 17)
 
 
+def _key(r, g, b):
+    return (r << 16) | (g << 8) | b
+
+
+# Colours and start centres whose first update puts the centres where a colour
+# of the second iteration (a sort-means pass) lies at exactly the same distance
+# from two of them (the centre positions are worked out in the comments).
+EXACT_TIES = [
+    # one channel: colours 0 (x3), 10, 15, 20, 30 and centres 6, 25 become
+    # centres 5, 25; colour 15 (cluster 0) is 10 from both and stays in 0
+    ([(0, 0, 0, 3), (10, 0, 0, 1), (15, 0, 0, 1), (20, 0, 0, 1), (30, 0, 0, 1)],
+     [(6.0, 0.0, 0.0), (25.0, 0.0, 0.0)]),
+    # three centres: the first update gives (15,5,0), (5,15,0), (14,16,11);
+    # colour (15,15,0), in cluster 2, is at squared distance 100 from centres
+    # 0 and 1, which row 2 lists as centre 1 (203) before centre 0 (243): the
+    # pass meets centre 1 first and must end at centre 0
+    ([(5, 15, 0, 1), (13, 17, 22, 1), (15, 5, 0, 1), (15, 15, 0, 1)],
+     [(15.0, 5.0, 0.0), (5.0, 15.0, 0.0), (14.0, 16.0, 8.0)]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(EXACT_TIES)))
+def test_kmeans_exact_ties_in_sort_means_passes(cqm, dev, ws_small, case):
+    """Exact distance ties met by the sort-means passes: the lower centre
+    index wins (also when the pass meets the higher one first), and the
+    distance and near-tie counts equal the oracle's, pruned and unpruned."""
+    _say(f"kmeans exact ties case {case}")
+    colours, c0 = EXACT_TIES[case]
+    rk = np.array([_key(r, g, b) for r, g, b, _ in colours], np.uint32)
+    rc = np.array([n for *_, n in colours], np.uint32)
+    assert np.all(np.diff(rk.astype(np.int64)) > 0)
+    c0 = np.array(c0, np.float64)
+    dk, dc = _to_dev(rk.view(np.int32), dev), _to_dev(rc.view(np.int32), dev)
+    for prune in (False, True):
+        r = oracle.kmeans(rk, rc, c0, 6, 0.0, prune)
+        g = cqm.cq_kmeans(dk, dc, _to_dev(c0, dev), 6, 0.0, prune, ws_small)
+        _compare_kmeans(g, r)
+        assert r.stats["iters"] >= 2 and r.stats["near_ties"] >= 1
+
+
 def test_kmeans_max_iters_one_and_nonfinite_start(cqm, dev, ws_small):
     _say("kmeans max_iters=1 / non-finite start")
     img = synth.blobs_on_gradient(64, 64, 7)
