@@ -31,37 +31,15 @@ constexpr int kMaxAssignChunk = 32768;  // colours per block: the (cluster, buck
 constexpr int kScatterChunk = 2048;  // colours per regrouping block
 
 // Adds the five cluster statistics (n, S_r, S_g, S_b, Q) of the valid lanes
-// to the LDS bins of their clusters.  Lanes of one wave that share a cluster
-// are summed first (up to four distinct clusters per wave); the rest add their
-// own values.
+// to the LDS bins of their clusters, one LDS atomic per value and lane (lanes
+// that share a cluster are serialized by the LDS unit, which costs the VALU
+// nothing; summing them across the wave first costs five 64-bit reductions
+// per distinct cluster).
 __device__ __forceinline__ void bin_add_vals(unsigned long long* bins, bool valid, int k,
                                              unsigned long long v0, unsigned long long v1,
                                              unsigned long long v2, unsigned long long v3,
                                              unsigned long long v4)
 {
-    const int lane = threadIdx.x & 63;
-    unsigned long long active = __ballot(valid);
-#pragma unroll 1
-    for (int round = 0; round < 4 && active; ++round) {
-        const int leader = __ffsll(active) - 1;
-        const int kb = __shfl(k, leader, 64);
-        const bool mine = valid && k == kb;
-        const unsigned long long mask = __ballot(mine);
-        const unsigned long long s0 = wave_sum(mine ? v0 : 0ull);
-        const unsigned long long s1 = wave_sum(mine ? v1 : 0ull);
-        const unsigned long long s2 = wave_sum(mine ? v2 : 0ull);
-        const unsigned long long s3 = wave_sum(mine ? v3 : 0ull);
-        const unsigned long long s4 = wave_sum(mine ? v4 : 0ull);
-        if (lane == leader) {
-            atomicAdd(&bins[kSumN + kb], s0);
-            atomicAdd(&bins[kSumS + 3 * kb + 0], s1);
-            atomicAdd(&bins[kSumS + 3 * kb + 1], s2);
-            atomicAdd(&bins[kSumS + 3 * kb + 2], s3);
-            atomicAdd(&bins[kSumQ + kb], s4);
-        }
-        if (mine) valid = false;
-        active &= ~mask;
-    }
     if (valid) {
         atomicAdd(&bins[kSumN + k], v0);
         atomicAdd(&bins[kSumS + 3 * k + 0], v1);
