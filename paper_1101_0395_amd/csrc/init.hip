@@ -838,7 +838,10 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
         // first position on ties (MMX).  All R entries, padding included,
         // in straight-line code: the registers of the run are never under a
         // branch.
-        const uint32_t none = j == 0 ? 0xFFFFFFFFu : 0u;
+        // (none is hidden from the compiler, which would otherwise turn the
+        // OR into a select after the minimum and hold R minima at once)
+        uint32_t none = j == 0 ? 0xFFFFFFFFu : 0u;
+        asm volatile("" : "+v"(none));
         const uint32_t cc = __builtin_amdgcn_udot4(pick_key, pick_key, 0u, false);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
@@ -853,7 +856,8 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
             // weight n D^2, or n in round 0 (where D^2 is still 2^32 - 1 for
             // a colour and 0 for padding, whose count is 0); two sums, so the
             // multiply-adds form two chains
-            const uint32_t wcap = j == 0 ? 1u : 0xFFFFFFFFu;
+            uint32_t wcap = j == 0 ? 1u : 0xFFFFFFFFu;
+            asm volatile("" : "+v"(wcap));
             uint64_t acc1 = 0;
 #pragma unroll
             for (int u = 0; u < R; u += 2) {
@@ -1013,8 +1017,8 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
 
 // ------------------------------------------------------------------ host
 // Colours per thread of the register kernels, smallest first.
-constexpr int kCoopVariants = 4;
-constexpr int kCoopR[kCoopVariants] = {4, 8, 16, 24};
+constexpr int kCoopVariants = 5;
+constexpr int kCoopR[kCoopVariants] = {4, 8, 16, 24, 32};
 
 // Colours per block of the register kernels (R colours per thread).
 int64_t coop_reg_colours(int R) { return int64_t(R) * kInitThreads; }
@@ -1028,17 +1032,18 @@ static const void* coop_kernel(int variant)
     case 8: return reinterpret_cast<const void*>(k_init_reg<8>);
     case 16: return reinterpret_cast<const void*>(k_init_reg<16>);
     case 24: return reinterpret_cast<const void*>(k_init_reg<24>);
+    case 32: return reinterpret_cast<const void*>(k_init_reg<32>);
     default: return reinterpret_cast<const void*>(k_init_coop);
     }
 }
 
 // Co-resident blocks of a cooperative initialization kernel on this device
-// (0: no cooperative launch).  variant: 4, 8, 16 or 24, the register kernels
+// (0: no cooperative launch).  variant: 4, 8, 16, 24 or 32, the register kernels
 // with that many colours per thread; 0, the kernel that keeps D^2 in global
 // memory.
 int coop_capacity(int variant)
 {
-    static int cached[kCoopVariants + 1] = {-1, -1, -1, -1, -1};
+    static int cached[kCoopVariants + 1] = {-1, -1, -1, -1, -1, -1};
     int slot = kCoopVariants;
     for (int v = 0; v < kCoopVariants; ++v)
         if (kCoopR[v] == variant) slot = v;
@@ -1060,13 +1065,13 @@ int coop_capacity(int variant)
 // n[j] colours of job j (0: none).  Jobs are taken largest first, in three
 // classes, each class in launches that fit the co-resident capacity of the
 // kernel that runs them:
-//  - at most 24576 colours: one register block each (a team of one block
+//  - at most 32768 colours: one register block each (a team of one block
 //    exchanges nothing through memory), with the smallest R that holds the
 //    launch's largest job;
-//  - up to kInitMaxBlocks x 24576 colours: teams of ceil(n / (R T))
+//  - up to kInitMaxBlocks x 32768 colours: teams of ceil(n / (R T))
 //    register blocks, with the smallest R for which the launch's teams fit
 //    the capacity (fewer colours per thread, less of each round's work per
-//    block), R = 24 when only that fits;
+//    block), R = 32 when only that fits;
 //  - more: kInitMaxBlocks blocks of the kernel that keeps D^2 in global
 //    memory.
 cq_status plan_coop(const std::vector<int64_t>& n, std::vector<CoopLaunch>& plan)
