@@ -110,6 +110,24 @@ def test_init_parity(cqm, dev, ws_small, scheme, K, seed):
     assert np.array_equal(got.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("n", [4096, 4097, 16384, 24577, 32768, 32769, 65537, 262145])
+def test_cooperative_init_at_capacity_boundaries(cqm, dev, ws_small, n):
+    """k-means++ and max-min on colour sets at the sizes where the
+    initialization changes the colours per thread a block holds (4096 to
+    32768 colours per block) or grows a team of blocks: bit-identical centres,
+    with counts from 1 up to 10^5 so that the draws' weights vary widely."""
+    _say(f"cooperative init n={n}")
+    rng = np.random.default_rng(n)
+    rk = np.sort(rng.choice(1 << 24, n, replace=False)).astype(np.uint32)
+    rc = np.minimum(rng.pareto(1.2, n) * 3 + 1, 1e5).astype(np.uint32)
+    dk, dc = _to_dev(rk.view(np.int32), dev), _to_dev(rc.view(np.int32), dev)
+    for scheme in (oracle.INIT_KMEANSPP, oracle.INIT_MAXMIN):
+        ref, ref_used = oracle.init(rk, rc, 256, scheme, n)
+        got, used = cqm.cq_init(dk, dc, 256, scheme, n, ws_small)
+        assert used == ref_used
+        assert np.array_equal(got.cpu().numpy(), ref), scheme
+
+
 def test_var_weighted_duplicates_and_sff_small_sets(cqm, dev, ws_small):
     """VAR where one colour's pixels span several groups (repeated centres),
     and SFF on sets smaller than its subset size (the subset is every colour)."""
