@@ -821,6 +821,11 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
         for (int u = qn; u < R; ++u) lcnt[u * kInitThreads + t] = 0u;
     }
     __syncthreads();  // the counts are in place (a thread wrote other threads' entries)
+    uint64_t run_n = 0;  // KPP: the run's pixel count (the weights of round 0)
+    if (kpp) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) run_n += lcnt[u * kInitThreads + t];
+    }
     uint64_t rng = J.seed;  // wave 0 draws; every block draws the same values
     uint32_t pick_key = 0;
     for (int j = 0; j < K; ++j) {
@@ -846,25 +851,28 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             asm volatile("" : "+v"(ky[u]));  // keeps x.x from being held across rounds
-            const uint32_t xx = __builtin_amdgcn_udot4(ky[u], ky[u], 0u, false);
+            const uint32_t xxcc = __builtin_amdgcn_udot4(ky[u], ky[u], cc, false);  // x.x + c.c
             const uint32_t xc = __builtin_amdgcn_udot4(ky[u], pick_key, 0u, false);
-            const uint32_t d = (xx + cc - 2u * xc) | none;
+            const uint32_t d = (xxcc - 2u * xc) | none;
             d2[u] = d2[u] < d ? d2[u] : d;
         }
         uint64_t acc = 0;
         if (kpp) {
-            // weight n D^2, or n in round 0 (where D^2 is still 2^32 - 1 for
-            // a colour and 0 for padding, whose count is 0); two sums, so the
-            // multiply-adds form two chains
-            uint32_t wcap = j == 0 ? 1u : 0xFFFFFFFFu;
-            asm volatile("" : "+v"(wcap));
-            uint64_t acc1 = 0;
+            // weight n D^2 in two sums, so that the multiply-adds form two
+            // chains; in round 0 the weights are the counts (the run's sum,
+            // taken once; padding has count 0).  The branch only reads the
+            // run's registers.
+            if (j == 0) {
+                acc = run_n;
+            } else {
+                uint64_t acc1 = 0;
 #pragma unroll
-            for (int u = 0; u < R; u += 2) {
-                acc += uint64_t(lcnt[u * kInitThreads + t]) * (d2[u] < wcap ? d2[u] : wcap);
-                if (u + 1 < R) acc1 += uint64_t(lcnt[(u + 1) * kInitThreads + t]) * (d2[u + 1] < wcap ? d2[u + 1] : wcap);
+                for (int u = 0; u < R; u += 2) {
+                    acc += uint64_t(lcnt[u * kInitThreads + t]) * d2[u];
+                    if (u + 1 < R) acc1 += uint64_t(lcnt[(u + 1) * kInitThreads + t]) * d2[u + 1];
+                }
+                acc += acc1;
             }
-            acc += acc1;
         } else {
             uint32_t best_m = d2[0], best_u = 0;
 #pragma unroll
