@@ -837,23 +837,22 @@ __global__ void __launch_bounds__(kInitThreads) k_init_reg(const JobDev* __restr
         // thread reads at the end of a round (state, owner, key) are written
         // again only after this round's barrier after step 1.
         // 1. own run: D^2 against the previous pick (from four-byte dot
-        // products of the packed colours: |x - c|^2 = x.x + c.c - 2 x.c; in
-        // round 0 there is no pick and nothing changes), then the run's sum
-        // of n D^2 (KPP; the counts alone in round 0) or its largest D^2,
-        // first position on ties (MMX).  All R entries, padding included,
-        // in straight-line code: the registers of the run are never under a
+        // products of the packed colours: |x - c|^2 = x.x + c.c - 2 x.c),
+        // then the run's sum of n D^2 (KPP; the counts alone in round 0) or
+        // its largest D^2, first position on ties (MMX).  In round 0 there is
+        // no pick (pick_key is 0): c.c is replaced by 2^31 - 1, so every
+        // colour's value, x.x + 2^31 - 1, exceeds any squared distance of
+        // two colours (at most 3 * 255^2), and the first real pick replaces
+        // it; padding keeps D^2 0.  All R entries, padding included, in
+        // straight-line code: the registers of the run are never under a
         // branch.
-        // (none is hidden from the compiler, which would otherwise turn the
-        // OR into a select after the minimum and hold R minima at once)
-        uint32_t none = j == 0 ? 0xFFFFFFFFu : 0u;
-        asm volatile("" : "+v"(none));
-        const uint32_t cc = __builtin_amdgcn_udot4(pick_key, pick_key, 0u, false);
+        const uint32_t cc = j == 0 ? 0x7FFFFFFFu : __builtin_amdgcn_udot4(pick_key, pick_key, 0u, false);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             asm volatile("" : "+v"(ky[u]));  // keeps x.x from being held across rounds
             const uint32_t xxcc = __builtin_amdgcn_udot4(ky[u], ky[u], cc, false);  // x.x + c.c
             const uint32_t xc = __builtin_amdgcn_udot4(ky[u], pick_key, 0u, false);
-            const uint32_t d = (xxcc - 2u * xc) | none;
+            const uint32_t d = xxcc - 2u * xc;
             d2[u] = d2[u] < d ? d2[u] : d;
         }
         uint64_t acc = 0;
