@@ -244,13 +244,11 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_part(const JobDev* __rest
 // a bitmap marks the positions where a segment starts, and each wave reads 64
 // consecutive positions per load, a lane's segment being the one before it
 // plus the marks up to the lane (a population count), so no lane searches.
-// Its keys are counted in LDS; the 8192 counters are cleared once, a bucket
-// marks the groups of 64 counters it touches, and only those are read back
-// and cleared again, so a bucket costs in proportion to its contents.  The
-// distinct keys go, in ascending order with their counts, to the bucket's
+// Its keys are counted in LDS with adds that return nothing, so a wave's adds
+// pipeline; all 8192 counters are read back (32 KiB of LDS, a fraction of a
+// microsecond) and the non-zero ones cleared again.  The distinct keys go, in ascending order with their counts, to the bucket's
 // place.  Dynamic LDS: the segment starts (tiles + 1 entries) and offsets
 // (tiles entries).
-constexpr int kGroups = kHistLow / 64;   // 128 groups of 64 counters
 constexpr int kHistWindow = 16384;       // positions per bitmap window
 static_assert(kHistWindow % (64 * (kHistThreads / 64)) == 0, "whole 64-position words per wave");
 
@@ -258,7 +256,6 @@ __global__ void __launch_bounds__(kHistThreads, 4) k_hist_count(const JobDev* __
                                                              const int* __restrict__ map, int B)
 {
     __shared__ uint32_t c[kHistLow];
-    __shared__ uint32_t touched[kGroups / 32];
     __shared__ uint64_t tmp[64];
     // small buckets: keys present and their ranks; large ones: segment starts of a window
     __shared__ __align__(8) uint32_t s_bits[kHistWindow / 32];
@@ -275,7 +272,6 @@ __global__ void __launch_bounds__(kHistThreads, 4) k_hist_count(const JobDev* __
     uint32_t* cstart = seg;
     int32_t* coff = reinterpret_cast<int32_t*>(seg + ntiles + 1);
     for (int t = threadIdx.x; t < kHistLow; t += kHistThreads) c[t] = 0u;
-    if (threadIdx.x < kGroups / 32) touched[threadIdx.x] = 0u;
     for (int t = threadIdx.x; t < kHistLow / 32; t += kHistThreads) s_bits[t] = 0u;
     const uint32_t* __restrict__ mat = gp(J.hmat);
     const uint16_t* __restrict__ hkeys = gp(J.hkeys);
@@ -471,40 +467,31 @@ __global__ void __launch_bounds__(kHistThreads, 4) k_hist_count(const JobDev* __
                     kq[u] = i < e ? uint32_t(hkeys[int64_t(coff[js]) + i]) : 0xffffffffu;
                 }
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (kq[u] == 0xffffffffu) continue;
-                    if (atomicAdd(&c[kq[u]], 1u) == 0u)
-                        atomicOr(&touched[kq[u] >> 11], 1u << ((kq[u] >> 6) & 31u));
-                }
+                for (int u = 0; u < kUnroll; ++u)
+                    if (kq[u] != 0xffffffffu) atomicAdd(&c[kq[u]], 1u);  // no return value: the adds pipeline
             }
             __syncthreads();  // the window's marks are read
         }
-        // thread t owns counters [t R, (t + 1) R), inside group t R / 64
-        const int g = threadIdx.x * R / 64;
-        const bool hit = (touched[g >> 5] >> (g & 31)) & 1u;
+        // thread t owns counters [t R, (t + 1) R)
         uint32_t v[R];
         uint32_t nz = 0;
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-            v[u] = hit ? c[threadIdx.x * R + u] : 0u;
+            v[u] = c[threadIdx.x * R + u];
             nz += v[u] != 0u;
         }
         uint32_t nuniq = 0;
         uint32_t o = block_exclusive_scan<uint32_t>(nz, reinterpret_cast<uint32_t*>(tmp), &nuniq);
-        if (hit) {
 #pragma unroll
-            for (int u = 0; u < R; ++u) {
-                if (v[u] != 0u) {
-                    hk[o] = uint16_t(threadIdx.x * R + u);
-                    hc[o] = v[u];
-                    ++o;
-                    c[threadIdx.x * R + u] = 0u;
-                }
+        for (int u = 0; u < R; ++u) {
+            if (v[u] != 0u) {
+                hk[o] = uint16_t(threadIdx.x * R + u);
+                hc[o] = v[u];
+                ++o;
+                c[threadIdx.x * R + u] = 0u;
             }
         }
         if (threadIdx.x == 0) gp(J.hnu)[b] = nuniq;
-        __syncthreads();  // every touched counter is cleared and the mask was read
-        if (threadIdx.x < kGroups / 32) touched[threadIdx.x] = 0u;
         // the small-bucket bitmap must start empty
         for (int t = threadIdx.x; t < kHistLow / 32; t += kHistThreads) s_bits[t] = 0u;
         __syncthreads();
