@@ -404,7 +404,14 @@ struct EventPair {
 cq_status run_histogram(Batch& b)
 {
     const int total = b.set_map(kMapHist, [&](int j) { return hist_blocks(hist_pixels(b.h[j])); });
-    const int count = b.set_map(kMapHistCount, [&](int j) { return hist_count_blocks(hist_pixels(b.h[j])); });
+    // Counting blocks: 256 or more per job, so that a few images fill the
+    // chip; 64 or more where the batch needs many rounds of resident blocks
+    // anyway (about 1024 of them), since a small image's blocks mostly find
+    // empty buckets and each block has a fixed cost.
+    int64_t at256 = 0;
+    for (const JobDev& J : b.h) at256 += hist_count_blocks(hist_pixels(J), 256);
+    const int cmin = at256 >= 8 * 1024 ? 64 : 256;
+    const int count = b.set_map(kMapHistCount, [&](int j) { return hist_count_blocks(hist_pixels(b.h[j]), cmin); });
     int64_t max_tiles = 1;
     for (const JobDev& J : b.h) max_tiles = hist_tiles(hist_pixels(J)) > max_tiles ? hist_tiles(hist_pixels(J)) : max_tiles;
     CQ_TRY(upload(b));

@@ -89,7 +89,7 @@ struct Batch {
 
 // kernels launched from the other translation units
 int hist_blocks(int64_t npix);
-int hist_count_blocks(int64_t npix);
+int hist_count_blocks(int64_t npix, int min_blocks);
 cq_status launch_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, uint32_t* keys,
                             uint32_t* counts, hipStream_t s);
 cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_hist_blocks, int total_count,

@@ -223,8 +223,8 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_part(const JobDev* __rest
     }
 }
 
-// Per job, hist_count_blocks(npix) blocks (a power of two from 256 up to one
-// per bucket); block c of C takes the virtual buckets c, c + C, ....  Virtual
+// Per job, hist_count_blocks(npix) blocks (a power of two from 64 or 256 up
+// to one per bucket); block c of C takes the virtual buckets c, c + C, ....  Virtual
 // bucket v = 8 j + x is bucket 256 (j / 32) + 32 x + j mod 32.  Workgroups
 // are handed to the eight XCDs in turn, so x = v mod 8 is the block's XCD (C
 // and every job's first block index are multiples of 8), and an XCD takes
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(kHistThreads, 4) k_hist_count(const JobDev* __
     // small buckets: keys present and their ranks; large ones: segment starts of a window
     __shared__ __align__(8) uint32_t s_bits[kHistWindow / 32];
     __shared__ uint32_t s_total, s_start, s_nseg;
-    __shared__ int s_def[kHistThreads / 64], s_ndef;  // buckets the wave pass leaves to the block
+    __shared__ int s_def[kHistBuckets / 64], s_ndef;  // buckets the wave pass leaves to the block (C >= 64)
     extern __shared__ uint32_t seg[];  // [ntiles + 1] starts, then [ntiles] offsets
     uint32_t* s_wpre = s_bits + kHistLow / 32;
     static_assert(kHistWindow / 32 >= 2 * (kHistLow / 32), "the small-bucket arrays fit the window bitmap");
@@ -286,21 +286,20 @@ __global__ void __launch_bounds__(kHistThreads, 4) k_hist_count(const JobDev* __
         const int j = vb >> 3;
         return (j >> 5) * 256 + (vb & 7) * 32 + (j & 31);
     };
-    // Wave pass (small images, whose tiles fit one wave, and blocks of at
-    // most one bucket per wave): wave w takes the block's bucket w on its
-    // own, with no block barrier.  Lane t scans tile t's segment; an empty
+    // Wave pass (small images, whose tiles fit one wave): wave w takes the
+    // block's buckets w, w + 8, ... on its own, with no block barrier.  Lane t scans tile t's segment; an empty
     // bucket, or one of at most 64 pixels, is finished here: each lane takes
     // one pixel (its tile is the last non-empty one starting at or before
     // it: a prefix maximum over positions marked in a 64-byte LDS row), the
     // wave sorts the keys (bitonic, across lanes), and the first lane of each
     // run of equal keys writes the key and the run's length at its rank.
     // Larger buckets are left to the block-wide code below.
-    const bool wave_pass = ntiles <= 64 && nmine <= kHistThreads / 64;
+    const bool wave_pass = ntiles <= 64 && nmine <= kHistBuckets / 64;
     if (wave_pass) {
         if (threadIdx.x == 0) s_ndef = 0;
         __syncthreads();
-        if (wave < nmine) {
-            const int b = bucket_of(wave);
+        for (int wi = wave; wi < nmine; wi += kHistThreads / 64) {
+            const int b = bucket_of(wi);
             const uint32_t m = lane < ntiles ? mat[int64_t(lane) * kHistBuckets + b] : 0u;
             const uint32_t len = m & 0xffffu, sst = m >> 16;
             const uint64_t v = (uint64_t(len != 0u) << 32) | len;
@@ -551,10 +550,10 @@ __global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __rest
 int hist_blocks(int64_t npix) { return int(hist_tiles(npix)); }
 
 // Counting blocks of a job: about one per 4096 pixels, a power of two
-// between 256 and one per bucket.
-int hist_count_blocks(int64_t npix)
+// between min_blocks (64 or 256) and one per bucket.
+int hist_count_blocks(int64_t npix, int min_blocks)
 {
-    int c = 256;
+    int c = min_blocks;
     while (c < kHistBuckets && int64_t(c) * 4096 < npix) c <<= 1;
     return c;
 }
