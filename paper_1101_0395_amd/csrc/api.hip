@@ -407,7 +407,8 @@ cq_status run_histogram(Batch& b)
     // Counting blocks: 256 or more per job, so that a few images fill the
     // chip; 64 or more where the batch needs many rounds of resident blocks
     // anyway (about 1024 of them), since a small image's blocks mostly find
-    // empty buckets and each block has a fixed cost.
+    // empty buckets and each block has a fixed cost; the pairs are then
+    // emitted four buckets per wave for the same reason.
     int64_t at256 = 0;
     for (const JobDev& J : b.h) at256 += hist_count_blocks(hist_pixels(J), 256);
     const int cmin = at256 >= 8 * 1024 ? 64 : 256;
@@ -415,7 +416,7 @@ cq_status run_histogram(Batch& b)
     int64_t max_tiles = 1;
     for (const JobDev& J : b.h) max_tiles = hist_tiles(hist_pixels(J)) > max_tiles ? hist_tiles(hist_pixels(J)) : max_tiles;
     CQ_TRY(upload(b));
-    return launch_histogram(b.d_jobs(), b.d_maps(), b.B, total, count, int(max_tiles), b.s);
+    return launch_histogram(b.d_jobs(), b.d_maps(), b.B, total, count, int(max_tiles), cmin == 64 ? 4 : 1, b.s);
 }
 
 // Once N' is known (from the histogram or from the caller).

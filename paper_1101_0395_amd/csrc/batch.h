@@ -93,7 +93,7 @@ int hist_count_blocks(int64_t npix, int min_blocks);
 cq_status launch_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t row_stride, uint32_t* keys,
                             uint32_t* counts, hipStream_t s);
 cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_hist_blocks, int total_count,
-                           int max_tiles, hipStream_t s);
+                           int max_tiles, int emit_per_wave, hipStream_t s);
 // One cooperative initialization launch: the kernel variant (8 or 32
 // colours per thread in registers; 0: D^2 in global memory), its jobs and
 // their team sizes.

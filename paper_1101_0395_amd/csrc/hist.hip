@@ -500,47 +500,51 @@ __global__ void __launch_bounds__(kHistThreads, 4) k_hist_count(const JobDev* __
 // The (key, count) pairs of every bucket, at the bucket's first output entry
 // (the exclusive prefix of the unique counts of the buckets, which each block
 // computes for itself from the 2048 counts); entries past `capacity` are not
-// written.  One wave per bucket, kHistThreads / 64 buckets per block; the
-// first block of a job also stores N'.
+// written.  Wave w of a block takes the buckets w, w + 8, ... of the block's
+// kEmitPerBlock * per_wave (per_wave 1, or 4 in a batch of many small images,
+// where the prefix would otherwise cost more than the pairs); the first
+// block of a job also stores N'.
 constexpr int kEmitPerBlock = kHistThreads / 64;
 
-__global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __restrict__ jobs)
+__global__ void __launch_bounds__(kHistThreads) k_hist_emit(const JobDev* __restrict__ jobs, int per_wave)
 {
     __shared__ uint32_t us[kHistBuckets];
     __shared__ uint32_t tmp[64];
-    constexpr int kBlocksPerJob = kHistBuckets / kEmitPerBlock;
-    const JobDev& J = jobs[blockIdx.x / kBlocksPerJob];
-    const int blk = blockIdx.x % kBlocksPerJob;
+    const int blocks_per_job = kHistBuckets / (kEmitPerBlock * per_wave);
+    const JobDev& J = jobs[blockIdx.x / blocks_per_job];
+    const int blk = blockIdx.x % blocks_per_job;
     const uint32_t n_unique = bucket_scan(gp(J.hnu), us, tmp);
     if (blk == 0 && threadIdx.x == 0) gp(J.meta)->n_unique = int64_t(n_unique);
     __syncthreads();
-    const int b = blk * kEmitPerBlock + int(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const uint32_t nb = gp(J.hnu)[b];
-    if (nb == 0) return;
-    const uint32_t start = gp(J.hbs)[b];
-    const uint16_t* __restrict__ hk = gp(J.hk2) + start;
-    const uint32_t* __restrict__ hc = gp(J.hcnt) + start;
-    const int64_t out = us[b];
-    uint32_t* __restrict__ keys = gp(J.keys);
-    uint32_t* __restrict__ counts = gp(J.counts);
-    const int64_t capacity = J.capacity;
-    constexpr int kUnroll = 16;  // loads in flight per lane (a bucket of a large image holds thousands)
-    for (uint32_t j0 = 0; j0 < nb; j0 += kUnroll * 64) {
-        uint32_t kq[kUnroll], cq[kUnroll];
+    for (int i = 0; i < per_wave; ++i) {
+        const int b = (blk * per_wave + i) * kEmitPerBlock + int(threadIdx.x >> 6);
+        const uint32_t nb = gp(J.hnu)[b];
+        if (nb == 0) continue;
+        const uint32_t start = gp(J.hbs)[b];
+        const uint16_t* __restrict__ hk = gp(J.hk2) + start;
+        const uint32_t* __restrict__ hc = gp(J.hcnt) + start;
+        const int64_t out = us[b];
+        uint32_t* __restrict__ keys = gp(J.keys);
+        uint32_t* __restrict__ counts = gp(J.counts);
+        const int64_t capacity = J.capacity;
+        constexpr int kUnroll = 16;  // loads in flight per lane (a bucket of a large image holds thousands)
+        for (uint32_t j0 = 0; j0 < nb; j0 += kUnroll * 64) {
+            uint32_t kq[kUnroll], cq[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint32_t j = j0 + u * 64 + lane;
-            kq[u] = j < nb ? uint32_t(hk[j]) : 0u;
-            cq[u] = j < nb ? hc[j] : 0u;
-        }
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t j = j0 + u * 64 + lane;
+                kq[u] = j < nb ? uint32_t(hk[j]) : 0u;
+                cq[u] = j < nb ? hc[j] : 0u;
+            }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint32_t j = j0 + u * 64 + lane;
-            const int64_t o = out + j;
-            if (j < nb && o < capacity) {
-                keys[o] = (uint32_t(b) << kHistLowBits) | kq[u];
-                counts[o] = cq[u];
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t j = j0 + u * 64 + lane;
+                const int64_t o = out + j;
+                if (j < nb && o < capacity) {
+                    keys[o] = (uint32_t(b) << kHistLowBits) | kq[u];
+                    counts[o] = cq[u];
+                }
             }
         }
     }
@@ -584,14 +588,15 @@ cq_status launch_pixel_keys(const uint8_t* img, int32_t H, int32_t W, int64_t ro
 }
 
 cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total_tiles, int total_count,
-                           int max_tiles, hipStream_t s)
+                           int max_tiles, int emit_per_wave, hipStream_t s)
 {
     const int* tmap = maps + kMapHist * (B + 1);
     const int* cmap = maps + kMapHistCount * (B + 1);
     const size_t seg_lds = sizeof(uint32_t) * (2 * size_t(max_tiles) + 1);
     CQ_TIMED_LAUNCH("k_hist_part", s, k_hist_part<<<total_tiles, kHistThreads, 0, s>>>(jobs, tmap, B));
     CQ_TIMED_LAUNCH("k_hist_count", s, k_hist_count<<<total_count, kHistThreads, seg_lds, s>>>(jobs, cmap, B));
-    CQ_TIMED_LAUNCH("k_hist_emit", s, k_hist_emit<<<kHistBuckets / kEmitPerBlock * B, kHistThreads, 0, s>>>(jobs));
+    CQ_TIMED_LAUNCH("k_hist_emit", s, k_hist_emit<<<kHistBuckets / (kEmitPerBlock * emit_per_wave) * B, kHistThreads, 0, s>>>(
+                                           jobs, emit_per_wave));
     return CQ_OK;
 }
 
