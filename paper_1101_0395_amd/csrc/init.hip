@@ -1078,7 +1078,9 @@ int coop_capacity(int variant)
 //  - up to kInitMaxBlocks x 32768 colours: teams of ceil(n / (R T))
 //    register blocks, with the smallest R for which the launch's teams fit
 //    the capacity (fewer colours per thread, less of each round's work per
-//    block), R = 32 when only that fits;
+//    block), R = 32 when only that fits; while jobs of the first class are
+//    left, such a launch keeps R = 32 and fills the CUs its teams leave with
+//    them (largest first), so that they need fewer launches of their own;
 //  - more: kInitMaxBlocks blocks of the kernel that keeps D^2 in global
 //    memory.
 cq_status plan_coop(const std::vector<int64_t>& n, std::vector<CoopLaunch>& plan)
@@ -1106,8 +1108,17 @@ cq_status plan_coop(const std::vector<int64_t>& n, std::vector<CoopLaunch>& plan
         while (v < kBig && coop_reg_colours(kCoopR[v]) < cnt) ++v;
         return v;
     };
+    // single-block jobs not yet placed: the tail of `order`, largest first,
+    // from `small`; a launch of teams takes them into the CUs its teams leave
+    std::vector<char> placed(n.size(), 0);
+    size_t small = order.size();
+    while (small > 0 && cls(order[small - 1]) == 2) --small;
     size_t q = 0;
     while (q < order.size()) {
+        if (placed[order[q]]) {
+            ++q;
+            continue;
+        }
         const int c = cls(order[q]);
         CoopLaunch w;
         const int v0 = c == 2 ? fit(n[order[q]]) : kBig;  // the launch's largest job comes first
@@ -1115,6 +1126,10 @@ cq_status plan_coop(const std::vector<int64_t>& n, std::vector<CoopLaunch>& plan
         int used = 0;
         while (q < order.size() && cls(order[q]) == c) {
             const int j = order[q];
+            if (placed[j]) {
+                ++q;
+                continue;
+            }
             int g = 1;
             if (c == 0) g = kInitMaxBlocks < capw ? kInitMaxBlocks : capw;
             if (c == 1) g = blocks_at(n[j], cmax);
@@ -1125,7 +1140,9 @@ cq_status plan_coop(const std::vector<int64_t>& n, std::vector<CoopLaunch>& plan
             ++q;
         }
         w.variant = c == 0 ? 0 : kCoopR[v0];
-        if (c == 1) {
+        bool smalls_left = false;
+        for (size_t i = small; i < order.size() && !smalls_left; ++i) smalls_left = !placed[order[i]];
+        if (c == 1 && !smalls_left) {
             // the smallest R whose teams fit
             for (int v = 0; v < kBig; ++v) {
                 const int64_t per = coop_reg_colours(kCoopR[v]);
@@ -1141,6 +1158,19 @@ cq_status plan_coop(const std::vector<int64_t>& n, std::vector<CoopLaunch>& plan
                     for (size_t i = 0; i < w.jobs.size(); ++i) w.blocks[i] = blocks_at(n[w.jobs[i]], per);
                     break;
                 }
+            }
+        }
+        if (c == 1 && smalls_left) {
+            // R = 32 (the fewest blocks per team) and the CUs left over to
+            // single-block jobs, largest first: they then need no launch of
+            // their own
+            for (size_t i = small; i < order.size() && used < capw; ++i) {
+                const int j = order[i];
+                if (placed[j]) continue;
+                w.jobs.push_back(j);
+                w.blocks.push_back(1);
+                placed[j] = 1;
+                ++used;
             }
         }
         plan.push_back(std::move(w));
