@@ -167,3 +167,29 @@ def test_benchmark_batch_matches_oracle(cqm, dev):
         for key in ("iters", "converged", "k_used", "n_unique", "ndc_total", "near_ties", "sse_final", "mse_float",
                     "mse_img"):
             assert st[key] == rs[key], (s, key)
+
+
+def test_init_launch_shares_cus_between_teams_and_single_blocks(cqm, dev):
+    """k-means++ and max-min jobs of more than 32768 colours (teams of
+    several blocks) and of fewer (one block each) in one batch: the launch
+    plan puts the single-block jobs into the CUs the teams leave, so they run
+    in the teams' launch.  Every job equals the oracle bit for bit."""
+    _say("init launch of teams and single-block jobs")
+    specs = [(300, 260, 64, oracle.INIT_KMEANSPP, 21), (280, 300, 64, oracle.INIT_MAXMIN, 22),
+             (320, 320, 256, oracle.INIT_KMEANSPP, 23)]
+    specs += [(40 + 7 * i, 50 + 5 * i, 16 if i % 2 else 64,
+               oracle.INIT_MAXMIN if i % 3 == 0 else oracle.INIT_KMEANSPP, 30 + i) for i in range(20)]
+    imgs = [_image(H, W, seed) for H, W, _, _, seed in specs]
+    jobs = [cqm.BatchJob(torch.from_numpy(im).to(dev), K, scheme, seed, 3, 1e-4, True)
+            for im, (H, W, K, scheme, seed) in zip(imgs, specs)]
+    ws = cqm.BatchWorkspace(jobs, dev)
+    stats = cqm.cq_quantize_batch(jobs, ws)
+    sizes = []
+    for job, im, st, (H, W, K, scheme, seed) in zip(jobs, imgs, stats, specs):
+        rp, ri, rr, rs = oracle.quantize(im, K, scheme, seed, 3, 1e-4, prune=True)
+        sizes.append(rs["n_unique"])
+        assert np.array_equal(job.palette.cpu().numpy(), rp), (H, W)
+        assert np.array_equal(job.idx.cpu().numpy(), ri), (H, W)
+        for key in ("iters", "k_used", "n_unique", "ndc_total", "near_ties", "sse_final"):
+            assert st[key] == rs[key], (H, W, key)
+    assert all(n > 32768 for n in sizes[:3]) and all(n <= 32768 for n in sizes[3:]), sizes
