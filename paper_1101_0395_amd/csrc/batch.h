@@ -9,6 +9,7 @@
 #include <deque>
 #include <vector>
 
+#include "coop_plan.h"
 #include "cq_internal.h"
 
 namespace cq {
@@ -97,11 +98,6 @@ cq_status launch_histogram(const JobDev* jobs, const int* maps, int B, int total
 // One cooperative initialization launch: the kernel variant (8 or 32
 // colours per thread in registers; 0: D^2 in global memory), its jobs and
 // their team sizes.
-struct CoopLaunch {
-    int variant = 32;
-    std::vector<int> jobs;
-    std::vector<int> blocks;
-};
 int coop_capacity(int variant);
 int64_t coop_reg_colours(int R);
 cq_status plan_coop(const std::vector<int64_t>& n, std::vector<CoopLaunch>& plan);

@@ -33,6 +33,16 @@ def test_engine_pool_allocator_matches_byte_map_model(tmp_path):
     assert " 0 mismatches" in out.stdout
 
 
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_cooperative_init_launch_plan(tmp_path):
+    exe = tmp_path / "coop_plan_check"
+    src = os.path.join(ROOT, "tests", "host", "coop_plan_check.cpp")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-I", CSRC, src, "-o", str(exe)],
+                   check=True, capture_output=True, text=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
+
+
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
 def test_public_structs_match_binding_layout(tmp_path):
     import ctypes
